@@ -1,0 +1,180 @@
+"""Benchmark: exponential-midpoint steps per second on one MI355X.
+
+Workload (default): the 4,096-atom diamond-like lattice with 13 functions per
+atom (53,248 x 53,248 complex K), cut-offs R_HS 10, R_K 16 and R_P 16 bohr,
+H = H0 + 0.5 diag(Mulliken charges) rebuilt every step, dt 0.05 a.u.  Every
+step rebuilds A = P(X H), the 6-term Taylor propagator and K <- U K U^dagger.
+Inputs are synthetic and seeded; all of them are resident in HBM before the
+timed region starts.
+
+Prints ONE JSON line with steps/s, the roofline of the dominant product
+kernel (algorithmic flops per launch over its average HIP-event duration) and
+the oracle's CPU rate on a bounded sample.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 (matrix and vector)
+METRIC = "propagation steps/s + block-SpGEMM GFLOP/s (% roofline) at stated dipole error vs FP64"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def make_workload(args):
+    from paper_1404_5776_amd import synth
+    cells = tuple(int(x) for x in args.cells.split("x"))
+    s = synth.config2(cells=cells, n_steps=args.steps)
+    return s
+
+
+def gpu_run(s, args):
+    import torch  # device memory and streams come from torch's runtime
+    from paper_1404_5776_amd import rtdm
+
+    torch.cuda.init()
+    stream = torch.cuda.current_stream()
+    ctx = rtdm.Context(0, h_model=s.h_model, h_gain=s.h_gain)
+    t = time.time()
+    ctx.load_system(s, stream)
+    log(f"set-up (neighbour lists, schedules, upload) {time.time() - t:.1f} s")
+    t = time.time()
+    iters, res = rtdm.rtdm_build_inverse(ctx.h, stream)
+    log(f"Hotelling inverse: {iters} iterations, residual {res:.2e}, {time.time() - t:.1f} s")
+    rtdm.rtdm_apply_kick(ctx.h, s.kappa, stream)
+    sched = {k: rtdm.rtdm_schedule_stats(ctx.h, k) for k in ("XH", "AT", "UK", "WU")}
+    log("triples per product:", {k: v[1] for k, v in sched.items()})
+    if args.warmup:
+        rtdm.rtdm_step(ctx.h, s.dt, args.warmup, stream)
+    torch.cuda.synchronize()
+    rtdm.rtdm_timing(ctx.h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rtdm.rtdm_step(ctx.h, s.dt, args.steps, stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = {k: rtdm.rtdm_timing_stats(ctx.h, k) for k in ("XH", "AT", "UK", "WU")}
+    rtdm.rtdm_timing(ctx.h, False)
+    trace = rtdm.rtdm_dipole_trace(ctx.h)
+    ctx.close()
+    return t1 - t0, stats, sched, trace
+
+
+def cpu_baseline(s, target_s: float):
+    """Oracle product rate on a bounded row sample of each product kind, scaled to steps/s."""
+    from oracle import oracle as O
+
+    st = O.setup(s)
+    rng = np.random.default_rng(0)
+    b = s.b
+    M = O.BSM(st.pat_p, b, rng.uniform(-1, 1, (st.pat_p.nnzb, b, b)) + 0j)
+    Kc = M if st.pat_k is st.pat_p else O.BSM(st.pat_k, b, rng.uniform(-1, 1, (st.pat_k.nnzb, b, b)) + 0j)
+    kinds = {"XH": (M, st.H0, st.pat_p, 0), "AT": (M, M, st.pat_p, 0), "UK": (M, Kc, st.pat_k, 0),
+             "WU": (Kc, M, st.pat_k, 1)}
+    per_kind = target_s / len(kinds)
+    rate = {}
+    total_rows = 0
+    for k, (A, B, pc, ob) in kinds.items():
+        rows = 8
+        while True:
+            lo = s.n_atoms // 2 - rows // 2
+            t = time.perf_counter()
+            _, trip = O.spgemm(A, B, pc, op_b=ob, rows=(lo, lo + rows))
+            dt = time.perf_counter() - t
+            if dt > 0.25 * per_kind or rows >= s.n_atoms:
+                break
+            rows = min(s.n_atoms, rows * 4)
+        rate[k] = trip / dt
+        total_rows += rows
+    return rate, total_rows
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cells", default="8x8x8", help="diamond conventional cells (8 atoms each)")
+    ap.add_argument("--cpu-seconds", type=float, default=16.0, help="oracle sample budget")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU design (spatial "
+                                   "domain decomposition with halo exchange) is described in DESIGN.md",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    t = time.time()
+    s = make_workload(args)
+    log(f"workload {s.name}: {s.n_atoms} atoms, b={s.b}, generated in {time.time() - t:.1f} s")
+    elapsed, stats, sched, trace = gpu_run(s, args)
+    steps_per_s = args.steps / elapsed
+
+    # dominant product kernel: the kind with the most kernel time
+    dom = max(stats, key=lambda k: stats[k][1])
+    n_l, ms, fl = stats[dom]
+    avg_s = ms / 1e3 / n_l
+    achieved = fl / n_l / avg_s / 1e12
+    tot_fl = sum(v[2] for v in stats.values())
+    tot_ms = sum(v[1] for v in stats.values())
+    flops_per_step = tot_fl / args.steps
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        t = time.time()
+        rate, rows = cpu_baseline(s, args.cpu_seconds)
+        # oracle seconds per step = sum over the step's products of triples / (triples per second)
+        per_step = {"XH": 1, "AT": 4, "UK": 1, "WU": 1}
+        sec = sum(per_step[k] * sched[k][1] / rate[k] for k in per_step)
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        cpu = {"value": 1.0 / sec, "unit": "steps/s", "cores": threads, "kind": "oracle",
+               "sample": f"oracle masked block products (complex128) on {rows} output atom rows of the "
+                         f"XH, AT, UK and WU products of this workload, triples/s per kind scaled by the "
+                         f"per-step triple counts (1 XH + 4 AT + 1 UK + 1 WU); {time.time() - t:.0f} s wall"}
+
+    out = {
+        "metric": METRIC,
+        "value": steps_per_s,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"diamond lattice {s.n_atoms} atoms x {s.b} functions, R_HS {s.R_HS} "
+                               f"R_P {s.R_P} R_K {s.R_K} bohr, Mulliken on-site H, EM + Taylor p=5, "
+                               f"dt {s.dt}",
+                   "atoms": s.n_atoms, "b": s.b},
+        "spgemm_gflops": tot_fl / (tot_ms / 1e3) / 1e9,
+        "spgemm_tflop_per_step": flops_per_step / 1e12,
+        "accuracy": "FP64 path; equals the FP64 oracle within 1e-10 relative in the parity tests, "
+                    "so its dipole error vs FP64 is at that level",
+        "roofline": {"bound": "mfma", "kernel": f"k_spgemm16 ({dom} product)", "achieved": achieved,
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": None, "avg_launch_ms": avg_s * 1e3,
+                     "flops_per_launch": fl / n_l},
+        "per_product_ms": {k: v[1] / max(v[0], 1) for k, v in stats.items()},
+        "trace_last": trace[-1, :6].tolist() if len(trace) else None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,232 @@
+/*
+ * rtdm.h -- truncated block-sparse density-matrix RT-TDDFT propagation on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library evolves the auxiliary density matrix K of a linear-scaling DFT
+ * code under the quantum Liouville equation in a non-orthogonal basis
+ * (O'Rourke & Bowler, arXiv:1404.5776, Sec. II.A):
+ *
+ *     i dK/dt = S^-1 H K - K H S^-1,   K(t+dt) = U K(t) U^dagger,
+ *     U = exp(-i S^-1 H(t+dt/2) dt)          (exponential midpoint, Eq. EM)
+ *
+ * with the exponential taken as a truncated Taylor series (Eq. matrix_exp,
+ * Sec. IV.B), S^-1 from Hotelling's iteration (Sec. V.A), and every matrix and
+ * every product truncated to a spatial cut-off radius on atom pairs
+ * (Sec. II.A, Sec. V.A, Sec. V.B).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns an int status: RTDM_OK (0) or a negative RTDM_E_*
+ *   code.  No C++ exception crosses this boundary.  rtdm_last_error(ctx)
+ *   returns a message for the last failing call on ctx (valid until the next
+ *   call on ctx).
+ * - A context is not thread-safe: use one context per host thread.
+ * - Atomic units: positions in bohr, time in a.u. (hbar = 1), energies in Ha.
+ * - Atoms keep the caller's order.  Matrices are stored in atom-pair blocks;
+ *   block (i, j) of a matrix of range R exists iff i == j or
+ *   dx*dx + dy*dy + dz*dz < R*R (double precision, no periodic images).
+ * - Blocks passed across the boundary are b x b row-major.  Complex data is
+ *   interleaved (re, im) double pairs ("complex128"); real data is double.
+ * - Host buffers stay owned by the caller and are copied; device buffers
+ *   passed in are read (or written) during the call on the given stream.
+ *   Device memory for the library's own state is allocated by the library
+ *   (hipMalloc) in set_ranges / upload / build_inverse and freed by
+ *   rtdm_destroy; rtdm_step allocates only when its observable buffer must
+ *   grow.
+ * - `hip_stream` is a hipStream_t (NULL = the device's null stream).  Calls
+ *   that take a stream enqueue work on it and return without waiting, except
+ *   those documented as synchronising (they return host scalars).
+ */
+#ifndef RTDM_H
+#define RTDM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rtdm_ctx rtdm_ctx;
+
+/* Status codes. */
+enum {
+    RTDM_OK = 0,
+    RTDM_E_ARG = -1,          /* bad argument (size, pointer, enum value) */
+    RTDM_E_STATE = -2,        /* call out of order (e.g. step before build_inverse) */
+    RTDM_E_OOM = -3,          /* device or host allocation failed */
+    RTDM_E_HIP = -4,          /* a HIP runtime call failed */
+    RTDM_E_NOCONV = -5,       /* Hotelling iteration did not converge */
+    RTDM_E_NUMERIC = -6,      /* non-finite value detected */
+    RTDM_E_UNSUPPORTED = -7   /* valid request this build does not implement */
+};
+
+/* Matrix slots.  Range and value type of each slot:
+ *   S, H0, H : R_HS, real symmetric (S: overlap, Sec. II.A; H0: Hamiltonian
+ *              as uploaded; H: the Hamiltonian used by the last propagator
+ *              build, H0 plus the on-site model shift)
+ *   X        : R_P,  real, the truncated inverse overlap (Sec. V.A)
+ *   A        : R_P,  real, the truncated product S^-1 H (Sec. V.A)
+ *   U        : R_P,  complex, the Taylor propagator (Eq. EM, Eq. matrix_exp)
+ *   K        : R_K,  complex Hermitian, the density matrix (Sec. II.A)
+ *   W        : R_K,  complex, the intermediate U K of the last step
+ * For tests, any slot may be uploaded and used as an operand of rtdm_multiply. */
+typedef enum {
+    RTDM_MAT_S = 0,
+    RTDM_MAT_H0 = 1,
+    RTDM_MAT_H = 2,
+    RTDM_MAT_X = 3,
+    RTDM_MAT_A = 4,
+    RTDM_MAT_U = 5,
+    RTDM_MAT_K = 6,
+    RTDM_MAT_W = 7,
+    RTDM_MAT_COUNT = 8
+} rtdm_mat;
+
+/* The truncated products of one step and of the inverse iteration. */
+typedef enum {
+    RTDM_PROD_XH = 0,   /* A = P_P(X H)                  (Sec. V.A)            */
+    RTDM_PROD_AT = 1,   /* T_n = P_P(c A T_{n-1})        (Eq. matrix_exp)      */
+    RTDM_PROD_UK = 2,   /* W = P_K(U K)                  (Sec. II.A solution)  */
+    RTDM_PROD_WU = 3,   /* K' = P_K(W U^dagger)          (Sec. II.A solution)  */
+    RTDM_PROD_SX = 4,   /* P_P(S X), also P_P(S U)       (Sec. V.A, Sec. IV)   */
+    RTDM_PROD_UV = 5,   /* P_P(U^dagger V)               (Sec. IV, Eq. s_unit) */
+    RTDM_PROD_COUNT = 6
+} rtdm_prod;
+
+enum { RTDM_PREC_FP64 = 0 };
+enum { RTDM_HMODEL_FIXED = 0, RTDM_HMODEL_MULLIKEN = 1 };
+enum { RTDM_INV_BLOCK_JACOBI = 0, RTDM_INV_COLD = 1, RTDM_INV_PREVIOUS = 2 };
+
+/* Options of a context (rtdm_default_options fills the defaults). */
+typedef struct {
+    int taylor_order;      /* p: Taylor orders 0..p of the exponential (Sec. IV.B: six terms -> 5) */
+    int unit_check_every;  /* m > 0: record ||U^dagger S U - S|| every m steps; 0: never */
+    int precision;         /* RTDM_PREC_FP64 */
+    int h_model;           /* RTDM_HMODEL_FIXED: H = H0; MULLIKEN: H = H0 + g diag(q_mid - q_ref) */
+    double h_gain;         /* g of the on-site model (default 0.5) */
+    int inv_start;         /* starting guess of the inverse iteration (default block-Jacobi) */
+    double inv_tol;        /* stop when ||X_{k+1}-X_k||_F / ||X_{k+1}||_F <= tol (default 1e-10) */
+    int inv_max_iter;      /* iteration cap (default 50) */
+} rtdm_options;
+
+/* Fill *opt with the defaults above.  Never fails for a non-NULL opt. */
+int rtdm_default_options(rtdm_options *opt);
+
+/* Create a context on HIP device `hip_device` (opt NULL = defaults).
+ * *out receives the context; the caller releases it with rtdm_destroy. */
+int rtdm_create(rtdm_ctx **out, int hip_device, const rtdm_options *opt);
+
+/* Release every host and device resource of ctx (NULL is accepted). */
+int rtdm_destroy(rtdm_ctx *ctx);
+
+/* Set the atoms: xyz[n][3] (bohr, host, copied) and nbf[n] functions per atom.
+ * This build requires every nbf[i] to be equal and in 1..16
+ * (RTDM_E_UNSUPPORTED otherwise).  Invalidates ranges, matrices and schedules. */
+int rtdm_set_geometry(rtdm_ctx *ctx, int64_t n_atoms, const double *xyz, const int32_t *nbf);
+
+/* Set the cut-off radii (Sec. II.A, Sec. V.A): R_HS for S and H, R_P for
+ * S^-1, S^-1 H and U, R_K for K (R_P <= 0 selects max(R_HS, R_K)).  Builds the
+ * neighbour lists of each range and the symbolic schedules of every product
+ * of RTDM_PROD_* (on the device; the triple counts are then fixed).  Zeroes
+ * every matrix.  Synchronises the device. */
+int rtdm_set_ranges(rtdm_ctx *ctx, double R_HS, double R_P, double R_K);
+
+/* Pattern of a slot's range: CSR over atoms, *row_ptr has n+1 entries and
+ * *col_idx has *nnzb ascending atom indices per row.  Host pointers owned by
+ * ctx, valid until the next set_geometry / set_ranges / destroy. */
+int rtdm_pattern(rtdm_ctx *ctx, rtdm_mat mat, int64_t *n_rows, int64_t *nnzb,
+                 const int64_t **row_ptr, const int32_t **col_idx);
+
+/* Upload a slot from blocks in rtdm_pattern order (nnzb blocks of b*b).
+ * is_complex: 1 = complex128 interleaved, 0 = double.  is_device: data is a
+ * device pointer (1) or host pointer (0).  Real slots (S, H0, H, X, A) refuse
+ * complex data whose imaginary part is not zero (RTDM_E_UNSUPPORTED).
+ * Host uploads synchronise the stream before returning. */
+int rtdm_upload(rtdm_ctx *ctx, rtdm_mat mat, const void *data, int is_complex,
+                int is_device, void *hip_stream);
+
+/* Upload a slot from host blocks in any order: rows[t], cols[t] name the
+ * atom pair of block t (nnzb blocks of b*b, complex128 if is_complex else
+ * double).  Blocks absent from the list are zero; a pair outside the slot's
+ * range is RTDM_E_ARG.  Synchronises the stream. */
+int rtdm_upload_coo(rtdm_ctx *ctx, rtdm_mat mat, int64_t nnzb, const int32_t *rows,
+                    const int32_t *cols, const void *data, int is_complex, void *hip_stream);
+
+/* Download a slot as complex128 interleaved blocks in rtdm_pattern order
+ * (real slots get zero imaginary parts) into dst (host or device).
+ * Synchronises the stream. */
+int rtdm_download(rtdm_ctx *ctx, rtdm_mat mat, void *dst, int is_device, void *hip_stream);
+
+/* The impulsive limit of the field of Sec. II.B on K:
+ * K_ij <- exp(i kappa . (r_i - r_j)) K_ij.  Records q_ref = Mulliken charges
+ * of K before the kick (if not recorded since the last K upload) and resets
+ * the observable trace and the charge history of the midpoint extrapolation. */
+int rtdm_apply_kick(rtdm_ctx *ctx, const double kappa[3], void *hip_stream);
+
+/* Truncated Hotelling inverse of S (Sec. V.A):
+ * X_{k+1} = P_P(2 X_k - X_k P_P(S X_k)) from the options' starting guess,
+ * until ||X_{k+1}-X_k||_F/||X_{k+1}||_F <= inv_tol.  A residual that rises
+ * after the first iteration or is not finite falls back to the block-Jacobi
+ * start when the guess was RTDM_INV_PREVIOUS, else returns RTDM_E_NOCONV.
+ * iters / residual (may be NULL) receive the iteration count and last
+ * residual.  Synchronises (one scalar read per iteration). */
+int rtdm_build_inverse(rtdm_ctx *ctx, void *hip_stream, int *iters, double *residual);
+
+/* n_steps exponential-midpoint steps of length dt (Sec. II.A, Eq. EM, Eq.
+ * matrix_exp): per step the midpoint H (options' model), A = P_P(X H), the
+ * Taylor propagator U on R_P, W = P_K(U K), K' = P_K(W U^dagger),
+ * K <- (K' + K'^dagger)/2, then the observables of the new K appended to the
+ * trace.  With a fixed H the propagator of the first step is reused.
+ * Asynchronous on hip_stream. */
+int rtdm_step(rtdm_ctx *ctx, double dt, int64_t n_steps, void *hip_stream);
+
+/* Observables of the current K: out[0..2] dipole P = -sum_i (r_i - r_c) q_i
+ * (Sec. II.B, Mulliken charges q_i = Re sum_j tr(K_ij S_ji), r_c the centroid),
+ * out[3] Tr(K S) (Sec. IV), out[4] ||K'-K'^dagger||_F/||K'||_F of the last
+ * step's product before Hermitisation, out[5] relative unitarity error
+ * ||P_P(U^dagger P_P(S U)) - S||_F / ||S||_F of the current U (Eq. s_unit,
+ * computed now).  Synchronises. */
+int rtdm_observables(rtdm_ctx *ctx, double out[6], void *hip_stream);
+
+/* Copy the trace recorded since the last kick: row s (s = 0..rows-1) holds
+ * t, Px, Py, Pz, Tr(KS), herm_err, unit_err (NaN unless measured at that
+ * step) after step s+1.  out has room for max_rows rows of 7 doubles.
+ * Synchronises the device. */
+int rtdm_dipole_trace(rtdm_ctx *ctx, double *out, int64_t max_rows, int64_t *rows);
+
+/* Unitarity of the current U (Sec. IV, Eq. s_unit, read in the non-orthogonal
+ * metric): out[0] = ||D||_F/||S||_F, out[1] = mean |D_ab|, out[2] = max |D_ab|
+ * with D = P_P(U^dagger P_P(S U)) - S over R_P's pattern.  Synchronises. */
+int rtdm_unitarity(rtdm_ctx *ctx, double out[3], void *hip_stream);
+
+/* Test entry: C = P_C(alpha op(A) op(B)) on the slots' patterns, where op is
+ * the identity (0) or the conjugate transpose (1).  The (range(A), range(B),
+ * range(C), op_a, op_b) combination must be one of RTDM_PROD_* (else
+ * RTDM_E_UNSUPPORTED).  C becomes complex if A, B or alpha is.  Async. */
+int rtdm_multiply(rtdm_ctx *ctx, rtdm_mat C, rtdm_mat A, rtdm_mat B, int op_a, int op_b,
+                  double alpha_re, double alpha_im, void *hip_stream);
+
+/* Symbolic sizes of a product: number of output blocks and of (i,k,j) block
+ * triples that survive all three cut-offs (the algorithmic unit of work,
+ * 2 b^3 flops per real block product). */
+int rtdm_schedule_stats(rtdm_ctx *ctx, rtdm_prod prod, int64_t *outputs, int64_t *triples);
+
+/* Per-launch HIP-event timing of the block-product kernels, for measurement.
+ * enable = 1 starts recording (and clears earlier records), 0 stops. */
+int rtdm_timing(rtdm_ctx *ctx, int enable);
+
+/* Totals of the recorded product launches of one kind: launches, summed
+ * kernel milliseconds, summed algorithmic flops.  Synchronises. */
+int rtdm_timing_stats(rtdm_ctx *ctx, rtdm_prod prod, int64_t *launches, double *total_ms,
+                      double *flops);
+
+/* Message of the last failing call on ctx ("" if none; a static message for
+ * a NULL ctx). */
+const char *rtdm_last_error(const rtdm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTDM_H */

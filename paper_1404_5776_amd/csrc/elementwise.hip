@@ -1,0 +1,492 @@
+// Block-wise and reduction kernels around the truncated products: Taylor-sum
+// updates, Hermitisation, the kick, Mulliken charges, the on-site H model,
+// observables and the block-Jacobi start of the inverse iteration.
+//
+// Every reduction is deterministic: a fixed grid of kRedBlocks workgroups,
+// each thread summing a fixed strided subset in a fixed order, a fixed LDS
+// tree per workgroup, then one workgroup summing the partials in a fixed
+// tree.  Results are therefore bit-identical from run to run.
+#include <cmath>
+
+#include "internal.h"
+
+namespace rtdm {
+
+constexpr int kT = 256;
+
+// ----------------------------------------------------------------- helpers
+
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Fixed-tree reduction of 4 slots (0..2 sums, 3 max) over a workgroup of kT threads.
+__device__ inline void block_reduce4(double v[4], double *sh)
+{
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sh[k * kT + t] = v[k];
+    __syncthreads();
+    for (int w = kT / 2; w >= 1; w >>= 1) {
+        if (t < w) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) sh[k * kT + t] += sh[k * kT + t + w];
+            sh[3 * kT + t] = fmax(sh[3 * kT + t], sh[3 * kT + t + w]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = sh[k * kT];
+}
+
+__device__ inline void write_partials(double v[4], double *partials)
+{
+    __shared__ double sh[4 * kT];
+    block_reduce4(v, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) partials[blockIdx.x * 4 + k] = v[k];
+    }
+}
+
+// ----------------------------------------------------------------- elementwise
+
+__global__ void k_axpby(int64_t n, double a, const double *__restrict__ x, double c,
+                        const double *__restrict__ y, double *__restrict__ out)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x)
+        out[e] = y ? a * x[e] + c * y[e] : a * x[e];
+}
+
+void launch_axpby(hipStream_t s, int64_t n, double a, const double *x, double c, const double *y,
+                  double *out)
+{
+    if (n == 0) return;
+    int64_t g = (n + kT - 1) / kT;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_axpby, dim3((unsigned)g), dim3(kT), 0, s, n, a, x, c, y, out);
+    RT_HIP(hipGetLastError());
+}
+
+__global__ void k_add_identity(int64_t n_atoms, int b, const int32_t *__restrict__ diag, double val,
+                               double *__restrict__ m)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_atoms * b) return;
+    const int64_t i = e / b;
+    const int a = (int)(e % b);
+    m[(int64_t)diag[i] * b * b + a * b + a] += val;
+}
+
+void launch_add_identity(hipStream_t s, int64_t n_atoms, int b, const int32_t *diag, double val,
+                         double *m)
+{
+    const int64_t n = n_atoms * b;
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_add_identity, dim3((unsigned)((n + kT - 1) / kT)), dim3(kT), 0, s, n_atoms,
+                       b, diag, val, m);
+    RT_HIP(hipGetLastError());
+}
+
+__global__ void k_kick(int64_t nnzb, int b, const int32_t *__restrict__ rowof,
+                       const int32_t *__restrict__ col, const double *__restrict__ xyz, double kx,
+                       double ky, double kz, double *__restrict__ kr, double *__restrict__ ki)
+{
+    const int bb = b * b;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnzb * bb;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = e / bb;
+        const int i = rowof[p], j = col[p];
+        const double ph = kx * (xyz[3 * i] - xyz[3 * j]) + ky * (xyz[3 * i + 1] - xyz[3 * j + 1]) +
+                          kz * (xyz[3 * i + 2] - xyz[3 * j + 2]);
+        double sn, cs;
+        sincos(ph, &sn, &cs);
+        const double xr = kr[e], xi = ki[e];
+        kr[e] = cs * xr - sn * xi;
+        ki[e] = cs * xi + sn * xr;
+    }
+}
+
+void launch_kick(hipStream_t s, int64_t nnzb, int b, const int32_t *rowof, const int32_t *col,
+                 const double *xyz, double kx, double ky, double kz, double *kr, double *ki)
+{
+    const int64_t n = nnzb * b * b;
+    if (n == 0) return;
+    int64_t g = (n + kT - 1) / kT;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_kick, dim3((unsigned)g), dim3(kT), 0, s, nnzb, b, rowof, col, xyz, kx, ky,
+                       kz, kr, ki);
+    RT_HIP(hipGetLastError());
+}
+
+// K_ij[a][c] = (Kn_ij[a][c] + conj(Kn_ji[c][a])) / 2
+__global__ __launch_bounds__(kT) void k_hermitize(int64_t nnzb, int b,
+                                                  const int32_t *__restrict__ trans,
+                                                  const double *__restrict__ knr,
+                                                  const double *__restrict__ kni,
+                                                  double *__restrict__ kr, double *__restrict__ ki,
+                                                  double *__restrict__ partials)
+{
+    const int bb = b * b;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x; e < nnzb * bb;
+         e += (int64_t)kRedBlocks * kT) {
+        const int64_t p = e / bb;
+        const int w = (int)(e - p * bb);
+        const int a = w / b, c = w - a * b;
+        const int64_t pe = (int64_t)trans[p] * bb + c * b + a;
+        const double xr = knr[e], xi = kni[e], yr = knr[pe], yi = -kni[pe];
+        kr[e] = 0.5 * (xr + yr);
+        ki[e] = 0.5 * (xi + yi);
+        const double dr = xr - yr, di = xi - yi;
+        v[0] += dr * dr + di * di;
+        v[1] += xr * xr + xi * xi;
+    }
+    write_partials(v, partials);
+}
+
+void launch_hermitize(hipStream_t s, int64_t nnzb, int b, const int32_t *trans, const double *knr,
+                      const double *kni, double *kr, double *ki, double *partials)
+{
+    hipLaunchKernelGGL(k_hermitize, dim3(kRedBlocks), dim3(kT), 0, s, nnzb, b, trans, knr, kni, kr,
+                       ki, partials);
+    RT_HIP(hipGetLastError());
+}
+
+// One wave per atom: q_i = Re sum_{j in S row i, (i,j) in K} sum_{a,c} K_ij[a][c] S_ji[c][a]
+__global__ __launch_bounds__(kT) void k_mulliken(int64_t n_atoms, int b,
+                                                 const int64_t *__restrict__ s_ptr,
+                                                 const int32_t *__restrict__ s_trans,
+                                                 const int32_t *__restrict__ s_to_k,
+                                                 const double *__restrict__ sv,
+                                                 const double *__restrict__ kr,
+                                                 double *__restrict__ q)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * (kT / 64) + (threadIdx.x >> 6);
+    if (i >= n_atoms) return;
+    const int bb = b * b;
+    double acc = 0.0;
+    for (int64_t p = s_ptr[i]; p < s_ptr[i + 1]; ++p) {
+        const int kb = s_to_k[p];
+        if (kb < 0) continue;
+        const int64_t st = (int64_t)s_trans[p] * bb;
+        const int64_t kk = (int64_t)kb * bb;
+        for (int w = lane; w < bb; w += 64) {
+            const int a = w / b, c = w - a * b;
+            acc += kr[kk + w] * sv[st + c * b + a];
+        }
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) q[i] = acc;
+}
+
+void launch_mulliken(hipStream_t s, int64_t n_atoms, int b, const int64_t *s_ptr,
+                     const int32_t *s_trans, const int32_t *s_to_k, const double *sv,
+                     const double *kr, double *q)
+{
+    if (n_atoms == 0) return;
+    const int per = kT / 64;
+    hipLaunchKernelGGL(k_mulliken, dim3((unsigned)((n_atoms + per - 1) / per)), dim3(kT), 0, s,
+                       n_atoms, b, s_ptr, s_trans, s_to_k, sv, kr, q);
+    RT_HIP(hipGetLastError());
+}
+
+__global__ void k_onsite_shift(int64_t n_atoms, int b, const int32_t *__restrict__ diag,
+                               double gain, const double *__restrict__ q_cur,
+                               const double *__restrict__ q_prev, const double *__restrict__ q_ref,
+                               double *__restrict__ h)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_atoms * b) return;
+    const int64_t i = e / b;
+    const int a = (int)(e % b);
+    const double qmid = 1.5 * q_cur[i] - 0.5 * q_prev[i];
+    h[(int64_t)diag[i] * b * b + a * b + a] += gain * (qmid - q_ref[i]);
+}
+
+void launch_onsite_shift(hipStream_t s, int64_t n_atoms, int b, const int32_t *diag, double gain,
+                         const double *q_cur, const double *q_prev, const double *q_ref, double *h)
+{
+    const int64_t n = n_atoms * b;
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_onsite_shift, dim3((unsigned)((n + kT - 1) / kT)), dim3(kT), 0, s, n_atoms,
+                       b, diag, gain, q_cur, q_prev, q_ref, h);
+    RT_HIP(hipGetLastError());
+}
+
+// Single workgroup: centroid, dipole P = -sum (r_i - r_c) q_i, Tr(KS) = sum q_i.
+__global__ __launch_bounds__(kT) void k_observables(int64_t n, const double *__restrict__ xyz,
+                                                    const double *__restrict__ q,
+                                                    const double *__restrict__ herm_sums, double t,
+                                                    double *__restrict__ row)
+{
+    __shared__ double sh[4 * kT];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = threadIdx.x; i < n; i += kT) {
+        v[0] += xyz[3 * i];
+        v[1] += xyz[3 * i + 1];
+        v[2] += xyz[3 * i + 2];
+    }
+    block_reduce4(v, sh);
+    const double cx = v[0] / (double)n, cy = v[1] / (double)n, cz = v[2] / (double)n;
+    __syncthreads();
+    double w[4] = {0.0, 0.0, 0.0, 0.0};
+    double tr = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kT) {
+        const double qi = q[i];
+        w[0] -= (xyz[3 * i] - cx) * qi;
+        w[1] -= (xyz[3 * i + 1] - cy) * qi;
+        w[2] -= (xyz[3 * i + 2] - cz) * qi;
+        tr += qi;
+    }
+    w[3] = 0.0;
+    block_reduce4(w, sh);
+    __syncthreads();
+    double u[4] = {tr, 0.0, 0.0, 0.0};
+    block_reduce4(u, sh);
+    if (threadIdx.x == 0) {
+        row[0] = t;
+        row[1] = w[0];
+        row[2] = w[1];
+        row[3] = w[2];
+        row[4] = u[0];
+        row[5] = herm_sums ? (herm_sums[1] > 0.0 ? sqrt(herm_sums[0] / herm_sums[1]) : 0.0) : 0.0;
+        row[6] = __builtin_nan("");
+        row[7] = 0.0;
+    }
+}
+
+void launch_observables(hipStream_t s, int64_t n_atoms, const double *xyz, const double *q,
+                        const double *herm_sums, double t, double *row)
+{
+    hipLaunchKernelGGL(k_observables, dim3(1), dim3(kT), 0, s, n_atoms, xyz, q, herm_sums, t, row);
+    RT_HIP(hipGetLastError());
+}
+
+// One thread per atom: Gauss-Jordan with partial pivoting on [S_ii | I] in scratch.
+__global__ void k_block_inverse(int64_t n_atoms, int b, const int32_t *__restrict__ s_diag,
+                                const double *__restrict__ sv, const int32_t *__restrict__ x_diag,
+                                double *__restrict__ xv, double *__restrict__ scratch)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_atoms) return;
+    const int w = 2 * b;
+    double *m = scratch + i * (int64_t)b * w;
+    const double *src = sv + (int64_t)s_diag[i] * b * b;
+    for (int r = 0; r < b; ++r)
+        for (int c = 0; c < w; ++c) m[r * w + c] = c < b ? src[r * b + c] : (c - b == r ? 1.0 : 0.0);
+    for (int col = 0; col < b; ++col) {
+        int piv = col;
+        double best = fabs(m[col * w + col]);
+        for (int r = col + 1; r < b; ++r)
+            if (fabs(m[r * w + col]) > best) { best = fabs(m[r * w + col]); piv = r; }
+        if (piv != col)
+            for (int c = 0; c < w; ++c) {
+                const double tmp = m[col * w + c];
+                m[col * w + c] = m[piv * w + c];
+                m[piv * w + c] = tmp;
+            }
+        const double inv = 1.0 / m[col * w + col];
+        for (int c = 0; c < w; ++c) m[col * w + c] *= inv;
+        for (int r = 0; r < b; ++r) {
+            if (r == col) continue;
+            const double f = m[r * w + col];
+            if (f != 0.0)
+                for (int c = 0; c < w; ++c) m[r * w + c] -= f * m[col * w + c];
+        }
+    }
+    double *dst = xv + (int64_t)x_diag[i] * b * b;
+    for (int r = 0; r < b; ++r)
+        for (int c = 0; c < b; ++c) dst[r * b + c] = m[r * w + b + c];
+}
+
+void launch_block_inverse(hipStream_t s, int64_t n_atoms, int b, const int32_t *s_diag,
+                          const double *sv, const int32_t *x_diag, double *xv, double *scratch)
+{
+    if (n_atoms == 0) return;
+    hipLaunchKernelGGL(k_block_inverse, dim3((unsigned)((n_atoms + 63) / 64)), dim3(64), 0, s,
+                       n_atoms, b, s_diag, sv, x_diag, xv, scratch);
+    RT_HIP(hipGetLastError());
+}
+
+__global__ void k_row_abs_max(int64_t n_atoms, int b, const int64_t *__restrict__ s_ptr,
+                              const double *__restrict__ sv, double *__restrict__ atom_max)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_atoms) return;
+    double best = 0.0;
+    for (int a = 0; a < b; ++a) {
+        double sum = 0.0;
+        for (int64_t p = s_ptr[i]; p < s_ptr[i + 1]; ++p)
+            for (int c = 0; c < b; ++c) sum += fabs(sv[p * b * b + a * b + c]);
+        best = fmax(best, sum);
+    }
+    atom_max[i] = best;
+}
+
+void launch_row_abs_max(hipStream_t s, int64_t n_atoms, int b, const int64_t *s_ptr,
+                        const double *sv, double *atom_max)
+{
+    if (n_atoms == 0) return;
+    hipLaunchKernelGGL(k_row_abs_max, dim3((unsigned)((n_atoms + kT - 1) / kT)), dim3(kT), 0, s,
+                       n_atoms, b, s_ptr, sv, atom_max);
+    RT_HIP(hipGetLastError());
+}
+
+// ----------------------------------------------------------------- reductions
+
+__global__ __launch_bounds__(kT) void k_red_diff2(int64_t n, const double *__restrict__ x,
+                                                  const double *__restrict__ y,
+                                                  double *__restrict__ partials)
+{
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x; e < n; e += (int64_t)kRedBlocks * kT) {
+        const double d = x[e] - y[e];
+        v[0] += d * d;
+        v[1] += x[e] * x[e];
+        v[3] = fmax(v[3], fabs(d));
+    }
+    write_partials(v, partials);
+}
+
+void launch_red_diff2(hipStream_t s, int64_t n, const double *x, const double *y, double *partials)
+{
+    hipLaunchKernelGGL(k_red_diff2, dim3(kRedBlocks), dim3(kT), 0, s, n, x, y, partials);
+    RT_HIP(hipGetLastError());
+}
+
+__global__ __launch_bounds__(kT) void k_red_unitarity(int64_t nnzb_p, int b,
+                                                      const int32_t *__restrict__ p_to_hs,
+                                                      const double *__restrict__ sv,
+                                                      const double *__restrict__ zr,
+                                                      const double *__restrict__ zi,
+                                                      double *__restrict__ partials)
+{
+    const int bb = b * b;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x; e < nnzb_p * bb;
+         e += (int64_t)kRedBlocks * kT) {
+        const int64_t p = e / bb;
+        const int w = (int)(e - p * bb);
+        const int hs = p_to_hs[p];
+        const double sval = hs >= 0 ? sv[(int64_t)hs * bb + w] : 0.0;
+        const double dr = zr[e] - sval, di = zi[e];
+        const double m2 = dr * dr + di * di;
+        const double m = sqrt(m2);
+        v[0] += m2;
+        v[1] += m;
+        v[3] = fmax(v[3], m);
+    }
+    write_partials(v, partials);
+}
+
+void launch_red_unitarity(hipStream_t s, int64_t nnzb_p, int b, const int32_t *p_to_hs,
+                          const double *sv, const double *zr, const double *zi, double *partials)
+{
+    hipLaunchKernelGGL(k_red_unitarity, dim3(kRedBlocks), dim3(kT), 0, s, nnzb_p, b, p_to_hs, sv, zr,
+                       zi, partials);
+    RT_HIP(hipGetLastError());
+}
+
+__global__ __launch_bounds__(kT) void k_red_sumsq(int64_t n, const double *__restrict__ x,
+                                                  double *__restrict__ partials)
+{
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x; e < n; e += (int64_t)kRedBlocks * kT) {
+        v[0] += x[e] * x[e];
+        v[3] = fmax(v[3], fabs(x[e]));
+    }
+    write_partials(v, partials);
+}
+
+void launch_red_sumsq(hipStream_t s, int64_t n, const double *x, double *partials)
+{
+    hipLaunchKernelGGL(k_red_sumsq, dim3(kRedBlocks), dim3(kT), 0, s, n, x, partials);
+    RT_HIP(hipGetLastError());
+}
+
+void launch_red_max(hipStream_t s, int64_t n, const double *x, double *partials)
+{
+    launch_red_sumsq(s, n, x, partials);
+}
+
+// One workgroup of kT threads sums kRedBlocks partials (kRedBlocks = 2 kT).
+__global__ __launch_bounds__(kT) void k_red_finish(const double *__restrict__ partials,
+                                                   double *__restrict__ out)
+{
+    __shared__ double sh[4 * kT];
+    const int t = threadIdx.x;
+    double v[4];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] = partials[t * 4 + k] + partials[(t + kT) * 4 + k];
+    v[3] = fmax(partials[t * 4 + 3], partials[(t + kT) * 4 + 3]);
+    block_reduce4(v, sh);
+    if (t == 0)
+        for (int k = 0; k < 4; ++k) out[k] = v[k];
+}
+
+void launch_red_finish(hipStream_t s, const double *partials, double *out)
+{
+    static_assert(kRedBlocks == 2 * kT, "finish kernel assumes two partials per thread");
+    hipLaunchKernelGGL(k_red_finish, dim3(1), dim3(kT), 0, s, partials, out);
+    RT_HIP(hipGetLastError());
+}
+
+__global__ void k_unit_to_row(const double *__restrict__ unit_sums,
+                              const double *__restrict__ s_norm2, double *__restrict__ row)
+{
+    if (threadIdx.x == 0) row[6] = sqrt(unit_sums[0] / s_norm2[0]);
+}
+
+void launch_unit_to_row(hipStream_t s, const double *unit_sums, const double *s_norm2, double *row)
+{
+    hipLaunchKernelGGL(k_unit_to_row, dim3(1), dim3(64), 0, s, unit_sums, s_norm2, row);
+    RT_HIP(hipGetLastError());
+}
+
+// ----------------------------------------------------------------- layout
+
+__global__ void k_split(int64_t n, const double *__restrict__ inter, double *__restrict__ re,
+                        double *__restrict__ im)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        re[e] = inter[2 * e];
+        if (im) im[e] = inter[2 * e + 1];
+    }
+}
+
+void launch_split(hipStream_t s, int64_t n, const double *inter, double *re, double *im)
+{
+    if (n == 0) return;
+    int64_t g = (n + kT - 1) / kT;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_split, dim3((unsigned)g), dim3(kT), 0, s, n, inter, re, im);
+    RT_HIP(hipGetLastError());
+}
+
+__global__ void k_interleave(int64_t n, const double *__restrict__ re, const double *__restrict__ im,
+                             double *__restrict__ inter)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        inter[2 * e] = re[e];
+        inter[2 * e + 1] = im ? im[e] : 0.0;
+    }
+}
+
+void launch_interleave(hipStream_t s, int64_t n, const double *re, const double *im, double *inter)
+{
+    if (n == 0) return;
+    int64_t g = (n + kT - 1) / kT;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_interleave, dim3((unsigned)g), dim3(kT), 0, s, n, re, im, inter);
+    RT_HIP(hipGetLastError());
+}
+
+}  // namespace rtdm

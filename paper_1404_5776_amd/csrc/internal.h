@@ -1,0 +1,135 @@
+// Internal declarations of the rtdm library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <utility>
+
+#include "rtdm.h"
+
+namespace rtdm {
+
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define RT_HIP(call)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            throw ::rtdm::Error(RTDM_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define RT_CHECK(cond, code, msg)                         \
+    do {                                                  \
+        if (!(cond)) throw ::rtdm::Error((code), (msg));  \
+    } while (0)
+
+// Owning device buffer.
+template <class T>
+struct DBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    DBuf(DBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DBuf &operator=(DBuf &&o) noexcept {
+        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~DBuf() { release(); }
+    void alloc(size_t count) {
+        if (count == n && p) return;
+        release();
+        if (count == 0) return;
+        hipError_t e = hipMalloc(reinterpret_cast<void **>(&p), count * sizeof(T));
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            throw Error(RTDM_E_OOM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+        }
+        n = count;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    size_t bytes() const { return n * sizeof(T); }
+};
+
+// ---------------------------------------------------------------- kernels
+
+// Symbolic phase of C = P_C(op(A) op(B)): per output block (i, j) of C, the
+// ascending k with op(A)_ik and op(B)_kj stored.
+void launch_sym_count(hipStream_t s, int64_t nout, const int32_t *c_rowof, const int32_t *c_col,
+                      const int64_t *a_ptr, const int32_t *a_col, const int64_t *b_ptr,
+                      const int32_t *b_col, int64_t *cnt);
+void launch_sym_fill(hipStream_t s, int64_t nout, const int32_t *c_rowof, const int32_t *c_col,
+                     const int64_t *a_ptr, const int32_t *a_col, const int32_t *a_trans,
+                     const int64_t *b_ptr, const int32_t *b_col, const int32_t *b_trans, int op_a,
+                     int op_b, const int64_t *off, int2 *trip);
+
+struct SpgemmArgs {
+    int64_t nout = 0;
+    const int64_t *off = nullptr;   // [nout+1] triple offsets
+    const int2 *trip = nullptr;     // (block of op(A), block of op(B)) per triple
+    const double *ar = nullptr, *ai = nullptr;   // ai null: A real
+    const double *br = nullptr, *bi = nullptr;   // bi null: B real
+    double *cr = nullptr, *ci = nullptr;         // ci null: C real
+    int b = 0;
+    int op_a = 0, op_b = 0;          // 1: conjugate transpose
+    double alpha_re = 1.0, alpha_im = 0.0;
+};
+void launch_spgemm(hipStream_t s, const SpgemmArgs &a);
+
+// out = a*x + c*y elementwise (y may be null: out = a*x).
+void launch_axpby(hipStream_t s, int64_t n, double a, const double *x, double c, const double *y,
+                  double *out);
+// m[diag blocks] += val * I.
+void launch_add_identity(hipStream_t s, int64_t n_atoms, int b, const int32_t *diag, double val,
+                         double *m);
+// K_ij *= exp(i kappa.(r_i - r_j)).
+void launch_kick(hipStream_t s, int64_t nnzb, int b, const int32_t *rowof, const int32_t *col,
+                 const double *xyz, double kx, double ky, double kz, double *kr, double *ki);
+// K = (Kn + Kn^H)/2 with partial sums of ||Kn - Kn^H||^2 and ||Kn||^2.
+void launch_hermitize(hipStream_t s, int64_t nnzb, int b, const int32_t *trans, const double *knr,
+                      const double *kni, double *kr, double *ki, double *partials);
+// q_i = Re sum_j tr(K_ij S_ji).
+void launch_mulliken(hipStream_t s, int64_t n_atoms, int b, const int64_t *s_ptr,
+                     const int32_t *s_trans, const int32_t *s_to_k, const double *sv,
+                     const double *kr, double *q);
+// H[diag] = H0[diag] + gain*(1.5 q_cur - 0.5 q_prev - q_ref) on the diagonal elements.
+void launch_onsite_shift(hipStream_t s, int64_t n_atoms, int b, const int32_t *diag, double gain,
+                         const double *q_cur, const double *q_prev, const double *q_ref, double *h);
+// Observable row: t, P(3), Tr(KS), herm_err from (partials -> sums), unit_err = NaN.
+void launch_observables(hipStream_t s, int64_t n_atoms, const double *xyz, const double *q,
+                        const double *herm_sums, double t, double *row);
+// X_ii = S_ii^{-1} (Gauss-Jordan, partial pivoting); other blocks untouched.
+void launch_block_inverse(hipStream_t s, int64_t n_atoms, int b, const int32_t *s_diag,
+                          const double *sv, const int32_t *x_diag, double *xv, double *scratch);
+// per-atom max absolute row sum of S.
+void launch_row_abs_max(hipStream_t s, int64_t n_atoms, int b, const int64_t *s_ptr,
+                        const double *sv, double *atom_max);
+
+// Deterministic reductions: partials[G][4] then finish -> out[4].
+constexpr int kRedBlocks = 512;
+void launch_red_diff2(hipStream_t s, int64_t n, const double *x, const double *y, double *partials);
+void launch_red_unitarity(hipStream_t s, int64_t nnzb_p, int b, const int32_t *p_to_hs,
+                          const double *sv, const double *zr, const double *zi, double *partials);
+void launch_red_sumsq(hipStream_t s, int64_t n, const double *x, double *partials);
+void launch_red_max(hipStream_t s, int64_t n, const double *x, double *partials);
+void launch_red_finish(hipStream_t s, const double *partials, double *out);
+// unit-row update: row[6] = sqrt(sums[0] / s2)
+void launch_unit_to_row(hipStream_t s, const double *unit_sums, const double *s_norm2, double *row);
+
+// interleave / split complex128
+void launch_split(hipStream_t s, int64_t n, const double *inter, double *re, double *im);
+void launch_interleave(hipStream_t s, int64_t n, const double *re, const double *im, double *inter);
+
+}  // namespace rtdm

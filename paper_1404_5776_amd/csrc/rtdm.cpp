@@ -1,0 +1,1062 @@
+// C ABI of the truncated block-sparse RT-TDDFT propagation library (rtdm.h).
+//
+// Host side: atom-pair neighbour lists (cell lists), symbolic schedules of
+// every truncated product, device storage of the blocked matrices (real and
+// imaginary parts in separate planes, blocks b*b row-major in pattern order),
+// the truncated Hotelling iteration (Sec. V.A), the exponential-midpoint step
+// with a Taylor propagator (Sec. II.A, Eq. EM, Eq. matrix_exp, Sec. IV.B) and
+// the observables (Sec. II.B dipole, Sec. IV charge and unitarity).
+//
+// The propagator uses that S, H and hence X ~ S^-1 and A = X H are real (the
+// paper's support functions and Hamiltonian are real): then
+// T_n = (-i dt / n) A T_{n-1} = (-i)^n tau_n with real tau_n = (dt/n) A tau_{n-1},
+// so U = sum_n T_n has Re U = tau_0 - tau_2 + tau_4 - ... and
+// Im U = -tau_1 + tau_3 - tau_5 + ..., and every product that builds U is a
+// real block product.  The values are the ones the complex recursion gives
+// (the other part of every term is exactly zero).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "internal.h"
+
+using namespace rtdm;
+
+namespace {
+
+enum Range { R_HS = 0, R_P = 1, R_K = 2 };
+
+struct Pattern {
+    double R = 0.0;
+    int64_t n = 0, nnzb = 0;
+    std::vector<int64_t> rowptr;
+    std::vector<int32_t> col, rowof, trans, diag;
+    DBuf<int64_t> d_rowptr;
+    DBuf<int32_t> d_col, d_rowof, d_trans, d_diag;
+};
+
+struct Mat {
+    int pat = -1;
+    bool cplx = false;
+    DBuf<double> re, im;
+};
+
+struct Sched {
+    int64_t nout = 0, ntrip = 0;
+    DBuf<int64_t> off;
+    DBuf<int2> trip;
+};
+
+struct TRec {
+    int prod;
+    int ev;
+    double flops;
+};
+
+const char *kProdName[RTDM_PROD_COUNT] = {"XH", "AT", "UK", "WU", "SX", "UV"};
+
+}  // namespace
+
+struct rtdm_ctx {
+    int device = 0;
+    rtdm_options opt{};
+    std::string err;
+
+    int64_t n = 0;
+    int b = 0;
+    std::vector<double> xyz;
+    DBuf<double> d_xyz;
+
+    double radius[3] = {0, 0, 0};
+    bool ranges_set = false;
+    std::vector<std::unique_ptr<Pattern>> pats;
+    int range_pat[3] = {-1, -1, -1};
+
+    Mat mats[RTDM_MAT_COUNT];
+    Mat tau[2], Kn, Xn, Wh, V, Z;
+    DBuf<double> scratch;       // block inverse scratch and staging
+
+    std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<Sched>> scheds;
+
+    DBuf<int32_t> s_to_k, p_to_hs;
+    DBuf<double> q_ref, q_a, q_b;
+    double *q_cur = nullptr, *q_prev = nullptr;
+    bool q_ref_valid = false, charges_valid = false;
+
+    bool uploaded[RTDM_MAT_COUNT] = {};
+    bool X_valid = false, U_valid = false, s_norm_valid = false;
+    double U_dt = 0.0;
+
+    DBuf<double> obs;
+    int64_t obs_cap = 0, obs_rows = 0;
+    double t_now = 0.0;
+    bool herm_valid = false;
+
+    DBuf<double> partials, herm_sums, unit_sums, s_norm2, hot_sums, atom_max, obs_tmp;
+
+    bool timing = false;
+    std::vector<hipEvent_t> events;
+    std::vector<TRec> recs;
+};
+
+namespace {
+
+void set_device(rtdm_ctx *c) { RT_HIP(hipSetDevice(c->device)); }
+
+int slot_range(int m)
+{
+    switch (m) {
+    case RTDM_MAT_S:
+    case RTDM_MAT_H0:
+    case RTDM_MAT_H: return R_HS;
+    case RTDM_MAT_X:
+    case RTDM_MAT_A:
+    case RTDM_MAT_U: return R_P;
+    default: return R_K;
+    }
+}
+
+bool slot_complex(int m) { return m == RTDM_MAT_U || m == RTDM_MAT_K || m == RTDM_MAT_W; }
+
+// Cut-off pattern of range R: cell lists of edge max(R, 1), kept pairs tested
+// as dx*dx + dy*dy + dz*dz < R*R, self pairs always kept, rows ascending.
+void build_pattern(Pattern &P, const std::vector<double> &xyz, int64_t n, double R)
+{
+    P.R = R;
+    P.n = n;
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], xyz[3 * i + a]);
+            hi[a] = std::max(hi[a], xyz[3 * i + a]);
+        }
+    double edge = std::max(R, 1.0);
+    int64_t nc[3];
+    for (;;) {
+        int64_t tot = 1;
+        for (int a = 0; a < 3; ++a) {
+            nc[a] = (int64_t)std::floor((hi[a] - lo[a]) / edge) + 1;
+            tot *= nc[a];
+        }
+        if (tot <= 4 * n + 64) break;
+        edge *= 1.5;
+    }
+    auto cell_of = [&](int64_t i, int a) {
+        int64_t c = (int64_t)std::floor((xyz[3 * i + a] - lo[a]) / edge);
+        return std::min(std::max<int64_t>(c, 0), nc[a] - 1);
+    };
+    const int64_t ncell = nc[0] * nc[1] * nc[2];
+    std::vector<int64_t> head(ncell + 1, 0), order(n);
+    std::vector<int64_t> cid(n);
+    for (int64_t i = 0; i < n; ++i) {
+        cid[i] = (cell_of(i, 0) * nc[1] + cell_of(i, 1)) * nc[2] + cell_of(i, 2);
+        head[cid[i] + 1]++;
+    }
+    for (int64_t c = 0; c < ncell; ++c) head[c + 1] += head[c];
+    {
+        std::vector<int64_t> fill(head.begin(), head.end() - 1);
+        for (int64_t i = 0; i < n; ++i) order[fill[cid[i]]++] = i;
+    }
+    const double R2 = R * R;
+    std::vector<std::vector<int32_t>> rows(n);
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t ci[3] = {cell_of(i, 0), cell_of(i, 1), cell_of(i, 2)};
+        auto &row = rows[i];
+        for (int64_t x = std::max<int64_t>(ci[0] - 1, 0); x <= std::min(ci[0] + 1, nc[0] - 1); ++x)
+            for (int64_t y = std::max<int64_t>(ci[1] - 1, 0); y <= std::min(ci[1] + 1, nc[1] - 1); ++y)
+                for (int64_t z = std::max<int64_t>(ci[2] - 1, 0); z <= std::min(ci[2] + 1, nc[2] - 1); ++z) {
+                    const int64_t c = (x * nc[1] + y) * nc[2] + z;
+                    for (int64_t q = head[c]; q < head[c + 1]; ++q) {
+                        const int64_t j = order[q];
+                        if (j == i) { row.push_back((int32_t)j); continue; }
+                        const double dx = xyz[3 * i] - xyz[3 * j];
+                        const double dy = xyz[3 * i + 1] - xyz[3 * j + 1];
+                        const double dz = xyz[3 * i + 2] - xyz[3 * j + 2];
+                        if (dx * dx + dy * dy + dz * dz < R2) row.push_back((int32_t)j);
+                    }
+                }
+        std::sort(row.begin(), row.end());
+    }
+    P.rowptr.assign(n + 1, 0);
+    for (int64_t i = 0; i < n; ++i) P.rowptr[i + 1] = P.rowptr[i] + (int64_t)rows[i].size();
+    P.nnzb = P.rowptr[n];
+    RT_CHECK(P.nnzb < (int64_t)INT32_MAX, RTDM_E_UNSUPPORTED, "more than 2^31 blocks in one pattern");
+    P.col.resize(P.nnzb);
+    P.rowof.resize(P.nnzb);
+    for (int64_t i = 0; i < n; ++i) {
+        std::copy(rows[i].begin(), rows[i].end(), P.col.begin() + P.rowptr[i]);
+        std::fill(P.rowof.begin() + P.rowptr[i], P.rowof.begin() + P.rowptr[i + 1], (int32_t)i);
+    }
+    auto find = [&](int64_t i, int32_t j) -> int64_t {
+        auto b0 = P.col.begin() + P.rowptr[i], b1 = P.col.begin() + P.rowptr[i + 1];
+        auto it = std::lower_bound(b0, b1, j);
+        return (it != b1 && *it == j) ? (int64_t)(it - P.col.begin()) : -1;
+    };
+    P.trans.resize(P.nnzb);
+    P.diag.resize(n);
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t p = P.rowptr[i]; p < P.rowptr[i + 1]; ++p) {
+            const int64_t t = find(P.col[p], (int32_t)i);
+            RT_CHECK(t >= 0, RTDM_E_NUMERIC, "cut-off pattern is not symmetric");
+            P.trans[p] = (int32_t)t;
+        }
+        P.diag[i] = (int32_t)find(i, (int32_t)i);
+    }
+    P.d_rowptr.alloc(n + 1);
+    P.d_col.alloc(P.nnzb);
+    P.d_rowof.alloc(P.nnzb);
+    P.d_trans.alloc(P.nnzb);
+    P.d_diag.alloc(n);
+    RT_HIP(hipMemcpy(P.d_rowptr.p, P.rowptr.data(), P.d_rowptr.bytes(), hipMemcpyHostToDevice));
+    RT_HIP(hipMemcpy(P.d_col.p, P.col.data(), P.d_col.bytes(), hipMemcpyHostToDevice));
+    RT_HIP(hipMemcpy(P.d_rowof.p, P.rowof.data(), P.d_rowof.bytes(), hipMemcpyHostToDevice));
+    RT_HIP(hipMemcpy(P.d_trans.p, P.trans.data(), P.d_trans.bytes(), hipMemcpyHostToDevice));
+    RT_HIP(hipMemcpy(P.d_diag.p, P.diag.data(), P.d_diag.bytes(), hipMemcpyHostToDevice));
+}
+
+Pattern &pat_of(rtdm_ctx *c, int range) { return *c->pats[c->range_pat[range]]; }
+
+int64_t elems(rtdm_ctx *c, const Mat &m) { return c->pats[m.pat]->nnzb * (int64_t)c->b * c->b; }
+
+void alloc_mat(rtdm_ctx *c, Mat &m, int range, bool cplx)
+{
+    m.pat = c->range_pat[range];
+    m.cplx = cplx;
+    const int64_t ne = pat_of(c, range).nnzb * (int64_t)c->b * c->b;
+    m.re.alloc(ne);
+    RT_HIP(hipMemset(m.re.p, 0, m.re.bytes()));
+    if (cplx) {
+        m.im.alloc(ne);
+        RT_HIP(hipMemset(m.im.p, 0, m.im.bytes()));
+    } else {
+        m.im.release();
+    }
+}
+
+void make_complex(rtdm_ctx *c, Mat &m, hipStream_t s)
+{
+    if (m.cplx) return;
+    m.im.alloc(m.re.n);
+    RT_HIP(hipMemsetAsync(m.im.p, 0, m.im.bytes(), s));
+    m.cplx = true;
+}
+
+// (pattern A, pattern B, pattern C, op_a, op_b) of each product kind.
+std::tuple<int, int, int, int, int> prod_key(rtdm_ctx *c, int prod)
+{
+    const int hs = c->range_pat[R_HS], p = c->range_pat[R_P], k = c->range_pat[R_K];
+    switch (prod) {
+    case RTDM_PROD_XH: return {p, hs, p, 0, 0};
+    case RTDM_PROD_AT: return {p, p, p, 0, 0};
+    case RTDM_PROD_UK: return {p, k, k, 0, 0};
+    case RTDM_PROD_WU: return {k, p, k, 0, 1};
+    case RTDM_PROD_SX: return {hs, p, p, 0, 0};
+    case RTDM_PROD_UV: return {p, p, p, 1, 0};
+    }
+    throw Error(RTDM_E_ARG, "unknown product kind");
+}
+
+Sched &schedule(rtdm_ctx *c, int prod)
+{
+    auto key = prod_key(c, prod);
+    auto it = c->scheds.find(key);
+    if (it != c->scheds.end()) return *it->second;
+    auto S = std::make_unique<Sched>();
+    const Pattern &A = *c->pats[std::get<0>(key)];
+    const Pattern &B = *c->pats[std::get<1>(key)];
+    const Pattern &C = *c->pats[std::get<2>(key)];
+    S->nout = C.nnzb;
+    DBuf<int64_t> cnt;
+    cnt.alloc(S->nout);
+    launch_sym_count(nullptr, S->nout, C.d_rowof.p, C.d_col.p, A.d_rowptr.p, A.d_col.p,
+                     B.d_rowptr.p, B.d_col.p, cnt.p);
+    std::vector<int64_t> h(S->nout + 1, 0);
+    RT_HIP(hipMemcpy(h.data() + 1, cnt.p, cnt.bytes(), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < S->nout; ++i) h[i + 1] += h[i];
+    S->ntrip = h[S->nout];
+    S->off.alloc(S->nout + 1);
+    RT_HIP(hipMemcpy(S->off.p, h.data(), S->off.bytes(), hipMemcpyHostToDevice));
+    S->trip.alloc(std::max<int64_t>(S->ntrip, 1));
+    launch_sym_fill(nullptr, S->nout, C.d_rowof.p, C.d_col.p, A.d_rowptr.p, A.d_col.p, A.d_trans.p,
+                    B.d_rowptr.p, B.d_col.p, B.d_trans.p, std::get<3>(key), std::get<4>(key),
+                    S->off.p, S->trip.p);
+    RT_HIP(hipDeviceSynchronize());
+    Sched &ref = *S;
+    c->scheds.emplace(key, std::move(S));
+    return ref;
+}
+
+hipEvent_t event_at(rtdm_ctx *c, size_t k)
+{
+    while (c->events.size() <= k) {
+        hipEvent_t e;
+        RT_HIP(hipEventCreate(&e));
+        c->events.push_back(e);
+    }
+    return c->events[k];
+}
+
+// C = P_C(alpha op(A) op(B)) with the schedule of `prod`.
+void product(rtdm_ctx *c, int prod, const Mat &A, const Mat &B, Mat &C, double alr, double ali,
+             hipStream_t s)
+{
+    Sched &S = schedule(c, prod);
+    auto key = prod_key(c, prod);
+    RT_CHECK(A.pat == std::get<0>(key) && B.pat == std::get<1>(key) && C.pat == std::get<2>(key),
+             RTDM_E_ARG, std::string("operand patterns do not match product ") + kProdName[prod]);
+    SpgemmArgs a;
+    a.nout = S.nout;
+    a.off = S.off.p;
+    a.trip = S.trip.p;
+    a.ar = A.re.p;
+    a.ai = A.cplx ? A.im.p : nullptr;
+    a.br = B.re.p;
+    a.bi = B.cplx ? B.im.p : nullptr;
+    a.cr = C.re.p;
+    a.ci = C.cplx ? C.im.p : nullptr;
+    a.b = c->b;
+    a.op_a = std::get<3>(key);
+    a.op_b = std::get<4>(key);
+    a.alpha_re = alr;
+    a.alpha_im = ali;
+    RT_CHECK(C.cplx || (!A.cplx && !B.cplx && ali == 0.0), RTDM_E_UNSUPPORTED,
+             "complex product into a real matrix");
+    if (c->timing) {
+        const size_t k = 2 * c->recs.size();
+        RT_HIP(hipEventRecord(event_at(c, k), s));
+        launch_spgemm(s, a);
+        RT_HIP(hipEventRecord(event_at(c, k + 1), s));
+        const double b3 = (double)c->b * c->b * c->b;
+        const double sub = (A.cplx ? 2.0 : 1.0) * (B.cplx ? 2.0 : 1.0);
+        c->recs.push_back({prod, (int)k, (double)S.ntrip * 2.0 * b3 * sub});
+    } else {
+        launch_spgemm(s, a);
+    }
+}
+
+void reduce_finish(rtdm_ctx *c, hipStream_t s, double *out) { launch_red_finish(s, c->partials.p, out); }
+
+void read_scalars(double *dst, const double *src, int n, hipStream_t s)
+{
+    RT_HIP(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    RT_HIP(hipStreamSynchronize(s));
+}
+
+void ensure_charges(rtdm_ctx *c, hipStream_t s)
+{
+    if (c->charges_valid) return;
+    Pattern &ps = pat_of(c, R_HS);
+    launch_mulliken(s, c->n, c->b, ps.d_rowptr.p, ps.d_trans.p, c->s_to_k.p, c->mats[RTDM_MAT_S].re.p,
+                    c->mats[RTDM_MAT_K].re.p, c->q_cur);
+    RT_HIP(hipMemcpyAsync(c->q_prev, c->q_cur, c->n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (!c->q_ref_valid) {
+        RT_HIP(hipMemcpyAsync(c->q_ref.p, c->q_cur, c->n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        c->q_ref_valid = true;
+    }
+    c->charges_valid = true;
+}
+
+void ensure_s_norm(rtdm_ctx *c, hipStream_t s)
+{
+    if (c->s_norm_valid) return;
+    launch_red_sumsq(s, elems(c, c->mats[RTDM_MAT_S]), c->mats[RTDM_MAT_S].re.p, c->partials.p);
+    reduce_finish(c, s, c->s_norm2.p);
+    c->s_norm_valid = true;
+}
+
+// U = sum_{n=0}^{p} (-i)^n tau_n with tau_0 = I, tau_1 = dt A, tau_n = (dt/n) P_P(A tau_{n-1}).
+void build_propagator(rtdm_ctx *c, double dt, hipStream_t s)
+{
+    Mat &A = c->mats[RTDM_MAT_A];
+    Mat &U = c->mats[RTDM_MAT_U];
+    const int64_t ne = elems(c, A);
+    const int p = c->opt.taylor_order;
+    RT_HIP(hipMemsetAsync(U.re.p, 0, U.re.bytes(), s));
+    RT_HIP(hipMemsetAsync(U.im.p, 0, U.im.bytes(), s));
+    launch_add_identity(s, c->n, c->b, pat_of(c, R_P).d_diag.p, 1.0, U.re.p);
+    if (p >= 1) {
+        launch_axpby(s, ne, dt, A.re.p, 0.0, nullptr, c->tau[0].re.p);
+        launch_axpby(s, ne, -1.0, c->tau[0].re.p, 1.0, U.im.p, U.im.p);
+    }
+    int cur = 0;
+    for (int k = 2; k <= p; ++k) {
+        Mat &src = c->tau[cur];
+        Mat &dst = c->tau[1 - cur];
+        product(c, RTDM_PROD_AT, A, src, dst, dt / k, 0.0, s);
+        switch (k % 4) {
+        case 0: launch_axpby(s, ne, 1.0, dst.re.p, 1.0, U.re.p, U.re.p); break;
+        case 1: launch_axpby(s, ne, -1.0, dst.re.p, 1.0, U.im.p, U.im.p); break;
+        case 2: launch_axpby(s, ne, -1.0, dst.re.p, 1.0, U.re.p, U.re.p); break;
+        default: launch_axpby(s, ne, 1.0, dst.re.p, 1.0, U.im.p, U.im.p); break;
+        }
+        cur = 1 - cur;
+    }
+}
+
+// D = P_P(U^dagger P_P(S U)) - S; sums into c->unit_sums.
+void unitarity_sums(rtdm_ctx *c, hipStream_t s)
+{
+    Mat &U = c->mats[RTDM_MAT_U];
+    product(c, RTDM_PROD_SX, c->mats[RTDM_MAT_S], U, c->V, 1.0, 0.0, s);
+    product(c, RTDM_PROD_UV, U, c->V, c->Z, 1.0, 0.0, s);
+    launch_red_unitarity(s, pat_of(c, R_P).nnzb, c->b, c->p_to_hs.p, c->mats[RTDM_MAT_S].re.p,
+                         c->Z.re.p, c->Z.im.p, c->partials.p);
+    reduce_finish(c, s, c->unit_sums.p);
+    ensure_s_norm(c, s);
+}
+
+void ensure_obs(rtdm_ctx *c, int64_t rows)
+{
+    if (rows <= c->obs_cap) return;
+    int64_t cap = std::max<int64_t>(2 * c->obs_cap, 1024);
+    while (cap < rows) cap *= 2;
+    DBuf<double> nb;
+    nb.alloc(cap * 8);
+    if (c->obs_rows > 0)
+        RT_HIP(hipMemcpy(nb.p, c->obs.p, c->obs_rows * 8 * sizeof(double), hipMemcpyDeviceToDevice));
+    c->obs = std::move(nb);
+    c->obs_cap = cap;
+}
+
+void require(bool cond, const char *msg) { RT_CHECK(cond, RTDM_E_STATE, msg); }
+
+void upload_planes(rtdm_ctx *c, int m, const double *re, const double *im, hipStream_t s)
+{
+    Mat &M = c->mats[m];
+    const int64_t ne = elems(c, M);
+    RT_HIP(hipMemcpyAsync(M.re.p, re, ne * sizeof(double), hipMemcpyHostToDevice, s));
+    if (M.cplx) {
+        if (im) RT_HIP(hipMemcpyAsync(M.im.p, im, ne * sizeof(double), hipMemcpyHostToDevice, s));
+        else RT_HIP(hipMemsetAsync(M.im.p, 0, M.im.bytes(), s));
+    }
+    RT_HIP(hipStreamSynchronize(s));
+}
+
+void after_upload(rtdm_ctx *c, int m)
+{
+    c->uploaded[m] = true;
+    switch (m) {
+    case RTDM_MAT_S:
+        c->X_valid = false;
+        c->U_valid = false;
+        c->s_norm_valid = false;
+        c->charges_valid = false;
+        c->q_ref_valid = false;
+        break;
+    case RTDM_MAT_H0: c->U_valid = false; break;
+    case RTDM_MAT_X: c->X_valid = true; c->U_valid = false; break;
+    case RTDM_MAT_K:
+        c->charges_valid = false;
+        c->q_ref_valid = false;
+        c->obs_rows = 0;
+        c->t_now = 0.0;
+        c->herm_valid = false;
+        break;
+    case RTDM_MAT_U: c->U_valid = true; break;
+    default: break;
+    }
+}
+
+}  // namespace
+
+// ================================================================== ABI
+
+#define API_BEGIN try {
+#define API_END(c)                                                \
+    }                                                             \
+    catch (const rtdm::Error &e) {                                \
+        if (c) (c)->err = e.what();                               \
+        return e.code;                                            \
+    }                                                             \
+    catch (const std::bad_alloc &) {                              \
+        if (c) (c)->err = "host allocation failed";               \
+        return RTDM_E_OOM;                                        \
+    }                                                             \
+    catch (const std::exception &e) {                             \
+        if (c) (c)->err = e.what();                               \
+        return RTDM_E_ARG;                                        \
+    }                                                             \
+    if (c) (c)->err.clear();                                      \
+    return RTDM_OK;
+
+extern "C" {
+
+int rtdm_default_options(rtdm_options *opt)
+{
+    if (!opt) return RTDM_E_ARG;
+    opt->taylor_order = 5;
+    opt->unit_check_every = 0;
+    opt->precision = RTDM_PREC_FP64;
+    opt->h_model = RTDM_HMODEL_FIXED;
+    opt->h_gain = 0.5;
+    opt->inv_start = RTDM_INV_BLOCK_JACOBI;
+    opt->inv_tol = 1e-10;
+    opt->inv_max_iter = 50;
+    return RTDM_OK;
+}
+
+int rtdm_create(rtdm_ctx **out, int hip_device, const rtdm_options *opt)
+{
+    if (!out) return RTDM_E_ARG;
+    *out = nullptr;
+    rtdm_ctx *c = nullptr;
+    try {
+        c = new rtdm_ctx();
+    } catch (...) {
+        return RTDM_E_OOM;
+    }
+    API_BEGIN
+    int ndev = 0;
+    RT_HIP(hipGetDeviceCount(&ndev));
+    RT_CHECK(hip_device >= 0 && hip_device < ndev, RTDM_E_ARG, "no such HIP device");
+    c->device = hip_device;
+    if (opt) c->opt = *opt;
+    else rtdm_default_options(&c->opt);
+    RT_CHECK(c->opt.taylor_order >= 0 && c->opt.taylor_order <= 32, RTDM_E_ARG, "taylor_order out of range");
+    RT_CHECK(c->opt.precision == RTDM_PREC_FP64, RTDM_E_UNSUPPORTED, "only FP64 is available");
+    RT_CHECK(c->opt.h_model == RTDM_HMODEL_FIXED || c->opt.h_model == RTDM_HMODEL_MULLIKEN, RTDM_E_ARG,
+             "unknown h_model");
+    RT_CHECK(c->opt.inv_start >= 0 && c->opt.inv_start <= RTDM_INV_PREVIOUS, RTDM_E_ARG, "unknown inv_start");
+    RT_CHECK(c->opt.inv_max_iter >= 1 && c->opt.inv_tol > 0, RTDM_E_ARG, "bad inverse options");
+    RT_CHECK(c->opt.unit_check_every >= 0, RTDM_E_ARG, "unit_check_every < 0");
+    set_device(c);
+    c->partials.alloc(kRedBlocks * 4);
+    c->herm_sums.alloc(4);
+    c->unit_sums.alloc(4);
+    c->s_norm2.alloc(4);
+    c->hot_sums.alloc(4);
+    c->obs_tmp.alloc(8);
+    *out = c;
+    }
+    catch (const rtdm::Error &e) {
+        const int code = e.code;
+        delete c;
+        return code;
+    }
+    catch (...) {
+        delete c;
+        return RTDM_E_HIP;
+    }
+    return RTDM_OK;
+}
+
+int rtdm_destroy(rtdm_ctx *c)
+{
+    if (!c) return RTDM_OK;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    for (auto e : c->events) (void)hipEventDestroy(e);
+    delete c;
+    return RTDM_OK;
+}
+
+int rtdm_set_geometry(rtdm_ctx *c, int64_t n_atoms, const double *xyz, const int32_t *nbf)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    RT_CHECK(n_atoms >= 1 && n_atoms < (int64_t)INT32_MAX && xyz && nbf, RTDM_E_ARG, "bad geometry arguments");
+    const int b = nbf[0];
+    for (int64_t i = 0; i < n_atoms; ++i)
+        RT_CHECK(nbf[i] == b, RTDM_E_UNSUPPORTED, "atoms with different numbers of functions");
+    RT_CHECK(b >= 1 && b <= 16, RTDM_E_UNSUPPORTED, "functions per atom must be 1..16");
+    for (int64_t e = 0; e < 3 * n_atoms; ++e) RT_CHECK(std::isfinite(xyz[e]), RTDM_E_ARG, "non-finite position");
+    RT_HIP(hipDeviceSynchronize());
+    c->scheds.clear();
+    c->pats.clear();
+    for (auto &m : c->mats) { m.re.release(); m.im.release(); m.pat = -1; }
+    c->ranges_set = false;
+    c->n = n_atoms;
+    c->b = b;
+    c->xyz.assign(xyz, xyz + 3 * n_atoms);
+    c->d_xyz.alloc(3 * n_atoms);
+    RT_HIP(hipMemcpy(c->d_xyz.p, xyz, c->d_xyz.bytes(), hipMemcpyHostToDevice));
+    std::fill(std::begin(c->uploaded), std::end(c->uploaded), false);
+    c->X_valid = c->U_valid = c->charges_valid = c->q_ref_valid = c->s_norm_valid = false;
+    API_END(c)
+}
+
+int rtdm_set_ranges(rtdm_ctx *c, double R_hs, double R_p, double R_k)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    require(c->n > 0, "set_geometry first");
+    RT_CHECK(std::isfinite(R_hs) && std::isfinite(R_k) && std::isfinite(R_p) && R_hs >= 0 && R_k >= 0,
+             RTDM_E_ARG, "bad ranges");
+    if (R_p <= 0) R_p = std::max(R_hs, R_k);
+    RT_HIP(hipDeviceSynchronize());
+    c->scheds.clear();
+    c->pats.clear();
+    const double r[3] = {R_hs, R_p, R_k};
+    for (int a = 0; a < 3; ++a) {
+        c->radius[a] = r[a];
+        c->range_pat[a] = -1;
+        for (int q = 0; q < a; ++q)
+            if (r[q] == r[a]) c->range_pat[a] = c->range_pat[q];
+        if (c->range_pat[a] < 0) {
+            auto P = std::make_unique<Pattern>();
+            build_pattern(*P, c->xyz, c->n, r[a]);
+            c->pats.push_back(std::move(P));
+            c->range_pat[a] = (int)c->pats.size() - 1;
+        }
+    }
+    for (int m = 0; m < RTDM_MAT_COUNT; ++m) alloc_mat(c, c->mats[m], slot_range(m), slot_complex(m));
+    alloc_mat(c, c->tau[0], R_P, false);
+    alloc_mat(c, c->tau[1], R_P, false);
+    alloc_mat(c, c->Kn, R_K, true);
+    alloc_mat(c, c->Xn, R_P, false);
+    alloc_mat(c, c->Wh, R_P, false);
+    alloc_mat(c, c->V, R_P, true);
+    alloc_mat(c, c->Z, R_P, true);
+    // maps between patterns
+    Pattern &ps = pat_of(c, R_HS), &pk = pat_of(c, R_K), &pp = pat_of(c, R_P);
+    auto find = [](const Pattern &P, int64_t i, int32_t j) -> int32_t {
+        auto b0 = P.col.begin() + P.rowptr[i], b1 = P.col.begin() + P.rowptr[i + 1];
+        auto it = std::lower_bound(b0, b1, j);
+        return (it != b1 && *it == j) ? (int32_t)(it - P.col.begin()) : -1;
+    };
+    std::vector<int32_t> s2k(ps.nnzb), p2s(pp.nnzb);
+    for (int64_t p = 0; p < ps.nnzb; ++p) s2k[p] = find(pk, ps.rowof[p], ps.col[p]);
+    for (int64_t p = 0; p < pp.nnzb; ++p) p2s[p] = find(ps, pp.rowof[p], pp.col[p]);
+    c->s_to_k.alloc(ps.nnzb);
+    c->p_to_hs.alloc(pp.nnzb);
+    RT_HIP(hipMemcpy(c->s_to_k.p, s2k.data(), c->s_to_k.bytes(), hipMemcpyHostToDevice));
+    RT_HIP(hipMemcpy(c->p_to_hs.p, p2s.data(), c->p_to_hs.bytes(), hipMemcpyHostToDevice));
+    c->q_ref.alloc(c->n);
+    c->q_a.alloc(c->n);
+    c->q_b.alloc(c->n);
+    c->q_cur = c->q_a.p;
+    c->q_prev = c->q_b.p;
+    c->atom_max.alloc(c->n);
+    c->scratch.alloc((size_t)c->n * c->b * 2 * c->b);
+    ensure_obs(c, 1024);
+    c->obs_rows = 0;
+    c->t_now = 0.0;
+    std::fill(std::begin(c->uploaded), std::end(c->uploaded), false);
+    c->X_valid = c->U_valid = c->charges_valid = c->q_ref_valid = c->s_norm_valid = false;
+    c->herm_valid = false;
+    c->ranges_set = true;
+    for (int prod : {RTDM_PROD_XH, RTDM_PROD_AT, RTDM_PROD_UK, RTDM_PROD_WU, RTDM_PROD_SX}) schedule(c, prod);
+    RT_HIP(hipDeviceSynchronize());
+    API_END(c)
+}
+
+int rtdm_pattern(rtdm_ctx *c, rtdm_mat mat, int64_t *n_rows, int64_t *nnzb, const int64_t **row_ptr,
+                 const int32_t **col_idx)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    require(c->ranges_set, "set_ranges first");
+    RT_CHECK(mat >= 0 && mat < RTDM_MAT_COUNT, RTDM_E_ARG, "bad matrix slot");
+    const Pattern &P = pat_of(c, slot_range(mat));
+    if (n_rows) *n_rows = P.n;
+    if (nnzb) *nnzb = P.nnzb;
+    if (row_ptr) *row_ptr = P.rowptr.data();
+    if (col_idx) *col_idx = P.col.data();
+    API_END(c)
+}
+
+int rtdm_upload(rtdm_ctx *c, rtdm_mat mat, const void *data, int is_complex, int is_device, void *stream)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    require(c->ranges_set, "set_ranges first");
+    RT_CHECK(mat >= 0 && mat < RTDM_MAT_COUNT && data, RTDM_E_ARG, "bad upload arguments");
+    hipStream_t s = (hipStream_t)stream;
+    Mat &M = c->mats[mat];
+    const int64_t ne = elems(c, M);
+    if (!is_device) {
+        const double *d = (const double *)data;
+        if (!is_complex) {
+            upload_planes(c, mat, d, nullptr, s);
+        } else {
+            std::vector<double> re(ne), im(ne);
+            bool nz = false;
+            for (int64_t e = 0; e < ne; ++e) {
+                re[e] = d[2 * e];
+                im[e] = d[2 * e + 1];
+                nz |= im[e] != 0.0;
+            }
+            RT_CHECK(M.cplx || !nz, RTDM_E_UNSUPPORTED, "complex data for a real matrix slot");
+            upload_planes(c, mat, re.data(), im.data(), s);
+        }
+    } else {
+        const double *d = (const double *)data;
+        if (!is_complex) {
+            RT_HIP(hipMemcpyAsync(M.re.p, d, ne * sizeof(double), hipMemcpyDeviceToDevice, s));
+            if (M.cplx) RT_HIP(hipMemsetAsync(M.im.p, 0, M.im.bytes(), s));
+        } else if (M.cplx) {
+            launch_split(s, ne, d, M.re.p, M.im.p);
+        } else {
+            DBuf<double> tmp;
+            tmp.alloc(ne);
+            launch_split(s, ne, d, M.re.p, tmp.p);
+            launch_red_sumsq(s, ne, tmp.p, c->partials.p);
+            reduce_finish(c, s, c->hot_sums.p);
+            double h[4];
+            read_scalars(h, c->hot_sums.p, 4, s);
+            RT_CHECK(h[3] == 0.0, RTDM_E_UNSUPPORTED, "complex data for a real matrix slot");
+        }
+    }
+    after_upload(c, mat);
+    API_END(c)
+}
+
+int rtdm_upload_coo(rtdm_ctx *c, rtdm_mat mat, int64_t nnzb, const int32_t *rows, const int32_t *cols,
+                    const void *data, int is_complex, void *stream)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    require(c->ranges_set, "set_ranges first");
+    RT_CHECK(mat >= 0 && mat < RTDM_MAT_COUNT && nnzb >= 0 && (nnzb == 0 || (rows && cols && data)),
+             RTDM_E_ARG, "bad upload arguments");
+    Mat &M = c->mats[mat];
+    const Pattern &P = *c->pats[M.pat];
+    const int64_t bb = (int64_t)c->b * c->b;
+    const int64_t ne = P.nnzb * bb;
+    std::vector<double> re(ne, 0.0), im;
+    if (M.cplx) im.assign(ne, 0.0);
+    const double *d = (const double *)data;
+    for (int64_t t = 0; t < nnzb; ++t) {
+        const int32_t i = rows[t], j = cols[t];
+        RT_CHECK(i >= 0 && i < c->n && j >= 0 && j < c->n, RTDM_E_ARG, "block index out of range");
+        auto b0 = P.col.begin() + P.rowptr[i], b1 = P.col.begin() + P.rowptr[i + 1];
+        auto it = std::lower_bound(b0, b1, j);
+        RT_CHECK(it != b1 && *it == j, RTDM_E_ARG,
+                 "block (" + std::to_string(i) + "," + std::to_string(j) + ") is outside the range");
+        const int64_t p = it - P.col.begin();
+        for (int64_t e = 0; e < bb; ++e) {
+            if (is_complex) {
+                re[p * bb + e] = d[2 * (t * bb + e)];
+                const double v = d[2 * (t * bb + e) + 1];
+                if (M.cplx) im[p * bb + e] = v;
+                else RT_CHECK(v == 0.0, RTDM_E_UNSUPPORTED, "complex data for a real matrix slot");
+            } else {
+                re[p * bb + e] = d[t * bb + e];
+            }
+        }
+    }
+    upload_planes(c, mat, re.data(), M.cplx ? im.data() : nullptr, (hipStream_t)stream);
+    after_upload(c, mat);
+    API_END(c)
+}
+
+int rtdm_download(rtdm_ctx *c, rtdm_mat mat, void *dst, int is_device, void *stream)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    require(c->ranges_set, "set_ranges first");
+    RT_CHECK(mat >= 0 && mat < RTDM_MAT_COUNT && dst, RTDM_E_ARG, "bad download arguments");
+    hipStream_t s = (hipStream_t)stream;
+    Mat &M = c->mats[mat];
+    const int64_t ne = elems(c, M);
+    if (is_device) {
+        launch_interleave(s, ne, M.re.p, M.cplx ? M.im.p : nullptr, (double *)dst);
+        RT_HIP(hipStreamSynchronize(s));
+    } else {
+        std::vector<double> re(ne), im(M.cplx ? ne : 0);
+        RT_HIP(hipMemcpyAsync(re.data(), M.re.p, ne * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (M.cplx) RT_HIP(hipMemcpyAsync(im.data(), M.im.p, ne * sizeof(double), hipMemcpyDeviceToHost, s));
+        RT_HIP(hipStreamSynchronize(s));
+        double *o = (double *)dst;
+        for (int64_t e = 0; e < ne; ++e) {
+            o[2 * e] = re[e];
+            o[2 * e + 1] = M.cplx ? im[e] : 0.0;
+        }
+    }
+    API_END(c)
+}
+
+int rtdm_apply_kick(rtdm_ctx *c, const double kappa[3], void *stream)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    require(c->ranges_set && c->uploaded[RTDM_MAT_K] && c->uploaded[RTDM_MAT_S], "upload S and K first");
+    RT_CHECK(kappa && std::isfinite(kappa[0]) && std::isfinite(kappa[1]) && std::isfinite(kappa[2]),
+             RTDM_E_ARG, "bad kick");
+    hipStream_t s = (hipStream_t)stream;
+    if (!c->q_ref_valid) {
+        c->charges_valid = false;
+        ensure_charges(c, s);
+    }
+    Mat &K = c->mats[RTDM_MAT_K];
+    const Pattern &P = pat_of(c, R_K);
+    launch_kick(s, P.nnzb, c->b, P.d_rowof.p, P.d_col.p, c->d_xyz.p, kappa[0], kappa[1], kappa[2], K.re.p,
+                K.im.p);
+    c->charges_valid = false;
+    c->obs_rows = 0;
+    c->t_now = 0.0;
+    c->herm_valid = false;
+    API_END(c)
+}
+
+int rtdm_build_inverse(rtdm_ctx *c, void *stream, int *iters, double *residual)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    require(c->ranges_set && c->uploaded[RTDM_MAT_S], "upload S first");
+    hipStream_t s = (hipStream_t)stream;
+    Mat &S = c->mats[RTDM_MAT_S];
+    Mat &X = c->mats[RTDM_MAT_X];
+    const Pattern &ps = pat_of(c, R_HS), &pp = pat_of(c, R_P);
+    const int64_t ne = elems(c, X);
+
+    auto start_block_jacobi = [&]() {
+        RT_HIP(hipMemsetAsync(X.re.p, 0, X.re.bytes(), s));
+        launch_block_inverse(s, c->n, c->b, ps.d_diag.p, S.re.p, pp.d_diag.p, X.re.p, c->scratch.p);
+    };
+    auto start_cold = [&]() {
+        launch_row_abs_max(s, c->n, c->b, ps.d_rowptr.p, S.re.p, c->atom_max.p);
+        launch_red_max(s, c->n, c->atom_max.p, c->partials.p);
+        reduce_finish(c, s, c->hot_sums.p);
+        double h[4];
+        read_scalars(h, c->hot_sums.p, 4, s);
+        RT_CHECK(h[3] > 0.0 && std::isfinite(h[3]), RTDM_E_NUMERIC, "S has no non-zero row");
+        RT_HIP(hipMemsetAsync(X.re.p, 0, X.re.bytes(), s));
+        launch_add_identity(s, c->n, c->b, pp.d_diag.p, 1.0 / h[3], X.re.p);
+    };
+    // Returns 1 converged, 0 diverged, -1 hit the cap.
+    auto run = [&](int &k_out, double &r_out) -> int {
+        std::vector<double> res;
+        for (int k = 0; k < c->opt.inv_max_iter; ++k) {
+            product(c, RTDM_PROD_SX, S, X, c->Wh, 1.0, 0.0, s);          // W = P_P(S X)
+            product(c, RTDM_PROD_AT, X, c->Wh, c->Xn, 1.0, 0.0, s);      // P_P(X W)
+            launch_axpby(s, ne, 2.0, X.re.p, -1.0, c->Xn.re.p, c->Xn.re.p);  // X' = 2X - XW
+            launch_red_diff2(s, ne, c->Xn.re.p, X.re.p, c->partials.p);
+            reduce_finish(c, s, c->hot_sums.p);
+            double h[4];
+            read_scalars(h, c->hot_sums.p, 4, s);
+            const double r = std::sqrt(h[0] / h[1]);
+            res.push_back(r);
+            k_out = k + 1;
+            r_out = r;
+            if (!std::isfinite(r) || (k >= 1 && r > res[res.size() - 2])) return 0;
+            std::swap(X.re, c->Xn.re);
+            if (r <= c->opt.inv_tol) return 1;
+        }
+        return -1;
+    };
+    int k = 0;
+    double r = 0.0;
+    int st;
+    if (c->opt.inv_start == RTDM_INV_PREVIOUS && c->X_valid) {
+        st = run(k, r);
+        if (st != 1) {
+            start_block_jacobi();
+            st = run(k, r);
+        }
+    } else {
+        if (c->opt.inv_start == RTDM_INV_COLD) start_cold();
+        else start_block_jacobi();
+        st = run(k, r);
+    }
+    if (iters) *iters = k;
+    if (residual) *residual = r;
+    c->X_valid = (st == 1);
+    c->U_valid = false;
+    RT_CHECK(st == 1, RTDM_E_NOCONV,
+             "Hotelling iteration " + std::string(st == 0 ? "diverged" : "hit the iteration cap") +
+                 " (residual " + std::to_string(r) + ")");
+    API_END(c)
+}
+
+int rtdm_step(rtdm_ctx *c, double dt, int64_t n_steps, void *stream)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    require(c->ranges_set && c->X_valid && c->uploaded[RTDM_MAT_K] && c->uploaded[RTDM_MAT_H0] &&
+                c->uploaded[RTDM_MAT_S],
+            "upload S, H0, K and build (or upload) the inverse first");
+    RT_CHECK(std::isfinite(dt) && n_steps >= 0, RTDM_E_ARG, "bad step arguments");
+    hipStream_t s = (hipStream_t)stream;
+    ensure_obs(c, c->obs_rows + n_steps);
+    ensure_charges(c, s);
+    Mat &H = c->mats[RTDM_MAT_H], &H0 = c->mats[RTDM_MAT_H0], &X = c->mats[RTDM_MAT_X];
+    Mat &A = c->mats[RTDM_MAT_A], &U = c->mats[RTDM_MAT_U], &K = c->mats[RTDM_MAT_K];
+    Mat &W = c->mats[RTDM_MAT_W];
+    const Pattern &ps = pat_of(c, R_HS), &pk = pat_of(c, R_K);
+    const bool mull = c->opt.h_model == RTDM_HMODEL_MULLIKEN;
+    for (int64_t st = 0; st < n_steps; ++st) {
+        if (mull || !c->U_valid || c->U_dt != dt) {
+            RT_HIP(hipMemcpyAsync(H.re.p, H0.re.p, H.re.bytes(), hipMemcpyDeviceToDevice, s));
+            if (mull)
+                launch_onsite_shift(s, c->n, c->b, ps.d_diag.p, c->opt.h_gain, c->q_cur, c->q_prev,
+                                    c->q_ref.p, H.re.p);
+            product(c, RTDM_PROD_XH, X, H, A, 1.0, 0.0, s);
+            build_propagator(c, dt, s);
+            c->U_valid = true;
+            c->U_dt = dt;
+        }
+        product(c, RTDM_PROD_UK, U, K, W, 1.0, 0.0, s);
+        product(c, RTDM_PROD_WU, W, U, c->Kn, 1.0, 0.0, s);
+        launch_hermitize(s, pk.nnzb, c->b, pk.d_trans.p, c->Kn.re.p, c->Kn.im.p, K.re.p, K.im.p,
+                         c->partials.p);
+        reduce_finish(c, s, c->herm_sums.p);
+        c->herm_valid = true;
+        std::swap(c->q_cur, c->q_prev);
+        launch_mulliken(s, c->n, c->b, ps.d_rowptr.p, ps.d_trans.p, c->s_to_k.p, c->mats[RTDM_MAT_S].re.p,
+                        K.re.p, c->q_cur);
+        c->t_now += dt;
+        double *row = c->obs.p + 8 * c->obs_rows;
+        launch_observables(s, c->n, c->d_xyz.p, c->q_cur, c->herm_sums.p, c->t_now, row);
+        if (c->opt.unit_check_every > 0 && (c->obs_rows + 1) % c->opt.unit_check_every == 0) {
+            unitarity_sums(c, s);
+            launch_unit_to_row(s, c->unit_sums.p, c->s_norm2.p, row);
+        }
+        c->obs_rows++;
+    }
+    API_END(c)
+}
+
+int rtdm_observables(rtdm_ctx *c, double out[6], void *stream)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    require(c->ranges_set && c->uploaded[RTDM_MAT_K] && c->uploaded[RTDM_MAT_S], "upload S and K first");
+    RT_CHECK(out, RTDM_E_ARG, "null output");
+    hipStream_t s = (hipStream_t)stream;
+    ensure_charges(c, s);
+    launch_observables(s, c->n, c->d_xyz.p, c->q_cur, c->herm_valid ? c->herm_sums.p : nullptr, c->t_now,
+                       c->obs_tmp.p);
+    double row[8];
+    read_scalars(row, c->obs_tmp.p, 8, s);
+    for (int k = 0; k < 5; ++k) out[k] = row[k + 1];
+    out[5] = std::nan("");
+    if (c->U_valid) {
+        unitarity_sums(c, s);
+        double u[4], s2[4];
+        read_scalars(u, c->unit_sums.p, 4, s);
+        read_scalars(s2, c->s_norm2.p, 4, s);
+        out[5] = std::sqrt(u[0] / s2[0]);
+    }
+    API_END(c)
+}
+
+int rtdm_dipole_trace(rtdm_ctx *c, double *out, int64_t max_rows, int64_t *rows)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    RT_CHECK(max_rows >= 0 && (out || max_rows == 0), RTDM_E_ARG, "bad trace buffer");
+    RT_HIP(hipDeviceSynchronize());
+    const int64_t nr = std::min(max_rows, c->obs_rows);
+    if (rows) *rows = c->obs_rows;
+    if (nr > 0) {
+        std::vector<double> tmp(nr * 8);
+        RT_HIP(hipMemcpy(tmp.data(), c->obs.p, tmp.size() * sizeof(double), hipMemcpyDeviceToHost));
+        for (int64_t r = 0; r < nr; ++r)
+            for (int k = 0; k < 7; ++k) out[7 * r + k] = tmp[8 * r + k];
+    }
+    API_END(c)
+}
+
+int rtdm_unitarity(rtdm_ctx *c, double out[3], void *stream)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    require(c->ranges_set && c->U_valid && c->uploaded[RTDM_MAT_S], "no propagator yet");
+    RT_CHECK(out, RTDM_E_ARG, "null output");
+    hipStream_t s = (hipStream_t)stream;
+    unitarity_sums(c, s);
+    double u[4], s2[4];
+    read_scalars(u, c->unit_sums.p, 4, s);
+    read_scalars(s2, c->s_norm2.p, 4, s);
+    out[0] = std::sqrt(u[0] / s2[0]);
+    out[1] = u[1] / ((double)pat_of(c, R_P).nnzb * c->b * c->b);
+    out[2] = u[3];
+    API_END(c)
+}
+
+int rtdm_multiply(rtdm_ctx *c, rtdm_mat Cm, rtdm_mat Am, rtdm_mat Bm, int op_a, int op_b, double alr,
+                  double ali, void *stream)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    require(c->ranges_set, "set_ranges first");
+    RT_CHECK(Am >= 0 && Am < RTDM_MAT_COUNT && Bm >= 0 && Bm < RTDM_MAT_COUNT && Cm >= 0 &&
+                 Cm < RTDM_MAT_COUNT && (op_a == 0 || op_a == 1) && (op_b == 0 || op_b == 1),
+             RTDM_E_ARG, "bad multiply arguments");
+    RT_CHECK(Cm != Am && Cm != Bm, RTDM_E_ARG, "output aliases an operand");
+    Mat &A = c->mats[Am], &B = c->mats[Bm], &C = c->mats[Cm];
+    const std::tuple<int, int, int, int, int> want{A.pat, B.pat, C.pat, op_a, op_b};
+    int prod = -1;
+    for (int q = 0; q < RTDM_PROD_COUNT; ++q)
+        if (prod_key(c, q) == want) { prod = q; break; }
+    RT_CHECK(prod >= 0, RTDM_E_UNSUPPORTED, "no product kind with these ranges and operations");
+    hipStream_t s = (hipStream_t)stream;
+    const bool cres = A.cplx || B.cplx || ali != 0.0;
+    RT_CHECK(C.cplx || !cres, RTDM_E_UNSUPPORTED, "complex result for a real matrix slot");
+    product(c, prod, A, B, C, alr, ali, s);
+    after_upload(c, Cm);
+    API_END(c)
+}
+
+int rtdm_schedule_stats(rtdm_ctx *c, rtdm_prod prod, int64_t *outputs, int64_t *triples)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    require(c->ranges_set, "set_ranges first");
+    RT_CHECK(prod >= 0 && prod < RTDM_PROD_COUNT, RTDM_E_ARG, "bad product kind");
+    Sched &S = schedule(c, prod);
+    if (outputs) *outputs = S.nout;
+    if (triples) *triples = S.ntrip;
+    API_END(c)
+}
+
+int rtdm_timing(rtdm_ctx *c, int enable)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    RT_HIP(hipDeviceSynchronize());
+    c->recs.clear();
+    c->timing = enable != 0;
+    API_END(c)
+}
+
+int rtdm_timing_stats(rtdm_ctx *c, rtdm_prod prod, int64_t *launches, double *total_ms, double *flops)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    RT_CHECK(prod >= 0 && prod < RTDM_PROD_COUNT, RTDM_E_ARG, "bad product kind");
+    RT_HIP(hipDeviceSynchronize());
+    int64_t n = 0;
+    double ms = 0.0, fl = 0.0;
+    for (const auto &r : c->recs) {
+        if (r.prod != prod) continue;
+        float t = 0.0f;
+        RT_HIP(hipEventElapsedTime(&t, c->events[r.ev], c->events[r.ev + 1]));
+        ++n;
+        ms += t;
+        fl += r.flops;
+    }
+    if (launches) *launches = n;
+    if (total_ms) *total_ms = ms;
+    if (flops) *flops = fl;
+    API_END(c)
+}
+
+const char *rtdm_last_error(const rtdm_ctx *c)
+{
+    if (!c) return "null context";
+    return c->err.c_str();
+}
+
+}  // extern "C"

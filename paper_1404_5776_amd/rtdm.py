@@ -1,0 +1,298 @@
+"""Python binding of librtdm.so (include/rtdm.h): the C names, argument marshalling only.
+
+Every step of the propagation runs in the library's HIP kernels; this module
+only converts numpy arrays / torch tensors to pointers and status codes to
+exceptions.  It fails loudly (RuntimeError at load) when the library has not
+been built: there is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import sys
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librtdm.so")
+
+MAT = {"S": 0, "H0": 1, "H": 2, "X": 3, "A": 4, "U": 5, "K": 6, "W": 7}
+PROD = {"XH": 0, "AT": 1, "UK": 2, "WU": 3, "SX": 4, "UV": 5}
+HMODEL = {"fixed": 0, "mulliken": 1}
+INV_START = {"block_jacobi": 0, "cold": 1, "previous": 2}
+
+STATUS = {0: "RTDM_OK", -1: "RTDM_E_ARG", -2: "RTDM_E_STATE", -3: "RTDM_E_OOM", -4: "RTDM_E_HIP",
+          -5: "RTDM_E_NOCONV", -6: "RTDM_E_NUMERIC", -7: "RTDM_E_UNSUPPORTED"}
+
+EXPORTED = ["rtdm_default_options", "rtdm_create", "rtdm_destroy", "rtdm_set_geometry",
+            "rtdm_set_ranges", "rtdm_pattern", "rtdm_upload", "rtdm_upload_coo", "rtdm_download",
+            "rtdm_apply_kick", "rtdm_build_inverse", "rtdm_step", "rtdm_observables",
+            "rtdm_dipole_trace", "rtdm_unitarity", "rtdm_multiply", "rtdm_schedule_stats",
+            "rtdm_timing", "rtdm_timing_stats", "rtdm_last_error"]
+
+
+class RtdmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("taylor_order", ctypes.c_int), ("unit_check_every", ctypes.c_int),
+                ("precision", ctypes.c_int), ("h_model", ctypes.c_int), ("h_gain", ctypes.c_double),
+                ("inv_start", ctypes.c_int), ("inv_tol", ctypes.c_double),
+                ("inv_max_iter", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load():
+    """Load librtdm.so (RuntimeError if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I, I64, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "rtdm_default_options": [P],
+        "rtdm_create": [ctypes.POINTER(P), I, P],
+        "rtdm_destroy": [P],
+        "rtdm_set_geometry": [P, I64, P, P],
+        "rtdm_set_ranges": [P, D, D, D],
+        "rtdm_pattern": [P, I, P, P, P, P],
+        "rtdm_upload": [P, I, P, I, I, P],
+        "rtdm_upload_coo": [P, I, I64, P, P, P, I, P],
+        "rtdm_download": [P, I, P, I, P],
+        "rtdm_apply_kick": [P, P, P],
+        "rtdm_build_inverse": [P, P, P, P],
+        "rtdm_step": [P, D, I64, P],
+        "rtdm_observables": [P, P, P],
+        "rtdm_dipole_trace": [P, P, I64, P],
+        "rtdm_unitarity": [P, P, P],
+        "rtdm_multiply": [P, I, I, I, I, I, D, D, P],
+        "rtdm_schedule_stats": [P, I, P, P],
+        "rtdm_timing": [P, I],
+        "rtdm_timing_stats": [P, I, P, P, P],
+        "rtdm_last_error": [P],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_char_p if name == "rtdm_last_error" else ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(ctx, rc: int):
+    if rc != 0:
+        msg = load().rtdm_last_error(ctx)
+        raise RtdmError(rc, msg.decode() if msg else "")
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        torch = sys.modules.get("torch")
+        if torch is not None and torch.cuda.is_initialized():
+            return torch.cuda.current_stream().cuda_stream
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _mat(m) -> int:
+    return MAT[m] if isinstance(m, str) else int(m)
+
+
+def _prod(p) -> int:
+    return PROD[p] if isinstance(p, str) else int(p)
+
+
+# ------------------------------------------------------------------ C names
+
+def rtdm_default_options() -> Options:
+    o = Options()
+    load().rtdm_default_options(ctypes.byref(o))
+    return o
+
+
+def rtdm_create(device: int = 0, options: Optional[Options] = None):
+    L = load()
+    h = ctypes.c_void_p()
+    rc = L.rtdm_create(ctypes.byref(h), int(device), ctypes.byref(options) if options is not None else None)
+    if rc != 0:
+        raise RtdmError(rc, "rtdm_create failed")
+    return h
+
+
+def rtdm_destroy(ctx) -> None:
+    _check(ctx, load().rtdm_destroy(ctx))
+
+
+def rtdm_set_geometry(ctx, xyz: np.ndarray, nbf: np.ndarray) -> None:
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    nbf = np.ascontiguousarray(nbf, dtype=np.int32)
+    _check(ctx, load().rtdm_set_geometry(ctx, xyz.shape[0], _p(xyz), _p(nbf)))
+
+
+def rtdm_set_ranges(ctx, R_HS: float, R_P: float, R_K: float) -> None:
+    _check(ctx, load().rtdm_set_ranges(ctx, float(R_HS), float(R_P), float(R_K)))
+
+
+def rtdm_pattern(ctx, mat) -> Tuple[np.ndarray, np.ndarray]:
+    n = ctypes.c_int64()
+    nnz = ctypes.c_int64()
+    rp = ctypes.POINTER(ctypes.c_int64)()
+    ci = ctypes.POINTER(ctypes.c_int32)()
+    _check(ctx, load().rtdm_pattern(ctx, _mat(mat), ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(rp),
+                                    ctypes.byref(ci)))
+    row_ptr = np.ctypeslib.as_array(rp, shape=(n.value + 1,)).copy()
+    col = np.ctypeslib.as_array(ci, shape=(nnz.value,)).copy() if nnz.value else np.zeros(0, np.int32)
+    return row_ptr, col
+
+
+def rtdm_upload(ctx, mat, data, stream=None) -> None:
+    """data: numpy (host) or torch CUDA tensor, real float64 or complex128, blocks in pattern order."""
+    if hasattr(data, "data_ptr"):
+        is_c = int(data.is_complex())
+        if not data.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        _check(ctx, load().rtdm_upload(ctx, _mat(mat), ctypes.c_void_p(data.data_ptr()), is_c,
+                                       int(data.is_cuda), _stream(stream)))
+        return
+    is_c = int(np.iscomplexobj(data))
+    arr = np.ascontiguousarray(data, dtype=np.complex128 if is_c else np.float64)
+    _check(ctx, load().rtdm_upload(ctx, _mat(mat), _p(arr), is_c, 0, _stream(stream)))
+
+
+def rtdm_upload_coo(ctx, mat, rows, cols, data, stream=None) -> None:
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    is_c = int(np.iscomplexobj(data))
+    arr = np.ascontiguousarray(data, dtype=np.complex128 if is_c else np.float64)
+    _check(ctx, load().rtdm_upload_coo(ctx, _mat(mat), rows.size, _p(rows), _p(cols), _p(arr), is_c,
+                                       _stream(stream)))
+
+
+def rtdm_download(ctx, mat, b: int, out=None, stream=None):
+    """Blocks of a slot as complex128 (nnzb, b, b); into `out` (torch CUDA tensor) if given."""
+    if out is not None:
+        _check(ctx, load().rtdm_download(ctx, _mat(mat), ctypes.c_void_p(out.data_ptr()), 1, _stream(stream)))
+        return out
+    _, col = rtdm_pattern(ctx, mat)
+    arr = np.empty((col.size, b, b), dtype=np.complex128)
+    _check(ctx, load().rtdm_download(ctx, _mat(mat), _p(arr), 0, _stream(stream)))
+    return arr
+
+
+def rtdm_apply_kick(ctx, kappa: Sequence[float], stream=None) -> None:
+    k = np.ascontiguousarray(kappa, dtype=np.float64)
+    _check(ctx, load().rtdm_apply_kick(ctx, _p(k), _stream(stream)))
+
+
+def rtdm_build_inverse(ctx, stream=None) -> Tuple[int, float]:
+    it = ctypes.c_int()
+    r = ctypes.c_double()
+    _check(ctx, load().rtdm_build_inverse(ctx, _stream(stream), ctypes.byref(it), ctypes.byref(r)))
+    return it.value, r.value
+
+
+def rtdm_step(ctx, dt: float, n_steps: int, stream=None) -> None:
+    _check(ctx, load().rtdm_step(ctx, float(dt), int(n_steps), _stream(stream)))
+
+
+def rtdm_observables(ctx, stream=None) -> np.ndarray:
+    out = np.zeros(6)
+    _check(ctx, load().rtdm_observables(ctx, _p(out), _stream(stream)))
+    return out
+
+
+def rtdm_dipole_trace(ctx, max_rows: int = 1 << 20) -> np.ndarray:
+    rows = ctypes.c_int64()
+    _check(ctx, load().rtdm_dipole_trace(ctx, None, 0, ctypes.byref(rows)))
+    n = min(rows.value, max_rows)
+    out = np.zeros((n, 7))
+    _check(ctx, load().rtdm_dipole_trace(ctx, _p(out), n, ctypes.byref(rows)))
+    return out
+
+
+def rtdm_unitarity(ctx, stream=None) -> np.ndarray:
+    out = np.zeros(3)
+    _check(ctx, load().rtdm_unitarity(ctx, _p(out), _stream(stream)))
+    return out
+
+
+def rtdm_multiply(ctx, C, A, B, op_a: int = 0, op_b: int = 0, alpha: complex = 1.0, stream=None) -> None:
+    a = complex(alpha)
+    _check(ctx, load().rtdm_multiply(ctx, _mat(C), _mat(A), _mat(B), int(op_a), int(op_b), a.real, a.imag,
+                                     _stream(stream)))
+
+
+def rtdm_schedule_stats(ctx, prod) -> Tuple[int, int]:
+    o = ctypes.c_int64()
+    t = ctypes.c_int64()
+    _check(ctx, load().rtdm_schedule_stats(ctx, _prod(prod), ctypes.byref(o), ctypes.byref(t)))
+    return o.value, t.value
+
+
+def rtdm_timing(ctx, enable: bool) -> None:
+    _check(ctx, load().rtdm_timing(ctx, int(bool(enable))))
+
+
+def rtdm_timing_stats(ctx, prod) -> Tuple[int, float, float]:
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    fl = ctypes.c_double()
+    _check(ctx, load().rtdm_timing_stats(ctx, _prod(prod), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl)))
+    return n.value, ms.value, fl.value
+
+
+def rtdm_last_error(ctx) -> str:
+    m = load().rtdm_last_error(ctx)
+    return m.decode() if m else ""
+
+
+# ------------------------------------------------------------------ convenience
+
+class Context:
+    """Owns one rtdm context; `load_system` runs the set-up calls for a generated system."""
+
+    def __init__(self, device: int = 0, **opts):
+        o = rtdm_default_options()
+        for k, v in opts.items():
+            if k == "h_model" and isinstance(v, str):
+                v = HMODEL[v]
+            if k == "inv_start" and isinstance(v, str):
+                v = INV_START[v]
+            setattr(o, k, v)
+        self.options = o
+        self.h = rtdm_create(device, o)
+        self.b = 0
+
+    def close(self):
+        if self.h is not None:
+            rtdm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load_system(self, sys_, stream=None):
+        self.b = sys_.b
+        rtdm_set_geometry(self.h, sys_.xyz, sys_.nbf)
+        rtdm_set_ranges(self.h, sys_.R_HS, sys_.R_P, sys_.R_K)
+        for name, m in (("S", sys_.S), ("H0", sys_.H0), ("K", sys_.K0)):
+            rtdm_upload_coo(self.h, name, m.rows, m.cols, m.data, stream)
+        return self

@@ -1,0 +1,55 @@
+"""CPU-side checks of the C ABI: the library loads and exports what rtdm.h declares."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1404_5776_amd import rtdm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "rtdm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rtdm_\w+)\s*\(", src)))
+
+
+def test_header_declares_the_binding_names():
+    assert _declared() == sorted(rtdm.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(rtdm.LIB_PATH)
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_binding_loads_and_defaults():
+    rtdm.load()
+    o = rtdm.rtdm_default_options()
+    assert o.taylor_order == 5 and o.h_gain == 0.5 and o.inv_tol == 1e-10 and o.inv_max_iter == 50
+    assert rtdm.load().rtdm_last_error(None) == b"null context"
+
+
+def test_null_context_is_an_argument_error():
+    L = rtdm.load()
+    assert L.rtdm_set_ranges(None, 1.0, 1.0, 1.0) == -1
+    assert L.rtdm_step(None, 0.05, 1, None) == -1
+    assert L.rtdm_destroy(None) == 0
+
+
+def _has_gpu():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+@pytest.mark.skipif(_has_gpu(), reason="checks the no-device error path")
+def test_create_without_a_device_fails_cleanly():
+    with pytest.raises(rtdm.RtdmError):
+        rtdm.rtdm_create(0)
