@@ -107,6 +107,9 @@ def main():
     ap.add_argument("--cells", default="8x8x8", help="diamond conventional cells (8 atoms each)")
     ap.add_argument("--cpu-seconds", type=float, default=16.0, help="oracle sample budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of MIB MiB (read + write) before the workload, "
+                         "so hardware byte counters can be scaled against a known size")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -115,6 +118,17 @@ def main():
                                    "domain decomposition with halo exchange) is described in DESIGN.md",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy * (1 << 20) // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {args.calibrate_copy} MiB")
+        del x, y
 
     t = time.time()
     s = make_workload(args)

@@ -200,6 +200,12 @@ int rtdm_dipole_trace(rtdm_ctx *ctx, double *out, int64_t max_rows, int64_t *row
  * with D = P_P(U^dagger P_P(S U)) - S over R_P's pattern.  Synchronises. */
 int rtdm_unitarity(rtdm_ctx *ctx, double out[3], void *hip_stream);
 
+/* Truncation error of the inverse (Sec. V.A, the paper's measure of the
+ * S^-1 truncation): D = P_P(X S) - I over R_P's pattern; out[0] = mean |D_ab|
+ * over the pattern's elements, out[1] = max |D_ab|, out[2] = ||D||_F.
+ * Needs a built or uploaded X.  Synchronises. */
+int rtdm_inverse_error(rtdm_ctx *ctx, double out[3], void *hip_stream);
+
 /* Test entry: C = P_C(alpha op(A) op(B)) on the slots' patterns, where op is
  * the identity (0) or the conjugate transpose (1).  The (range(A), range(B),
  * range(C), op_a, op_b) combination must be one of RTDM_PROD_* (else

@@ -282,6 +282,14 @@ def hotelling(S: BSM, pat_x: Pattern, X0: Optional[BSM] = None, tol: float = 1e-
     return InverseResult(X, len(res), res, fell_back)
 
 
+def inverse_error(X: BSM, S: BSM, pat_p: Pattern) -> Tuple[float, float, float]:
+    """Truncation error of S^-1 (Sec. V.A): D = P_P(X S) - I; (mean |D|, max |D|, ||D||_F)."""
+    XS, _ = spgemm(X, S, pat_p)
+    D = axpby(1.0, XS, -1.0, identity(pat_p, X.b))
+    a = np.abs(D.val)
+    return float(a.mean()), float(a.max()), frob(D)
+
+
 def taylor_propagator(A: BSM, dt: float, p: int, pat_u: Pattern) -> BSM:
     """U = sum_{n=0}^{p} T_n (Eq. matrix_exp, Eq. EM), truncated to pat_u at every product."""
     T = identity(pat_u, A.b)

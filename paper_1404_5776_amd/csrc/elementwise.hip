@@ -393,6 +393,35 @@ void launch_red_unitarity(hipStream_t s, int64_t nnzb_p, int b, const int32_t *p
     RT_HIP(hipGetLastError());
 }
 
+__global__ __launch_bounds__(kT) void k_red_minus_identity(int64_t nnzb, int b,
+                                                           const int32_t *__restrict__ rowof,
+                                                           const int32_t *__restrict__ col,
+                                                           const double *__restrict__ v,
+                                                           double *__restrict__ partials)
+{
+    const int bb = b * b;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x; e < nnzb * bb;
+         e += (int64_t)kRedBlocks * kT) {
+        const int64_t p = e / bb;
+        const int w = (int)(e - p * bb);
+        const double id = (rowof[p] == col[p] && w % (b + 1) == 0) ? 1.0 : 0.0;
+        const double d = v[e] - id;
+        acc[0] += d * d;
+        acc[1] += fabs(d);
+        acc[3] = fmax(acc[3], fabs(d));
+    }
+    write_partials(acc, partials);
+}
+
+void launch_red_minus_identity(hipStream_t s, int64_t nnzb, int b, const int32_t *rowof,
+                               const int32_t *col, const double *v, double *partials)
+{
+    hipLaunchKernelGGL(k_red_minus_identity, dim3(kRedBlocks), dim3(kT), 0, s, nnzb, b, rowof, col, v,
+                       partials);
+    RT_HIP(hipGetLastError());
+}
+
 __global__ __launch_bounds__(kT) void k_red_sumsq(int64_t n, const double *__restrict__ x,
                                                   double *__restrict__ partials)
 {

@@ -122,6 +122,9 @@ constexpr int kRedBlocks = 512;
 void launch_red_diff2(hipStream_t s, int64_t n, const double *x, const double *y, double *partials);
 void launch_red_unitarity(hipStream_t s, int64_t nnzb_p, int b, const int32_t *p_to_hs,
                           const double *sv, const double *zr, const double *zi, double *partials);
+// sums of |v - I| over a pattern's elements: [0] sum |d|^2, [1] sum |d|, [3] max |d|
+void launch_red_minus_identity(hipStream_t s, int64_t nnzb, int b, const int32_t *rowof,
+                               const int32_t *col, const double *v, double *partials);
 void launch_red_sumsq(hipStream_t s, int64_t n, const double *x, double *partials);
 void launch_red_max(hipStream_t s, int64_t n, const double *x, double *partials);
 void launch_red_finish(hipStream_t s, const double *partials, double *out);

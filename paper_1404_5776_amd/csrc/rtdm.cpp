@@ -981,6 +981,26 @@ int rtdm_unitarity(rtdm_ctx *c, double out[3], void *stream)
     API_END(c)
 }
 
+int rtdm_inverse_error(rtdm_ctx *c, double out[3], void *stream)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    require(c->ranges_set && c->X_valid && c->uploaded[RTDM_MAT_S], "build or upload the inverse first");
+    RT_CHECK(out, RTDM_E_ARG, "null output");
+    hipStream_t s = (hipStream_t)stream;
+    product(c, RTDM_PROD_XH, c->mats[RTDM_MAT_X], c->mats[RTDM_MAT_S], c->Wh, 1.0, 0.0, s);
+    const Pattern &pp = pat_of(c, R_P);
+    launch_red_minus_identity(s, pp.nnzb, c->b, pp.d_rowof.p, pp.d_col.p, c->Wh.re.p, c->partials.p);
+    reduce_finish(c, s, c->hot_sums.p);
+    double h[4];
+    read_scalars(h, c->hot_sums.p, 4, s);
+    out[0] = h[1] / ((double)pp.nnzb * c->b * c->b);
+    out[1] = h[3];
+    out[2] = std::sqrt(h[0]);
+    API_END(c)
+}
+
 int rtdm_multiply(rtdm_ctx *c, rtdm_mat Cm, rtdm_mat Am, rtdm_mat Bm, int op_a, int op_b, double alr,
                   double ali, void *stream)
 {

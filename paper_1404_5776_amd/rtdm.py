@@ -29,7 +29,7 @@ STATUS = {0: "RTDM_OK", -1: "RTDM_E_ARG", -2: "RTDM_E_STATE", -3: "RTDM_E_OOM", 
 EXPORTED = ["rtdm_default_options", "rtdm_create", "rtdm_destroy", "rtdm_set_geometry",
             "rtdm_set_ranges", "rtdm_pattern", "rtdm_upload", "rtdm_upload_coo", "rtdm_download",
             "rtdm_apply_kick", "rtdm_build_inverse", "rtdm_step", "rtdm_observables",
-            "rtdm_dipole_trace", "rtdm_unitarity", "rtdm_multiply", "rtdm_schedule_stats",
+            "rtdm_dipole_trace", "rtdm_unitarity", "rtdm_inverse_error", "rtdm_multiply", "rtdm_schedule_stats",
             "rtdm_timing", "rtdm_timing_stats", "rtdm_last_error"]
 
 
@@ -74,6 +74,7 @@ def load():
         "rtdm_observables": [P, P, P],
         "rtdm_dipole_trace": [P, P, I64, P],
         "rtdm_unitarity": [P, P, P],
+        "rtdm_inverse_error": [P, P, P],
         "rtdm_multiply": [P, I, I, I, I, I, D, D, P],
         "rtdm_schedule_stats": [P, I, P, P],
         "rtdm_timing": [P, I],
@@ -228,6 +229,12 @@ def rtdm_dipole_trace(ctx, max_rows: int = 1 << 20) -> np.ndarray:
 def rtdm_unitarity(ctx, stream=None) -> np.ndarray:
     out = np.zeros(3)
     _check(ctx, load().rtdm_unitarity(ctx, _p(out), _stream(stream)))
+    return out
+
+
+def rtdm_inverse_error(ctx, stream=None) -> np.ndarray:
+    out = np.zeros(3)
+    _check(ctx, load().rtdm_inverse_error(ctx, _p(out), _stream(stream)))
     return out
 
 

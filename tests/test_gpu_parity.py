@@ -112,6 +112,9 @@ def test_inverse_matches_oracle(case):
     assert abs(r - ref.residuals[-1]) <= 1e-6 * ref.residuals[-1] + 1e-15
     X = rtdm.rtdm_download(ctx.h, "X", s.b)
     assert rel(X, ref.X.val) <= TOL
+    err = rtdm.rtdm_inverse_error(ctx.h)
+    want = O.inverse_error(ref.X, st.S, st.pat_p)
+    np.testing.assert_allclose(err, want, rtol=1e-6, atol=1e-16)
 
 
 def test_cold_and_previous_starts_match_oracle():

@@ -374,3 +374,22 @@ def test_mulliken_midpoint_is_second_order():
     e = [np.abs(final(dt) - ref).max() for dt in (0.2, 0.1, 0.05)]
     orders = [math.log2(e[i] / e[i + 1]) for i in range(2)]
     assert all(1.8 < o < 2.3 for o in orders), orders
+
+
+def test_inverse_error_vanishes_untruncated_and_falls_with_range():
+    """Sec. V.A: the mean |S^-1 S - I| element is zero for the exact inverse and
+    decreases towards zero as the truncation range of S^-1 grows."""
+    s = synth.diamond_lattice((2, 2, 2), 4, 6.0, 12.0, seed=13, k0="exact")
+    S = O.from_coo(s.S, O.pattern(s.xyz, s.R_HS), s.b)
+    errs = []
+    for R in (6.0, 9.0, 12.0, 40.0):
+        pat = O.pattern(s.xyz, R)
+        X = O.hotelling(S, pat, tol=1e-14).X
+        mean, mx, fro = O.inverse_error(X, S, pat)
+        Xd, Sd = X.to_dense(), S.to_dense()
+        D = np.where(_masks(pat, s.b), Xd @ Sd - np.eye(Sd.shape[0]), 0)   # dense, independent
+        assert abs(mean - np.abs(D).sum() / (pat.nnzb * s.b * s.b)) < 1e-15
+        assert abs(mx - np.abs(D).max()) < 1e-15
+        errs.append(mean)
+    assert all(e1 > e2 for e1, e2 in zip(errs, errs[1:]))
+    assert errs[-1] < 1e-14
