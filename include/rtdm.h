@@ -94,7 +94,11 @@ typedef enum {
     RTDM_PROD_COUNT = 6
 } rtdm_prod;
 
-enum { RTDM_PREC_FP64 = 0 };
+/* Arithmetic of the block products of rtdm_step and rtdm_multiply: FP64
+ * matrix cores, or FP32 matrix cores with FP32 accumulation (b = 4 and 13).
+ * Storage, reductions, observables, the inverse iteration and the unitarity
+ * check always run in FP64. */
+enum { RTDM_PREC_FP64 = 0, RTDM_PREC_FP32 = 1 };
 enum { RTDM_HMODEL_FIXED = 0, RTDM_HMODEL_MULLIKEN = 1 };
 enum { RTDM_INV_BLOCK_JACOBI = 0, RTDM_INV_COLD = 1, RTDM_INV_PREVIOUS = 2 };
 
@@ -102,7 +106,7 @@ enum { RTDM_INV_BLOCK_JACOBI = 0, RTDM_INV_COLD = 1, RTDM_INV_PREVIOUS = 2 };
 typedef struct {
     int taylor_order;      /* p: Taylor orders 0..p of the exponential (Sec. IV.B: six terms -> 5) */
     int unit_check_every;  /* m > 0: record ||U^dagger S U - S|| every m steps; 0: never */
-    int precision;         /* RTDM_PREC_FP64 */
+    int precision;         /* RTDM_PREC_FP64 or RTDM_PREC_FP32 (block products only) */
     int h_model;           /* RTDM_HMODEL_FIXED: H = H0; MULLIKEN: H = H0 + g diag(q_mid - q_ref) */
     double h_gain;         /* g of the on-site model (default 0.5) */
     int inv_start;         /* starting guess of the inverse iteration (default block-Jacobi) */

@@ -338,6 +338,29 @@ void launch_row_abs_max(hipStream_t s, int64_t n_atoms, int b, const int64_t *s_
     RT_HIP(hipGetLastError());
 }
 
+__global__ void k_transpose_blocks(int64_t nblocks, int b, const double *__restrict__ in,
+                                   double *__restrict__ out)
+{
+    const int bb = b * b;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nblocks * bb;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = e / bb;
+        const int w = (int)(e - p * bb);
+        const int r = w / b, c = w - r * b;
+        out[p * bb + c * b + r] = in[e];
+    }
+}
+
+void launch_transpose_blocks(hipStream_t s, int64_t nblocks, int b, const double *in, double *out)
+{
+    const int64_t n = nblocks * b * b;
+    if (n == 0) return;
+    int64_t g = (n + kT - 1) / kT;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_transpose_blocks, dim3((unsigned)g), dim3(kT), 0, s, nblocks, b, in, out);
+    RT_HIP(hipGetLastError());
+}
+
 // ----------------------------------------------------------------- reductions
 
 __global__ __launch_bounds__(kT) void k_red_diff2(int64_t n, const double *__restrict__ x,

@@ -85,8 +85,16 @@ struct SpgemmArgs {
     int b = 0;
     int op_a = 0, op_b = 0;          // 1: conjugate transpose
     double alpha_re = 1.0, alpha_im = 0.0;
+    int precision = RTDM_PREC_FP64;  // arithmetic of the block products
+    const double *zero = nullptr;    // 256 zero doubles (operand of lanes without data)
 };
 void launch_spgemm(hipStream_t s, const SpgemmArgs &a);
+// Same product with the left operand given as column-major blocks, the right
+// operand's op(B)[m][r] at m*B + r (conj_b: conjugated) and the output written
+// column-major if out_col_major.  b = 13, FP64.
+void launch_spgemm_cm(hipStream_t s, const SpgemmArgs &a, int conj_b, int out_col_major);
+// out[p] = in[p]^T for every b x b block (nblocks blocks).
+void launch_transpose_blocks(hipStream_t s, int64_t nblocks, int b, const double *in, double *out);
 
 // out = a*x + c*y elementwise (y may be null: out = a*x).
 void launch_axpby(hipStream_t s, int64_t n, double a, const double *x, double c, const double *y,

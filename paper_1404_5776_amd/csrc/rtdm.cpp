@@ -79,6 +79,9 @@ struct rtdm_ctx {
 
     Mat mats[RTDM_MAT_COUNT];
     Mat tau[2], Kn, Xn, Wh, V, Z;
+    // column-major block copies of the step's left operands (b = 13, FP64)
+    Mat Xc, Ac, Uc, Wc;
+    bool Xc_valid = false, W_in_cm = false;
     DBuf<double> scratch;       // block inverse scratch and staging
 
     std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<Sched>> scheds;
@@ -97,8 +100,9 @@ struct rtdm_ctx {
     double t_now = 0.0;
     bool herm_valid = false;
 
-    DBuf<double> partials, herm_sums, unit_sums, s_norm2, hot_sums, atom_max, obs_tmp;
+    DBuf<double> partials, herm_sums, unit_sums, s_norm2, hot_sums, atom_max, obs_tmp, zero;
 
+    int prec = RTDM_PREC_FP64;  // arithmetic of the products being issued
     bool timing = false;
     std::vector<hipEvent_t> events;
     std::vector<TRec> recs;
@@ -324,6 +328,7 @@ void product(rtdm_ctx *c, int prod, const Mat &A, const Mat &B, Mat &C, double a
     a.op_b = std::get<4>(key);
     a.alpha_re = alr;
     a.alpha_im = ali;
+    a.precision = c->prec;
     RT_CHECK(C.cplx || (!A.cplx && !B.cplx && ali == 0.0), RTDM_E_UNSUPPORTED,
              "complex product into a real matrix");
     if (c->timing) {
@@ -338,6 +343,52 @@ void product(rtdm_ctx *c, int prod, const Mat &A, const Mat &B, Mat &C, double a
         launch_spgemm(s, a);
     }
 }
+
+// Step product with the column-major copy Acm of the left operand (see
+// launch_spgemm_cm); same schedule, timing and flop accounting as product().
+void product_cm(rtdm_ctx *c, int prod, const Mat &Acm, const Mat &B, Mat &C, int conj_b, int out_cm,
+                double alr, hipStream_t s)
+{
+    Sched &S = schedule(c, prod);
+    auto key = prod_key(c, prod);
+    RT_CHECK(Acm.pat == std::get<0>(key) && B.pat == std::get<1>(key) && C.pat == std::get<2>(key),
+             RTDM_E_ARG, std::string("operand patterns do not match product ") + kProdName[prod]);
+    SpgemmArgs a;
+    a.nout = S.nout;
+    a.off = S.off.p;
+    a.trip = S.trip.p;
+    a.ar = Acm.re.p;
+    a.ai = Acm.cplx ? Acm.im.p : nullptr;
+    a.br = B.re.p;
+    a.bi = B.cplx ? B.im.p : nullptr;
+    a.cr = C.re.p;
+    a.ci = C.cplx ? C.im.p : nullptr;
+    a.b = c->b;
+    a.alpha_re = alr;
+    a.zero = c->zero.p;
+    RT_CHECK(C.cplx || (!Acm.cplx && !B.cplx), RTDM_E_UNSUPPORTED, "complex product into a real matrix");
+    if (c->timing) {
+        const size_t k = 2 * c->recs.size();
+        RT_HIP(hipEventRecord(event_at(c, k), s));
+        launch_spgemm_cm(s, a, conj_b, out_cm);
+        RT_HIP(hipEventRecord(event_at(c, k + 1), s));
+        const double b3 = (double)c->b * c->b * c->b;
+        const double sub = (Acm.cplx ? 2.0 : 1.0) * (B.cplx ? 2.0 : 1.0);
+        c->recs.push_back({prod, (int)k, (double)S.ntrip * 2.0 * b3 * sub});
+    } else {
+        launch_spgemm_cm(s, a, conj_b, out_cm);
+    }
+}
+
+// Column-major copy of every block of M (both planes).
+void transpose_into(rtdm_ctx *c, const Mat &M, Mat &out, hipStream_t s)
+{
+    const int64_t nb = c->pats[M.pat]->nnzb;
+    launch_transpose_blocks(s, nb, c->b, M.re.p, out.re.p);
+    if (M.cplx) launch_transpose_blocks(s, nb, c->b, M.im.p, out.im.p);
+}
+
+bool use_cm(rtdm_ctx *c) { return c->b == 13 && c->prec == RTDM_PREC_FP64; }
 
 void reduce_finish(rtdm_ctx *c, hipStream_t s, double *out) { launch_red_finish(s, c->partials.p, out); }
 
@@ -387,7 +438,8 @@ void build_propagator(rtdm_ctx *c, double dt, hipStream_t s)
     for (int k = 2; k <= p; ++k) {
         Mat &src = c->tau[cur];
         Mat &dst = c->tau[1 - cur];
-        product(c, RTDM_PROD_AT, A, src, dst, dt / k, 0.0, s);
+        if (use_cm(c)) product_cm(c, RTDM_PROD_AT, c->Ac, src, dst, 0, 0, dt / k, s);
+        else product(c, RTDM_PROD_AT, A, src, dst, dt / k, 0.0, s);
         switch (k % 4) {
         case 0: launch_axpby(s, ne, 1.0, dst.re.p, 1.0, U.re.p, U.re.p); break;
         case 1: launch_axpby(s, ne, -1.0, dst.re.p, 1.0, U.im.p, U.im.p); break;
@@ -396,6 +448,7 @@ void build_propagator(rtdm_ctx *c, double dt, hipStream_t s)
         }
         cur = 1 - cur;
     }
+    if (use_cm(c)) transpose_into(c, U, c->Uc, s);
 }
 
 // D = P_P(U^dagger P_P(S U)) - S; sums into c->unit_sums.
@@ -449,7 +502,7 @@ void after_upload(rtdm_ctx *c, int m)
         c->q_ref_valid = false;
         break;
     case RTDM_MAT_H0: c->U_valid = false; break;
-    case RTDM_MAT_X: c->X_valid = true; c->U_valid = false; break;
+    case RTDM_MAT_X: c->X_valid = true; c->U_valid = false; c->Xc_valid = false; break;
     case RTDM_MAT_K:
         c->charges_valid = false;
         c->q_ref_valid = false;
@@ -458,6 +511,7 @@ void after_upload(rtdm_ctx *c, int m)
         c->herm_valid = false;
         break;
     case RTDM_MAT_U: c->U_valid = true; break;
+    case RTDM_MAT_W: c->W_in_cm = false; break;
     default: break;
     }
 }
@@ -518,7 +572,8 @@ int rtdm_create(rtdm_ctx **out, int hip_device, const rtdm_options *opt)
     if (opt) c->opt = *opt;
     else rtdm_default_options(&c->opt);
     RT_CHECK(c->opt.taylor_order >= 0 && c->opt.taylor_order <= 32, RTDM_E_ARG, "taylor_order out of range");
-    RT_CHECK(c->opt.precision == RTDM_PREC_FP64, RTDM_E_UNSUPPORTED, "only FP64 is available");
+    RT_CHECK(c->opt.precision == RTDM_PREC_FP64 || c->opt.precision == RTDM_PREC_FP32, RTDM_E_ARG,
+             "unknown precision");
     RT_CHECK(c->opt.h_model == RTDM_HMODEL_FIXED || c->opt.h_model == RTDM_HMODEL_MULLIKEN, RTDM_E_ARG,
              "unknown h_model");
     RT_CHECK(c->opt.inv_start >= 0 && c->opt.inv_start <= RTDM_INV_PREVIOUS, RTDM_E_ARG, "unknown inv_start");
@@ -531,6 +586,8 @@ int rtdm_create(rtdm_ctx **out, int hip_device, const rtdm_options *opt)
     c->s_norm2.alloc(4);
     c->hot_sums.alloc(4);
     c->obs_tmp.alloc(8);
+    c->zero.alloc(256);
+    RT_HIP(hipMemset(c->zero.p, 0, c->zero.bytes()));
     *out = c;
     }
     catch (const rtdm::Error &e) {
@@ -614,6 +671,14 @@ int rtdm_set_ranges(rtdm_ctx *c, double R_hs, double R_p, double R_k)
     alloc_mat(c, c->Wh, R_P, false);
     alloc_mat(c, c->V, R_P, true);
     alloc_mat(c, c->Z, R_P, true);
+    if (c->b == 13) {
+        alloc_mat(c, c->Xc, R_P, false);
+        alloc_mat(c, c->Ac, R_P, false);
+        alloc_mat(c, c->Uc, R_P, true);
+        alloc_mat(c, c->Wc, R_K, true);
+    }
+    c->Xc_valid = false;
+    c->W_in_cm = false;
     // maps between patterns
     Pattern &ps = pat_of(c, R_HS), &pk = pat_of(c, R_K), &pp = pat_of(c, R_P);
     auto find = [](const Pattern &P, int64_t i, int32_t j) -> int32_t {
@@ -759,6 +824,10 @@ int rtdm_download(rtdm_ctx *c, rtdm_mat mat, void *dst, int is_device, void *str
     hipStream_t s = (hipStream_t)stream;
     Mat &M = c->mats[mat];
     const int64_t ne = elems(c, M);
+    if (mat == RTDM_MAT_W && c->W_in_cm) {             // the step keeps W column-major
+        transpose_into(c, c->Wc, M, s);
+        c->W_in_cm = false;
+    }
     if (is_device) {
         launch_interleave(s, ne, M.re.p, M.cplx ? M.im.p : nullptr, (double *)dst);
         RT_HIP(hipStreamSynchronize(s));
@@ -864,6 +933,7 @@ int rtdm_build_inverse(rtdm_ctx *c, void *stream, int *iters, double *residual)
     if (iters) *iters = k;
     if (residual) *residual = r;
     c->X_valid = (st == 1);
+    c->Xc_valid = false;
     c->U_valid = false;
     RT_CHECK(st == 1, RTDM_E_NOCONV,
              "Hotelling iteration " + std::string(st == 0 ? "diverged" : "hit the iteration cap") +
@@ -888,19 +958,41 @@ int rtdm_step(rtdm_ctx *c, double dt, int64_t n_steps, void *stream)
     Mat &W = c->mats[RTDM_MAT_W];
     const Pattern &ps = pat_of(c, R_HS), &pk = pat_of(c, R_K);
     const bool mull = c->opt.h_model == RTDM_HMODEL_MULLIKEN;
+    const double t_start = c->t_now;
+    struct PrecScope {
+        rtdm_ctx *c;
+        ~PrecScope() { c->prec = RTDM_PREC_FP64; }
+    } scope{c};
     for (int64_t st = 0; st < n_steps; ++st) {
+        c->prec = c->opt.precision;
         if (mull || !c->U_valid || c->U_dt != dt) {
             RT_HIP(hipMemcpyAsync(H.re.p, H0.re.p, H.re.bytes(), hipMemcpyDeviceToDevice, s));
             if (mull)
                 launch_onsite_shift(s, c->n, c->b, ps.d_diag.p, c->opt.h_gain, c->q_cur, c->q_prev,
                                     c->q_ref.p, H.re.p);
-            product(c, RTDM_PROD_XH, X, H, A, 1.0, 0.0, s);
+            if (use_cm(c)) {
+                if (!c->Xc_valid) {
+                    transpose_into(c, X, c->Xc, s);
+                    c->Xc_valid = true;
+                }
+                product_cm(c, RTDM_PROD_XH, c->Xc, H, A, 0, 0, 1.0, s);
+                transpose_into(c, A, c->Ac, s);
+            } else {
+                product(c, RTDM_PROD_XH, X, H, A, 1.0, 0.0, s);
+            }
             build_propagator(c, dt, s);
             c->U_valid = true;
             c->U_dt = dt;
         }
-        product(c, RTDM_PROD_UK, U, K, W, 1.0, 0.0, s);
-        product(c, RTDM_PROD_WU, W, U, c->Kn, 1.0, 0.0, s);
+        if (use_cm(c)) {
+            product_cm(c, RTDM_PROD_UK, c->Uc, K, c->Wc, 0, 1, 1.0, s);     // W, column-major
+            product_cm(c, RTDM_PROD_WU, c->Wc, c->Uc, c->Kn, 1, 0, 1.0, s); // B = U^dagger
+            c->W_in_cm = true;
+        } else {
+            product(c, RTDM_PROD_UK, U, K, W, 1.0, 0.0, s);
+            product(c, RTDM_PROD_WU, W, U, c->Kn, 1.0, 0.0, s);
+            c->W_in_cm = false;
+        }
         launch_hermitize(s, pk.nnzb, c->b, pk.d_trans.p, c->Kn.re.p, c->Kn.im.p, K.re.p, K.im.p,
                          c->partials.p);
         reduce_finish(c, s, c->herm_sums.p);
@@ -908,10 +1000,11 @@ int rtdm_step(rtdm_ctx *c, double dt, int64_t n_steps, void *stream)
         std::swap(c->q_cur, c->q_prev);
         launch_mulliken(s, c->n, c->b, ps.d_rowptr.p, ps.d_trans.p, c->s_to_k.p, c->mats[RTDM_MAT_S].re.p,
                         K.re.p, c->q_cur);
-        c->t_now += dt;
+        c->t_now = t_start + (double)(st + 1) * dt;
         double *row = c->obs.p + 8 * c->obs_rows;
         launch_observables(s, c->n, c->d_xyz.p, c->q_cur, c->herm_sums.p, c->t_now, row);
         if (c->opt.unit_check_every > 0 && (c->obs_rows + 1) % c->opt.unit_check_every == 0) {
+            c->prec = RTDM_PREC_FP64;               // the unitarity check stays FP64
             unitarity_sums(c, s);
             launch_unit_to_row(s, c->unit_sums.p, c->s_norm2.p, row);
         }
@@ -1021,7 +1114,14 @@ int rtdm_multiply(rtdm_ctx *c, rtdm_mat Cm, rtdm_mat Am, rtdm_mat Bm, int op_a, 
     hipStream_t s = (hipStream_t)stream;
     const bool cres = A.cplx || B.cplx || ali != 0.0;
     RT_CHECK(C.cplx || !cres, RTDM_E_UNSUPPORTED, "complex result for a real matrix slot");
-    product(c, prod, A, B, C, alr, ali, s);
+    c->prec = c->opt.precision;
+    try {
+        product(c, prod, A, B, C, alr, ali, s);
+    } catch (...) {
+        c->prec = RTDM_PREC_FP64;
+        throw;
+    }
+    c->prec = RTDM_PREC_FP64;
     after_upload(c, Cm);
     API_END(c)
 }

@@ -18,6 +18,8 @@
 // operands are split into real and imaginary planes, so a complex block
 // product is four real tile products (re*re, im*im, re*im, im*re) sharing the
 // operand loads; a real operand skips the products it does not need.
+#include <cstdlib>
+
 #include "internal.h"
 
 namespace rtdm {
@@ -97,10 +99,11 @@ void launch_sym_fill(hipStream_t s, int64_t nout, const int32_t *c_rowof, const 
 
 // ----------------------------------------------------------------- numeric
 
-// MFMA 16x16x4 f64 operand layout (wave of 64 lanes, lane = 16*q + r):
+// MFMA 16x16x4 f64 operand layout (wave of 64 lanes, lane = 16*q + r), as
+// measured on gfx950:
 //   A operand: lane supplies A[r][q]   (row r of the 16x4 slice, column q)
 //   B operand: lane supplies B[q][r]   (row q of the 4x16 slice, column r)
-//   D (4 doubles per lane): element e of lane is D[4*q + e][r]
+//   D (4 doubles per lane): element e of lane is D[4*e + q][r]
 template <bool AC, bool BC, int OPA, int OPB>
 __global__ __launch_bounds__(256) void k_spgemm16(
     int64_t nout, const int64_t *__restrict__ off, const int2 *__restrict__ trip,
@@ -138,7 +141,7 @@ __global__ __launch_bounds__(256) void k_spgemm16(
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        const int row = 4 * q + e, col = r;
+        const int row = 4 * e + q, col = r;
         if (row < b && col < b) {
             const double re = rr[e] - ii[e];
             const double im = ri[e] + ir[e];
@@ -155,7 +158,47 @@ __global__ __launch_bounds__(256) void k_spgemm16(
 // indices instead of padding every triple from B to a multiple of 4.  Lane
 // (q, r) supplies index kappa = 4*s + q at step s.  The operands of step s+1
 // are loaded before the matrix-core work of step s is issued.
-template <int B, bool AC, bool BC, int OPA, int OPB>
+// Kernel choice for b = 13 (generic products: 0 direct gathers, 1 LDS-staged;
+// step products: 0 four-triple groups, 2 direct gathers); RTDM_B13_KERNEL
+// overrides it for measurements.
+static int kernel_variant()
+{
+    static int v = [] {
+        const char *e = getenv("RTDM_B13_KERNEL");
+        return e ? atoi(e) : 0;
+    }();
+    return v;
+}
+
+// Matrix-core step on one 16x16 tile: FP64 (v_mfma_f64_16x16x4_f64) or
+// FP32 (v_mfma_f32_16x16x4_f32).  Both take A[r][q] / B[q][r] from lane
+// 16*q + r; element e of the result sits in row 4*e + q for FP64 and in row
+// 4*q + e for FP32 (measured on gfx950).
+template <class T> struct Mfma16;
+template <> struct Mfma16<double> {
+    typedef double acc_t __attribute__((ext_vector_type(4)));
+    static __device__ inline acc_t step(double a, double b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int row(int e, int q) { return 4 * e + q; }
+};
+template <> struct Mfma16<float> {
+    typedef float acc_t __attribute__((ext_vector_type(4)));
+    static __device__ inline acc_t step(float a, float b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int row(int e, int q) { return 4 * q + e; }
+};
+
+// TA / TB: the stored block is read transposed (op(A)[r][m] at m*B + r, op(B)[m][r]
+// at r*B + m); CJA / CJB: conjugate; LC: write the output block column-major.
+// A conjugate transpose of a row-major block is TA = CJA = 1; a column-major
+// copy of a left operand is TA = 1, CJA = 0, so that the 16 lanes of a row
+// group read contiguous doubles.
+template <int B, bool AC, bool BC, int TA, int TB, class T = double, int CJA = TA, int CJB = TB,
+          int LC = 0>
 __global__ __launch_bounds__(256) void k_spgemm_kc(
     int64_t nout, const int64_t *__restrict__ off, const int2 *__restrict__ trip,
     const double *__restrict__ ar, const double *__restrict__ ai, const double *__restrict__ br,
@@ -173,22 +216,22 @@ __global__ __launch_bounds__(256) void k_spgemm_kc(
     const int nt = (int)(off[c + 1] - t0);
     const int steps = (B * nt + 3) >> 2;
     // per-lane element offsets inside a block for op(A)[r][m] and op(B)[m][r]
-    const int oa_r = OPA ? r : r * B;          // + m * (OPA ? B : 1)
-    const int ob_r = OPB ? r * B : r;          // + m * (OPB ? 1 : B)
-    constexpr int sa = OPA ? B : 1, sb = OPB ? 1 : B;
+    const int oa_r = TA ? r : r * B;           // + m * (TA ? B : 1)
+    const int ob_r = TB ? r * B : r;           // + m * (TB ? 1 : B)
+    constexpr int sa = TA ? B : 1, sb = TB ? 1 : B;
 
     int tt = 0, m = q;                         // B >= 4: the first step stays in triple 0
     int2 ab = nt > 0 ? trip[t0] : make_int2(0, 0);
-    double xar = 0.0, xai = 0.0, xbr = 0.0, xbi = 0.0;
-    auto fetch = [&](double &far, double &fai, double &fbr, double &fbi) {
-        far = fai = fbr = fbi = 0.0;
+    T xar = 0, xai = 0, xbr = 0, xbi = 0;
+    auto fetch = [&](T &far, T &fai, T &fbr, T &fbi) {
+        far = fai = fbr = fbi = 0;
         if (tt < nt && rv) {
             const int64_t pa = (int64_t)ab.x * BB + oa_r + m * sa;
             const int64_t pb = (int64_t)ab.y * BB + ob_r + m * sb;
-            far = ar[pa];
-            fbr = br[pb];
-            if (AC) fai = OPA ? -ai[pa] : ai[pa];
-            if (BC) fbi = OPB ? -bi[pb] : bi[pb];
+            far = (T)ar[pa];
+            fbr = (T)br[pb];
+            if (AC) fai = (T)(CJA ? -ai[pa] : ai[pa]);
+            if (BC) fbi = (T)(CJB ? -bi[pb] : bi[pb]);
         }
     };
     auto advance = [&]() {
@@ -199,16 +242,17 @@ __global__ __launch_bounds__(256) void k_spgemm_kc(
             if (tt < nt) ab = trip[t0 + tt];
         }
     };
-    d4 rr = {0, 0, 0, 0}, ii = {0, 0, 0, 0}, ri = {0, 0, 0, 0}, ir = {0, 0, 0, 0};
+    typedef typename Mfma16<T>::acc_t acc_t;
+    acc_t rr = {0, 0, 0, 0}, ii = {0, 0, 0, 0}, ri = {0, 0, 0, 0}, ir = {0, 0, 0, 0};
     fetch(xar, xai, xbr, xbi);
     for (int s = 0; s < steps; ++s) {
         advance();
-        double nar, nai, nbr, nbi;
+        T nar, nai, nbr, nbi;
         fetch(nar, nai, nbr, nbi);
-        rr = __builtin_amdgcn_mfma_f64_16x16x4f64(xar, xbr, rr, 0, 0, 0);
-        if (AC && BC) ii = __builtin_amdgcn_mfma_f64_16x16x4f64(xai, xbi, ii, 0, 0, 0);
-        if (BC) ri = __builtin_amdgcn_mfma_f64_16x16x4f64(xar, xbi, ri, 0, 0, 0);
-        if (AC) ir = __builtin_amdgcn_mfma_f64_16x16x4f64(xai, xbr, ir, 0, 0, 0);
+        rr = Mfma16<T>::step(xar, xbr, rr);
+        if (AC && BC) ii = Mfma16<T>::step(xai, xbi, ii);
+        if (BC) ri = Mfma16<T>::step(xar, xbi, ri);
+        if (AC) ir = Mfma16<T>::step(xai, xbr, ir);
         xar = nar;
         xai = nai;
         xbr = nbr;
@@ -216,7 +260,148 @@ __global__ __launch_bounds__(256) void k_spgemm_kc(
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        const int row = 4 * q + e, col = r;
+        const int row = Mfma16<T>::row(e, q), col = r;
+        if (row < B && col < B) {
+            const double re = (double)rr[e] - (double)ii[e];
+            const double im = (double)ri[e] + (double)ir[e];
+            const int64_t o = c * BB + (LC ? col * B + row : row * B + col);
+            cr[o] = alr * re - ali * im;
+            if (ci) ci[o] = alr * im + ali * re;
+        }
+    }
+}
+
+// Step products, B = 13 or 16: the contraction of one output block runs over
+// groups of four triples.  In each 4-wide MFMA step the lane group q (16
+// lanes) supplies element s of the group's q-th triple, so B steps consume
+// the four triples exactly (the order of the contraction sum is the only
+// difference from a triple-by-triple loop).  The left operand is a
+// column-major copy (op(A)[r][s] at s*B + r) and the right operand has
+// op(B)[s][r] at s*B + r, so every load is a per-group base pointer plus a
+// compile-time offset; lanes without data (rows r >= B, or past the last
+// triple) point at a zero block.  Conjugation is a sign applied to the
+// accumulated imaginary products at the end.
+template <int B, bool AC, bool BC, int CJA, int CJB, int LC>
+__global__ __launch_bounds__(256) void k_spgemm_q4(
+    int64_t nout, const int64_t *__restrict__ off, const int2 *__restrict__ trip,
+    const double *__restrict__ ar, const double *__restrict__ ai, const double *__restrict__ br,
+    const double *__restrict__ bi, double *__restrict__ cr, double *__restrict__ ci, double alr,
+    double ali, const double *__restrict__ zero)
+{
+    static_assert(B >= 4 && B <= 16, "k_spgemm_q4 needs 4 <= B <= 16");
+    constexpr int BB = B * B;
+    const int lane = threadIdx.x & 63;
+    const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= nout) return;                     // uniform across the wave
+    const int r = lane & 15, q = lane >> 4;
+    const bool rv = r < B;
+    const int64_t t0 = off[c];
+    const int nt = (int)(off[c + 1] - t0);
+    typedef Mfma16<double>::acc_t acc_t;
+    acc_t rr = {0, 0, 0, 0}, ii = {0, 0, 0, 0}, ri = {0, 0, 0, 0}, ir = {0, 0, 0, 0};
+    for (int g = 0; g < nt; g += 4) {
+        const double *pa = zero, *pai = zero, *pb = zero, *pbi = zero;
+        if (rv && g + q < nt) {
+            const int2 ab = trip[t0 + g + q];
+            const int64_t oa = (int64_t)ab.x * BB + r, ob = (int64_t)ab.y * BB + r;
+            pa = ar + oa;
+            pb = br + ob;
+            if (AC) pai = ai + oa;
+            if (BC) pbi = bi + ob;
+        }
+#pragma unroll
+        for (int st = 0; st < B; ++st) {
+            const double xa = pa[st * B], xb = pb[st * B];
+            rr = Mfma16<double>::step(xa, xb, rr);
+            if (AC && BC) ii = Mfma16<double>::step(pai[st * B], pbi[st * B], ii);
+            if (BC) ri = Mfma16<double>::step(xa, pbi[st * B], ri);
+            if (AC) ir = Mfma16<double>::step(pai[st * B], xb, ir);
+        }
+    }
+    // op(A)_im = sa * A_im, op(B)_im = sb * B_im
+    constexpr double sa = CJA ? -1.0 : 1.0, sb = CJB ? -1.0 : 1.0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int row = Mfma16<double>::row(e, q), col = r;
+        if (row < B && col < B) {
+            const double re = rr[e] - (sa * sb) * ii[e];
+            const double im = sb * ri[e] + sa * ir[e];
+            const int64_t o = c * BB + (LC ? col * B + row : row * B + col);
+            cr[o] = alr * re - ali * im;
+            if (ci) ci[o] = alr * im + ali * re;
+        }
+    }
+}
+
+// LDS-staged variant for a compile-time block size B: the operand blocks of CH
+// triples of the wave's output block are first copied into the wave's own LDS
+// region with coalesced loads (each block plane is B*B contiguous doubles),
+// then the MFMA fragments of the B*CH contraction indices of the chunk are
+// read from LDS (for B = 13, CH = 4 that is exactly 13 steps of 4).  Every
+// wave owns its region, so no workgroup barrier is needed: a wave's LDS
+// operations execute in issue order.
+template <int B, bool AC, bool BC, int OPA, int OPB, int CH, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_spgemm_lds(
+    int64_t nout, const int64_t *__restrict__ off, const int2 *__restrict__ trip,
+    const double *__restrict__ ar, const double *__restrict__ ai, const double *__restrict__ br,
+    const double *__restrict__ bi, double *__restrict__ cr, double *__restrict__ ci, double alr,
+    double ali)
+{
+    constexpr int BB = B * B;
+    constexpr int NPA = AC ? 2 : 1, NPB = BC ? 2 : 1;
+    constexpr int PL = (NPA + NPB) * BB;       // staged doubles per triple
+    constexpr int STEPS = (B * CH + 3) / 4;
+    __shared__ double lds[WPB][CH * PL];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t c = (int64_t)blockIdx.x * WPB + w;
+    if (c >= nout) return;                     // uniform across the wave
+    double *L = lds[w];
+    const int r = lane & 15, q = lane >> 4;
+    const bool rv = r < B;
+    const int64_t t0 = off[c];
+    const int nt = (int)(off[c + 1] - t0);
+    typedef Mfma16<double>::acc_t acc_t;
+    acc_t rr = {0, 0, 0, 0}, ii = {0, 0, 0, 0}, ri = {0, 0, 0, 0}, ir = {0, 0, 0, 0};
+    for (int tc = 0; tc < nt; tc += CH) {
+        const int nch = nt - tc < CH ? nt - tc : CH;
+        for (int u = 0; u < nch; ++u) {
+            const int2 ab = trip[t0 + tc + u];
+            const int64_t pa = (int64_t)ab.x * BB, pb = (int64_t)ab.y * BB;
+            double *d = L + u * PL;
+            for (int e = lane; e < BB; e += 64) {
+                d[e] = ar[pa + e];
+                if (AC) d[BB + e] = ai[pa + e];
+                d[NPA * BB + e] = br[pb + e];
+                if (BC) d[(NPA + 1) * BB + e] = bi[pb + e];
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        const int kv = B * nch;
+#pragma unroll
+        for (int s = 0; s < STEPS; ++s) {
+            const int kap = 4 * s + q;
+            const int u = kap / B, m = kap - u * B;
+            double xar = 0.0, xai = 0.0, xbr = 0.0, xbi = 0.0;
+            if (kap < kv && rv) {
+                const double *la = L + u * PL;
+                const double *lb = la + NPA * BB;
+                const int ia = OPA ? (m * B + r) : (r * B + m);   // op(A)[r][m]
+                const int ib = OPB ? (r * B + m) : (m * B + r);   // op(B)[m][r]
+                xar = la[ia];
+                xbr = lb[ib];
+                if (AC) xai = OPA ? -la[BB + ia] : la[BB + ia];
+                if (BC) xbi = OPB ? -lb[BB + ib] : lb[BB + ib];
+            }
+            rr = Mfma16<double>::step(xar, xbr, rr);
+            if (AC && BC) ii = Mfma16<double>::step(xai, xbi, ii);
+            if (BC) ri = Mfma16<double>::step(xar, xbi, ri);
+            if (AC) ir = Mfma16<double>::step(xai, xbr, ir);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int row = Mfma16<double>::row(e, q), col = r;
         if (row < B && col < B) {
             const double re = rr[e] - ii[e];
             const double im = ri[e] + ir[e];
@@ -227,12 +412,120 @@ __global__ __launch_bounds__(256) void k_spgemm_kc(
     }
 }
 
+template <int B, bool AC, bool BC, int OA, int OB>
+static void launch_lds(hipStream_t s, const SpgemmArgs &a)
+{
+    constexpr int WPB = (AC && BC) ? 2 : 4;
+    hipLaunchKernelGGL((k_spgemm_lds<B, AC, BC, OA, OB, 4, WPB>),
+                       dim3((unsigned)((a.nout + WPB - 1) / WPB)), dim3(64 * WPB), 0, s, a.nout,
+                       a.off, a.trip, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re, a.alpha_im);
+}
+
+// b = 4: v_mfma_f64_4x4x4_4b_f64 runs four independent 4x4x4 products, one
+// per "MFMA block".  Each output block needs SUB real sub-products (1: real x
+// real; 2: one operand complex; 4: complex x complex: re*re, im*im, re*im,
+// im*re), so a wave serves 4/SUB output blocks, each on SUB MFMA blocks, with
+// no padding anywhere: one instruction per step does one block triple of 4/SUB
+// outputs.  Lane layout (measured on gfx950), lane = 16*q + 4*g + r:
+//   MFMA block g; A operand A_g[r][q]; B operand B_g[q][r]; D: D_g[q][r].
+// The wave's outputs advance in lock-step over their triple lists; a finished
+// output feeds zeros.
+template <int SUB, bool AC, bool BC, int OPA, int OPB>
+__global__ __launch_bounds__(256) void k_spgemm_b4(
+    int64_t nout, const int64_t *__restrict__ off, const int2 *__restrict__ trip,
+    const double *__restrict__ ar, const double *__restrict__ ai, const double *__restrict__ br,
+    const double *__restrict__ bi, double *__restrict__ cr, double *__restrict__ ci, double alr,
+    double ali)
+{
+    constexpr int OUT = 4 / SUB;               // outputs per wave
+    const int lane = threadIdx.x & 63;
+    const int g = (lane >> 2) & 3, r = lane & 3, q = lane >> 4;
+    const int sub = g % SUB;                   // which real sub-product this MFMA block runs
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t c0 = wave * OUT;
+    if (c0 >= nout) return;                    // uniform across the wave
+    const int64_t c = c0 + g / SUB;            // this lane's output block
+    const bool live = c < nout;
+    const int64_t t0 = live ? off[c] : 0;
+    const int nt = live ? (int)(off[c + 1] - t0) : 0;
+    // longest list of the wave (the four MFMA blocks sit 4 lanes apart)
+    int ntmax = max(nt, __shfl_xor(nt, 4, 64));
+    ntmax = max(ntmax, __shfl_xor(ntmax, 8, 64));
+    // operand planes of this sub-product: sub 0 re*re, 1 im*im, 2 re*im, 3 im*re (SUB = 4);
+    // SUB = 2: sub 0 re*re, sub 1 the product with the complex operand's imaginary part.
+    bool a_im = false, b_im = false;
+    if (SUB == 4) { a_im = (sub == 1 || sub == 3); b_im = (sub == 1 || sub == 2); }
+    if (SUB == 2) { a_im = AC && sub == 1; b_im = BC && sub == 1; }
+    const double *pa = a_im ? ai : ar;
+    const double *pb = b_im ? bi : br;
+    const double sa = (a_im && OPA) ? -1.0 : 1.0;
+    const double sb = (b_im && OPB) ? -1.0 : 1.0;
+    const int ia = OPA ? (q * 4 + r) : (r * 4 + q);   // op(A)[r][q]
+    const int ib = OPB ? (r * 4 + q) : (q * 4 + r);   // op(B)[q][r]
+    double acc = 0.0;
+    double xa = 0.0, xb = 0.0;
+    if (nt > 0) {
+        const int2 ab = trip[t0];
+        xa = sa * pa[(int64_t)ab.x * 16 + ia];
+        xb = sb * pb[(int64_t)ab.y * 16 + ib];
+    }
+    for (int t = 0; t < ntmax; ++t) {
+        double na = 0.0, nb = 0.0;
+        if (t + 1 < nt) {
+            const int2 ab = trip[t0 + t + 1];
+            na = sa * pa[(int64_t)ab.x * 16 + ia];
+            nb = sb * pb[(int64_t)ab.y * 16 + ib];
+        }
+        acc = __builtin_amdgcn_mfma_f64_4x4x4f64(xa, xb, acc, 0, 0, 0);
+        xa = na;
+        xb = nb;
+    }
+    // combine the sub-products of each output (MFMA blocks are 4 lanes apart)
+    double re = acc, im = 0.0;
+    if (SUB == 4) {
+        const double d1 = __shfl_down(acc, 4, 64);    // block g+1
+        const double d2 = __shfl_down(acc, 8, 64);    // block g+2
+        const double d3 = __shfl_down(acc, 12, 64);   // block g+3
+        re = acc - d1;
+        im = d2 + d3;
+    } else if (SUB == 2) {
+        im = __shfl_down(acc, 4, 64);
+    }
+    if (live && sub == 0) {
+        const int64_t o = c * 16 + q * 4 + r;
+        cr[o] = alr * re - ali * im;
+        if (ci) ci[o] = alr * im + ali * re;
+    }
+}
+
+template <int SUB, bool AC, bool BC, int OA, int OB>
+static void launch_b4(hipStream_t s, const SpgemmArgs &a)
+{
+    constexpr int OUT = 4 / SUB;
+    const int64_t waves = (a.nout + OUT - 1) / OUT;
+    hipLaunchKernelGGL((k_spgemm_b4<SUB, AC, BC, OA, OB>), dim3((unsigned)((waves + 3) / 4)), dim3(256),
+                       0, s, a.nout, a.off, a.trip, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re,
+                       a.alpha_im);
+}
+
 template <bool AC, bool BC>
 static void dispatch_ops(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
 {
 #define RT_LAUNCH(OA, OB)                                                                        \
     do {                                                                                         \
-        if (a.b == 13)                                                                           \
+        if (a.precision == RTDM_PREC_FP32 && a.b == 13)                                          \
+            hipLaunchKernelGGL((k_spgemm_kc<13, AC, BC, OA, OB, float>), g, t, 0, s, a.nout,     \
+                               a.off, a.trip, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re,    \
+                               a.alpha_im);                                                      \
+        else if (a.precision == RTDM_PREC_FP32 && a.b >= 4)                                      \
+            hipLaunchKernelGGL((k_spgemm_kc<4, AC, BC, OA, OB, float>), g, t, 0, s, a.nout,      \
+                               a.off, a.trip, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re,    \
+                               a.alpha_im);                                                      \
+        else if (a.b == 4)                                                                       \
+            launch_b4<(AC && BC) ? 4 : ((AC || BC) ? 2 : 1), AC, BC, OA, OB>(s, a);              \
+        else if (a.b == 13 && kernel_variant() == 1)                                             \
+            launch_lds<13, AC, BC, OA, OB>(s, a);                                                \
+        else if (a.b == 13)                                                                      \
             hipLaunchKernelGGL((k_spgemm_kc<13, AC, BC, OA, OB>), g, t, 0, s, a.nout, a.off,     \
                                a.trip, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re,           \
                                a.alpha_im);                                                      \
@@ -251,10 +544,48 @@ static void dispatch_ops(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
 #undef RT_LAUNCH
 }
 
+// Step products with a column-major copy of the left operand (op(A)[r][m] at
+// m*B + r) and a right operand whose op(B)[m][r] sits at m*B + r (row-major
+// B, or the column-major copy of a matrix used conjugate-transposed).
+template <bool AC, bool BC, int CJB, int LC>
+static void launch_cm(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
+{
+    if (kernel_variant() == 2)
+        hipLaunchKernelGGL((k_spgemm_kc<13, AC, BC, 1, 0, double, 0, CJB, LC>), g, t, 0, s, a.nout,
+                           a.off, a.trip, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re, a.alpha_im);
+    else
+        hipLaunchKernelGGL((k_spgemm_q4<13, AC, BC, 0, CJB, LC>), g, t, 0, s, a.nout, a.off, a.trip,
+                           a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re, a.alpha_im, a.zero);
+}
+
+void launch_spgemm_cm(hipStream_t s, const SpgemmArgs &a, int conj_b, int out_col_major)
+{
+    if (a.nout == 0) return;
+    RT_CHECK(a.b == 13 && a.precision == RTDM_PREC_FP64, RTDM_E_UNSUPPORTED,
+             "column-major step products need b = 13 and FP64");
+    const dim3 g((unsigned)((a.nout + 3) / 4)), t(256);
+    const bool ac = a.ai != nullptr, bc = a.bi != nullptr;
+#define RT_CM(AC_, BC_)                                                            \
+    do {                                                                           \
+        if (conj_b && out_col_major) launch_cm<AC_, BC_, 1, 1>(s, a, g, t);        \
+        else if (conj_b) launch_cm<AC_, BC_, 1, 0>(s, a, g, t);                    \
+        else if (out_col_major) launch_cm<AC_, BC_, 0, 1>(s, a, g, t);             \
+        else launch_cm<AC_, BC_, 0, 0>(s, a, g, t);                                \
+    } while (0)
+    if (ac && bc) RT_CM(true, true);
+    else if (ac) RT_CM(true, false);
+    else if (bc) RT_CM(false, true);
+    else RT_CM(false, false);
+#undef RT_CM
+    RT_HIP(hipGetLastError());
+}
+
 void launch_spgemm(hipStream_t s, const SpgemmArgs &a)
 {
     if (a.nout == 0) return;
     RT_CHECK(a.b >= 1 && a.b <= 16, RTDM_E_UNSUPPORTED, "block size must be 1..16");
+    RT_CHECK(a.precision == RTDM_PREC_FP64 || (a.precision == RTDM_PREC_FP32 && (a.b == 4 || a.b == 13)),
+             RTDM_E_UNSUPPORTED, "FP32 products need b = 4 or 13");
     const dim3 g((unsigned)((a.nout + 3) / 4)), t(256);
     const bool ac = a.ai != nullptr, bc = a.bi != nullptr;
     if (ac && bc) dispatch_ops<true, true>(s, a, g, t);

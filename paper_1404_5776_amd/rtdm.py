@@ -22,6 +22,7 @@ MAT = {"S": 0, "H0": 1, "H": 2, "X": 3, "A": 4, "U": 5, "K": 6, "W": 7}
 PROD = {"XH": 0, "AT": 1, "UK": 2, "WU": 3, "SX": 4, "UV": 5}
 HMODEL = {"fixed": 0, "mulliken": 1}
 INV_START = {"block_jacobi": 0, "cold": 1, "previous": 2}
+PRECISION = {"fp64": 0, "fp32": 1}
 
 STATUS = {0: "RTDM_OK", -1: "RTDM_E_ARG", -2: "RTDM_E_STATE", -3: "RTDM_E_OOM", -4: "RTDM_E_HIP",
           -5: "RTDM_E_NOCONV", -6: "RTDM_E_NUMERIC", -7: "RTDM_E_UNSUPPORTED"}
@@ -280,6 +281,8 @@ class Context:
                 v = HMODEL[v]
             if k == "inv_start" and isinstance(v, str):
                 v = INV_START[v]
+            if k == "precision" and isinstance(v, str):
+                v = PRECISION[v]
             setattr(o, k, v)
         self.options = o
         self.h = rtdm_create(device, o)

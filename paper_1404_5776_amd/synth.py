@@ -30,7 +30,7 @@ Recipe (all lengths in bohr, energies in hartree):
   + eta*sym(U(-1,1)); H_ij = -t0 exp(-(d/3.37)^2) U(-1,1), symmetric;
   gap = 1.0, t0 = 0.05, eta = 0.05;
 * K0 (real symmetric, kept only for pairs closer than R_K):
-  - "exact": lowest floor(b/2)*N eigenvectors V of the generalized problem
+  - "exact": lowest floor(b/2)*N (N/2 for b = 1) eigenvectors V of the generalized problem
     H0 v = e S v (V^T S V = I), K0 = V V^T (spinless, so K0 S K0 = K0);
   - "local": for systems too large for a dense eigensolver, a
     divide-and-conquer density matrix (W. Yang, Phys. Rev. Lett. 66, 1438
@@ -283,12 +283,17 @@ def dense_to_coo(dense: np.ndarray, xyz: np.ndarray, b: int, R: float) -> BlockC
     return BlockCOO(rows, cols, data)
 
 
+def n_occupied(n_atoms: int, b: int) -> int:
+    """floor(b/2) occupied states per atom (half of all states for b = 1)."""
+    return n_atoms * (b // 2) if b >= 2 else max(1, n_atoms // 2)
+
+
 def k0_exact(S: BlockCOO, H0: BlockCOO, xyz, b, R_K) -> BlockCOO:
     from scipy.linalg import eigh
     n = xyz.shape[0]
     Sd = coo_to_dense(S, n, b)
     Hd = coo_to_dense(H0, n, b)
-    nocc = n * (b // 2)
+    nocc = n_occupied(n, b)
     w, V = eigh(Hd, Sd, subset_by_index=[0, nocc - 1])
     K = V @ V.T
     return dense_to_coo(0.5 * (K + K.T), xyz, b, R_K)
@@ -341,7 +346,7 @@ def k0_local(S: BlockCOO, H0: BlockCOO, xyz, b, R_K, r_loc: float = 4.5) -> Bloc
         Ht = Li @ Hl @ np.transpose(Li, (0, 2, 1))
         Ht = 0.5 * (Ht + np.transpose(Ht, (0, 2, 1)))
         w, Y = np.linalg.eigh(Ht)
-        nocc = m * (b // 2)
+        nocc = n_occupied(m, b)
         V = np.transpose(Li, (0, 2, 1)) @ Y[:, :, :nocc]
         Kl = V @ np.transpose(V, (0, 2, 1))                    # (g, mb, mb)
         for gi, i in enumerate(atoms):

@@ -24,3 +24,12 @@ def assert_same_pattern(ctx, slot, pat: O.Pattern):
     rp, col = rtdm.rtdm_pattern(ctx.h, slot)
     np.testing.assert_array_equal(rp, pat.row_ptr)
     np.testing.assert_array_equal(col, pat.col)
+
+
+def dipole_floor(q: np.ndarray, xyz: np.ndarray) -> float:
+    """Rounding floor of P = -sum_i (r_i - r_c) q_i: the sum nearly cancels, so
+    two FP64 implementations summing in different orders agree only to about
+    log2(n) * eps * sum_i |r_i - r_c| |q_i| (forward error of a tree-order sum)."""
+    rc = xyz.mean(axis=0)
+    S = np.abs((xyz - rc) * q[:, None]).sum(axis=0).max()
+    return 2.0 * np.log2(max(len(q), 2)) * np.finfo(float).eps * S

@@ -13,7 +13,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_1404_5776_amd import rtdm, synth
-from tests._common import TOL, assert_same_pattern, gpu_context, rel
+from tests._common import TOL, assert_same_pattern, dipole_floor, gpu_context, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -149,7 +149,7 @@ def test_kick_and_observables_match_oracle(case):
     obs = rtdm.rtdm_observables(ctx.h)
     q = O.mulliken(Kref, st.S)
     P = O.dipole(q, st.xyz)
-    np.testing.assert_allclose(obs[:3], P, rtol=0, atol=TOL * max(1.0, np.abs(P).max()))
+    np.testing.assert_allclose(obs[:3], P, rtol=0, atol=TOL * np.abs(P).max() + dipole_floor(q, st.xyz))
     assert abs(obs[3] - q.sum()) <= TOL * abs(q.sum())
 
 
@@ -167,12 +167,16 @@ def _propagation_parity(s, n_steps, unit_every=0, **opts):
     ctx.close()
     ref = O.propagate(st, n_steps, s.dt, s.kappa, h_model=s.h_model)
     assert it == ref.inverse.iters
-    P0 = O.dipole(O.mulliken(O.kick(st.K0, st.xyz, s.kappa), st.S), st.xyz)
-    np.testing.assert_allclose(obs0[:3], P0, rtol=0, atol=TOL * np.abs(P0).max())
+    q0 = O.mulliken(O.kick(st.K0, st.xyz, s.kappa), st.S)
+    P0 = O.dipole(q0, st.xyz)
+    floor = dipole_floor(q0, st.xyz)
+    np.testing.assert_allclose(obs0[:3], P0, rtol=0, atol=TOL * np.abs(P0).max() + floor)
     assert tr.shape == (n_steps, 7)
-    np.testing.assert_allclose(tr[:, 0], ref.rows[:, 0], rtol=1e-15)
+    np.testing.assert_allclose(tr[:, 0], ref.rows[:, 0], rtol=1e-14)
     induced = np.abs(ref.rows[:, 1:4] - P0).max()
-    assert np.abs(tr[:, 1:4] - ref.rows[:, 1:4]).max() <= TOL * induced
+    err = np.abs(tr[:, 1:4] - ref.rows[:, 1:4]).max()
+    print(f"dipole error {err:.2e}, induced {induced:.2e}, rounding floor {floor:.2e}")
+    assert err <= TOL * induced + floor
     assert np.abs(tr[:, 4] - ref.rows[:, 4]).max() <= TOL * np.abs(ref.rows[:, 4]).max()
     np.testing.assert_allclose(tr[:, 5], ref.rows[:, 5], rtol=1e-4, atol=1e-15)
     assert rel(K, ref.K.val) <= TOL

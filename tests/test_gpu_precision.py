@@ -1,0 +1,59 @@
+"""Reduced-precision block products against the FP64 oracle.
+
+FP32 matrix-core products keep FP64 storage, reductions and observables.
+Stated tolerances: one product within 1e-6 relative (Frobenius) of the oracle
+(FP32 rounding of the operands and of each accumulation step, ~2^-24 times a
+modest growth factor); 100 steps of the 64-atom cluster keep the induced
+dipole within 1e-4 of its peak and Tr(KS) within 1e-6 relative.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1404_5776_amd import rtdm, synth
+from tests._common import gpu_context, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("b", [4, 13])
+def test_fp32_products_within_stated_tolerance(b):
+    rng = np.random.default_rng(200 + b)
+    xyz = synth.cluster_positions(40, rng)
+    s = synth.build_system("fp32", xyz, b, 6.0, 8.0, 200 + b)
+    st = O.setup(s)
+    ctx = gpu_context(s, precision="fp32")
+    for kind, (Cs, As, Bs, ob, pa, ca, pb, cb, pc) in {
+            "AT": ("U", "A", "X", 0, st.pat_p, False, st.pat_p, False, st.pat_p),
+            "UK": ("W", "U", "K", 0, st.pat_p, True, st.pat_k, True, st.pat_k),
+            "WU": ("K", "W", "U", 1, st.pat_k, True, st.pat_p, True, st.pat_k)}.items():
+        a = synth.random_blocks(pa.rows(), pa.col, b, 1, ca)
+        bm = synth.random_blocks(pb.rows(), pb.col, b, 2, cb)
+        rtdm.rtdm_upload(ctx.h, As, a)
+        rtdm.rtdm_upload(ctx.h, Bs, bm)
+        rtdm.rtdm_multiply(ctx.h, Cs, As, Bs, 0, ob)
+        got = rtdm.rtdm_download(ctx.h, Cs, b)
+        want, _ = O.spgemm(O.BSM(pa, b, a + 0j), O.BSM(pb, b, bm + 0j), pc, op_b=ob)
+        e = rel(got, want.val)
+        print(f"fp32 {kind} b={b}: relative error {e:.2e}")
+        assert e <= 1e-6, kind
+    ctx.close()
+
+
+def test_fp32_propagation_error_stated():
+    s = synth.config1()
+    st = O.setup(s)
+    ctx = gpu_context(s, precision="fp32")
+    rtdm.rtdm_build_inverse(ctx.h)
+    rtdm.rtdm_apply_kick(ctx.h, s.kappa)
+    rtdm.rtdm_step(ctx.h, s.dt, 100)
+    tr = rtdm.rtdm_dipole_trace(ctx.h)
+    ctx.close()
+    ref = O.propagate(st, 100, s.dt, s.kappa)
+    P0 = O.dipole(O.mulliken(O.kick(st.K0, st.xyz, s.kappa), st.S), st.xyz)
+    induced = np.abs(ref.rows[:, 1:4] - P0).max()
+    e_dip = np.abs(tr[:, 1:4] - ref.rows[:, 1:4]).max() / induced
+    e_tr = np.abs(tr[:, 4] - ref.rows[:, 4]).max() / abs(ref.rows[0, 4])
+    print(f"fp32 64-atom cluster, 100 steps: dipole error {e_dip:.2e} of peak induced, Tr(KS) {e_tr:.2e}")
+    assert e_dip <= 1e-4 and e_tr <= 1e-6
