@@ -24,6 +24,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 (matrix and vector)
+# Identifies the product kernel build whose HBM traffic profiles/traffic.json holds;
+# change it whenever the kernel changes so that a stale figure is not reported.
+KERNEL_TAG = "q4-b13-xcd-tile64-v1"
+
+
+def measured_traffic(dom):
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        t = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_tag") != KERNEL_TAG or t.get("product") != dom:
+        return None
+    return t["bytes_per_launch"]
 METRIC = "propagation steps/s + block-SpGEMM GFLOP/s (% roofline) at stated dipole error vs FP64"
 
 
@@ -125,9 +139,9 @@ def main():
         x = torch.ones(n, dtype=torch.float64, device="cuda")
         y = torch.empty_like(x)
         for _ in range(3):
-            y.copy_(x)
+            torch.mul(x, 1.0, out=y)        # one elementwise kernel: reads MIB MiB, writes MIB MiB
         torch.cuda.synchronize()
-        log(f"copy calibration: 3 copies of {args.calibrate_copy} MiB")
+        log(f"copy calibration: 3 elementwise copies of {args.calibrate_copy} MiB")
         del x, y
 
     t = time.time()
@@ -179,9 +193,10 @@ def main():
         "spgemm_tflop_per_step": flops_per_step / 1e12,
         "accuracy": "FP64 path; equals the FP64 oracle within 1e-10 relative in the parity tests, "
                     "so its dipole error vs FP64 is at that level",
-        "roofline": {"bound": "mfma", "kernel": f"k_spgemm16 ({dom} product)", "achieved": achieved,
+        "roofline": {"bound": "mfma", "kernel": f"k_spgemm_q4<13> ({dom} product)", "achieved": achieved,
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": None, "avg_launch_ms": avg_s * 1e3,
+                     "traffic": measured_traffic(dom), "traffic_unit": "bytes per launch",
+                     "avg_launch_ms": avg_s * 1e3,
                      "flops_per_launch": fl / n_l},
         "per_product_ms": {k: v[1] / max(v[0], 1) for k, v in stats.items()},
         "trace_last": trace[-1, :6].tolist() if len(trace) else None,

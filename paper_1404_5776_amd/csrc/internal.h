@@ -87,6 +87,7 @@ struct SpgemmArgs {
     double alpha_re = 1.0, alpha_im = 0.0;
     int precision = RTDM_PREC_FP64;  // arithmetic of the block products
     const double *zero = nullptr;    // 256 zero doubles (operand of lanes without data)
+    const int32_t *order = nullptr;  // processing order of the output blocks (null: storage order)
 };
 void launch_spgemm(hipStream_t s, const SpgemmArgs &a);
 // Same product with the left operand given as column-major blocks, the right

@@ -15,6 +15,7 @@
 // real block product.  The values are the ones the complex recursion gives
 // (the other part of every term is exactly zero).
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -50,7 +51,40 @@ struct Sched {
     int64_t nout = 0, ntrip = 0;
     DBuf<int64_t> off;
     DBuf<int2> trip;
+    DBuf<int32_t> order;   // processing order of the output blocks (row tiles, then columns)
 };
+
+// Processing order of the output blocks of pattern C: rows are cut into
+// tiles of `tile_i` consecutive atoms and columns into tiles of `tile_j`
+// consecutive atoms; a row tile is processed column tile by column tile, and
+// inside a column tile column by column, row by row.  Consecutive outputs then
+// share their right-operand blocks (same column), and the left- and
+// right-operand blocks of one (row tile, column tile) pair stay in L2 while
+// its outputs run.
+std::vector<int32_t> tile_order(const Pattern &C, int tile_i, int tile_j)
+{
+    std::vector<int32_t> order;
+    order.reserve(C.nnzb);
+    struct E { int32_t jt, j, p; };
+    std::vector<E> buf;
+    for (int64_t i0 = 0; i0 < C.n; i0 += tile_i) {
+        const int64_t i1 = std::min<int64_t>(C.n, i0 + tile_i);
+        buf.clear();
+        for (int64_t p = C.rowptr[i0]; p < C.rowptr[i1]; ++p)
+            buf.push_back({C.col[p] / tile_j, C.col[p], (int32_t)p});
+        std::stable_sort(buf.begin(), buf.end(), [](const E &x, const E &y) {
+            return x.jt != y.jt ? x.jt < y.jt : x.j < y.j;
+        });
+        for (auto &e : buf) order.push_back(e.p);
+    }
+    return order;
+}
+
+int env_int(const char *name, int dflt)
+{
+    const char *e = getenv(name);
+    return e ? std::max(1, atoi(e)) : dflt;
+}
 
 struct TRec {
     int prod;
@@ -289,6 +323,12 @@ Sched &schedule(rtdm_ctx *c, int prod)
     launch_sym_fill(nullptr, S->nout, C.d_rowof.p, C.d_col.p, A.d_rowptr.p, A.d_col.p, A.d_trans.p,
                     B.d_rowptr.p, B.d_col.p, B.d_trans.p, std::get<3>(key), std::get<4>(key),
                     S->off.p, S->trip.p);
+    {
+        const std::vector<int32_t> ord = tile_order(C, env_int("RTDM_ROW_TILE", 64), env_int("RTDM_COL_TILE", 1 << 30));
+        S->order.alloc(std::max<size_t>(ord.size(), 1));
+        if (!ord.empty())
+            RT_HIP(hipMemcpy(S->order.p, ord.data(), ord.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
     RT_HIP(hipDeviceSynchronize());
     Sched &ref = *S;
     c->scheds.emplace(key, std::move(S));
@@ -366,6 +406,7 @@ void product_cm(rtdm_ctx *c, int prod, const Mat &Acm, const Mat &B, Mat &C, int
     a.b = c->b;
     a.alpha_re = alr;
     a.zero = c->zero.p;
+    a.order = getenv("RTDM_NO_ORDER") ? nullptr : S.order.p;
     RT_CHECK(C.cplx || (!Acm.cplx && !B.cplx), RTDM_E_UNSUPPORTED, "complex product into a real matrix");
     if (c->timing) {
         const size_t k = 2 * c->recs.size();

@@ -170,6 +170,23 @@ static int kernel_variant()
     return v;
 }
 
+// Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by
+// block index.  xcd_block() renumbers them so that XCD x runs the contiguous
+// range [x*per, (x+1)*per) of logical blocks: neighbouring output blocks, which
+// share operand blocks, then meet in the same L2.  The grid is launched with
+// 8*per blocks; logical indices >= the real count exit.
+constexpr int kXcds = 8;
+__device__ inline int64_t xcd_block(int64_t nblocks, int remap = 1)
+{
+    if (!remap) return blockIdx.x;
+    const int64_t per = (nblocks + kXcds - 1) / kXcds;
+    return (int64_t)(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+}
+static inline unsigned xcd_grid(int64_t nblocks)
+{
+    return (unsigned)(((nblocks + kXcds - 1) / kXcds) * kXcds);
+}
+
 // Matrix-core step on one 16x16 tile: FP64 (v_mfma_f64_16x16x4_f64) or
 // FP32 (v_mfma_f32_16x16x4_f32).  Both take A[r][q] / B[q][r] from lane
 // 16*q + r; element e of the result sits in row 4*e + q for FP64 and in row
@@ -286,13 +303,14 @@ __global__ __launch_bounds__(256) void k_spgemm_q4(
     int64_t nout, const int64_t *__restrict__ off, const int2 *__restrict__ trip,
     const double *__restrict__ ar, const double *__restrict__ ai, const double *__restrict__ br,
     const double *__restrict__ bi, double *__restrict__ cr, double *__restrict__ ci, double alr,
-    double ali, const double *__restrict__ zero)
+    double ali, const double *__restrict__ zero, const int32_t *__restrict__ order, int remap)
 {
     static_assert(B >= 4 && B <= 16, "k_spgemm_q4 needs 4 <= B <= 16");
     constexpr int BB = B * B;
     const int lane = threadIdx.x & 63;
-    const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (c >= nout) return;                     // uniform across the wave
+    const int64_t w = xcd_block((nout + 3) / 4, remap) * 4 + (threadIdx.x >> 6);
+    if (w >= nout) return;                     // uniform across the wave
+    const int64_t c = order ? (int64_t)order[w] : w;
     const int r = lane & 15, q = lane >> 4;
     const bool rv = r < B;
     const int64_t t0 = off[c];
@@ -319,6 +337,80 @@ __global__ __launch_bounds__(256) void k_spgemm_q4(
         }
     }
     // op(A)_im = sa * A_im, op(B)_im = sb * B_im
+    constexpr double sa = CJA ? -1.0 : 1.0, sb = CJB ? -1.0 : 1.0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int row = Mfma16<double>::row(e, q), col = r;
+        if (row < B && col < B) {
+            const double re = rr[e] - (sa * sb) * ii[e];
+            const double im = sb * ri[e] + sa * ir[e];
+            const int64_t o = c * BB + (LC ? col * B + row : row * B + col);
+            cr[o] = alr * re - ali * im;
+            if (ci) ci[o] = alr * im + ali * re;
+        }
+    }
+}
+
+// k_spgemm_q4 with the operands of the next group of four triples loaded into
+// registers while the matrix cores work on the current group, so the load
+// latency of one group hides behind B*SUB MFMAs of the previous one.
+template <int B, bool AC, bool BC, int CJA, int CJB, int LC>
+__global__ __launch_bounds__(256) void k_spgemm_q4p(
+    int64_t nout, const int64_t *__restrict__ off, const int2 *__restrict__ trip,
+    const double *__restrict__ ar, const double *__restrict__ ai, const double *__restrict__ br,
+    const double *__restrict__ bi, double *__restrict__ cr, double *__restrict__ ci, double alr,
+    double ali, const double *__restrict__ zero, const int32_t *__restrict__ order)
+{
+    static_assert(B >= 4 && B <= 16, "k_spgemm_q4p needs 4 <= B <= 16");
+    constexpr int BB = B * B;
+    const int lane = threadIdx.x & 63;
+    const int64_t w = xcd_block((nout + 3) / 4) * 4 + (threadIdx.x >> 6);
+    if (w >= nout) return;                     // uniform across the wave
+    const int64_t c = order ? (int64_t)order[w] : w;
+    const int r = lane & 15, q = lane >> 4;
+    const bool rv = r < B;
+    const int64_t t0 = off[c];
+    const int nt = (int)(off[c + 1] - t0);
+    typedef Mfma16<double>::acc_t acc_t;
+    acc_t rr = {0, 0, 0, 0}, ii = {0, 0, 0, 0}, ri = {0, 0, 0, 0}, ir = {0, 0, 0, 0};
+    double ca[B], cai[B], cb[B], cbi[B];       // current group
+    auto load = [&](int g, double *xa, double *xai, double *xb, double *xbi) {
+        const double *pa = zero, *pai = zero, *pb = zero, *pbi = zero;
+        if (rv && g + q < nt) {
+            const int2 ab = trip[t0 + g + q];
+            const int64_t oa = (int64_t)ab.x * BB + r, ob = (int64_t)ab.y * BB + r;
+            pa = ar + oa;
+            pb = br + ob;
+            if (AC) pai = ai + oa;
+            if (BC) pbi = bi + ob;
+        }
+#pragma unroll
+        for (int st = 0; st < B; ++st) {
+            xa[st] = pa[st * B];
+            xb[st] = pb[st * B];
+            if (AC) xai[st] = pai[st * B];
+            if (BC) xbi[st] = pbi[st * B];
+        }
+    };
+    if (nt > 0) load(0, ca, cai, cb, cbi);
+    for (int g = 0; g < nt; g += 4) {
+        double na[B], nai[B], nb[B], nbi[B];
+        if (g + 4 < nt) load(g + 4, na, nai, nb, nbi);
+#pragma unroll
+        for (int st = 0; st < B; ++st) {
+            rr = Mfma16<double>::step(ca[st], cb[st], rr);
+            if (AC && BC) ii = Mfma16<double>::step(cai[st], cbi[st], ii);
+            if (BC) ri = Mfma16<double>::step(ca[st], cbi[st], ri);
+            if (AC) ir = Mfma16<double>::step(cai[st], cb[st], ir);
+        }
+#pragma unroll
+        for (int st = 0; st < B; ++st) {
+            ca[st] = na[st];
+            cb[st] = nb[st];
+            if (AC) cai[st] = nai[st];
+            if (BC) cbi[st] = nbi[st];
+        }
+    }
     constexpr double sa = CJA ? -1.0 : 1.0, sb = CJB ? -1.0 : 1.0;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -553,9 +645,14 @@ static void launch_cm(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
     if (kernel_variant() == 2)
         hipLaunchKernelGGL((k_spgemm_kc<13, AC, BC, 1, 0, double, 0, CJB, LC>), g, t, 0, s, a.nout,
                            a.off, a.trip, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re, a.alpha_im);
+    else if (kernel_variant() == 3)
+        hipLaunchKernelGGL((k_spgemm_q4p<13, AC, BC, 0, CJB, LC>), dim3(xcd_grid(g.x)), t, 0, s, a.nout,
+                           a.off, a.trip, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re, a.alpha_im,
+                           a.zero, a.order);
     else
-        hipLaunchKernelGGL((k_spgemm_q4<13, AC, BC, 0, CJB, LC>), g, t, 0, s, a.nout, a.off, a.trip,
-                           a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re, a.alpha_im, a.zero);
+        hipLaunchKernelGGL((k_spgemm_q4<13, AC, BC, 0, CJB, LC>), dim3(xcd_grid(g.x)), t, 0, s, a.nout,
+                           a.off, a.trip, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re, a.alpha_im,
+                           a.zero, a.order, getenv("RTDM_NO_XCD") ? 0 : 1);
 }
 
 void launch_spgemm_cm(hipStream_t s, const SpgemmArgs &a, int conj_b, int out_col_major)
