@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 (matrix and vector)
 # Identifies the product kernel build whose HBM traffic profiles/traffic.json holds;
 # change it whenever the kernel changes so that a stale figure is not reported.
-KERNEL_TAG = "q4-b13-xcd-tile64-v1"
+KERNEL_TAG = "q4-b13-xcd-tile64-wpb16-v2"
 
 
 def measured_traffic(dom):
@@ -52,13 +52,14 @@ def make_workload(args):
     return s
 
 
-def gpu_run(s, args):
+def gpu_run(s, args, precision="fp64", taylor_low_from=3):
     import torch  # device memory and streams come from torch's runtime
     from paper_1404_5776_amd import rtdm
 
     torch.cuda.init()
     stream = torch.cuda.current_stream()
-    ctx = rtdm.Context(0, h_model=s.h_model, h_gain=s.h_gain)
+    ctx = rtdm.Context(0, h_model=s.h_model, h_gain=s.h_gain, precision=precision,
+                       taylor_low_from=taylor_low_from)
     t = time.time()
     ctx.load_system(s, stream)
     log(f"set-up (neighbour lists, schedules, upload) {time.time() - t:.1f} s")
@@ -66,6 +67,7 @@ def gpu_run(s, args):
     iters, res = rtdm.rtdm_build_inverse(ctx.h, stream)
     log(f"Hotelling inverse: {iters} iterations, residual {res:.2e}, {time.time() - t:.1f} s")
     rtdm.rtdm_apply_kick(ctx.h, s.kappa, stream)
+    p0 = rtdm.rtdm_observables(ctx.h, stream)[:3]
     sched = {k: rtdm.rtdm_schedule_stats(ctx.h, k) for k in ("XH", "AT", "UK", "WU")}
     log("triples per product:", {k: v[1] for k, v in sched.items()})
     if args.warmup:
@@ -81,7 +83,7 @@ def gpu_run(s, args):
     rtdm.rtdm_timing(ctx.h, False)
     trace = rtdm.rtdm_dipole_trace(ctx.h)
     ctx.close()
-    return t1 - t0, stats, sched, trace
+    return t1 - t0, stats, sched, trace, p0
 
 
 def cpu_baseline(s, target_s: float):
@@ -121,6 +123,9 @@ def main():
     ap.add_argument("--cells", default="8x8x8", help="diamond conventional cells (8 atoms each)")
     ap.add_argument("--cpu-seconds", type=float, default=16.0, help="oracle sample budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the reduced-precision run (FP32 Taylor terms) compared against the FP64 run")
+    ap.add_argument("--low-from", type=int, default=3, help="first Taylor order in FP32 for the mixed run")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (read + write) before the workload, "
                          "so hardware byte counters can be scaled against a known size")
@@ -147,8 +152,20 @@ def main():
     t = time.time()
     s = make_workload(args)
     log(f"workload {s.name}: {s.n_atoms} atoms, b={s.b}, generated in {time.time() - t:.1f} s")
-    elapsed, stats, sched, trace = gpu_run(s, args)
+    elapsed, stats, sched, trace, p0 = gpu_run(s, args)
     steps_per_s = args.steps / elapsed
+    mixed = None
+    if not args.no_mixed:
+        el2, stats2, _, trace2, _ = gpu_run(s, args, precision="fp32_taylor", taylor_low_from=args.low_from)
+        n = min(len(trace), len(trace2))
+        induced = np.abs(trace[:n, 1:4] - p0).max()
+        err = np.abs(trace2[:n, 1:4] - trace[:n, 1:4]).max()
+        mixed = {"mode": f"Taylor terms of order >= {args.low_from} on FP32 matrix cores with FP32 storage; "
+                         f"X H, U K, W U^dagger, reductions and observables FP64",
+                 "steps_per_s": args.steps / el2, "speedup_vs_fp64": elapsed / el2,
+                 "dipole_error_vs_fp64": err / induced, "dipole_error_abs": err,
+                 "compared_steps": int(n), "warmup_steps_before_compare": args.warmup,
+                 "per_product_ms": {k: v[1] / max(v[0], 1) for k, v in stats2.items()}}
 
     # dominant product kernel: the kind with the most kernel time
     dom = max(stats, key=lambda k: stats[k][1])
@@ -201,6 +218,7 @@ def main():
         "per_product_ms": {k: v[1] / max(v[0], 1) for k, v in stats.items()},
         "trace_last": trace[-1, :6].tolist() if len(trace) else None,
         "cpu_baseline": cpu,
+        "mixed_precision": mixed,
     }
     print(json.dumps(out))
 

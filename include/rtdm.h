@@ -94,11 +94,17 @@ typedef enum {
     RTDM_PROD_COUNT = 6
 } rtdm_prod;
 
-/* Arithmetic of the block products of rtdm_step and rtdm_multiply: FP64
- * matrix cores, or FP32 matrix cores with FP32 accumulation (b = 4 and 13).
- * Storage, reductions, observables, the inverse iteration and the unitarity
- * check always run in FP64. */
-enum { RTDM_PREC_FP64 = 0, RTDM_PREC_FP32 = 1 };
+/* Arithmetic of the block products of rtdm_step and rtdm_multiply:
+ *   FP64        FP64 matrix cores;
+ *   FP32        every product on FP32 matrix cores with FP32 accumulation;
+ *   FP32_TAYLOR only the Taylor-term products T_n = P(c A T_{n-1}) with
+ *               n >= taylor_low_from in FP32 (their norms shrink like
+ *               (dt |A|)^n / n!, so their rounding enters U scaled down); the
+ *               terms are stored in FP32 and summed into U in FP64;
+ *               A = P(X H), U K and W U^dagger stay FP64.
+ * FP32 forms need b = 4 or 13.  Storage, reductions, observables, the inverse
+ * iteration and the unitarity check always run in FP64. */
+enum { RTDM_PREC_FP64 = 0, RTDM_PREC_FP32 = 1, RTDM_PREC_FP32_TAYLOR = 2 };
 enum { RTDM_HMODEL_FIXED = 0, RTDM_HMODEL_MULLIKEN = 1 };
 enum { RTDM_INV_BLOCK_JACOBI = 0, RTDM_INV_COLD = 1, RTDM_INV_PREVIOUS = 2 };
 
@@ -106,12 +112,13 @@ enum { RTDM_INV_BLOCK_JACOBI = 0, RTDM_INV_COLD = 1, RTDM_INV_PREVIOUS = 2 };
 typedef struct {
     int taylor_order;      /* p: Taylor orders 0..p of the exponential (Sec. IV.B: six terms -> 5) */
     int unit_check_every;  /* m > 0: record ||U^dagger S U - S|| every m steps; 0: never */
-    int precision;         /* RTDM_PREC_FP64 or RTDM_PREC_FP32 (block products only) */
+    int precision;         /* RTDM_PREC_* (block products only) */
     int h_model;           /* RTDM_HMODEL_FIXED: H = H0; MULLIKEN: H = H0 + g diag(q_mid - q_ref) */
     double h_gain;         /* g of the on-site model (default 0.5) */
     int inv_start;         /* starting guess of the inverse iteration (default block-Jacobi) */
     double inv_tol;        /* stop when ||X_{k+1}-X_k||_F / ||X_{k+1}||_F <= tol (default 1e-10) */
     int inv_max_iter;      /* iteration cap (default 50) */
+    int taylor_low_from;   /* RTDM_PREC_FP32_TAYLOR: first Taylor order n computed in FP32 (>= 2, default 3) */
 } rtdm_options;
 
 /* Fill *opt with the defaults above.  Never fails for a non-NULL opt. */

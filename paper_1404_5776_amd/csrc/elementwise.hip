@@ -361,6 +361,49 @@ void launch_transpose_blocks(hipStream_t s, int64_t nblocks, int b, const double
     RT_HIP(hipGetLastError());
 }
 
+__global__ void k_to_f32(int64_t nblocks, int b, int transpose, const double *__restrict__ in,
+                         float *__restrict__ out)
+{
+    const int bb = b * b;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nblocks * bb;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        int64_t o = e;
+        if (transpose) {
+            const int64_t p = e / bb;
+            const int w = (int)(e - p * bb);
+            const int r = w / b, c = w - r * b;
+            o = p * bb + c * b + r;
+        }
+        out[o] = (float)in[e];
+    }
+}
+
+void launch_to_f32(hipStream_t s, int64_t nblocks, int b, int transpose, const double *in, float *out)
+{
+    const int64_t n = nblocks * b * b;
+    if (n == 0) return;
+    int64_t g = (n + kT - 1) / kT;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)g), dim3(kT), 0, s, nblocks, b, transpose, in, out);
+    RT_HIP(hipGetLastError());
+}
+
+__global__ void k_axpy_f32(int64_t n, double a, const float *__restrict__ x, double *__restrict__ y)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x)
+        y[e] += a * (double)x[e];
+}
+
+void launch_axpy_f32(hipStream_t s, int64_t n, double a, const float *x, double *y)
+{
+    if (n == 0) return;
+    int64_t g = (n + kT - 1) / kT;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_axpy_f32, dim3((unsigned)g), dim3(kT), 0, s, n, a, x, y);
+    RT_HIP(hipGetLastError());
+}
+
 // ----------------------------------------------------------------- reductions
 
 __global__ __launch_bounds__(kT) void k_red_diff2(int64_t n, const double *__restrict__ x,

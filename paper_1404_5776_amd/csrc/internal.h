@@ -94,6 +94,14 @@ void launch_spgemm(hipStream_t s, const SpgemmArgs &a);
 // operand's op(B)[m][r] at m*B + r (conj_b: conjugated) and the output written
 // column-major if out_col_major.  b = 13, FP64.
 void launch_spgemm_cm(hipStream_t s, const SpgemmArgs &a, int conj_b, int out_col_major);
+// Real FP32 step product: a32 column-major left operand, b32 row-major right
+// operand, c32 = alpha * P_C(A B) row-major FP32 (b = 13).
+void launch_spgemm_r32(hipStream_t s, const SpgemmArgs &a, const float *a32, const float *b32, float *c32,
+                       const float *zero32);
+// out = (float)in, optionally transposing every b x b block.
+void launch_to_f32(hipStream_t s, int64_t nblocks, int b, int transpose, const double *in, float *out);
+// y += a * (double)x
+void launch_axpy_f32(hipStream_t s, int64_t n, double a, const float *x, double *y);
 // out[p] = in[p]^T for every b x b block (nblocks blocks).
 void launch_transpose_blocks(hipStream_t s, int64_t nblocks, int b, const double *in, double *out);
 

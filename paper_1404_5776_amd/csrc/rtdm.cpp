@@ -116,6 +116,8 @@ struct rtdm_ctx {
     // column-major block copies of the step's left operands (b = 13, FP64)
     Mat Xc, Ac, Uc, Wc;
     bool Xc_valid = false, W_in_cm = false;
+    // FP32 copies for the reduced-precision Taylor terms (b = 13)
+    DBuf<float> Ac32, tau32[2], zero32;
     DBuf<double> scratch;       // block inverse scratch and staging
 
     std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<Sched>> scheds;
@@ -468,6 +470,9 @@ void build_propagator(rtdm_ctx *c, double dt, hipStream_t s)
     Mat &U = c->mats[RTDM_MAT_U];
     const int64_t ne = elems(c, A);
     const int p = c->opt.taylor_order;
+    const bool low32 = c->opt.precision == RTDM_PREC_FP32_TAYLOR && c->Ac32.p != nullptr;
+    const int n0 = c->opt.precision == RTDM_PREC_FP64 ? p + 1
+                   : (c->opt.precision == RTDM_PREC_FP32 ? 2 : c->opt.taylor_low_from);
     RT_HIP(hipMemsetAsync(U.re.p, 0, U.re.bytes(), s));
     RT_HIP(hipMemsetAsync(U.im.p, 0, U.im.bytes(), s));
     launch_add_identity(s, c->n, c->b, pat_of(c, R_P).d_diag.p, 1.0, U.re.p);
@@ -475,17 +480,48 @@ void build_propagator(rtdm_ctx *c, double dt, hipStream_t s)
         launch_axpby(s, ne, dt, A.re.p, 0.0, nullptr, c->tau[0].re.p);
         launch_axpby(s, ne, -1.0, c->tau[0].re.p, 1.0, U.im.p, U.im.p);
     }
-    int cur = 0;
+    // (-i)^k: k%4 == 0 -> +Re, 1 -> -Im, 2 -> -Re, 3 -> +Im
+    auto add_term = [&](int k, const double *t64, const float *t32) {
+        const double sign = (k % 4 == 0 || k % 4 == 3) ? 1.0 : -1.0;
+        double *dst = (k % 2 == 0) ? U.re.p : U.im.p;
+        if (t64) launch_axpby(s, ne, sign, t64, 1.0, dst, dst);
+        else launch_axpy_f32(s, ne, sign, t32, dst);
+    };
+    int cur = 0;          // tau[cur] (FP64) or tau32[cur] (FP32) holds tau_{k-1}
+    bool in32 = false;
+    if (low32 && n0 <= p) launch_to_f32(s, pat_of(c, R_P).nnzb, c->b, 0, c->Ac.re.p, c->Ac32.p);
     for (int k = 2; k <= p; ++k) {
-        Mat &src = c->tau[cur];
-        Mat &dst = c->tau[1 - cur];
-        if (use_cm(c)) product_cm(c, RTDM_PROD_AT, c->Ac, src, dst, 0, 0, dt / k, s);
-        else product(c, RTDM_PROD_AT, A, src, dst, dt / k, 0.0, s);
-        switch (k % 4) {
-        case 0: launch_axpby(s, ne, 1.0, dst.re.p, 1.0, U.re.p, U.re.p); break;
-        case 1: launch_axpby(s, ne, -1.0, dst.re.p, 1.0, U.im.p, U.im.p); break;
-        case 2: launch_axpby(s, ne, -1.0, dst.re.p, 1.0, U.re.p, U.re.p); break;
-        default: launch_axpby(s, ne, 1.0, dst.re.p, 1.0, U.im.p, U.im.p); break;
+        if (low32 && k >= n0) {
+            if (!in32) {
+                launch_to_f32(s, pat_of(c, R_P).nnzb, c->b, 0, c->tau[cur].re.p, c->tau32[cur].p);
+                in32 = true;
+            }
+            Sched &S = schedule(c, RTDM_PROD_AT);
+            SpgemmArgs a;
+            a.nout = S.nout;
+            a.off = S.off.p;
+            a.trip = S.trip.p;
+            a.b = c->b;
+            a.alpha_re = dt / k;
+            a.order = S.order.p;
+            const size_t ev = 2 * c->recs.size();
+            if (c->timing) RT_HIP(hipEventRecord(event_at(c, ev), s));
+            launch_spgemm_r32(s, a, c->Ac32.p, c->tau32[cur].p, c->tau32[1 - cur].p, c->zero32.p);
+            if (c->timing) {
+                RT_HIP(hipEventRecord(event_at(c, ev + 1), s));
+                const double b3 = (double)c->b * c->b * c->b;
+                c->recs.push_back({RTDM_PROD_AT, (int)ev, (double)S.ntrip * 2.0 * b3});
+            }
+            add_term(k, nullptr, c->tau32[1 - cur].p);
+        } else {
+            Mat &src = c->tau[cur];
+            Mat &dst = c->tau[1 - cur];
+            const int saved = c->prec;
+            if (k >= n0) c->prec = RTDM_PREC_FP32;
+            if (use_cm(c)) product_cm(c, RTDM_PROD_AT, c->Ac, src, dst, 0, 0, dt / k, s);
+            else product(c, RTDM_PROD_AT, A, src, dst, dt / k, 0.0, s);
+            c->prec = saved;
+            add_term(k, dst.re.p, nullptr);
         }
         cur = 1 - cur;
     }
@@ -592,6 +628,7 @@ int rtdm_default_options(rtdm_options *opt)
     opt->inv_start = RTDM_INV_BLOCK_JACOBI;
     opt->inv_tol = 1e-10;
     opt->inv_max_iter = 50;
+    opt->taylor_low_from = 3;
     return RTDM_OK;
 }
 
@@ -613,13 +650,14 @@ int rtdm_create(rtdm_ctx **out, int hip_device, const rtdm_options *opt)
     if (opt) c->opt = *opt;
     else rtdm_default_options(&c->opt);
     RT_CHECK(c->opt.taylor_order >= 0 && c->opt.taylor_order <= 32, RTDM_E_ARG, "taylor_order out of range");
-    RT_CHECK(c->opt.precision == RTDM_PREC_FP64 || c->opt.precision == RTDM_PREC_FP32, RTDM_E_ARG,
+    RT_CHECK(c->opt.precision >= RTDM_PREC_FP64 && c->opt.precision <= RTDM_PREC_FP32_TAYLOR, RTDM_E_ARG,
              "unknown precision");
     RT_CHECK(c->opt.h_model == RTDM_HMODEL_FIXED || c->opt.h_model == RTDM_HMODEL_MULLIKEN, RTDM_E_ARG,
              "unknown h_model");
     RT_CHECK(c->opt.inv_start >= 0 && c->opt.inv_start <= RTDM_INV_PREVIOUS, RTDM_E_ARG, "unknown inv_start");
     RT_CHECK(c->opt.inv_max_iter >= 1 && c->opt.inv_tol > 0, RTDM_E_ARG, "bad inverse options");
     RT_CHECK(c->opt.unit_check_every >= 0, RTDM_E_ARG, "unit_check_every < 0");
+    RT_CHECK(c->opt.taylor_low_from >= 2, RTDM_E_ARG, "taylor_low_from < 2");
     set_device(c);
     c->partials.alloc(kRedBlocks * 4);
     c->herm_sums.alloc(4);
@@ -712,6 +750,17 @@ int rtdm_set_ranges(rtdm_ctx *c, double R_hs, double R_p, double R_k)
     alloc_mat(c, c->Wh, R_P, false);
     alloc_mat(c, c->V, R_P, true);
     alloc_mat(c, c->Z, R_P, true);
+    c->Ac32.release();
+    c->tau32[0].release();
+    c->tau32[1].release();
+    if (c->b == 13 && c->opt.precision == RTDM_PREC_FP32_TAYLOR) {
+        const int64_t ne = pat_of(c, R_P).nnzb * (int64_t)c->b * c->b;
+        c->Ac32.alloc(ne);
+        c->tau32[0].alloc(ne);
+        c->tau32[1].alloc(ne);
+        c->zero32.alloc(256);
+        RT_HIP(hipMemset(c->zero32.p, 0, c->zero32.bytes()));
+    }
     if (c->b == 13) {
         alloc_mat(c, c->Xc, R_P, false);
         alloc_mat(c, c->Ac, R_P, false);
@@ -1004,8 +1053,9 @@ int rtdm_step(rtdm_ctx *c, double dt, int64_t n_steps, void *stream)
         rtdm_ctx *c;
         ~PrecScope() { c->prec = RTDM_PREC_FP64; }
     } scope{c};
+    const int step_prec = c->opt.precision == RTDM_PREC_FP32 ? RTDM_PREC_FP32 : RTDM_PREC_FP64;
     for (int64_t st = 0; st < n_steps; ++st) {
-        c->prec = c->opt.precision;
+        c->prec = step_prec;
         if (mull || !c->U_valid || c->U_dt != dt) {
             RT_HIP(hipMemcpyAsync(H.re.p, H0.re.p, H.re.bytes(), hipMemcpyDeviceToDevice, s));
             if (mull)
@@ -1155,7 +1205,7 @@ int rtdm_multiply(rtdm_ctx *c, rtdm_mat Cm, rtdm_mat Am, rtdm_mat Bm, int op_a, 
     hipStream_t s = (hipStream_t)stream;
     const bool cres = A.cplx || B.cplx || ali != 0.0;
     RT_CHECK(C.cplx || !cres, RTDM_E_UNSUPPORTED, "complex result for a real matrix slot");
-    c->prec = c->opt.precision;
+    c->prec = c->opt.precision == RTDM_PREC_FP32 ? RTDM_PREC_FP32 : RTDM_PREC_FP64;
     try {
         product(c, prod, A, B, C, alr, ali, s);
     } catch (...) {

@@ -298,8 +298,8 @@ __global__ __launch_bounds__(256) void k_spgemm_kc(
 // compile-time offset; lanes without data (rows r >= B, or past the last
 // triple) point at a zero block.  Conjugation is a sign applied to the
 // accumulated imaginary products at the end.
-template <int B, bool AC, bool BC, int CJA, int CJB, int LC>
-__global__ __launch_bounds__(256) void k_spgemm_q4(
+template <int B, bool AC, bool BC, int CJA, int CJB, int LC, int WPB = 4>
+__global__ __launch_bounds__(64 * WPB) void k_spgemm_q4(
     int64_t nout, const int64_t *__restrict__ off, const int2 *__restrict__ trip,
     const double *__restrict__ ar, const double *__restrict__ ai, const double *__restrict__ br,
     const double *__restrict__ bi, double *__restrict__ cr, double *__restrict__ ci, double alr,
@@ -308,7 +308,7 @@ __global__ __launch_bounds__(256) void k_spgemm_q4(
     static_assert(B >= 4 && B <= 16, "k_spgemm_q4 needs 4 <= B <= 16");
     constexpr int BB = B * B;
     const int lane = threadIdx.x & 63;
-    const int64_t w = xcd_block((nout + 3) / 4, remap) * 4 + (threadIdx.x >> 6);
+    const int64_t w = xcd_block((nout + WPB - 1) / WPB, remap) * WPB + (threadIdx.x >> 6);
     if (w >= nout) return;                     // uniform across the wave
     const int64_t c = order ? (int64_t)order[w] : w;
     const int r = lane & 15, q = lane >> 4;
@@ -639,6 +639,15 @@ static void dispatch_ops(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
 // Step products with a column-major copy of the left operand (op(A)[r][m] at
 // m*B + r) and a right operand whose op(B)[m][r] sits at m*B + r (row-major
 // B, or the column-major copy of a matrix used conjugate-transposed).
+static int waves_per_block()
+{
+    static int v = [] {
+        const char *e = getenv("RTDM_WPB");
+        return e ? atoi(e) : 16;
+    }();
+    return v;
+}
+
 template <bool AC, bool BC, int CJB, int LC>
 static void launch_cm(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
 {
@@ -649,10 +658,19 @@ static void launch_cm(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
         hipLaunchKernelGGL((k_spgemm_q4p<13, AC, BC, 0, CJB, LC>), dim3(xcd_grid(g.x)), t, 0, s, a.nout,
                            a.off, a.trip, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re, a.alpha_im,
                            a.zero, a.order);
-    else
-        hipLaunchKernelGGL((k_spgemm_q4<13, AC, BC, 0, CJB, LC>), dim3(xcd_grid(g.x)), t, 0, s, a.nout,
-                           a.off, a.trip, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re, a.alpha_im,
-                           a.zero, a.order, getenv("RTDM_NO_XCD") ? 0 : 1);
+    else {
+        const int wpb = waves_per_block();
+        const int remap = getenv("RTDM_NO_XCD") ? 0 : 1;
+        const unsigned grid = xcd_grid((a.nout + wpb - 1) / wpb);
+#define RT_Q4(W)                                                                                  \
+    hipLaunchKernelGGL((k_spgemm_q4<13, AC, BC, 0, CJB, LC, W>), dim3(grid), dim3(64 * W), 0, s,    \
+                       a.nout, a.off, a.trip, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re,       \
+                       a.alpha_im, a.zero, a.order, remap)
+        if (wpb == 16) RT_Q4(16);
+        else if (wpb == 8) RT_Q4(8);
+        else RT_Q4(4);
+#undef RT_Q4
+    }
 }
 
 void launch_spgemm_cm(hipStream_t s, const SpgemmArgs &a, int conj_b, int out_col_major)
@@ -674,6 +692,62 @@ void launch_spgemm_cm(hipStream_t s, const SpgemmArgs &a, int conj_b, int out_co
     else if (bc) RT_CM(false, true);
     else RT_CM(false, false);
 #undef RT_CM
+    RT_HIP(hipGetLastError());
+}
+
+
+// FP32 variant of k_spgemm_q4 for real operands (the Taylor-term products of
+// the reduced-precision form): column-major FP32 left operand, row-major FP32
+// right operand, v_mfma_f32_16x16x4_f32 with FP32 accumulation, FP32 output
+// scaled by alpha.  Same four-triple grouping, order and XCD mapping.
+template <int B, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_spgemm_q4r32(
+    int64_t nout, const int64_t *__restrict__ off, const int2 *__restrict__ trip,
+    const float *__restrict__ a, const float *__restrict__ b, float *__restrict__ cout, float alpha,
+    const float *__restrict__ zero, const int32_t *__restrict__ order)
+{
+    constexpr int BB = B * B;
+    const int lane = threadIdx.x & 63;
+    const int64_t w = xcd_block((nout + WPB - 1) / WPB) * WPB + (threadIdx.x >> 6);
+    if (w >= nout) return;                     // uniform across the wave
+    const int64_t c = order ? (int64_t)order[w] : w;
+    const int r = lane & 15, q = lane >> 4;
+    const bool rv = r < B;
+    const int64_t t0 = off[c];
+    const int nt = (int)(off[c + 1] - t0);
+    typedef Mfma16<float>::acc_t acc_t;
+    acc_t acc = {0, 0, 0, 0};
+    for (int g = 0; g < nt; g += 4) {
+        const float *pa = zero, *pb = zero;
+        if (rv && g + q < nt) {
+            const int2 ab = trip[t0 + g + q];
+            pa = a + (int64_t)ab.x * BB + r;
+            pb = b + (int64_t)ab.y * BB + r;
+        }
+#pragma unroll
+        for (int st = 0; st < B; ++st) acc = Mfma16<float>::step(pa[st * B], pb[st * B], acc);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int row = Mfma16<float>::row(e, q), col = r;
+        if (row < B && col < B) cout[c * BB + row * B + col] = alpha * acc[e];
+    }
+}
+
+void launch_spgemm_r32(hipStream_t s, const SpgemmArgs &a, const float *a32, const float *b32, float *c32,
+                       const float *zero32)
+{
+    if (a.nout == 0) return;
+    RT_CHECK(a.b == 13, RTDM_E_UNSUPPORTED, "FP32 step products need b = 13");
+    const int wpb = waves_per_block();
+    const unsigned grid = xcd_grid((a.nout + wpb - 1) / wpb);
+#define RT_R32(W)                                                                                  \
+    hipLaunchKernelGGL((k_spgemm_q4r32<13, W>), dim3(grid), dim3(64 * W), 0, s, a.nout, a.off, a.trip, \
+                       a32, b32, c32, (float)a.alpha_re, zero32, a.order)
+    if (wpb == 16) RT_R32(16);
+    else if (wpb == 8) RT_R32(8);
+    else RT_R32(4);
+#undef RT_R32
     RT_HIP(hipGetLastError());
 }
 

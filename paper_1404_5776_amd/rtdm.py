@@ -22,7 +22,7 @@ MAT = {"S": 0, "H0": 1, "H": 2, "X": 3, "A": 4, "U": 5, "K": 6, "W": 7}
 PROD = {"XH": 0, "AT": 1, "UK": 2, "WU": 3, "SX": 4, "UV": 5}
 HMODEL = {"fixed": 0, "mulliken": 1}
 INV_START = {"block_jacobi": 0, "cold": 1, "previous": 2}
-PRECISION = {"fp64": 0, "fp32": 1}
+PRECISION = {"fp64": 0, "fp32": 1, "fp32_taylor": 2}
 
 STATUS = {0: "RTDM_OK", -1: "RTDM_E_ARG", -2: "RTDM_E_STATE", -3: "RTDM_E_OOM", -4: "RTDM_E_HIP",
           -5: "RTDM_E_NOCONV", -6: "RTDM_E_NUMERIC", -7: "RTDM_E_UNSUPPORTED"}
@@ -44,7 +44,7 @@ class Options(ctypes.Structure):
     _fields_ = [("taylor_order", ctypes.c_int), ("unit_check_every", ctypes.c_int),
                 ("precision", ctypes.c_int), ("h_model", ctypes.c_int), ("h_gain", ctypes.c_double),
                 ("inv_start", ctypes.c_int), ("inv_tol", ctypes.c_double),
-                ("inv_max_iter", ctypes.c_int)]
+                ("inv_max_iter", ctypes.c_int), ("taylor_low_from", ctypes.c_int)]
 
 
 _lib = None
