@@ -106,7 +106,12 @@ typedef enum {
  * iteration and the unitarity check always run in FP64. */
 enum { RTDM_PREC_FP64 = 0, RTDM_PREC_FP32 = 1, RTDM_PREC_FP32_TAYLOR = 2 };
 enum { RTDM_HMODEL_FIXED = 0, RTDM_HMODEL_MULLIKEN = 1 };
-enum { RTDM_INV_BLOCK_JACOBI = 0, RTDM_INV_COLD = 1, RTDM_INV_PREVIOUS = 2 };
+/* Starting guess of the inverse iteration: block-Jacobi blockdiag(S_ii^-1);
+ * cold I / (largest absolute row sum of S); the current X; or the learned
+ * guess (rtdm_mlp_*): for every block of S's range, 2 delta_ij I - S_ij plus
+ * the network's correction, zero elsewhere.  PREVIOUS and LEARNED fall back
+ * to block-Jacobi when the iteration diverges from them. */
+enum { RTDM_INV_BLOCK_JACOBI = 0, RTDM_INV_COLD = 1, RTDM_INV_PREVIOUS = 2, RTDM_INV_LEARNED = 3 };
 
 /* Options of a context (rtdm_default_options fills the defaults). */
 typedef struct {
@@ -210,6 +215,45 @@ int rtdm_dipole_trace(rtdm_ctx *ctx, double *out, int64_t max_rows, int64_t *row
  * metric): out[0] = ||D||_F/||S||_F, out[1] = mean |D_ab|, out[2] = max |D_ab|
  * with D = P_P(U^dagger P_P(S U)) - S over R_P's pattern.  Synchronises. */
 int rtdm_unitarity(rtdm_ctx *ctx, double out[3], void *hip_stream);
+
+/* Outcome of the last rtdm_build_inverse: iterations summed over the start
+ * and, if taken, the block-Jacobi fallback; fell_back = 1 if the fallback ran.
+ * Either pointer may be NULL. */
+int rtdm_inverse_info(rtdm_ctx *ctx, int *iters_total, int *fell_back);
+
+/* ---- learned starting guess (a two-layer perceptron, hidden width 128) ----
+ * The network maps the descriptor of an atom-pair block (i, j) of S's range,
+ *   d = [(r_i - r_j)/R_HS (3), |r_i - r_j|/R_HS, S_ij (b*b, row-major)]  (4 + b*b floats),
+ * to a correction y (b*b floats) of the first-order start 2 delta_ij I - S_ij.
+ * Parameters (FP32 master copy, this order): W1 (128 x in, row-major), b1
+ * (128), W2 (out x 128), b2 (out); the forward pass uses FP16 copies of W1 and
+ * W2 with FP32 accumulation: y = W2 tanh(W1 d + b1) + b2.  Training minimises
+ * the mean squared error over the collected samples with Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8).  The network's size follows the
+ * geometry's b; it survives rtdm_set_ranges, not rtdm_set_geometry with a
+ * different b.  All calls synchronise. */
+int rtdm_mlp_params(rtdm_ctx *ctx, int64_t *n_params, int *in, int *hidden, int *out);
+/* Initialise the weights (uniform +-1/sqrt(fan_in), second layer scaled by 0.1,
+ * zero biases) from `seed`, reset Adam's state. */
+int rtdm_mlp_init(rtdm_ctx *ctx, uint64_t seed);
+/* Set / read the FP32 master weights (host arrays of n_params floats). */
+int rtdm_mlp_set_weights(rtdm_ctx *ctx, const float *w, int64_t n);
+int rtdm_mlp_get_weights(rtdm_ctx *ctx, float *w, int64_t n);
+/* Append training samples from the current S and the converged X: up to
+ * max_samples blocks of S's range chosen by a seeded shuffle; the target is
+ * X_ij - (2 delta_ij I - S_ij).  *total receives the dataset size. */
+int rtdm_mlp_collect(rtdm_ctx *ctx, int64_t max_samples, uint64_t seed, int64_t *total);
+int rtdm_mlp_clear(rtdm_ctx *ctx);
+/* Adam over `epochs` passes of the dataset in seeded random mini-batches of
+ * `batch` samples at learning rate lr; *loss receives the mean squared error
+ * of the last epoch (per output element). */
+int rtdm_mlp_train(rtdm_ctx *ctx, int epochs, int batch, double lr, uint64_t seed, double *loss);
+/* Test entries: the loss (mean squared error per output element) and its
+ * gradient w.r.t. the master weights for n host samples (desc n x in, target
+ * n x out), without updating; and the forward pass for n host descriptors. */
+int rtdm_mlp_loss_grad(rtdm_ctx *ctx, int64_t n, const float *desc, const float *target, double *loss,
+                       float *grad);
+int rtdm_mlp_predict(rtdm_ctx *ctx, int64_t n, const float *desc, float *y);
 
 /* Truncation error of the inverse (Sec. V.A, the paper's measure of the
  * S^-1 truncation): D = P_P(X S) - I over R_P's pattern; out[0] = mean |D_ab|

@@ -1,6 +1,7 @@
 // Internal declarations of the rtdm library (not part of the C ABI).
 #pragma once
 
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -151,5 +152,27 @@ void launch_unit_to_row(hipStream_t s, const double *unit_sums, const double *s_
 // interleave / split complex128
 void launch_split(hipStream_t s, int64_t n, const double *inter, double *re, double *im);
 void launch_interleave(hipStream_t s, int64_t n, const double *re, const double *im, double *inter);
+
+// ---------------------------------------------------------------- learned start
+constexpr int kMlpHidden = 128;
+void launch_mlp_desc(hipStream_t s, int64_t n, int b, const int32_t *blk, const int32_t *rowof,
+                     const int32_t *col, const double *xyz, const double *sv, double inv_r, float *desc);
+void launch_mlp_target(hipStream_t s, int64_t n, int b, const int32_t *blk, const int32_t *x_of,
+                       const int32_t *rowof, const int32_t *col, const double *sv, const double *xv,
+                       float *tgt);
+void launch_mlp_forward(hipStream_t s, int64_t n, int in, int out, const int32_t *idx, const float *x,
+                        const __half *w1, const float *b1, const __half *w2, const float *b2, float *hid,
+                        float *y);
+void launch_mlp_delta(hipStream_t s, int64_t n, int out, const int32_t *idx, const float *tgt, const float *y,
+                      const float *hid, const __half *w2, float *dy, float *dh, float *sqerr);
+void launch_mlp_grad(hipStream_t s, int64_t n, int in, int out, const int32_t *idx, const float *x,
+                     const float *hid, const float *dy, const float *dh, float *grad);
+void launch_adam(hipStream_t s, int64_t np, int64_t nw1, int64_t nb1, int64_t nw2, const float *grad, float *w,
+                 float *m, float *v, float lr, float beta1, float beta2, float eps, int step, __half *w1h,
+                 __half *w2h);
+void launch_to_half(hipStream_t s, int64_t n, const float *x, __half *y);
+void launch_mlp_apply(hipStream_t s, int64_t n, int b, const int32_t *blk, const int32_t *x_of,
+                      const int32_t *rowof, const int32_t *col, const double *sv, const float *y, double *xv);
+void launch_sum_f32(hipStream_t s, int64_t n, const float *x, double *out);
 
 }  // namespace rtdm

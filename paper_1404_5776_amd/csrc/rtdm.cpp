@@ -21,6 +21,8 @@
 #include <map>
 #include <memory>
 #include <new>
+#include <numeric>
+#include <random>
 #include <tuple>
 #include <vector>
 
@@ -94,6 +96,22 @@ struct TRec {
 
 const char *kProdName[RTDM_PROD_COUNT] = {"XH", "AT", "UK", "WU", "SX", "UV"};
 
+// Learned starting guess: network parameters, Adam state, training samples.
+struct MlpState {
+    int b = 0, in = 0, out = 0;
+    int64_t nw1 = 0, nb1 = 0, nw2 = 0, nb2 = 0, np = 0;
+    DBuf<float> w, m, v, grad;
+    DBuf<__half> w1h, w2h;
+    int step = 0;
+    bool ready = false;
+    DBuf<float> ds_x, ds_t;
+    int64_t ns = 0, cap = 0;
+    DBuf<float> hid, y, dy, dh, sqerr, tx, tt;
+    int64_t work_n = 0;
+    DBuf<int32_t> idx;
+    DBuf<double> dsum;
+};
+
 }  // namespace
 
 struct rtdm_ctx {
@@ -139,6 +157,9 @@ struct rtdm_ctx {
     DBuf<double> partials, herm_sums, unit_sums, s_norm2, hot_sums, atom_max, obs_tmp, zero;
 
     int prec = RTDM_PREC_FP64;  // arithmetic of the products being issued
+    MlpState mlp;
+    DBuf<int32_t> hs_to_p, hs_iota;
+    int inv_iters_total = 0, inv_fell_back = 0;
     bool timing = false;
     std::vector<hipEvent_t> events;
     std::vector<TRec> recs;
@@ -593,6 +614,66 @@ void after_upload(rtdm_ctx *c, int m)
     }
 }
 
+void mlp_configure(rtdm_ctx *c)
+{
+    MlpState &M = c->mlp;
+    RT_CHECK(c->b > 0, RTDM_E_STATE, "set_geometry first");
+    if (M.b == c->b && M.np > 0) return;
+    M = MlpState();
+    M.b = c->b;
+    M.in = 4 + c->b * c->b;
+    M.out = c->b * c->b;
+    M.nw1 = (int64_t)kMlpHidden * M.in;
+    M.nb1 = kMlpHidden;
+    M.nw2 = (int64_t)M.out * kMlpHidden;
+    M.nb2 = M.out;
+    M.np = M.nw1 + M.nb1 + M.nw2 + M.nb2;
+    M.w.alloc(M.np);
+    M.m.alloc(M.np);
+    M.v.alloc(M.np);
+    M.grad.alloc(M.np);
+    M.w1h.alloc(M.nw1);
+    M.w2h.alloc(M.nw2);
+    M.dsum.alloc(1);
+}
+
+void mlp_sync_half(rtdm_ctx *c, hipStream_t s)
+{
+    MlpState &M = c->mlp;
+    launch_to_half(s, M.nw1, M.w.p, M.w1h.p);
+    launch_to_half(s, M.nw2, M.w.p + M.nw1 + M.nb1, M.w2h.p);
+}
+
+void mlp_work(rtdm_ctx *c, int64_t n)
+{
+    MlpState &M = c->mlp;
+    if (n <= M.work_n) return;
+    M.hid.alloc((size_t)n * kMlpHidden);
+    M.y.alloc((size_t)n * M.out);
+    M.dy.alloc((size_t)n * M.out);
+    M.dh.alloc((size_t)n * kMlpHidden);
+    M.sqerr.alloc(n);
+    M.work_n = n;
+}
+
+const float *mlp_b1(const MlpState &M) { return M.w.p + M.nw1; }
+const float *mlp_b2(const MlpState &M) { return M.w.p + M.nw1 + M.nb1 + M.nw2; }
+
+// loss (mean squared error per output element) and gradient of n samples
+// (x_idx selects rows of x and t; null = rows 0..n-1).
+double mlp_loss_grad(rtdm_ctx *c, int64_t n, const int32_t *idx, const float *x, const float *t, hipStream_t s)
+{
+    MlpState &M = c->mlp;
+    mlp_work(c, n);
+    launch_mlp_forward(s, n, M.in, M.out, idx, x, M.w1h.p, mlp_b1(M), M.w2h.p, mlp_b2(M), M.hid.p, M.y.p);
+    launch_mlp_delta(s, n, M.out, idx, t, M.y.p, M.hid.p, M.w2h.p, M.dy.p, M.dh.p, M.sqerr.p);
+    launch_mlp_grad(s, n, M.in, M.out, idx, x, M.hid.p, M.dy.p, M.dh.p, M.grad.p);
+    launch_sum_f32(s, n, M.sqerr.p, M.dsum.p);
+    double sum = 0.0;
+    read_scalars(&sum, M.dsum.p, 1, s);
+    return sum / ((double)n * M.out);
+}
+
 }  // namespace
 
 // ================================================================== ABI
@@ -654,7 +735,7 @@ int rtdm_create(rtdm_ctx **out, int hip_device, const rtdm_options *opt)
              "unknown precision");
     RT_CHECK(c->opt.h_model == RTDM_HMODEL_FIXED || c->opt.h_model == RTDM_HMODEL_MULLIKEN, RTDM_E_ARG,
              "unknown h_model");
-    RT_CHECK(c->opt.inv_start >= 0 && c->opt.inv_start <= RTDM_INV_PREVIOUS, RTDM_E_ARG, "unknown inv_start");
+    RT_CHECK(c->opt.inv_start >= 0 && c->opt.inv_start <= RTDM_INV_LEARNED, RTDM_E_ARG, "unknown inv_start");
     RT_CHECK(c->opt.inv_max_iter >= 1 && c->opt.inv_tol > 0, RTDM_E_ARG, "bad inverse options");
     RT_CHECK(c->opt.unit_check_every >= 0, RTDM_E_ARG, "unit_check_every < 0");
     RT_CHECK(c->opt.taylor_low_from >= 2, RTDM_E_ARG, "taylor_low_from < 2");
@@ -779,6 +860,15 @@ int rtdm_set_ranges(rtdm_ctx *c, double R_hs, double R_p, double R_k)
     std::vector<int32_t> s2k(ps.nnzb), p2s(pp.nnzb);
     for (int64_t p = 0; p < ps.nnzb; ++p) s2k[p] = find(pk, ps.rowof[p], ps.col[p]);
     for (int64_t p = 0; p < pp.nnzb; ++p) p2s[p] = find(ps, pp.rowof[p], pp.col[p]);
+    std::vector<int32_t> s2p(ps.nnzb), iota(ps.nnzb);
+    for (int64_t p = 0; p < ps.nnzb; ++p) {
+        s2p[p] = find(pp, ps.rowof[p], ps.col[p]);
+        iota[p] = (int32_t)p;
+    }
+    c->hs_to_p.alloc(ps.nnzb);
+    c->hs_iota.alloc(ps.nnzb);
+    RT_HIP(hipMemcpy(c->hs_to_p.p, s2p.data(), c->hs_to_p.bytes(), hipMemcpyHostToDevice));
+    RT_HIP(hipMemcpy(c->hs_iota.p, iota.data(), c->hs_iota.bytes(), hipMemcpyHostToDevice));
     c->s_to_k.alloc(ps.nnzb);
     c->p_to_hs.alloc(pp.nnzb);
     RT_HIP(hipMemcpy(c->s_to_k.p, s2k.data(), c->s_to_k.bytes(), hipMemcpyHostToDevice));
@@ -1006,19 +1096,40 @@ int rtdm_build_inverse(rtdm_ctx *c, void *stream, int *iters, double *residual)
         }
         return -1;
     };
+    auto start_learned = [&]() {
+        MlpState &M = c->mlp;
+        RT_CHECK(M.ready && M.b == c->b, RTDM_E_STATE, "no trained network for the learned start");
+        const int64_t n = ps.nnzb;
+        DBuf<float> desc, y;
+        desc.alloc((size_t)n * M.in);
+        y.alloc((size_t)n * M.out);
+        const double inv_r = c->radius[R_HS] > 0 ? 1.0 / c->radius[R_HS] : 1.0;
+        launch_mlp_desc(s, n, c->b, c->hs_iota.p, ps.d_rowof.p, ps.d_col.p, c->d_xyz.p, S.re.p, inv_r, desc.p);
+        launch_mlp_forward(s, n, M.in, M.out, nullptr, desc.p, M.w1h.p, mlp_b1(M), M.w2h.p, mlp_b2(M),
+                           nullptr, y.p);
+        RT_HIP(hipMemsetAsync(X.re.p, 0, X.re.bytes(), s));
+        launch_mlp_apply(s, n, c->b, c->hs_iota.p, c->hs_to_p.p, ps.d_rowof.p, ps.d_col.p, S.re.p, y.p, X.re.p);
+        RT_HIP(hipStreamSynchronize(s));
+    };
     int k = 0;
     double r = 0.0;
     int st;
-    if (c->opt.inv_start == RTDM_INV_PREVIOUS && c->X_valid) {
+    c->inv_fell_back = 0;
+    if ((c->opt.inv_start == RTDM_INV_PREVIOUS && c->X_valid) || c->opt.inv_start == RTDM_INV_LEARNED) {
+        if (c->opt.inv_start == RTDM_INV_LEARNED) start_learned();
         st = run(k, r);
+        c->inv_iters_total = k;
         if (st != 1) {
+            c->inv_fell_back = 1;
             start_block_jacobi();
             st = run(k, r);
+            c->inv_iters_total += k;
         }
     } else {
         if (c->opt.inv_start == RTDM_INV_COLD) start_cold();
         else start_block_jacobi();
         st = run(k, r);
+        c->inv_iters_total = k;
     }
     if (iters) *iters = k;
     if (residual) *residual = r;
@@ -1261,6 +1372,220 @@ int rtdm_timing_stats(rtdm_ctx *c, rtdm_prod prod, int64_t *launches, double *to
     if (launches) *launches = n;
     if (total_ms) *total_ms = ms;
     if (flops) *flops = fl;
+    API_END(c)
+}
+
+int rtdm_inverse_info(rtdm_ctx *c, int *iters_total, int *fell_back)
+{
+    if (!c) return RTDM_E_ARG;
+    if (iters_total) *iters_total = c->inv_iters_total;
+    if (fell_back) *fell_back = c->inv_fell_back;
+    c->err.clear();
+    return RTDM_OK;
+}
+
+int rtdm_mlp_params(rtdm_ctx *c, int64_t *n_params, int *in, int *hidden, int *out)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    mlp_configure(c);
+    if (n_params) *n_params = c->mlp.np;
+    if (in) *in = c->mlp.in;
+    if (hidden) *hidden = kMlpHidden;
+    if (out) *out = c->mlp.out;
+    API_END(c)
+}
+
+int rtdm_mlp_set_weights(rtdm_ctx *c, const float *w, int64_t n)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    mlp_configure(c);
+    MlpState &M = c->mlp;
+    RT_CHECK(w && n == M.np, RTDM_E_ARG, "weight count does not match the network");
+    for (int64_t e = 0; e < n; ++e) RT_CHECK(std::isfinite(w[e]), RTDM_E_NUMERIC, "non-finite weight");
+    RT_HIP(hipMemcpy(M.w.p, w, M.w.bytes(), hipMemcpyHostToDevice));
+    RT_HIP(hipMemset(M.m.p, 0, M.m.bytes()));
+    RT_HIP(hipMemset(M.v.p, 0, M.v.bytes()));
+    M.step = 0;
+    mlp_sync_half(c, nullptr);
+    RT_HIP(hipDeviceSynchronize());
+    M.ready = true;
+    API_END(c)
+}
+
+int rtdm_mlp_get_weights(rtdm_ctx *c, float *w, int64_t n)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    mlp_configure(c);
+    RT_CHECK(w && n == c->mlp.np, RTDM_E_ARG, "weight count does not match the network");
+    RT_HIP(hipMemcpy(w, c->mlp.w.p, c->mlp.w.bytes(), hipMemcpyDeviceToHost));
+    API_END(c)
+}
+
+int rtdm_mlp_init(rtdm_ctx *c, uint64_t seed)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    mlp_configure(c);
+    MlpState &M = c->mlp;
+    std::vector<float> w(M.np, 0.0f);
+    std::mt19937_64 rng(seed);
+    std::uniform_real_distribution<double> U(-1.0, 1.0);
+    const double a1 = 1.0 / std::sqrt((double)M.in), a2 = 0.1 / std::sqrt((double)kMlpHidden);
+    for (int64_t e = 0; e < M.nw1; ++e) w[e] = (float)(a1 * U(rng));
+    for (int64_t e = 0; e < M.nw2; ++e) w[M.nw1 + M.nb1 + e] = (float)(a2 * U(rng));
+    RT_HIP(hipMemcpy(M.w.p, w.data(), M.w.bytes(), hipMemcpyHostToDevice));
+    RT_HIP(hipMemset(M.m.p, 0, M.m.bytes()));
+    RT_HIP(hipMemset(M.v.p, 0, M.v.bytes()));
+    M.step = 0;
+    mlp_sync_half(c, nullptr);
+    RT_HIP(hipDeviceSynchronize());
+    M.ready = true;
+    API_END(c)
+}
+
+int rtdm_mlp_collect(rtdm_ctx *c, int64_t max_samples, uint64_t seed, int64_t *total)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    require(c->ranges_set && c->uploaded[RTDM_MAT_S] && c->X_valid, "build the inverse first");
+    RT_CHECK(max_samples >= 0, RTDM_E_ARG, "max_samples < 0");
+    mlp_configure(c);
+    MlpState &M = c->mlp;
+    const Pattern &ps = pat_of(c, R_HS);
+    std::vector<int32_t> pos(ps.nnzb);
+    std::iota(pos.begin(), pos.end(), 0);
+    std::mt19937_64 rng(seed);
+    for (int64_t e = (int64_t)pos.size() - 1; e > 0; --e) {
+        std::uniform_int_distribution<int64_t> pick(0, e);
+        std::swap(pos[e], pos[pick(rng)]);
+    }
+    const int64_t k = std::min<int64_t>(max_samples, (int64_t)pos.size());
+    pos.resize(k);
+    std::sort(pos.begin(), pos.end());
+    std::vector<int32_t> hs2p(ps.nnzb);
+    RT_HIP(hipMemcpy(hs2p.data(), c->hs_to_p.p, c->hs_to_p.bytes(), hipMemcpyDeviceToHost));
+    std::vector<int32_t> xo(k);
+    for (int64_t e = 0; e < k; ++e) xo[e] = hs2p[pos[e]];
+    if (M.ns + k > M.cap) {
+        const int64_t cap = std::max<int64_t>(M.ns + k, 2 * M.cap);
+        DBuf<float> nx, nt;
+        nx.alloc((size_t)cap * M.in);
+        nt.alloc((size_t)cap * M.out);
+        if (M.ns > 0) {
+            RT_HIP(hipMemcpy(nx.p, M.ds_x.p, (size_t)M.ns * M.in * sizeof(float), hipMemcpyDeviceToDevice));
+            RT_HIP(hipMemcpy(nt.p, M.ds_t.p, (size_t)M.ns * M.out * sizeof(float), hipMemcpyDeviceToDevice));
+        }
+        M.ds_x = std::move(nx);
+        M.ds_t = std::move(nt);
+        M.cap = cap;
+    }
+    DBuf<int32_t> blk, xof;
+    blk.alloc(std::max<int64_t>(k, 1));
+    xof.alloc(std::max<int64_t>(k, 1));
+    if (k > 0) {
+        RT_HIP(hipMemcpy(blk.p, pos.data(), k * sizeof(int32_t), hipMemcpyHostToDevice));
+        RT_HIP(hipMemcpy(xof.p, xo.data(), k * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    const double inv_r = c->radius[R_HS] > 0 ? 1.0 / c->radius[R_HS] : 1.0;
+    launch_mlp_desc(nullptr, k, c->b, blk.p, ps.d_rowof.p, ps.d_col.p, c->d_xyz.p, c->mats[RTDM_MAT_S].re.p,
+                    inv_r, M.ds_x.p + (size_t)M.ns * M.in);
+    launch_mlp_target(nullptr, k, c->b, blk.p, xof.p, ps.d_rowof.p, ps.d_col.p, c->mats[RTDM_MAT_S].re.p,
+                      c->mats[RTDM_MAT_X].re.p, M.ds_t.p + (size_t)M.ns * M.out);
+    RT_HIP(hipDeviceSynchronize());
+    M.ns += k;
+    if (total) *total = M.ns;
+    API_END(c)
+}
+
+int rtdm_mlp_clear(rtdm_ctx *c)
+{
+    if (!c) return RTDM_E_ARG;
+    c->mlp.ns = 0;
+    c->err.clear();
+    return RTDM_OK;
+}
+
+int rtdm_mlp_train(rtdm_ctx *c, int epochs, int batch, double lr, uint64_t seed, double *loss)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    mlp_configure(c);
+    MlpState &M = c->mlp;
+    require(M.ready && M.ns > 0, "initialise the network and collect samples first");
+    RT_CHECK(epochs >= 1 && batch >= 1 && lr > 0 && std::isfinite(lr), RTDM_E_ARG, "bad training arguments");
+    const int64_t bs = std::min<int64_t>(batch, M.ns);
+    mlp_work(c, bs);
+    M.idx.alloc(M.ns);
+    std::vector<int32_t> perm(M.ns);
+    double last = 0.0;
+    for (int ep = 0; ep < epochs; ++ep) {
+        std::iota(perm.begin(), perm.end(), 0);
+        std::mt19937_64 rng(seed + 7919ull * (uint64_t)ep);
+        for (int64_t e = (int64_t)perm.size() - 1; e > 0; --e) {
+            std::uniform_int_distribution<int64_t> pick(0, e);
+            std::swap(perm[e], perm[pick(rng)]);
+        }
+        RT_HIP(hipMemcpy(M.idx.p, perm.data(), perm.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        double sum = 0.0;
+        int64_t cnt = 0;
+        for (int64_t b0 = 0; b0 + bs <= M.ns; b0 += bs) {
+            const double l = mlp_loss_grad(c, bs, M.idx.p + b0, M.ds_x.p, M.ds_t.p, nullptr);
+            launch_adam(nullptr, M.np, M.nw1, M.nb1, M.nw2, M.grad.p, M.w.p, M.m.p, M.v.p, (float)lr, 0.9f,
+                        0.999f, 1e-8f, ++M.step, M.w1h.p, M.w2h.p);
+            sum += l * bs;
+            cnt += bs;
+        }
+        last = sum / (double)cnt;
+        RT_CHECK(std::isfinite(last), RTDM_E_NUMERIC, "training loss is not finite");
+    }
+    RT_HIP(hipDeviceSynchronize());
+    if (loss) *loss = last;
+    API_END(c)
+}
+
+int rtdm_mlp_loss_grad(rtdm_ctx *c, int64_t n, const float *desc, const float *target, double *loss, float *grad)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    mlp_configure(c);
+    MlpState &M = c->mlp;
+    require(M.ready, "initialise the network first");
+    RT_CHECK(n >= 1 && desc && target, RTDM_E_ARG, "bad samples");
+    M.tx.alloc((size_t)n * M.in);
+    M.tt.alloc((size_t)n * M.out);
+    RT_HIP(hipMemcpy(M.tx.p, desc, M.tx.bytes(), hipMemcpyHostToDevice));
+    RT_HIP(hipMemcpy(M.tt.p, target, M.tt.bytes(), hipMemcpyHostToDevice));
+    const double l = mlp_loss_grad(c, n, nullptr, M.tx.p, M.tt.p, nullptr);
+    if (loss) *loss = l;
+    if (grad) RT_HIP(hipMemcpy(grad, M.grad.p, M.grad.bytes(), hipMemcpyDeviceToHost));
+    API_END(c)
+}
+
+int rtdm_mlp_predict(rtdm_ctx *c, int64_t n, const float *desc, float *y)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    mlp_configure(c);
+    MlpState &M = c->mlp;
+    require(M.ready, "initialise the network first");
+    RT_CHECK(n >= 1 && desc && y, RTDM_E_ARG, "bad samples");
+    M.tx.alloc((size_t)n * M.in);
+    mlp_work(c, n);
+    RT_HIP(hipMemcpy(M.tx.p, desc, M.tx.bytes(), hipMemcpyHostToDevice));
+    launch_mlp_forward(nullptr, n, M.in, M.out, nullptr, M.tx.p, M.w1h.p, mlp_b1(M), M.w2h.p, mlp_b2(M), nullptr,
+                       M.y.p);
+    RT_HIP(hipMemcpy(y, M.y.p, (size_t)n * M.out * sizeof(float), hipMemcpyDeviceToHost));
     API_END(c)
 }
 

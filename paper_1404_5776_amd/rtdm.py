@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "librtdm.so")
 MAT = {"S": 0, "H0": 1, "H": 2, "X": 3, "A": 4, "U": 5, "K": 6, "W": 7}
 PROD = {"XH": 0, "AT": 1, "UK": 2, "WU": 3, "SX": 4, "UV": 5}
 HMODEL = {"fixed": 0, "mulliken": 1}
-INV_START = {"block_jacobi": 0, "cold": 1, "previous": 2}
+INV_START = {"block_jacobi": 0, "cold": 1, "previous": 2, "learned": 3}
 PRECISION = {"fp64": 0, "fp32": 1, "fp32_taylor": 2}
 
 STATUS = {0: "RTDM_OK", -1: "RTDM_E_ARG", -2: "RTDM_E_STATE", -3: "RTDM_E_OOM", -4: "RTDM_E_HIP",
@@ -31,7 +31,9 @@ EXPORTED = ["rtdm_default_options", "rtdm_create", "rtdm_destroy", "rtdm_set_geo
             "rtdm_set_ranges", "rtdm_pattern", "rtdm_upload", "rtdm_upload_coo", "rtdm_download",
             "rtdm_apply_kick", "rtdm_build_inverse", "rtdm_step", "rtdm_observables",
             "rtdm_dipole_trace", "rtdm_unitarity", "rtdm_inverse_error", "rtdm_multiply", "rtdm_schedule_stats",
-            "rtdm_timing", "rtdm_timing_stats", "rtdm_last_error"]
+            "rtdm_timing", "rtdm_timing_stats", "rtdm_inverse_info", "rtdm_mlp_params", "rtdm_mlp_init",
+            "rtdm_mlp_set_weights", "rtdm_mlp_get_weights", "rtdm_mlp_collect", "rtdm_mlp_clear",
+            "rtdm_mlp_train", "rtdm_mlp_loss_grad", "rtdm_mlp_predict", "rtdm_last_error"]
 
 
 class RtdmError(RuntimeError):
@@ -80,6 +82,16 @@ def load():
         "rtdm_schedule_stats": [P, I, P, P],
         "rtdm_timing": [P, I],
         "rtdm_timing_stats": [P, I, P, P, P],
+        "rtdm_inverse_info": [P, P, P],
+        "rtdm_mlp_params": [P, P, P, P, P],
+        "rtdm_mlp_init": [P, ctypes.c_uint64],
+        "rtdm_mlp_set_weights": [P, P, I64],
+        "rtdm_mlp_get_weights": [P, P, I64],
+        "rtdm_mlp_collect": [P, I64, ctypes.c_uint64, P],
+        "rtdm_mlp_clear": [P],
+        "rtdm_mlp_train": [P, I, I, D, ctypes.c_uint64, P],
+        "rtdm_mlp_loss_grad": [P, I64, P, P, P, P],
+        "rtdm_mlp_predict": [P, I64, P, P],
         "rtdm_last_error": [P],
     }
     for name, args in sig.items():
@@ -262,6 +274,69 @@ def rtdm_timing_stats(ctx, prod) -> Tuple[int, float, float]:
     fl = ctypes.c_double()
     _check(ctx, load().rtdm_timing_stats(ctx, _prod(prod), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl)))
     return n.value, ms.value, fl.value
+
+
+def rtdm_inverse_info(ctx) -> Tuple[int, int]:
+    it = ctypes.c_int()
+    fb = ctypes.c_int()
+    _check(ctx, load().rtdm_inverse_info(ctx, ctypes.byref(it), ctypes.byref(fb)))
+    return it.value, fb.value
+
+
+def rtdm_mlp_params(ctx) -> Tuple[int, int, int, int]:
+    n = ctypes.c_int64()
+    i, h, o = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(ctx, load().rtdm_mlp_params(ctx, ctypes.byref(n), ctypes.byref(i), ctypes.byref(h), ctypes.byref(o)))
+    return n.value, i.value, h.value, o.value
+
+
+def rtdm_mlp_init(ctx, seed: int) -> None:
+    _check(ctx, load().rtdm_mlp_init(ctx, int(seed)))
+
+
+def rtdm_mlp_set_weights(ctx, w) -> None:
+    a = np.ascontiguousarray(w, dtype=np.float32)
+    _check(ctx, load().rtdm_mlp_set_weights(ctx, _p(a), a.size))
+
+
+def rtdm_mlp_get_weights(ctx) -> np.ndarray:
+    n = rtdm_mlp_params(ctx)[0]
+    a = np.zeros(n, dtype=np.float32)
+    _check(ctx, load().rtdm_mlp_get_weights(ctx, _p(a), n))
+    return a
+
+
+def rtdm_mlp_collect(ctx, max_samples: int, seed: int) -> int:
+    t = ctypes.c_int64()
+    _check(ctx, load().rtdm_mlp_collect(ctx, int(max_samples), int(seed), ctypes.byref(t)))
+    return t.value
+
+
+def rtdm_mlp_clear(ctx) -> None:
+    _check(ctx, load().rtdm_mlp_clear(ctx))
+
+
+def rtdm_mlp_train(ctx, epochs: int, batch: int, lr: float, seed: int) -> float:
+    l = ctypes.c_double()
+    _check(ctx, load().rtdm_mlp_train(ctx, int(epochs), int(batch), float(lr), int(seed), ctypes.byref(l)))
+    return l.value
+
+
+def rtdm_mlp_loss_grad(ctx, desc, target) -> Tuple[float, np.ndarray]:
+    d = np.ascontiguousarray(desc, dtype=np.float32)
+    t = np.ascontiguousarray(target, dtype=np.float32)
+    g = np.zeros(rtdm_mlp_params(ctx)[0], dtype=np.float32)
+    l = ctypes.c_double()
+    _check(ctx, load().rtdm_mlp_loss_grad(ctx, d.shape[0], _p(d), _p(t), ctypes.byref(l), _p(g)))
+    return l.value, g
+
+
+def rtdm_mlp_predict(ctx, desc) -> np.ndarray:
+    d = np.ascontiguousarray(desc, dtype=np.float32)
+    out = rtdm_mlp_params(ctx)[3]
+    y = np.zeros((d.shape[0], out), dtype=np.float32)
+    _check(ctx, load().rtdm_mlp_predict(ctx, d.shape[0], _p(d), _p(y)))
+    return y
 
 
 def rtdm_last_error(ctx) -> str:

@@ -1,0 +1,111 @@
+"""Learned starting guess of the inverse iteration: kernels against the oracle,
+and what a trained network gains over the plain block-Jacobi start.
+
+Tolerances: the GPU forward pass accumulates in FP32 (the oracle in FP64 with
+the same FP16-rounded weights), so predictions agree to 1e-5 of their scale
+and gradients to 1e-4 of theirs.  Inverses reached from any start are the
+same fixed point within the iteration's tolerance (1e-10), so they are
+compared at 1e-8 relative.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import mlp as OM
+from oracle import oracle as O
+from paper_1404_5776_amd import rtdm, synth
+from tests._common import gpu_context, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _lattice(seed, cells=(3, 3, 3)):
+    return synth.diamond_lattice(cells, 4, 10.0, 12.0, seed=seed, k0="local", h_model="mulliken")
+
+
+def _seeded_weights(n_in, n_out, seed, scale=0.3):
+    rng = np.random.default_rng(seed)
+    return (scale * rng.uniform(-1, 1, OM.n_params(n_in, n_out))).astype(np.float32)
+
+
+def test_forward_and_gradient_match_oracle():
+    s = _lattice(60)
+    ctx = gpu_context(s)
+    n, n_in, hid, n_out = rtdm.rtdm_mlp_params(ctx.h)
+    assert (n_in, hid, n_out) == (20, 128, 16) and n == OM.n_params(n_in, n_out)
+    w = _seeded_weights(n_in, n_out, 61)
+    rtdm.rtdm_mlp_set_weights(ctx.h, w)
+    assert np.array_equal(rtdm.rtdm_mlp_get_weights(ctx.h), w)
+    rng = np.random.default_rng(62)
+    x = rng.normal(size=(300, n_in)).astype(np.float32)
+    t = rng.normal(size=(300, n_out)).astype(np.float32)
+    y = rtdm.rtdm_mlp_predict(ctx.h, x)
+    yo, _ = OM.forward(w.astype(np.float64), x, n_in, n_out)
+    assert np.abs(y - yo).max() <= 1e-5 * np.abs(yo).max()
+    loss, g = rtdm.rtdm_mlp_loss_grad(ctx.h, x, t)
+    lo, go = OM.loss_grad(w.astype(np.float64), x, t, n_in, n_out)
+    assert abs(loss - lo) <= 1e-5 * lo
+    assert np.abs(g - go).max() <= 1e-4 * np.abs(go).max()
+    ctx.close()
+
+
+@pytest.mark.parametrize("zero_net", [True, False])
+def test_learned_start_matches_oracle(zero_net):
+    """The start 2 delta I - S + y(d) and the iteration from it, against the oracle."""
+    s = _lattice(63)
+    st = O.setup(s)
+    ctx = gpu_context(s, inv_start="learned")
+    n, n_in, _, n_out = rtdm.rtdm_mlp_params(ctx.h)
+    w = np.zeros(n, np.float32) if zero_net else _seeded_weights(n_in, n_out, 64, scale=0.02)
+    rtdm.rtdm_mlp_set_weights(ctx.h, w)
+    it, _ = rtdm.rtdm_build_inverse(ctx.h)
+    total, fell_back = rtdm.rtdm_inverse_info(ctx.h)
+    X = rtdm.rtdm_download(ctx.h, "X", s.b)
+    ctx.close()
+    # oracle: its own descriptors, forward pass and start on S's blocks
+    d = OM.descriptors(st.xyz, st.S, s.R_HS)
+    y, _ = OM.forward(w.astype(np.float64), d.astype(np.float32), n_in, n_out)
+    X0 = O.zeros(st.pat_p, s.b)
+    pos = st.pat_p.index(st.S.pat.rows(), st.S.pat.col)
+    X0.val[pos] = OM.first_order_start(st.S) + y.reshape(-1, s.b, s.b)
+    ref = O.hotelling(st.S, st.pat_p, X0=X0)
+    assert fell_back == int(ref.fell_back)
+    if zero_net:
+        assert it == ref.iters
+    assert rel(X, ref.X.val) <= 1e-8
+
+
+def test_trained_network_gains_over_block_jacobi():
+    """Train on inverses of three lattices, apply to a held-out lattice: fewer
+    iterations to the 1e-10 residual, same inverse as the block-Jacobi start."""
+    train_seeds, test_seed = (70, 71, 72), 73
+    ctx = None
+    for k, seed in enumerate(train_seeds):
+        s = _lattice(seed)
+        if ctx is None:
+            ctx = gpu_context(s)
+            rtdm.rtdm_mlp_init(ctx.h, 7)
+        else:
+            ctx.load_system(s)
+        rtdm.rtdm_build_inverse(ctx.h)
+        total = rtdm.rtdm_mlp_collect(ctx.h, 4000, 100 + k)
+    assert total == 12000
+    loss = rtdm.rtdm_mlp_train(ctx.h, 60, 256, 2e-3, 11)
+    w = rtdm.rtdm_mlp_get_weights(ctx.h)
+    ctx.close()
+    s = _lattice(test_seed)
+    base = gpu_context(s)
+    it_bj, _ = rtdm.rtdm_build_inverse(base.h)
+    X_bj = rtdm.rtdm_download(base.h, "X", s.b)
+    base.close()
+    lrn = gpu_context(s, inv_start="learned")
+    rtdm.rtdm_mlp_set_weights(lrn.h, w)
+    it_l, res = rtdm.rtdm_build_inverse(lrn.h)
+    total, fell_back = rtdm.rtdm_inverse_info(lrn.h)
+    X_l = rtdm.rtdm_download(lrn.h, "X", s.b)
+    lrn.close()
+    print(f"training loss {loss:.3e}; iterations to 1e-10: block-Jacobi {it_bj}, learned {it_l} "
+          f"(fell back: {bool(fell_back)})")
+    assert not fell_back
+    assert it_l < it_bj
+    assert rel(X_l, X_bj) <= 1e-8

@@ -393,3 +393,24 @@ def test_inverse_error_vanishes_untruncated_and_falls_with_range():
         errs.append(mean)
     assert all(e1 > e2 for e1, e2 in zip(errs, errs[1:]))
     assert errs[-1] < 1e-14
+
+
+def test_mlp_oracle_gradient_matches_finite_differences():
+    """Central differences of the network's loss pin the oracle's backward pass
+    (weights exactly representable in FP16, so the rounding is the identity)."""
+    from oracle import mlp
+    rng = np.random.default_rng(40)
+    n_in, n_out, n = 7, 5, 9
+    w = (rng.uniform(-0.5, 0.5, mlp.n_params(n_in, n_out))).astype(np.float16).astype(np.float64)
+    x = rng.normal(size=(n, n_in))
+    t = rng.normal(size=(n, n_out))
+    loss, g = mlp.loss_grad(w, x, t, n_in, n_out, fp16=False)
+    eps = 1e-6
+    for k in rng.choice(w.size, 60, replace=False):
+        wp, wm = w.copy(), w.copy()
+        wp[k] += eps
+        wm[k] -= eps
+        fd = (mlp.loss_grad(wp, x, t, n_in, n_out, fp16=False)[0] -
+              mlp.loss_grad(wm, x, t, n_in, n_out, fp16=False)[0]) / (2 * eps)
+        assert abs(fd - g[k]) <= 1e-7 * max(1.0, abs(g[k]))
+    assert abs(loss - ((mlp.forward(w, x, n_in, n_out, False)[0] - t) ** 2).mean()) < 1e-15
