@@ -124,6 +124,7 @@ typedef struct {
     double inv_tol;        /* stop when ||X_{k+1}-X_k||_F / ||X_{k+1}||_F <= tol (default 1e-10) */
     int inv_max_iter;      /* iteration cap (default 50) */
     int taylor_low_from;   /* RTDM_PREC_FP32_TAYLOR: first Taylor order n computed in FP32 (>= 2, default 3) */
+    int use_graph;         /* 1: rtdm_step replays one captured HIP graph per step (default 0) */
 } rtdm_options;
 
 /* Fill *opt with the defaults above.  Never fails for a non-NULL opt. */
@@ -215,6 +216,30 @@ int rtdm_dipole_trace(rtdm_ctx *ctx, double *out, int64_t max_rows, int64_t *row
  * metric): out[0] = ||D||_F/||S||_F, out[1] = mean |D_ab|, out[2] = max |D_ab|
  * with D = P_P(U^dagger P_P(S U)) - S over R_P's pattern.  Synchronises. */
 int rtdm_unitarity(rtdm_ctx *ctx, double out[3], void *hip_stream);
+
+/* ---- batches of independent systems ----
+ * A batch is one geometry whose atoms fall into contiguous groups placed so
+ * that no pair of atoms of different groups is within any range: every
+ * matrix is then block-diagonal over groups and every product launch serves
+ * all groups.  group_ptr[g] .. group_ptr[g+1]-1 are the atoms of group g
+ * (group_ptr[0] = 0, group_ptr[n_groups] = n_atoms).  With more than one
+ * group rtdm_step also records per-group observables.  Call after
+ * rtdm_set_ranges; RTDM_E_ARG if a kept pair crosses groups. */
+int rtdm_set_groups(rtdm_ctx *ctx, int64_t n_groups, const int64_t *group_ptr);
+/* K_ij <- exp(i kappa_g . (r_i - r_j)) K_ij with kappa_g = kappa[3g..3g+2]
+ * the kick of the group of atoms i and j; otherwise as rtdm_apply_kick. */
+int rtdm_apply_kick_groups(rtdm_ctx *ctx, const double *kappa, void *hip_stream);
+/* Per-group trace since the last kick: out[(s * n_groups + g) * 4 + 0..3] =
+ * (Px, Py, Pz, Tr(KS)) of group g after step s+1, the dipole taken about the
+ * group's centroid.  Synchronises. */
+int rtdm_group_trace(rtdm_ctx *ctx, double *out, int64_t max_rows, int64_t *rows);
+
+/* Time candidate launch shapes of the step's block products (workgroups of
+ * 4, 8 or 16 waves; output tiles of 16, 64 or 256 atom rows) on the current
+ * matrices and keep the fastest; b = 13 only (other block sizes have one
+ * shape).  Overwrites W and the Taylor-term work buffers.  *wpb, *row_tile
+ * (may be NULL) receive the choice.  Synchronises. */
+int rtdm_autotune(rtdm_ctx *ctx, void *hip_stream, int *wpb, int *row_tile);
 
 /* Outcome of the last rtdm_build_inverse: iterations summed over the start
  * and, if taken, the block-Jacobi fallback; fell_back = 1 if the fallback ran.

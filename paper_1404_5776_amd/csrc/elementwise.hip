@@ -220,10 +220,14 @@ void launch_onsite_shift(hipStream_t s, int64_t n_atoms, int b, const int32_t *d
 }
 
 // Single workgroup: centroid, dipole P = -sum (r_i - r_c) q_i, Tr(KS) = sum q_i.
+// With a step state st/tt the row is out + 8 * st[0], the time tt[0] +
+// (st[1] + 1) * tt[1], and both counters advance; without one (st null) the
+// row is `out` and the time `t`.
 __global__ __launch_bounds__(kT) void k_observables(int64_t n, const double *__restrict__ xyz,
                                                     const double *__restrict__ q,
                                                     const double *__restrict__ herm_sums, double t,
-                                                    double *__restrict__ row)
+                                                    double *__restrict__ out, int64_t *st,
+                                                    const double *__restrict__ tt)
 {
     __shared__ double sh[4 * kT];
     double v[4] = {0.0, 0.0, 0.0, 0.0};
@@ -250,7 +254,8 @@ __global__ __launch_bounds__(kT) void k_observables(int64_t n, const double *__r
     double u[4] = {tr, 0.0, 0.0, 0.0};
     block_reduce4(u, sh);
     if (threadIdx.x == 0) {
-        row[0] = t;
+        double *row = st ? out + 8 * st[0] : out;
+        row[0] = st ? tt[0] + (double)(st[1] + 1) * tt[1] : t;
         row[1] = w[0];
         row[2] = w[1];
         row[3] = w[2];
@@ -264,7 +269,30 @@ __global__ __launch_bounds__(kT) void k_observables(int64_t n, const double *__r
 void launch_observables(hipStream_t s, int64_t n_atoms, const double *xyz, const double *q,
                         const double *herm_sums, double t, double *row)
 {
-    hipLaunchKernelGGL(k_observables, dim3(1), dim3(kT), 0, s, n_atoms, xyz, q, herm_sums, t, row);
+    hipLaunchKernelGGL(k_observables, dim3(1), dim3(kT), 0, s, n_atoms, xyz, q, herm_sums, t, row,
+                       (int64_t *)nullptr, (const double *)nullptr);
+    RT_HIP(hipGetLastError());
+}
+
+// Advance the step state after a step's observables (st[0]++, st[1]++).
+__global__ void k_step_end(int64_t *st)
+{
+    if (threadIdx.x == 0) {
+        st[0] += 1;
+        st[1] += 1;
+    }
+}
+
+void launch_observables_step(hipStream_t s, int64_t n_atoms, const double *xyz, const double *q,
+                             const double *herm_sums, double *obs, int64_t *st, const double *tt)
+{
+    hipLaunchKernelGGL(k_observables, dim3(1), dim3(kT), 0, s, n_atoms, xyz, q, herm_sums, 0.0, obs, st, tt);
+    RT_HIP(hipGetLastError());
+}
+
+void launch_step_end(hipStream_t s, int64_t *st)
+{
+    hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, s, st);
     RT_HIP(hipGetLastError());
 }
 
@@ -401,6 +429,127 @@ void launch_axpy_f32(hipStream_t s, int64_t n, double a, const float *x, double 
     int64_t g = (n + kT - 1) / kT;
     if (g > 65536) g = 65536;
     hipLaunchKernelGGL(k_axpy_f32, dim3((unsigned)g), dim3(kT), 0, s, n, a, x, y);
+    RT_HIP(hipGetLastError());
+}
+
+__global__ void k_fill(int64_t n, double v, double *__restrict__ out)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x)
+        out[e] = v;
+}
+
+void launch_fill(hipStream_t s, int64_t n, double v, double *out)
+{
+    if (n == 0) return;
+    int64_t g = (n + kT - 1) / kT;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)g), dim3(kT), 0, s, n, v, out);
+    RT_HIP(hipGetLastError());
+}
+
+// Step state kept on the device so that one captured step can be replayed:
+// st[0] = next trace row, st[1] = steps done in this call, and
+// tt[0] = time at the start of the call, tt[1] = dt.
+__global__ void k_step_begin(int64_t *st, double *tt, double t0, double dt)
+{
+    if (threadIdx.x == 0) {
+        st[1] = 0;
+        tt[0] = t0;
+        tt[1] = dt;
+    }
+}
+
+void launch_step_begin(hipStream_t s, int64_t *st, double *tt, double t0, double dt)
+{
+    hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(64), 0, s, st, tt, t0, dt);
+    RT_HIP(hipGetLastError());
+}
+
+// Per-group observables of the new K (one workgroup per group of contiguous
+// atoms): centroid, dipole -sum (r_i - r_c) q_i and Tr(KS) = sum q_i, written
+// to out[row][g][0..3] with row = st[0].
+__global__ __launch_bounds__(kT) void k_group_obs(const int64_t *__restrict__ gptr,
+                                                  const double *__restrict__ xyz,
+                                                  const double *__restrict__ q,
+                                                  const int64_t *__restrict__ st, int64_t n_groups,
+                                                  double *__restrict__ out)
+{
+    __shared__ double sh[4 * kT];
+    const int64_t g = blockIdx.x;
+    const int64_t a0 = gptr[g], a1 = gptr[g + 1];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = a0 + threadIdx.x; i < a1; i += kT) {
+        v[0] += xyz[3 * i];
+        v[1] += xyz[3 * i + 1];
+        v[2] += xyz[3 * i + 2];
+    }
+    block_reduce4(v, sh);
+    const double na = (double)(a1 - a0);
+    const double cx = v[0] / na, cy = v[1] / na, cz = v[2] / na;
+    __syncthreads();
+    double w[4] = {0.0, 0.0, 0.0, 0.0};
+    double tr = 0.0;
+    for (int64_t i = a0 + threadIdx.x; i < a1; i += kT) {
+        const double qi = q[i];
+        w[0] -= (xyz[3 * i] - cx) * qi;
+        w[1] -= (xyz[3 * i + 1] - cy) * qi;
+        w[2] -= (xyz[3 * i + 2] - cz) * qi;
+        tr += qi;
+    }
+    block_reduce4(w, sh);
+    __syncthreads();
+    double u[4] = {tr, 0.0, 0.0, 0.0};
+    block_reduce4(u, sh);
+    if (threadIdx.x == 0) {
+        double *o = out + (st[0] * n_groups + g) * 4;
+        o[0] = w[0];
+        o[1] = w[1];
+        o[2] = w[2];
+        o[3] = u[0];
+    }
+}
+
+void launch_group_obs(hipStream_t s, int64_t n_groups, const int64_t *gptr, const double *xyz, const double *q,
+                      const int64_t *st, double *out)
+{
+    if (n_groups == 0) return;
+    hipLaunchKernelGGL(k_group_obs, dim3((unsigned)n_groups), dim3(kT), 0, s, gptr, xyz, q, st, n_groups, out);
+    RT_HIP(hipGetLastError());
+}
+
+// K_ij *= exp(i kappa_g . (r_i - r_j)) with the kick of atom i's group (pairs
+// never cross groups in a block-diagonal batch).
+__global__ void k_kick_groups(int64_t nnzb, int b, const int32_t *__restrict__ rowof,
+                              const int32_t *__restrict__ col, const double *__restrict__ xyz,
+                              const int32_t *__restrict__ group, const double *__restrict__ kappa,
+                              double *__restrict__ kr, double *__restrict__ ki)
+{
+    const int bb = b * b;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnzb * bb;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = e / bb;
+        const int i = rowof[p], j = col[p];
+        const double *k = kappa + 3 * group[i];
+        const double ph = k[0] * (xyz[3 * i] - xyz[3 * j]) + k[1] * (xyz[3 * i + 1] - xyz[3 * j + 1]) +
+                          k[2] * (xyz[3 * i + 2] - xyz[3 * j + 2]);
+        double sn, cs;
+        sincos(ph, &sn, &cs);
+        const double xr = kr[e], xi = ki[e];
+        kr[e] = cs * xr - sn * xi;
+        ki[e] = cs * xi + sn * xr;
+    }
+}
+
+void launch_kick_groups(hipStream_t s, int64_t nnzb, int b, const int32_t *rowof, const int32_t *col,
+                        const double *xyz, const int32_t *group, const double *kappa, double *kr, double *ki)
+{
+    const int64_t n = nnzb * b * b;
+    if (n == 0) return;
+    int64_t g = (n + kT - 1) / kT;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_kick_groups, dim3((unsigned)g), dim3(kT), 0, s, nnzb, b, rowof, col, xyz, group, kappa,
+                       kr, ki);
     RT_HIP(hipGetLastError());
 }
 

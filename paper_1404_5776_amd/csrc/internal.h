@@ -89,6 +89,7 @@ struct SpgemmArgs {
     int precision = RTDM_PREC_FP64;  // arithmetic of the block products
     const double *zero = nullptr;    // 256 zero doubles (operand of lanes without data)
     const int32_t *order = nullptr;  // processing order of the output blocks (null: storage order)
+    int wpb = 16;                    // waves per workgroup of the step kernels (4, 8, 16)
 };
 void launch_spgemm(hipStream_t s, const SpgemmArgs &a);
 // Same product with the left operand given as column-major blocks, the right
@@ -128,6 +129,16 @@ void launch_onsite_shift(hipStream_t s, int64_t n_atoms, int b, const int32_t *d
 // Observable row: t, P(3), Tr(KS), herm_err from (partials -> sums), unit_err = NaN.
 void launch_observables(hipStream_t s, int64_t n_atoms, const double *xyz, const double *q,
                         const double *herm_sums, double t, double *row);
+// The same observables written to obs + 8 * st[0] at time tt[0] + (st[1] + 1) * tt[1].
+void launch_observables_step(hipStream_t s, int64_t n_atoms, const double *xyz, const double *q,
+                             const double *herm_sums, double *obs, int64_t *st, const double *tt);
+void launch_step_begin(hipStream_t s, int64_t *st, double *tt, double t0, double dt);
+void launch_step_end(hipStream_t s, int64_t *st);
+void launch_fill(hipStream_t s, int64_t n, double v, double *out);
+void launch_group_obs(hipStream_t s, int64_t n_groups, const int64_t *gptr, const double *xyz, const double *q,
+                      const int64_t *st, double *out);
+void launch_kick_groups(hipStream_t s, int64_t nnzb, int b, const int32_t *rowof, const int32_t *col,
+                        const double *xyz, const int32_t *group, const double *kappa, double *kr, double *ki);
 // X_ii = S_ii^{-1} (Gauss-Jordan, partial pivoting); other blocks untouched.
 void launch_block_inverse(hipStream_t s, int64_t n_atoms, int b, const int32_t *s_diag,
                           const double *sv, const int32_t *x_diag, double *xv, double *scratch);

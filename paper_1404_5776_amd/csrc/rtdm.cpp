@@ -82,11 +82,7 @@ std::vector<int32_t> tile_order(const Pattern &C, int tile_i, int tile_j)
     return order;
 }
 
-int env_int(const char *name, int dflt)
-{
-    const char *e = getenv(name);
-    return e ? std::max(1, atoi(e)) : dflt;
-}
+
 
 struct TRec {
     int prod;
@@ -159,6 +155,24 @@ struct rtdm_ctx {
     int prec = RTDM_PREC_FP64;  // arithmetic of the products being issued
     MlpState mlp;
     DBuf<int32_t> hs_to_p, hs_iota;
+    // device step state (trace row, steps in call; start time, dt) and groups
+    DBuf<int64_t> step_st;
+    DBuf<double> step_tt;
+    bool obs_reset_pending = true;
+    int64_t n_groups = 1;
+    std::vector<int64_t> gptr;
+    DBuf<int64_t> d_gptr;
+    DBuf<int32_t> d_group;
+    DBuf<double> obs_g, kick_g;
+    // captured step
+    hipStream_t gstream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool capturing = false;
+    double graph_dt = 0.0;
+    bool graph_rebuilds_u = false;
+    // launch shape of the step products
+    int wpb = 16, row_tile = 64;
     int inv_iters_total = 0, inv_fell_back = 0;
     bool timing = false;
     std::vector<hipEvent_t> events;
@@ -347,7 +361,7 @@ Sched &schedule(rtdm_ctx *c, int prod)
                     B.d_rowptr.p, B.d_col.p, B.d_trans.p, std::get<3>(key), std::get<4>(key),
                     S->off.p, S->trip.p);
     {
-        const std::vector<int32_t> ord = tile_order(C, env_int("RTDM_ROW_TILE", 64), env_int("RTDM_COL_TILE", 1 << 30));
+        const std::vector<int32_t> ord = tile_order(C, c->row_tile, 1 << 30);
         S->order.alloc(std::max<size_t>(ord.size(), 1));
         if (!ord.empty())
             RT_HIP(hipMemcpy(S->order.p, ord.data(), ord.size() * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -394,7 +408,8 @@ void product(rtdm_ctx *c, int prod, const Mat &A, const Mat &B, Mat &C, double a
     a.precision = c->prec;
     RT_CHECK(C.cplx || (!A.cplx && !B.cplx && ali == 0.0), RTDM_E_UNSUPPORTED,
              "complex product into a real matrix");
-    if (c->timing) {
+    a.wpb = c->wpb;
+    if (c->timing && !c->capturing) {
         const size_t k = 2 * c->recs.size();
         RT_HIP(hipEventRecord(event_at(c, k), s));
         launch_spgemm(s, a);
@@ -429,9 +444,10 @@ void product_cm(rtdm_ctx *c, int prod, const Mat &Acm, const Mat &B, Mat &C, int
     a.b = c->b;
     a.alpha_re = alr;
     a.zero = c->zero.p;
-    a.order = getenv("RTDM_NO_ORDER") ? nullptr : S.order.p;
+    a.order = S.order.p;
+    a.wpb = c->wpb;
     RT_CHECK(C.cplx || (!Acm.cplx && !B.cplx), RTDM_E_UNSUPPORTED, "complex product into a real matrix");
-    if (c->timing) {
+    if (c->timing && !c->capturing) {
         const size_t k = 2 * c->recs.size();
         RT_HIP(hipEventRecord(event_at(c, k), s));
         launch_spgemm_cm(s, a, conj_b, out_cm);
@@ -494,8 +510,8 @@ void build_propagator(rtdm_ctx *c, double dt, hipStream_t s)
     const bool low32 = c->opt.precision == RTDM_PREC_FP32_TAYLOR && c->Ac32.p != nullptr;
     const int n0 = c->opt.precision == RTDM_PREC_FP64 ? p + 1
                    : (c->opt.precision == RTDM_PREC_FP32 ? 2 : c->opt.taylor_low_from);
-    RT_HIP(hipMemsetAsync(U.re.p, 0, U.re.bytes(), s));
-    RT_HIP(hipMemsetAsync(U.im.p, 0, U.im.bytes(), s));
+    launch_fill(s, ne, 0.0, U.re.p);   // kernels, not memsets: this code may be captured in a graph
+    launch_fill(s, ne, 0.0, U.im.p);
     launch_add_identity(s, c->n, c->b, pat_of(c, R_P).d_diag.p, 1.0, U.re.p);
     if (p >= 1) {
         launch_axpby(s, ne, dt, A.re.p, 0.0, nullptr, c->tau[0].re.p);
@@ -525,10 +541,12 @@ void build_propagator(rtdm_ctx *c, double dt, hipStream_t s)
             a.b = c->b;
             a.alpha_re = dt / k;
             a.order = S.order.p;
+            a.wpb = c->wpb;
+            const bool rec = c->timing && !c->capturing;
             const size_t ev = 2 * c->recs.size();
-            if (c->timing) RT_HIP(hipEventRecord(event_at(c, ev), s));
+            if (rec) RT_HIP(hipEventRecord(event_at(c, ev), s));
             launch_spgemm_r32(s, a, c->Ac32.p, c->tau32[cur].p, c->tau32[1 - cur].p, c->zero32.p);
-            if (c->timing) {
+            if (rec) {
                 RT_HIP(hipEventRecord(event_at(c, ev + 1), s));
                 const double b3 = (double)c->b * c->b * c->b;
                 c->recs.push_back({RTDM_PROD_AT, (int)ev, (double)S.ntrip * 2.0 * b3});
@@ -561,9 +579,18 @@ void unitarity_sums(rtdm_ctx *c, hipStream_t s)
     ensure_s_norm(c, s);
 }
 
+void drop_graph(rtdm_ctx *c)
+{
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+}
+
 void ensure_obs(rtdm_ctx *c, int64_t rows)
 {
-    if (rows <= c->obs_cap) return;
+    const int64_t G = c->n_groups > 1 ? c->n_groups : 0;
+    if (rows <= c->obs_cap && (G == 0 || (int64_t)c->obs_g.n >= c->obs_cap * G * 4)) return;
     int64_t cap = std::max<int64_t>(2 * c->obs_cap, 1024);
     while (cap < rows) cap *= 2;
     DBuf<double> nb;
@@ -571,7 +598,15 @@ void ensure_obs(rtdm_ctx *c, int64_t rows)
     if (c->obs_rows > 0)
         RT_HIP(hipMemcpy(nb.p, c->obs.p, c->obs_rows * 8 * sizeof(double), hipMemcpyDeviceToDevice));
     c->obs = std::move(nb);
+    if (G > 0) {
+        DBuf<double> ng;
+        ng.alloc(cap * G * 4);
+        if (c->obs_rows > 0 && c->obs_g.p)
+            RT_HIP(hipMemcpy(ng.p, c->obs_g.p, c->obs_rows * G * 4 * sizeof(double), hipMemcpyDeviceToDevice));
+        c->obs_g = std::move(ng);
+    }
     c->obs_cap = cap;
+    drop_graph(c);   // the captured step refers to the trace buffers
 }
 
 void require(bool cond, const char *msg) { RT_CHECK(cond, RTDM_E_STATE, msg); }
@@ -604,6 +639,7 @@ void after_upload(rtdm_ctx *c, int m)
     case RTDM_MAT_K:
         c->charges_valid = false;
         c->q_ref_valid = false;
+        c->obs_reset_pending = true;
         c->obs_rows = 0;
         c->t_now = 0.0;
         c->herm_valid = false;
@@ -710,6 +746,7 @@ int rtdm_default_options(rtdm_options *opt)
     opt->inv_tol = 1e-10;
     opt->inv_max_iter = 50;
     opt->taylor_low_from = 3;
+    opt->use_graph = 0;
     return RTDM_OK;
 }
 
@@ -768,6 +805,8 @@ int rtdm_destroy(rtdm_ctx *c)
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     for (auto e : c->events) (void)hipEventDestroy(e);
+    drop_graph(c);
+    if (c->gstream) (void)hipStreamDestroy(c->gstream);
     delete c;
     return RTDM_OK;
 }
@@ -880,6 +919,14 @@ int rtdm_set_ranges(rtdm_ctx *c, double R_hs, double R_p, double R_k)
     c->q_prev = c->q_b.p;
     c->atom_max.alloc(c->n);
     c->scratch.alloc((size_t)c->n * c->b * 2 * c->b);
+    drop_graph(c);
+    c->n_groups = 1;
+    c->gptr.clear();
+    c->obs_g.release();
+    c->step_st.alloc(2);
+    c->step_tt.alloc(2);
+    c->obs_reset_pending = true;
+    c->obs_cap = 0;
     ensure_obs(c, 1024);
     c->obs_rows = 0;
     c->t_now = 0.0;
@@ -1044,6 +1091,7 @@ int rtdm_apply_kick(rtdm_ctx *c, const double kappa[3], void *stream)
                 K.im.p);
     c->charges_valid = false;
     c->obs_rows = 0;
+    c->obs_reset_pending = true;
     c->t_now = 0.0;
     c->herm_valid = false;
     API_END(c)
@@ -1142,6 +1190,64 @@ int rtdm_build_inverse(rtdm_ctx *c, void *stream, int *iters, double *residual)
     API_END(c)
 }
 
+namespace {
+
+// One exponential-midpoint step on stream s.  Everything here is a kernel
+// launch (no memset or memcpy), so the same sequence can be captured into a
+// HIP graph and replayed; the trace row and the time come from the device
+// step state.
+void step_body(rtdm_ctx *c, double dt, bool rebuild_u, hipStream_t s)
+{
+    Mat &H = c->mats[RTDM_MAT_H], &H0 = c->mats[RTDM_MAT_H0], &X = c->mats[RTDM_MAT_X];
+    Mat &A = c->mats[RTDM_MAT_A], &U = c->mats[RTDM_MAT_U], &K = c->mats[RTDM_MAT_K];
+    Mat &W = c->mats[RTDM_MAT_W];
+    const Pattern &ps = pat_of(c, R_HS), &pk = pat_of(c, R_K);
+    const bool mull = c->opt.h_model == RTDM_HMODEL_MULLIKEN;
+    c->prec = c->opt.precision == RTDM_PREC_FP32 ? RTDM_PREC_FP32 : RTDM_PREC_FP64;
+    if (rebuild_u) {
+        launch_axpby(s, elems(c, H), 1.0, H0.re.p, 0.0, nullptr, H.re.p);            // H = H0
+        if (mull)
+            launch_onsite_shift(s, c->n, c->b, ps.d_diag.p, c->opt.h_gain, c->q_cur, c->q_prev, c->q_ref.p,
+                                H.re.p);
+        if (use_cm(c)) {
+            if (!c->Xc_valid) {
+                transpose_into(c, X, c->Xc, s);
+                c->Xc_valid = true;
+            }
+            product_cm(c, RTDM_PROD_XH, c->Xc, H, A, 0, 0, 1.0, s);
+            transpose_into(c, A, c->Ac, s);
+        } else {
+            product(c, RTDM_PROD_XH, X, H, A, 1.0, 0.0, s);
+        }
+        build_propagator(c, dt, s);
+        c->U_valid = true;
+        c->U_dt = dt;
+    }
+    if (use_cm(c)) {
+        product_cm(c, RTDM_PROD_UK, c->Uc, K, c->Wc, 0, 1, 1.0, s);     // W, column-major
+        product_cm(c, RTDM_PROD_WU, c->Wc, c->Uc, c->Kn, 1, 0, 1.0, s); // B = U^dagger
+        c->W_in_cm = true;
+    } else {
+        product(c, RTDM_PROD_UK, U, K, W, 1.0, 0.0, s);
+        product(c, RTDM_PROD_WU, W, U, c->Kn, 1.0, 0.0, s);
+        c->W_in_cm = false;
+    }
+    launch_hermitize(s, pk.nnzb, c->b, pk.d_trans.p, c->Kn.re.p, c->Kn.im.p, K.re.p, K.im.p, c->partials.p);
+    reduce_finish(c, s, c->herm_sums.p);
+    c->herm_valid = true;
+    launch_axpby(s, c->n, 1.0, c->q_cur, 0.0, nullptr, c->q_prev);                 // q(t - dt) <- q(t)
+    launch_mulliken(s, c->n, c->b, ps.d_rowptr.p, ps.d_trans.p, c->s_to_k.p, c->mats[RTDM_MAT_S].re.p, K.re.p,
+                    c->q_cur);
+    launch_observables_step(s, c->n, c->d_xyz.p, c->q_cur, c->herm_sums.p, c->obs.p, c->step_st.p,
+                            c->step_tt.p);
+    if (c->n_groups > 1)
+        launch_group_obs(s, c->n_groups, c->d_gptr.p, c->d_xyz.p, c->q_cur, c->step_st.p, c->obs_g.p);
+    launch_step_end(s, c->step_st.p);
+    c->prec = RTDM_PREC_FP64;
+}
+
+}  // namespace
+
 int rtdm_step(rtdm_ctx *c, double dt, int64_t n_steps, void *stream)
 {
     if (!c) return RTDM_E_ARG;
@@ -1152,66 +1258,203 @@ int rtdm_step(rtdm_ctx *c, double dt, int64_t n_steps, void *stream)
             "upload S, H0, K and build (or upload) the inverse first");
     RT_CHECK(std::isfinite(dt) && n_steps >= 0, RTDM_E_ARG, "bad step arguments");
     hipStream_t s = (hipStream_t)stream;
+    if (c->opt.use_graph && !s) {
+        if (!c->gstream) RT_HIP(hipStreamCreate(&c->gstream));
+        s = c->gstream;
+    }
     ensure_obs(c, c->obs_rows + n_steps);
     ensure_charges(c, s);
-    Mat &H = c->mats[RTDM_MAT_H], &H0 = c->mats[RTDM_MAT_H0], &X = c->mats[RTDM_MAT_X];
-    Mat &A = c->mats[RTDM_MAT_A], &U = c->mats[RTDM_MAT_U], &K = c->mats[RTDM_MAT_K];
-    Mat &W = c->mats[RTDM_MAT_W];
-    const Pattern &ps = pat_of(c, R_HS), &pk = pat_of(c, R_K);
-    const bool mull = c->opt.h_model == RTDM_HMODEL_MULLIKEN;
+    if (c->obs_reset_pending) {
+        RT_HIP(hipMemsetAsync(c->step_st.p, 0, c->step_st.bytes(), s));
+        c->obs_reset_pending = false;
+    }
+    launch_step_begin(s, c->step_st.p, c->step_tt.p, c->t_now, dt);
     const double t_start = c->t_now;
-    struct PrecScope {
-        rtdm_ctx *c;
-        ~PrecScope() { c->prec = RTDM_PREC_FP64; }
-    } scope{c};
-    const int step_prec = c->opt.precision == RTDM_PREC_FP32 ? RTDM_PREC_FP32 : RTDM_PREC_FP64;
-    for (int64_t st = 0; st < n_steps; ++st) {
-        c->prec = step_prec;
-        if (mull || !c->U_valid || c->U_dt != dt) {
-            RT_HIP(hipMemcpyAsync(H.re.p, H0.re.p, H.re.bytes(), hipMemcpyDeviceToDevice, s));
-            if (mull)
-                launch_onsite_shift(s, c->n, c->b, ps.d_diag.p, c->opt.h_gain, c->q_cur, c->q_prev,
-                                    c->q_ref.p, H.re.p);
-            if (use_cm(c)) {
-                if (!c->Xc_valid) {
-                    transpose_into(c, X, c->Xc, s);
-                    c->Xc_valid = true;
-                }
-                product_cm(c, RTDM_PROD_XH, c->Xc, H, A, 0, 0, 1.0, s);
-                transpose_into(c, A, c->Ac, s);
-            } else {
-                product(c, RTDM_PROD_XH, X, H, A, 1.0, 0.0, s);
-            }
-            build_propagator(c, dt, s);
-            c->U_valid = true;
-            c->U_dt = dt;
-        }
-        if (use_cm(c)) {
-            product_cm(c, RTDM_PROD_UK, c->Uc, K, c->Wc, 0, 1, 1.0, s);     // W, column-major
-            product_cm(c, RTDM_PROD_WU, c->Wc, c->Uc, c->Kn, 1, 0, 1.0, s); // B = U^dagger
-            c->W_in_cm = true;
-        } else {
-            product(c, RTDM_PROD_UK, U, K, W, 1.0, 0.0, s);
-            product(c, RTDM_PROD_WU, W, U, c->Kn, 1.0, 0.0, s);
-            c->W_in_cm = false;
-        }
-        launch_hermitize(s, pk.nnzb, c->b, pk.d_trans.p, c->Kn.re.p, c->Kn.im.p, K.re.p, K.im.p,
-                         c->partials.p);
-        reduce_finish(c, s, c->herm_sums.p);
-        c->herm_valid = true;
-        std::swap(c->q_cur, c->q_prev);
-        launch_mulliken(s, c->n, c->b, ps.d_rowptr.p, ps.d_trans.p, c->s_to_k.p, c->mats[RTDM_MAT_S].re.p,
-                        K.re.p, c->q_cur);
-        c->t_now = t_start + (double)(st + 1) * dt;
-        double *row = c->obs.p + 8 * c->obs_rows;
-        launch_observables(s, c->n, c->d_xyz.p, c->q_cur, c->herm_sums.p, c->t_now, row);
+    const bool mull = c->opt.h_model == RTDM_HMODEL_MULLIKEN;
+    auto after_step = [&](int64_t k) {
+        c->t_now = t_start + (double)(k + 1) * dt;
         if (c->opt.unit_check_every > 0 && (c->obs_rows + 1) % c->opt.unit_check_every == 0) {
             c->prec = RTDM_PREC_FP64;               // the unitarity check stays FP64
             unitarity_sums(c, s);
-            launch_unit_to_row(s, c->unit_sums.p, c->s_norm2.p, row);
+            launch_unit_to_row(s, c->unit_sums.p, c->s_norm2.p, c->obs.p + 8 * c->obs_rows);
         }
         c->obs_rows++;
+    };
+    int64_t k = 0;
+    // a fixed H needs its propagator once: build it in an ordinary step
+    while (k < n_steps && (!mull && (!c->U_valid || c->U_dt != dt))) {
+        step_body(c, dt, true, s);
+        after_step(k++);
     }
+    if (k < n_steps && c->opt.use_graph) {
+        if (c->gexec && (c->graph_dt != dt || c->graph_rebuilds_u != mull)) drop_graph(c);
+        if (!c->gexec) {
+            c->capturing = true;
+            RT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            try {
+                step_body(c, dt, mull, s);
+            } catch (...) {
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(s, &g);
+                if (g) (void)hipGraphDestroy(g);
+                c->capturing = false;
+                throw;
+            }
+            RT_HIP(hipStreamEndCapture(s, &c->graph));
+            c->capturing = false;
+            RT_HIP(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+            c->graph_dt = dt;
+            c->graph_rebuilds_u = mull;
+        }
+        for (; k < n_steps; ++k) {
+            RT_HIP(hipGraphLaunch(c->gexec, s));
+            after_step(k);
+        }
+    }
+    for (; k < n_steps; ++k) {
+        step_body(c, dt, mull || !c->U_valid || c->U_dt != dt, s);
+        after_step(k);
+    }
+    API_END(c)
+}
+
+int rtdm_set_groups(rtdm_ctx *c, int64_t n_groups, const int64_t *group_ptr)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    require(c->ranges_set, "set_ranges first");
+    RT_CHECK(n_groups >= 1 && group_ptr && group_ptr[0] == 0 && group_ptr[n_groups] == c->n, RTDM_E_ARG,
+             "group_ptr must run from 0 to n_atoms");
+    std::vector<int32_t> grp(c->n);
+    for (int64_t g = 0; g < n_groups; ++g) {
+        RT_CHECK(group_ptr[g + 1] > group_ptr[g], RTDM_E_ARG, "empty group");
+        for (int64_t i = group_ptr[g]; i < group_ptr[g + 1]; ++i) grp[i] = (int32_t)g;
+    }
+    for (auto &P : c->pats)
+        for (int64_t p = 0; p < P->nnzb; ++p)
+            RT_CHECK(grp[P->rowof[p]] == grp[P->col[p]], RTDM_E_ARG,
+                     "a kept pair crosses groups: place the groups further apart");
+    RT_HIP(hipDeviceSynchronize());
+    c->n_groups = n_groups;
+    c->gptr.assign(group_ptr, group_ptr + n_groups + 1);
+    c->d_gptr.alloc(n_groups + 1);
+    c->d_group.alloc(c->n);
+    RT_HIP(hipMemcpy(c->d_gptr.p, group_ptr, c->d_gptr.bytes(), hipMemcpyHostToDevice));
+    RT_HIP(hipMemcpy(c->d_group.p, grp.data(), c->d_group.bytes(), hipMemcpyHostToDevice));
+    c->obs_g.release();
+    c->obs_cap = 0;
+    ensure_obs(c, std::max<int64_t>(c->obs_rows, 1024));
+    drop_graph(c);
+    API_END(c)
+}
+
+int rtdm_apply_kick_groups(rtdm_ctx *c, const double *kappa, void *stream)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    require(c->ranges_set && c->uploaded[RTDM_MAT_K] && c->uploaded[RTDM_MAT_S], "upload S and K first");
+    RT_CHECK(kappa, RTDM_E_ARG, "null kicks");
+    for (int64_t e = 0; e < 3 * c->n_groups; ++e) RT_CHECK(std::isfinite(kappa[e]), RTDM_E_ARG, "bad kick");
+    hipStream_t s = (hipStream_t)stream;
+    if (!c->q_ref_valid) {
+        c->charges_valid = false;
+        ensure_charges(c, s);
+    }
+    if (c->n_groups == 1) {
+        const Pattern &P = pat_of(c, R_K);
+        launch_kick(s, P.nnzb, c->b, P.d_rowof.p, P.d_col.p, c->d_xyz.p, kappa[0], kappa[1], kappa[2],
+                    c->mats[RTDM_MAT_K].re.p, c->mats[RTDM_MAT_K].im.p);
+    } else {
+        c->kick_g.alloc(3 * c->n_groups);
+        RT_HIP(hipMemcpyAsync(c->kick_g.p, kappa, c->kick_g.bytes(), hipMemcpyHostToDevice, s));
+        const Pattern &P = pat_of(c, R_K);
+        launch_kick_groups(s, P.nnzb, c->b, P.d_rowof.p, P.d_col.p, c->d_xyz.p, c->d_group.p, c->kick_g.p,
+                           c->mats[RTDM_MAT_K].re.p, c->mats[RTDM_MAT_K].im.p);
+        RT_HIP(hipStreamSynchronize(s));
+    }
+    c->charges_valid = false;
+    c->obs_rows = 0;
+    c->obs_reset_pending = true;
+    c->t_now = 0.0;
+    c->herm_valid = false;
+    API_END(c)
+}
+
+int rtdm_group_trace(rtdm_ctx *c, double *out, int64_t max_rows, int64_t *rows)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    RT_CHECK(max_rows >= 0 && (out || max_rows == 0), RTDM_E_ARG, "bad trace buffer");
+    RT_CHECK(c->n_groups > 1, RTDM_E_STATE, "no groups set");
+    RT_HIP(hipDeviceSynchronize());
+    const int64_t nr = std::min(max_rows, c->obs_rows);
+    if (rows) *rows = c->obs_rows;
+    if (nr > 0)
+        RT_HIP(hipMemcpy(out, c->obs_g.p, nr * c->n_groups * 4 * sizeof(double), hipMemcpyDeviceToHost));
+    API_END(c)
+}
+
+int rtdm_autotune(rtdm_ctx *c, void *stream, int *wpb_out, int *tile_out)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    require(c->ranges_set, "set_ranges first");
+    hipStream_t s = (hipStream_t)stream;
+    if (c->b == 13) {
+        const int wpbs[3] = {4, 8, 16}, tiles[3] = {16, 64, 256};
+        hipEvent_t e0, e1;
+        RT_HIP(hipEventCreate(&e0));
+        RT_HIP(hipEventCreate(&e1));
+        double best = 1e300;
+        int bw = c->wpb, bt = c->row_tile;
+        const bool timing = c->timing;
+        c->timing = false;
+        for (int tile : tiles) {
+            c->row_tile = tile;
+            for (auto &kv : c->scheds) {
+                // re-derive the processing order of every schedule for this tile
+                const std::vector<int32_t> ord = tile_order(*c->pats[std::get<2>(kv.first)], tile, 1 << 30);
+                if (!ord.empty())
+                    RT_HIP(hipMemcpy(kv.second->order.p, ord.data(), ord.size() * sizeof(int32_t),
+                                     hipMemcpyHostToDevice));
+            }
+            for (int w : wpbs) {
+                c->wpb = w;
+                product_cm(c, RTDM_PROD_UK, c->Uc, c->mats[RTDM_MAT_K], c->Wc, 0, 1, 1.0, s);   // warm-up
+                RT_HIP(hipEventRecord(e0, s));
+                product_cm(c, RTDM_PROD_UK, c->Uc, c->mats[RTDM_MAT_K], c->Wc, 0, 1, 1.0, s);
+                product_cm(c, RTDM_PROD_AT, c->Ac, c->tau[0], c->tau[1], 0, 0, 1.0, s);
+                RT_HIP(hipEventRecord(e1, s));
+                RT_HIP(hipEventSynchronize(e1));
+                float ms = 0.0f;
+                RT_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) {
+                    best = ms;
+                    bw = w;
+                    bt = tile;
+                }
+            }
+        }
+        c->timing = timing;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        c->wpb = bw;
+        c->row_tile = bt;
+        for (auto &kv : c->scheds) {
+            const std::vector<int32_t> ord = tile_order(*c->pats[std::get<2>(kv.first)], bt, 1 << 30);
+            if (!ord.empty())
+                RT_HIP(hipMemcpy(kv.second->order.p, ord.data(), ord.size() * sizeof(int32_t),
+                                 hipMemcpyHostToDevice));
+        }
+        c->W_in_cm = true;
+        drop_graph(c);
+    }
+    if (wpb_out) *wpb_out = c->wpb;
+    if (tile_out) *tile_out = c->row_tile;
     API_END(c)
 }
 

@@ -639,15 +639,6 @@ static void dispatch_ops(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
 // Step products with a column-major copy of the left operand (op(A)[r][m] at
 // m*B + r) and a right operand whose op(B)[m][r] sits at m*B + r (row-major
 // B, or the column-major copy of a matrix used conjugate-transposed).
-static int waves_per_block()
-{
-    static int v = [] {
-        const char *e = getenv("RTDM_WPB");
-        return e ? atoi(e) : 16;
-    }();
-    return v;
-}
-
 template <bool AC, bool BC, int CJB, int LC>
 static void launch_cm(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
 {
@@ -659,7 +650,7 @@ static void launch_cm(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
                            a.off, a.trip, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re, a.alpha_im,
                            a.zero, a.order);
     else {
-        const int wpb = waves_per_block();
+        const int wpb = a.wpb;
         const int remap = getenv("RTDM_NO_XCD") ? 0 : 1;
         const unsigned grid = xcd_grid((a.nout + wpb - 1) / wpb);
 #define RT_Q4(W)                                                                                  \
@@ -739,7 +730,7 @@ void launch_spgemm_r32(hipStream_t s, const SpgemmArgs &a, const float *a32, con
 {
     if (a.nout == 0) return;
     RT_CHECK(a.b == 13, RTDM_E_UNSUPPORTED, "FP32 step products need b = 13");
-    const int wpb = waves_per_block();
+    const int wpb = a.wpb;
     const unsigned grid = xcd_grid((a.nout + wpb - 1) / wpb);
 #define RT_R32(W)                                                                                  \
     hipLaunchKernelGGL((k_spgemm_q4r32<13, W>), dim3(grid), dim3(64 * W), 0, s, a.nout, a.off, a.trip, \

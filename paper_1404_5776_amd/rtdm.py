@@ -33,7 +33,8 @@ EXPORTED = ["rtdm_default_options", "rtdm_create", "rtdm_destroy", "rtdm_set_geo
             "rtdm_dipole_trace", "rtdm_unitarity", "rtdm_inverse_error", "rtdm_multiply", "rtdm_schedule_stats",
             "rtdm_timing", "rtdm_timing_stats", "rtdm_inverse_info", "rtdm_mlp_params", "rtdm_mlp_init",
             "rtdm_mlp_set_weights", "rtdm_mlp_get_weights", "rtdm_mlp_collect", "rtdm_mlp_clear",
-            "rtdm_mlp_train", "rtdm_mlp_loss_grad", "rtdm_mlp_predict", "rtdm_last_error"]
+            "rtdm_mlp_train", "rtdm_mlp_loss_grad", "rtdm_mlp_predict", "rtdm_set_groups",
+            "rtdm_apply_kick_groups", "rtdm_group_trace", "rtdm_autotune", "rtdm_last_error"]
 
 
 class RtdmError(RuntimeError):
@@ -46,7 +47,7 @@ class Options(ctypes.Structure):
     _fields_ = [("taylor_order", ctypes.c_int), ("unit_check_every", ctypes.c_int),
                 ("precision", ctypes.c_int), ("h_model", ctypes.c_int), ("h_gain", ctypes.c_double),
                 ("inv_start", ctypes.c_int), ("inv_tol", ctypes.c_double),
-                ("inv_max_iter", ctypes.c_int), ("taylor_low_from", ctypes.c_int)]
+                ("inv_max_iter", ctypes.c_int), ("taylor_low_from", ctypes.c_int), ("use_graph", ctypes.c_int)]
 
 
 _lib = None
@@ -92,6 +93,10 @@ def load():
         "rtdm_mlp_train": [P, I, I, D, ctypes.c_uint64, P],
         "rtdm_mlp_loss_grad": [P, I64, P, P, P, P],
         "rtdm_mlp_predict": [P, I64, P, P],
+        "rtdm_set_groups": [P, I64, P],
+        "rtdm_apply_kick_groups": [P, P, P],
+        "rtdm_group_trace": [P, P, I64, P],
+        "rtdm_autotune": [P, P, P, P],
         "rtdm_last_error": [P],
     }
     for name, args in sig.items():
@@ -339,6 +344,32 @@ def rtdm_mlp_predict(ctx, desc) -> np.ndarray:
     return y
 
 
+def rtdm_set_groups(ctx, group_ptr) -> None:
+    g = np.ascontiguousarray(group_ptr, dtype=np.int64)
+    _check(ctx, load().rtdm_set_groups(ctx, g.size - 1, _p(g)))
+
+
+def rtdm_apply_kick_groups(ctx, kappa, stream=None) -> None:
+    k = np.ascontiguousarray(kappa, dtype=np.float64).reshape(-1)
+    _check(ctx, load().rtdm_apply_kick_groups(ctx, _p(k), _stream(stream)))
+
+
+def rtdm_group_trace(ctx, n_groups: int, max_rows: int = 1 << 20) -> np.ndarray:
+    rows = ctypes.c_int64()
+    _check(ctx, load().rtdm_group_trace(ctx, None, 0, ctypes.byref(rows)))
+    n = min(rows.value, max_rows)
+    out = np.zeros((n, n_groups, 4))
+    _check(ctx, load().rtdm_group_trace(ctx, _p(out), n, ctypes.byref(rows)))
+    return out
+
+
+def rtdm_autotune(ctx, stream=None) -> Tuple[int, int]:
+    w = ctypes.c_int()
+    t = ctypes.c_int()
+    _check(ctx, load().rtdm_autotune(ctx, _stream(stream), ctypes.byref(w), ctypes.byref(t)))
+    return w.value, t.value
+
+
 def rtdm_last_error(ctx) -> str:
     m = load().rtdm_last_error(ctx)
     return m.decode() if m else ""
@@ -373,6 +404,47 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def load_batch(self, systems, kicks, stream=None):
+        """One geometry holding every (system, kick) pair as its own group.
+
+        systems: generated systems with equal b and ranges; kicks[k]: the kick
+        vectors of systems[k].  Replicas are laid out along x with gaps wider
+        than every range, so the matrices are block-diagonal over groups.
+        Returns the group pointer.  The kicks are applied by rtdm_apply_kick_groups.
+        """
+        s0 = systems[0]
+        gap = 2.0 * max(s0.R_HS, s0.R_K, s0.R_P) + 1.0
+        xyz, rows, cols = [], {"S": [], "H0": [], "K": []}, {"S": [], "H0": [], "K": []}
+        data = {"S": [], "H0": [], "K": []}
+        gptr, kap = [0], []
+        x0 = 0.0
+        n = 0
+        for sys_, ks in zip(systems, kicks):
+            assert sys_.b == s0.b and (sys_.R_HS, sys_.R_K, sys_.R_P) == (s0.R_HS, s0.R_K, s0.R_P)
+            for k in ks:
+                shift = np.array([x0 - sys_.xyz[:, 0].min(), 0.0, 0.0])
+                xyz.append(sys_.xyz + shift)
+                x0 += np.ptp(sys_.xyz[:, 0]) + gap
+                for name, m in (("S", sys_.S), ("H0", sys_.H0), ("K", sys_.K0)):
+                    rows[name].append(m.rows + n)
+                    cols[name].append(m.cols + n)
+                    data[name].append(m.data)
+                n += sys_.n_atoms
+                gptr.append(n)
+                kap.append(k)
+        self.b = s0.b
+        xyz = np.concatenate(xyz)
+        rtdm_set_geometry(self.h, xyz, np.full(n, s0.b, dtype=np.int32))
+        rtdm_set_ranges(self.h, s0.R_HS, s0.R_P, s0.R_K)
+        rtdm_set_groups(self.h, gptr)
+        for name in ("S", "H0", "K"):
+            rtdm_upload_coo(self.h, name, np.concatenate(rows[name]), np.concatenate(cols[name]),
+                            np.concatenate(data[name]), stream)
+        self.batch_xyz = xyz
+        self.group_ptr = np.asarray(gptr)
+        self.group_kicks = np.asarray(kap, dtype=np.float64)
+        return self.group_ptr
 
     def load_system(self, sys_, stream=None):
         self.b = sys_.b

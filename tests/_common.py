@@ -29,7 +29,9 @@ def assert_same_pattern(ctx, slot, pat: O.Pattern):
 def dipole_floor(q: np.ndarray, xyz: np.ndarray) -> float:
     """Rounding floor of P = -sum_i (r_i - r_c) q_i: the sum nearly cancels, so
     two FP64 implementations summing in different orders agree only to about
-    log2(n) * eps * sum_i |r_i - r_c| |q_i| (forward error of a tree-order sum)."""
+    log2(n) * eps * sum_i |r_i - r_c| |q_i| (forward error of a tree-order sum).
+    The centroid r_c is itself a sum with error up to log2(n) * eps * |r_c|,
+    and that error is multiplied by the total charge sum_i q_i."""
     rc = xyz.mean(axis=0)
-    S = np.abs((xyz - rc) * q[:, None]).sum(axis=0).max()
-    return 2.0 * np.log2(max(len(q), 2)) * np.finfo(float).eps * S
+    S = np.abs((xyz - rc) * q[:, None]).sum(axis=0) + np.abs(rc) * abs(q.sum())
+    return 2.0 * np.log2(max(len(q), 2)) * np.finfo(float).eps * S.max()

@@ -1,0 +1,112 @@
+"""Batches of independent systems, captured step graphs and the launch-shape tuner.
+
+A batch holds every (system, kick) pair as its own group of a block-diagonal
+geometry; each group must follow the oracle's propagation of that system
+with that kick (same 1e-10 bar and dipole rounding floor as single systems).
+Graph replays must reproduce the eager steps bit for bit; tuning the launch
+shape must not change any result bit.
+"""
+
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1404_5776_amd import rtdm, synth
+from tests._common import TOL, dipole_floor, gpu_context, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _clusters():
+    out = []
+    for k, n in enumerate((30, 55, 41)):
+        xyz = synth.cluster_positions(n, np.random.default_rng(91 + k))
+        out.append(synth.build_system(f"c{n}", xyz, 4, 8.0, 12.0, 95 + k, k0="exact"))
+    return out
+
+
+@pytest.mark.parametrize("h_model", ["fixed", "mulliken"])
+def test_batch_of_clusters_with_xyz_kicks_matches_oracle(h_model):
+    systems = _clusters()
+    kicks = [[(0.01, 0, 0), (0, 0.01, 0), (0, 0, 0.01)]] * len(systems)
+    print(f"[gpu] batch of {len(systems)} clusters x 3 kicks, h_model={h_model}", flush=True)
+    ctx = rtdm.Context(0, h_model=h_model)
+    gptr = ctx.load_batch(systems, kicks)
+    G = len(gptr) - 1
+    assert G == 9
+    rtdm.rtdm_build_inverse(ctx.h)
+    rtdm.rtdm_apply_kick_groups(ctx.h, ctx.group_kicks)
+    n_steps = 12
+    rtdm.rtdm_step(ctx.h, 0.05, n_steps)
+    gtr = rtdm.rtdm_group_trace(ctx.h, G)
+    K = rtdm.rtdm_download(ctx.h, "K", 4)
+    rp, col = rtdm.rtdm_pattern(ctx.h, "K")
+    xyz = ctx.batch_xyz
+    ctx.close()
+    rows = np.repeat(np.arange(rp.size - 1), np.diff(rp))
+    g = 0
+    for sys_, ks in zip(systems, kicks):
+        for kap in ks:
+            a0 = gptr[g]
+            # the oracle runs on the group's own (shifted) coordinates, the
+            # inputs the batch was given
+            st = O.setup(dataclasses.replace(sys_, xyz=xyz[a0:gptr[g + 1]]))
+            ref = O.propagate(st, n_steps, 0.05, kap, h_model=h_model)
+            sel = (rows >= a0) & (rows < gptr[g + 1])
+            # this group's K blocks, in the oracle's pattern order (same relative order)
+            assert rel(K[sel], ref.K.val) <= TOL
+            q0 = O.mulliken(O.kick(st.K0, st.xyz, kap), st.S)
+            P0 = O.dipole(q0, st.xyz)
+            induced = np.abs(ref.rows[:, 1:4] - P0).max()
+            err = np.abs(gtr[:, g, :3] - ref.rows[:, 1:4]).max()
+            assert err <= TOL * induced + dipole_floor(q0, st.xyz)
+            assert np.abs(gtr[:, g, 3] - ref.rows[:, 4]).max() <= TOL * abs(ref.rows[0, 4])
+            g += 1
+
+
+def _run(s, steps_chunks, use_graph, **opts):
+    ctx = gpu_context(s, use_graph=int(use_graph), **opts)
+    rtdm.rtdm_build_inverse(ctx.h)
+    rtdm.rtdm_apply_kick(ctx.h, s.kappa)
+    for n in steps_chunks:
+        rtdm.rtdm_step(ctx.h, s.dt, n)
+        rtdm.rtdm_observables(ctx.h)          # eager work and a synchronisation between replays
+    out = (rtdm.rtdm_download(ctx.h, "K", s.b), rtdm.rtdm_dipole_trace(ctx.h))
+    ctx.close()
+    return out
+
+
+@pytest.mark.parametrize("which", ["fixed_b4", "mulliken_b4", "mulliken_b13"])
+def test_graph_replays_equal_eager_steps(which):
+    s = {"fixed_b4": synth.config1,
+         "mulliken_b4": lambda: synth.diamond_lattice((3, 3, 3), 4, 10.0, 12.0, seed=22, h_model="mulliken"),
+         "mulliken_b13": lambda: synth.diamond_lattice((2, 2, 2), 13, 10.0, 16.0, seed=21, k0="local",
+                                                       h_model="mulliken")}[which]()
+    chunks = (3, 4, 5)
+    K_e, tr_e = _run(s, chunks, False, h_model=s.h_model)
+    K_g, tr_g = _run(s, chunks, True, h_model=s.h_model)
+    assert tr_e.shape == tr_g.shape == (sum(chunks), 7)
+    for r in range(tr_e.shape[0]):                      # every replayed step
+        assert np.array_equal(tr_e[r, :6], tr_g[r, :6]), r
+    assert np.array_equal(K_e, K_g)
+
+
+def test_autotune_keeps_results_bit_identical():
+    s = synth.diamond_lattice((2, 2, 2), 13, 10.0, 16.0, seed=23, k0="local", h_model="mulliken")
+    K_ref, tr_ref = _run(s, (4,), False, h_model="mulliken")
+    ctx = gpu_context(s, h_model="mulliken")
+    rtdm.rtdm_build_inverse(ctx.h)
+    rtdm.rtdm_step(ctx.h, s.dt, 1)                      # fills U, K for the timing runs
+    wpb, tile = rtdm.rtdm_autotune(ctx.h)
+    assert wpb in (4, 8, 16) and tile in (16, 64, 256)
+    ctx.load_system(s)                                   # fresh state, tuned shape kept
+    rtdm.rtdm_build_inverse(ctx.h)
+    rtdm.rtdm_apply_kick(ctx.h, s.kappa)
+    rtdm.rtdm_step(ctx.h, s.dt, 4)
+    K = rtdm.rtdm_download(ctx.h, "K", s.b)
+    tr = rtdm.rtdm_dipole_trace(ctx.h)
+    ctx.close()
+    assert np.array_equal(K, K_ref)
+    assert np.array_equal(tr[:, :6], tr_ref[:, :6])
