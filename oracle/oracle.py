@@ -399,6 +399,86 @@ def setup(sys_) -> Setup:
 
 
 @dataclasses.dataclass
+class Field:
+    """External field of Gaussian time profile (Sec. II.B, linear response):
+    E(t) = E0 exp(-(t - t0)^2 / (2 sigma^2)).  The external potential is
+    -E(t) . r; the electrons (charge -1) have the potential energy +E(t) . r,
+    so an impulsive field of integral -kappa is the kick exp(i kappa . r)."""
+    E0: Tuple[float, float, float]
+    t0: float
+    sigma: float
+
+    def at(self, t: float) -> np.ndarray:
+        return np.asarray(self.E0, dtype=np.float64) * np.exp(-(t - self.t0) ** 2 / (2.0 * self.sigma ** 2))
+
+
+def field_term(S: BSM, xyz: np.ndarray, E: np.ndarray) -> BSM:
+    """Matrix of the electrons' energy E . (r - r_c) on the support functions, in
+    the position model of the dipole reading: <i|r|j> = (r_i + r_j)/2 S_ij,
+    r_c the atom centroid."""
+    rc = xyz.mean(axis=0)
+    r = S.pat.rows()
+    c = S.pat.col.astype(np.int64)
+    mid = 0.5 * ((xyz[r] - rc) + (xyz[c] - rc))          # (nnzb, 3)
+    return BSM(S.pat, S.b, (mid @ np.asarray(E, dtype=np.float64))[:, None, None] * S.val)
+
+
+def hamiltonian(st: "Setup", q_eff: Optional[np.ndarray], q_ref: np.ndarray, t: float, h_model: str,
+                h_gain: float, field: Optional[Field]) -> BSM:
+    """H at time t: H0, plus g diag(q_eff - q_ref) for the Mulliken model, plus
+    the external field term."""
+    H = st.H0
+    if h_model == "mulliken":
+        H = add_onsite(H, h_gain * (q_eff - q_ref))
+    if field is not None:
+        H = axpby(1.0, H, 1.0, field_term(st.S, st.xyz, field.at(t)))
+    return H
+
+
+M4_THETA = (0.5 - np.sqrt(3.0) / 6.0, 0.5 + np.sqrt(3.0) / 6.0)
+
+
+def complex_taylor(M: BSM, p: int, pat_u: Pattern) -> BSM:
+    """U = sum_{n=0}^{p} T_n, T_0 = I, T_1 = M, T_n = P_U(M T_{n-1}) / n: the
+    truncated Taylor series of exp(M) for a general (complex) exponent."""
+    T = identity(pat_u, M.b)
+    U = T.copy()
+    if p >= 1:
+        T = M.copy()
+        U = axpby(1.0, U, 1.0, T)
+    for n in range(2, p + 1):
+        T, _ = spgemm(M, T, pat_u, alpha=1.0 / n)
+        U = axpby(1.0, U, 1.0, T)
+    return U
+
+
+def build_u(kind: str, A_at, dt: float, p: int, pat_u: Pattern) -> BSM:
+    """One step's propagator from A(theta) = P(X H(t + theta dt)) (Sec. II.A):
+
+    * em   (Eq. EM):   exp(-i dt A(1/2))
+    * etrs (ETRS):     exp(-i dt/2 A(1)) exp(-i dt/2 A(0)), product truncated to P_U
+    * m4   (Magnus):   exp(M), M = -i dt/2 (A1 + A2) - (sqrt(3) dt^2 / 12) [A2, A1],
+                       A_k = A(theta_k), theta_{1,2} = 1/2 -/+ sqrt(3)/6 (Gauss-Legendre),
+                       commutator from the two truncated products.
+    """
+    if kind == "em":
+        return taylor_propagator(A_at(0.5), dt, p, pat_u)
+    if kind == "etrs":
+        U1 = taylor_propagator(A_at(0.0), 0.5 * dt, p, pat_u)
+        U2 = taylor_propagator(A_at(1.0), 0.5 * dt, p, pat_u)
+        U, _ = spgemm(U2, U1, pat_u)
+        return U
+    if kind == "m4":
+        A1, A2 = A_at(M4_THETA[0]), A_at(M4_THETA[1])
+        C21, _ = spgemm(A2, A1, pat_u)
+        C12, _ = spgemm(A1, A2, pat_u)
+        comm = axpby(1.0, C21, -1.0, C12)
+        M = axpby(-0.5j * dt, axpby(1.0, A1, 1.0, A2), -np.sqrt(3.0) * dt * dt / 12.0, comm)
+        return complex_taylor(M, p, pat_u)
+    raise ValueError(f"unknown propagator {kind}")
+
+
+@dataclasses.dataclass
 class Trace:
     rows: np.ndarray          # (n_steps, 6): t, Px, Py, Pz, Tr(KS), herm_err
     K: BSM
@@ -409,30 +489,77 @@ class Trace:
 
 def propagate(st: Setup, n_steps: int, dt: float, kappa: Sequence[float], h_model: str = "fixed",
               h_gain: float = 0.5, p: int = 5, X: Optional[InverseResult] = None,
-              inv_tol: float = 1e-10) -> Trace:
-    """Kick K0 and take n exponential-midpoint steps (Secs. II.A, II.B, IV, V.A)."""
+              inv_tol: float = 1e-10, propagator: str = "em", field: Optional[Field] = None,
+              sc_steps: int = 0, sc_iters: int = 0, t_start: float = 0.0,
+              q_ref: Optional[np.ndarray] = None) -> Trace:
+    """Kick K0 and take n steps (Secs. II.A, II.B, IV, V.A).
+
+    The charges entering H at t + theta dt are extrapolated from the last two
+    steps, q = q(t) + theta (q(t) - q(t - dt)) (predictor).  For the first
+    sc_steps steps the step is repeated sc_iters more times with the charges
+    interpolated between q(t) and the q(t + dt) of the previous pass,
+    q = q(t) + theta (q(t + dt) - q(t)) (corrector; Sec. IV.A, self-consistent
+    H_+).  The field's own time dependence is evaluated exactly, at
+    t = t_start + (s + theta) dt in step s.  q_ref defaults to q(K0)."""
     inv = X if X is not None else hotelling(st.S, st.pat_p, tol=inv_tol)
     Xm = inv.X
-    q_ref = mulliken(st.K0, st.S)
+    if q_ref is None:
+        q_ref = mulliken(st.K0, st.S)
     K = kick(st.K0, st.xyz, kappa)
     q_cur = mulliken(K, st.S)
     q_prev = q_cur.copy()
     U = None
     rows = []
+    varying = h_model == "mulliken" or field is not None
     for s in range(n_steps):
-        if h_model == "mulliken" or U is None:
-            if h_model == "mulliken":
-                q_mid = 1.5 * q_cur - 0.5 * q_prev
-                H = add_onsite(st.H0, h_gain * (q_mid - q_ref))
-            else:
-                H = st.H0
-            A, _ = spgemm(Xm, H, st.pat_p)
-            U = taylor_propagator(A, dt, p, st.pat_p)
-        W, _ = spgemm(U, K, st.pat_k)
-        Kn, _ = spgemm(W, U, st.pat_k, op_b=1)
-        he = herm_error(Kn)
-        K = hermitize(Kn)
-        q_prev, q_cur = q_cur, mulliken(K, st.S)
+        t = t_start + s * dt
+        passes = 1 + (sc_iters if s < sc_steps else 0)
+        q_new = None
+        for it in range(passes):
+            if varying or U is None:
+                if it == 0:
+                    q_at = lambda th: q_cur + th * (q_cur - q_prev)
+                else:
+                    q_at = lambda th, qn=q_new: q_cur + th * (qn - q_cur)
+
+                def A_at(th):
+                    H = hamiltonian(st, q_at(th), q_ref, t + th * dt, h_model, h_gain, field)
+                    return spgemm(Xm, H, st.pat_p)[0]
+
+                U = build_u(propagator, A_at, dt, p, st.pat_p)
+            W, _ = spgemm(U, K, st.pat_k)
+            Kn, _ = spgemm(W, U, st.pat_k, op_b=1)
+            he = herm_error(Kn)
+            Kh = hermitize(Kn)
+            q_new = mulliken(Kh, st.S)
+        K = Kh
+        q_prev, q_cur = q_cur, q_new
         P = dipole(q_cur, st.xyz)
-        rows.append([(s + 1) * dt, P[0], P[1], P[2], q_cur.sum(), he])
+        rows.append([t_start + (s + 1) * dt, P[0], P[1], P[2], q_cur.sum(), he])
     return Trace(np.asarray(rows).reshape(-1, 6), K, U, Xm, inv)
+
+
+def spectrum(P: np.ndarray, P0: np.ndarray, dt: float, E: Optional[np.ndarray], kappa: Optional[np.ndarray],
+             gamma: float, omegas: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+    """Damped transform of the induced dipole (Sec. II.B, linear response).
+
+    P: (n, 3) dipole after steps 1..n (times t_k = k dt); P0: dipole at t = 0.
+    F[f](w) = sum_{k=0}^{n} f(t_k) exp((i w - gamma) t_k) dt.  The polarisability
+    alpha_jj(w) = F[P_j - P0_j](w) / F[E_j](w) for a field along axis j; for a kick exp(i kappa . r) the
+    field transform is -kappa_j (impulsive field of integral -kappa).  Returns
+    alpha (n_w, 3) complex (NaN where direction j has no field) and the
+    strength function S(w) = (2 w / pi) Im(sum_j alpha_jj / 3).
+    """
+    n = P.shape[0]
+    t = dt * np.arange(n + 1)
+    dP = np.vstack([np.zeros((1, 3)), P - P0[None, :]])
+    ph = np.exp((1j * omegas[:, None] - gamma) * t[None, :]) * dt      # (n_w, n+1)
+    FP = ph @ dP                                                        # (n_w, 3)
+    if E is not None:
+        FE = ph @ E                                                     # E: (n+1, 3) at t_k
+    else:
+        FE = np.broadcast_to(-np.asarray(kappa, dtype=np.float64), FP.shape).astype(complex)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        alpha = np.where(np.abs(FE) > 0, FP / np.where(FE == 0, 1, FE), np.nan)
+    tr = np.nansum(alpha, axis=1)
+    return alpha, 2.0 * omegas / np.pi * np.imag(tr / 3.0)
