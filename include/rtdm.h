@@ -112,6 +112,20 @@ enum { RTDM_HMODEL_FIXED = 0, RTDM_HMODEL_MULLIKEN = 1 };
  * the network's correction, zero elsewhere.  PREVIOUS and LEARNED fall back
  * to block-Jacobi when the iteration diverges from them. */
 enum { RTDM_INV_BLOCK_JACOBI = 0, RTDM_INV_COLD = 1, RTDM_INV_PREVIOUS = 2, RTDM_INV_LEARNED = 3 };
+/* Propagator of one step (Sec. II.A), with A(theta) = P_P(X H(t + theta dt)):
+ *   EM    exponential midpoint (Eq. EM): U = exp(-i dt A(1/2));
+ *   ETRS  enforced time-reversal symmetry: U = P_P(exp(-i dt/2 A(1)) exp(-i dt/2 A(0)));
+ *   M4    fourth-order Magnus with two Gauss-Legendre points
+ *         theta_{1,2} = 1/2 -/+ sqrt(3)/6: U = exp(M),
+ *         M = -i dt/2 (A_1 + A_2) - (sqrt(3) dt^2 / 12) (P_P(A_2 A_1) - P_P(A_1 A_2)).
+ * Each exponential is the truncated Taylor series of order taylor_order with
+ * every product truncated to R_P (EM and ETRS: real recursion on A; M4:
+ * complex recursion T_n = P_P(M T_{n-1}) / n).  ETRS and M4 need
+ * RTDM_PREC_FP64.  Charges entering H(t + theta dt): extrapolated
+ * q(t) + theta (q(t) - q(t - dt)); in the first sc_steps steps after a kick
+ * the step is repeated sc_iters times with q(t) + theta (q(t + dt) - q(t)),
+ * q(t + dt) from the previous pass (self-consistent H, Sec. IV.A). */
+enum { RTDM_PROP_EM = 0, RTDM_PROP_ETRS = 1, RTDM_PROP_M4 = 2 };
 
 /* Options of a context (rtdm_default_options fills the defaults). */
 typedef struct {
@@ -125,6 +139,9 @@ typedef struct {
     int inv_max_iter;      /* iteration cap (default 50) */
     int taylor_low_from;   /* RTDM_PREC_FP32_TAYLOR: first Taylor order n computed in FP32 (>= 2, default 3) */
     int use_graph;         /* 1: rtdm_step replays one captured HIP graph per step (default 0) */
+    int propagator;        /* RTDM_PROP_* (default EM) */
+    int sc_steps;          /* steps after a kick with corrector passes (default 0) */
+    int sc_iters;          /* corrector passes per such step (default 2) */
 } rtdm_options;
 
 /* Fill *opt with the defaults above.  Never fails for a non-NULL opt. */
@@ -190,12 +207,12 @@ int rtdm_apply_kick(rtdm_ctx *ctx, const double kappa[3], void *hip_stream);
  * residual.  Synchronises (one scalar read per iteration). */
 int rtdm_build_inverse(rtdm_ctx *ctx, void *hip_stream, int *iters, double *residual);
 
-/* n_steps exponential-midpoint steps of length dt (Sec. II.A, Eq. EM, Eq.
- * matrix_exp): per step the midpoint H (options' model), A = P_P(X H), the
- * Taylor propagator U on R_P, W = P_K(U K), K' = P_K(W U^dagger),
- * K <- (K' + K'^dagger)/2, then the observables of the new K appended to the
- * trace.  With a fixed H the propagator of the first step is reused.
- * Asynchronous on hip_stream. */
+/* n_steps steps of length dt (Sec. II.A, Eq. EM, Eq. matrix_exp): per step
+ * H at the propagator's time points (options' model and field), A = P_P(X H),
+ * the Taylor propagator U on R_P (RTDM_PROP_*), W = P_K(U K),
+ * K' = P_K(W U^dagger), K <- (K' + K'^dagger)/2, then the observables of the
+ * new K appended to the trace.  With a fixed H and no field the propagator of
+ * the first step is reused.  Asynchronous on hip_stream. */
 int rtdm_step(rtdm_ctx *ctx, double dt, int64_t n_steps, void *hip_stream);
 
 /* Observables of the current K: out[0..2] dipole P = -sum_i (r_i - r_c) q_i
@@ -216,6 +233,27 @@ int rtdm_dipole_trace(rtdm_ctx *ctx, double *out, int64_t max_rows, int64_t *row
  * metric): out[0] = ||D||_F/||S||_F, out[1] = mean |D_ab|, out[2] = max |D_ab|
  * with D = P_P(U^dagger P_P(S U)) - S over R_P's pattern.  Synchronises. */
 int rtdm_unitarity(rtdm_ctx *ctx, double out[3], void *hip_stream);
+
+/* External field of Gaussian time profile (Sec. II.B, linear response):
+ * E(t) = E0 exp(-(t - t0)^2 / (2 sigma^2)) enters H(t) as the electrons'
+ * energy E(t) . (r - r_c) (external potential -E . r, electron charge -1),
+ * in the position model <i|r|j> = (r_i + r_j)/2 S_ij on R_HS, r_c the
+ * centroid of the atom's group.  Time t counts from the last kick.  E0 = 0
+ * removes the field.  sigma > 0.  Host arguments, no device work. */
+int rtdm_set_field(rtdm_ctx *ctx, const double E0[3], double t0, double sigma);
+
+/* Damped transform of the trace since the last kick (Sec. II.B):
+ * F[f](w) = sum_{k=0}^{n} f(t_k) exp((i w - gamma) t_k) dt over t_k = k dt,
+ * with the induced dipole P(t_k) - P0 (zero at k = 0).  alpha_jj(w) =
+ * F[P_j - P0_j] / F[E_j]: with kappa non-NULL the trace followed the kick
+ * exp(i kappa . r), whose field transform is -kappa_j; else the field of
+ * rtdm_set_field, sampled at t_k.  group < 0 uses the whole-system trace,
+ * group >= 0 that group's trace.  omega[n_omega] (host).  alpha receives
+ * [n_omega][3][2] (re, im; NaN where F[E_j] = 0), strength (may be NULL)
+ * [n_omega] S(w) = (2 w / pi) Im(sum_j alpha_jj / 3) over the j with a
+ * field.  Synchronises. */
+int rtdm_spectrum(rtdm_ctx *ctx, int64_t group, const double P0[3], const double *kappa, double gamma,
+                  int64_t n_omega, const double *omega, double *alpha, double *strength, void *hip_stream);
 
 /* ---- batches of independent systems ----
  * A batch is one geometry whose atoms fall into contiguous groups placed so

@@ -196,26 +196,147 @@ void launch_mulliken(hipStream_t s, int64_t n_atoms, int b, const int64_t *s_ptr
     RT_HIP(hipGetLastError());
 }
 
+// H_ii += g (q_eff,i - q_ref,i) on the diagonal of atom i's block, with the
+// charges at the step's time point q_eff = q_a + theta (q_x - q_y):
+// extrapolation (q_x, q_y) = (q(t), q(t - dt)) or interpolation
+// (q(t + dt), q(t)), q_a = q(t).
 __global__ void k_onsite_shift(int64_t n_atoms, int b, const int32_t *__restrict__ diag,
-                               double gain, const double *__restrict__ q_cur,
-                               const double *__restrict__ q_prev, const double *__restrict__ q_ref,
-                               double *__restrict__ h)
+                               double gain, const double *__restrict__ q_a, double theta,
+                               const double *__restrict__ q_x, const double *__restrict__ q_y,
+                               const double *__restrict__ q_ref, double *__restrict__ h)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n_atoms * b) return;
     const int64_t i = e / b;
     const int a = (int)(e % b);
-    const double qmid = 1.5 * q_cur[i] - 0.5 * q_prev[i];
-    h[(int64_t)diag[i] * b * b + a * b + a] += gain * (qmid - q_ref[i]);
+    const double q = q_a[i] + theta * (q_x[i] - q_y[i]);
+    h[(int64_t)diag[i] * b * b + a * b + a] += gain * (q - q_ref[i]);
 }
 
 void launch_onsite_shift(hipStream_t s, int64_t n_atoms, int b, const int32_t *diag, double gain,
-                         const double *q_cur, const double *q_prev, const double *q_ref, double *h)
+                         const double *q_a, double theta, const double *q_x, const double *q_y,
+                         const double *q_ref, double *h)
 {
     const int64_t n = n_atoms * b;
     if (n == 0) return;
     hipLaunchKernelGGL(k_onsite_shift, dim3((unsigned)((n + kT - 1) / kT)), dim3(kT), 0, s, n_atoms,
-                       b, diag, gain, q_cur, q_prev, q_ref, h);
+                       b, diag, gain, q_a, theta, q_x, q_y, q_ref, h);
+    RT_HIP(hipGetLastError());
+}
+
+// H_ij += (E(t) . ((r_i + r_j)/2 - r_c)) S_ij on the pattern of S, with the
+// Gaussian profile E(t) = E0 exp(-(t - t0)^2 / (2 sigma^2)) at the device
+// step time t = tt[0] + (st[1] + theta) tt[1] and r_c the centre of the
+// group of atom i (centre[3 g..3 g+2]).
+__global__ void k_field(int64_t nnzb, int b, const int32_t *__restrict__ rowof,
+                        const int32_t *__restrict__ col, const double *__restrict__ xyz,
+                        const int32_t *__restrict__ group, const double *__restrict__ centre,
+                        const double *__restrict__ sv, double ex, double ey, double ez, double t0,
+                        double sigma, const int64_t *__restrict__ st, const double *__restrict__ tt,
+                        double theta, double *__restrict__ h)
+{
+    const int64_t bb = (int64_t)b * b;
+    const double t = tt[0] + ((double)st[1] + theta) * tt[1];
+    const double d = t - t0;
+    const double f = exp(-(d * d) / (2.0 * sigma * sigma));
+    const double E[3] = {ex * f, ey * f, ez * f};
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnzb * bb;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = e / bb;
+        const int64_t i = rowof[p], j = col[p];
+        const double *c = centre + 3 * (group ? group[i] : 0);
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) v += 0.5 * ((xyz[3 * i + k] - c[k]) + (xyz[3 * j + k] - c[k])) * E[k];
+        h[e] += v * sv[e];
+    }
+}
+
+void launch_field(hipStream_t s, int64_t nnzb, int b, const int32_t *rowof, const int32_t *col,
+                  const double *xyz, const int32_t *group, const double *centre, const double *sv,
+                  const double E0[3], double t0, double sigma, const int64_t *st, const double *tt,
+                  double theta, double *h)
+{
+    const int64_t n = nnzb * (int64_t)b * b;
+    if (n == 0) return;
+    const int64_t g = std::min<int64_t>((n + kT - 1) / kT, 65536);
+    hipLaunchKernelGGL(k_field, dim3((unsigned)g), dim3(kT), 0, s, nnzb, b, rowof, col, xyz, group, centre,
+                       sv, E0[0], E0[1], E0[2], t0, sigma, st, tt, theta, h);
+    RT_HIP(hipGetLastError());
+}
+
+// Damped transform of a dipole trace, one thread per frequency, the sum over
+// time points in order: F[f](w) = sum_{k=0}^{n} f(t_k) exp((i w - gamma) t_k) dt,
+// t_k = k dt, f = P - P0 (zero at k = 0; P(t_k) = trace[(k-1) * stride + off
+// + 0..2] for k >= 1).  The field transform is -kappa (kick) or the sum over
+// the Gaussian field sampled at t_k.  alpha[w][j] = F[P_j - P0_j] / F[E_j]
+// (NaN where F[E_j] = 0), strength[w] = (2 w / pi) Im(sum_j alpha_jj / 3).
+__global__ void k_spectrum(int64_t n_omega, const double *__restrict__ omega, double gamma, double dt,
+                           int64_t n, const double *__restrict__ trace, int64_t stride, int64_t off,
+                           double p0x, double p0y, double p0z, int kick, double kx, double ky, double kz,
+                           double t0, double sigma, double *__restrict__ alpha, double *__restrict__ strength)
+{
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= n_omega) return;
+    const double om = omega[w];
+    const double P0[3] = {p0x, p0y, p0z};
+    const double E0[3] = {kx, ky, kz};
+    double fr[3] = {0.0, 0.0, 0.0}, fi[3] = {0.0, 0.0, 0.0};
+    double er[3] = {0.0, 0.0, 0.0}, ei[3] = {0.0, 0.0, 0.0};
+    for (int64_t k = 0; k <= n; ++k) {
+        const double t = (double)k * dt;
+        const double m = exp(-gamma * t) * dt;
+        double sn, cs;
+        sincos(om * t, &sn, &cs);
+        const double pr = m * cs, pi = m * sn;
+        if (k > 0) {
+            const double *row = trace + (k - 1) * stride + off;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const double f = row[j] - P0[j];
+                fr[j] += pr * f;
+                fi[j] += pi * f;
+            }
+        }
+        if (!kick) {
+            const double d = t - t0;
+            const double g = exp(-(d * d) / (2.0 * sigma * sigma));
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                er[j] += pr * (E0[j] * g);
+                ei[j] += pi * (E0[j] * g);
+            }
+        }
+    }
+    double tr_im = 0.0;
+    for (int j = 0; j < 3; ++j) {
+        double ar, ai;
+        if (kick) {
+            er[j] = -E0[j];
+            ei[j] = 0.0;
+        }
+        if (er[j] == 0.0 && ei[j] == 0.0) {
+            ar = ai = __builtin_nan("");
+        } else {
+            const double den = er[j] * er[j] + ei[j] * ei[j];
+            ar = (fr[j] * er[j] + fi[j] * ei[j]) / den;
+            ai = (fi[j] * er[j] - fr[j] * ei[j]) / den;
+            tr_im += ai;
+        }
+        alpha[(w * 3 + j) * 2] = ar;
+        alpha[(w * 3 + j) * 2 + 1] = ai;
+    }
+    if (strength) strength[w] = 2.0 * om / M_PI * (tr_im / 3.0);
+}
+
+void launch_spectrum(hipStream_t s, int64_t n_omega, const double *omega, double gamma, double dt, int64_t n,
+                     const double *trace, int64_t stride, int64_t off, const double P0[3], int kick,
+                     const double E0[3], double t0, double sigma, double *alpha, double *strength)
+{
+    if (n_omega == 0) return;
+    hipLaunchKernelGGL(k_spectrum, dim3((unsigned)((n_omega + 63) / 64)), dim3(64), 0, s, n_omega, omega, gamma,
+                       dt, n, trace, stride, off, P0[0], P0[1], P0[2], kick, E0[0], E0[1], E0[2], t0, sigma,
+                       alpha, strength);
     RT_HIP(hipGetLastError());
 }
 

@@ -125,7 +125,15 @@ void launch_mulliken(hipStream_t s, int64_t n_atoms, int b, const int64_t *s_ptr
                      const double *kr, double *q);
 // H[diag] = H0[diag] + gain*(1.5 q_cur - 0.5 q_prev - q_ref) on the diagonal elements.
 void launch_onsite_shift(hipStream_t s, int64_t n_atoms, int b, const int32_t *diag, double gain,
-                         const double *q_cur, const double *q_prev, const double *q_ref, double *h);
+                         const double *q_a, double theta, const double *q_x, const double *q_y,
+                         const double *q_ref, double *h);
+void launch_field(hipStream_t s, int64_t nnzb, int b, const int32_t *rowof, const int32_t *col,
+                  const double *xyz, const int32_t *group, const double *centre, const double *sv,
+                  const double E0[3], double t0, double sigma, const int64_t *st, const double *tt,
+                  double theta, double *h);
+void launch_spectrum(hipStream_t s, int64_t n_omega, const double *omega, double gamma, double dt, int64_t n,
+                     const double *trace, int64_t stride, int64_t off, const double P0[3], int kick,
+                     const double E0[3], double t0, double sigma, double *alpha, double *strength);
 // Observable row: t, P(3), Tr(KS), herm_err from (partials -> sums), unit_err = NaN.
 void launch_observables(hipStream_t s, int64_t n_atoms, const double *xyz, const double *q,
                         const double *herm_sums, double t, double *row);

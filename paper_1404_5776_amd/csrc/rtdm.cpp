@@ -174,6 +174,16 @@ struct rtdm_ctx {
     // launch shape of the step products
     int wpb = 16, row_tile = 64;
     int inv_iters_total = 0, inv_fell_back = 0;
+    // ETRS / Magnus work matrices and the self-consistent corrector's state
+    Mat E1, E2, E3, A1, Kt;
+    DBuf<double> q_c;           // q(t + dt) of the previous pass
+    int64_t step_count = 0;     // steps since the last kick
+    double trace_dt = 0.0;
+    bool trace_dt_mixed = false;
+    // external field E0 exp(-(t - t0)^2 / (2 sigma^2)); centres of the groups
+    bool field_on = false;
+    double field_E0[3] = {0.0, 0.0, 0.0}, field_t0 = 0.0, field_sigma = 1.0;
+    DBuf<double> d_centre;
     bool timing = false;
     std::vector<hipEvent_t> events;
     std::vector<TRec> recs;
@@ -642,6 +652,8 @@ void after_upload(rtdm_ctx *c, int m)
         c->obs_reset_pending = true;
         c->obs_rows = 0;
         c->t_now = 0.0;
+        c->step_count = 0;
+        c->trace_dt_mixed = false;
         c->herm_valid = false;
         break;
     case RTDM_MAT_U: c->U_valid = true; break;
@@ -747,6 +759,9 @@ int rtdm_default_options(rtdm_options *opt)
     opt->inv_max_iter = 50;
     opt->taylor_low_from = 3;
     opt->use_graph = 0;
+    opt->propagator = RTDM_PROP_EM;
+    opt->sc_steps = 0;
+    opt->sc_iters = 2;
     return RTDM_OK;
 }
 
@@ -776,6 +791,11 @@ int rtdm_create(rtdm_ctx **out, int hip_device, const rtdm_options *opt)
     RT_CHECK(c->opt.inv_max_iter >= 1 && c->opt.inv_tol > 0, RTDM_E_ARG, "bad inverse options");
     RT_CHECK(c->opt.unit_check_every >= 0, RTDM_E_ARG, "unit_check_every < 0");
     RT_CHECK(c->opt.taylor_low_from >= 2, RTDM_E_ARG, "taylor_low_from < 2");
+    RT_CHECK(c->opt.propagator >= RTDM_PROP_EM && c->opt.propagator <= RTDM_PROP_M4, RTDM_E_ARG,
+             "unknown propagator");
+    RT_CHECK(c->opt.propagator == RTDM_PROP_EM || c->opt.precision == RTDM_PREC_FP64, RTDM_E_UNSUPPORTED,
+             "ETRS and M4 need RTDM_PREC_FP64");
+    RT_CHECK(c->opt.sc_steps >= 0 && c->opt.sc_iters >= 0, RTDM_E_ARG, "sc_steps / sc_iters < 0");
     set_device(c);
     c->partials.alloc(kRedBlocks * 4);
     c->herm_sums.alloc(4);
@@ -889,6 +909,16 @@ int rtdm_set_ranges(rtdm_ctx *c, double R_hs, double R_p, double R_k)
     }
     c->Xc_valid = false;
     c->W_in_cm = false;
+    if (c->opt.propagator != RTDM_PROP_EM) {
+        alloc_mat(c, c->E1, R_P, true);
+        alloc_mat(c, c->E2, R_P, true);
+        alloc_mat(c, c->E3, R_P, true);
+        alloc_mat(c, c->A1, R_P, false);
+    }
+    if (c->opt.sc_steps > 0 && c->opt.sc_iters > 0) {
+        alloc_mat(c, c->Kt, R_K, true);
+        c->q_c.alloc(c->n);
+    }
     // maps between patterns
     Pattern &ps = pat_of(c, R_HS), &pk = pat_of(c, R_K), &pp = pat_of(c, R_P);
     auto find = [](const Pattern &P, int64_t i, int32_t j) -> int32_t {
@@ -923,6 +953,16 @@ int rtdm_set_ranges(rtdm_ctx *c, double R_hs, double R_p, double R_k)
     c->n_groups = 1;
     c->gptr.clear();
     c->obs_g.release();
+    {
+        double cen[3] = {0.0, 0.0, 0.0};
+        for (int64_t i = 0; i < c->n; ++i)
+            for (int k = 0; k < 3; ++k) cen[k] += c->xyz[3 * i + k];
+        for (int k = 0; k < 3; ++k) cen[k] /= (double)c->n;
+        c->d_centre.alloc(3);
+        RT_HIP(hipMemcpy(c->d_centre.p, cen, sizeof(cen), hipMemcpyHostToDevice));
+    }
+    c->step_count = 0;
+    c->trace_dt_mixed = false;
     c->step_st.alloc(2);
     c->step_tt.alloc(2);
     c->obs_reset_pending = true;
@@ -1093,6 +1133,8 @@ int rtdm_apply_kick(rtdm_ctx *c, const double kappa[3], void *stream)
     c->obs_rows = 0;
     c->obs_reset_pending = true;
     c->t_now = 0.0;
+    c->step_count = 0;
+    c->trace_dt_mixed = false;
     c->herm_valid = false;
     API_END(c)
 }
@@ -1192,52 +1234,159 @@ int rtdm_build_inverse(rtdm_ctx *c, void *stream, int *iters, double *residual)
 
 namespace {
 
-// One exponential-midpoint step on stream s.  Everything here is a kernel
-// launch (no memset or memcpy), so the same sequence can be captured into a
-// HIP graph and replayed; the trace row and the time come from the device
-// step state.
-void step_body(rtdm_ctx *c, double dt, bool rebuild_u, hipStream_t s)
+bool h_varies(rtdm_ctx *c) { return c->opt.h_model == RTDM_HMODEL_MULLIKEN || c->field_on; }
+
+// Kernel copy of both planes (graph-safe).
+void copy_mat(rtdm_ctx *c, const Mat &src, Mat &dst, hipStream_t s)
 {
-    Mat &H = c->mats[RTDM_MAT_H], &H0 = c->mats[RTDM_MAT_H0], &X = c->mats[RTDM_MAT_X];
-    Mat &A = c->mats[RTDM_MAT_A], &U = c->mats[RTDM_MAT_U], &K = c->mats[RTDM_MAT_K];
-    Mat &W = c->mats[RTDM_MAT_W];
-    const Pattern &ps = pat_of(c, R_HS), &pk = pat_of(c, R_K);
-    const bool mull = c->opt.h_model == RTDM_HMODEL_MULLIKEN;
-    c->prec = c->opt.precision == RTDM_PREC_FP32 ? RTDM_PREC_FP32 : RTDM_PREC_FP64;
-    if (rebuild_u) {
-        launch_axpby(s, elems(c, H), 1.0, H0.re.p, 0.0, nullptr, H.re.p);            // H = H0
-        if (mull)
-            launch_onsite_shift(s, c->n, c->b, ps.d_diag.p, c->opt.h_gain, c->q_cur, c->q_prev, c->q_ref.p,
-                                H.re.p);
-        if (use_cm(c)) {
-            if (!c->Xc_valid) {
-                transpose_into(c, X, c->Xc, s);
-                c->Xc_valid = true;
-            }
-            product_cm(c, RTDM_PROD_XH, c->Xc, H, A, 0, 0, 1.0, s);
-            transpose_into(c, A, c->Ac, s);
-        } else {
-            product(c, RTDM_PROD_XH, X, H, A, 1.0, 0.0, s);
-        }
-        build_propagator(c, dt, s);
-        c->U_valid = true;
-        c->U_dt = dt;
+    const int64_t ne = elems(c, src);
+    launch_axpby(s, ne, 1.0, src.re.p, 0.0, nullptr, dst.re.p);
+    if (dst.cplx) {
+        if (src.cplx) launch_axpby(s, ne, 1.0, src.im.p, 0.0, nullptr, dst.im.p);
+        else launch_fill(s, ne, 0.0, dst.im.p);
     }
+}
+
+// H(t + theta dt) into H: H0, the on-site term of the charges at that time
+// point (extrapolated from q(t - dt), q(t); or, in a corrector pass,
+// interpolated towards the q(t + dt) of the previous pass), and the field.
+void build_h(rtdm_ctx *c, double theta, bool corr, hipStream_t s)
+{
+    Mat &H = c->mats[RTDM_MAT_H], &H0 = c->mats[RTDM_MAT_H0];
+    const Pattern &ps = pat_of(c, R_HS);
+    launch_axpby(s, elems(c, H), 1.0, H0.re.p, 0.0, nullptr, H.re.p);
+    if (c->opt.h_model == RTDM_HMODEL_MULLIKEN) {
+        if (corr)
+            launch_onsite_shift(s, c->n, c->b, ps.d_diag.p, c->opt.h_gain, c->q_cur, theta, c->q_c.p, c->q_cur,
+                                c->q_ref.p, H.re.p);
+        else
+            launch_onsite_shift(s, c->n, c->b, ps.d_diag.p, c->opt.h_gain, c->q_cur, theta, c->q_cur, c->q_prev,
+                                c->q_ref.p, H.re.p);
+    }
+    if (c->field_on)
+        launch_field(s, ps.nnzb, c->b, ps.d_rowof.p, ps.d_col.p, c->d_xyz.p, c->n_groups > 1 ? c->d_group.p : nullptr,
+                     c->d_centre.p, c->mats[RTDM_MAT_S].re.p, c->field_E0, c->field_t0, c->field_sigma,
+                     c->step_st.p, c->step_tt.p, theta, H.re.p);
+}
+
+// A = P_P(X H(t + theta dt)) (and its column-major copy on the b = 13 path).
+void make_a(rtdm_ctx *c, double theta, bool corr, hipStream_t s)
+{
+    Mat &H = c->mats[RTDM_MAT_H], &X = c->mats[RTDM_MAT_X], &A = c->mats[RTDM_MAT_A];
+    build_h(c, theta, corr, s);
     if (use_cm(c)) {
-        product_cm(c, RTDM_PROD_UK, c->Uc, K, c->Wc, 0, 1, 1.0, s);     // W, column-major
-        product_cm(c, RTDM_PROD_WU, c->Wc, c->Uc, c->Kn, 1, 0, 1.0, s); // B = U^dagger
-        c->W_in_cm = true;
+        if (!c->Xc_valid) {
+            transpose_into(c, X, c->Xc, s);
+            c->Xc_valid = true;
+        }
+        product_cm(c, RTDM_PROD_XH, c->Xc, H, A, 0, 0, 1.0, s);
+        transpose_into(c, A, c->Ac, s);
     } else {
-        product(c, RTDM_PROD_UK, U, K, W, 1.0, 0.0, s);
-        product(c, RTDM_PROD_WU, W, U, c->Kn, 1.0, 0.0, s);
-        c->W_in_cm = false;
+        product(c, RTDM_PROD_XH, X, H, A, 1.0, 0.0, s);
     }
-    launch_hermitize(s, pk.nnzb, c->b, pk.d_trans.p, c->Kn.re.p, c->Kn.im.p, K.re.p, K.im.p, c->partials.p);
+}
+
+// The step's propagator U (and its column-major copy) for the options'
+// scheme; corr selects interpolated charges (a corrector pass).
+void build_u(rtdm_ctx *c, double dt, bool corr, hipStream_t s)
+{
+    Mat &A = c->mats[RTDM_MAT_A], &U = c->mats[RTDM_MAT_U];
+    switch (c->opt.propagator) {
+    case RTDM_PROP_EM:
+        make_a(c, 0.5, corr, s);
+        build_propagator(c, dt, s);
+        break;
+    case RTDM_PROP_ETRS:
+        // U = P_P(exp(-i dt/2 A(1)) exp(-i dt/2 A(0)))
+        make_a(c, 0.0, corr, s);
+        build_propagator(c, 0.5 * dt, s);
+        copy_mat(c, U, c->E1, s);
+        make_a(c, 1.0, corr, s);
+        build_propagator(c, 0.5 * dt, s);
+        product(c, RTDM_PROD_AT, U, c->E1, c->E2, 1.0, 0.0, s);
+        copy_mat(c, c->E2, U, s);
+        if (use_cm(c)) transpose_into(c, U, c->Uc, s);
+        break;
+    case RTDM_PROP_M4: {
+        // M = -i dt/2 (A1 + A2) - (sqrt(3) dt^2 / 12) (P(A2 A1) - P(A1 A2)), U = sum_n M^n / n!
+        const double th1 = 0.5 - std::sqrt(3.0) / 6.0, th2 = 0.5 + std::sqrt(3.0) / 6.0;
+        const int64_t ne = elems(c, A);
+        make_a(c, th1, corr, s);
+        copy_mat(c, A, c->A1, s);
+        make_a(c, th2, corr, s);                                              // A = A2
+        product(c, RTDM_PROD_AT, A, c->A1, c->tau[0], 1.0, 0.0, s);           // A2 A1
+        product(c, RTDM_PROD_AT, c->A1, A, c->tau[1], 1.0, 0.0, s);           // A1 A2
+        launch_axpby(s, ne, 1.0, c->tau[0].re.p, -1.0, c->tau[1].re.p, c->tau[0].re.p);
+        launch_axpby(s, ne, -std::sqrt(3.0) * dt * dt / 12.0, c->tau[0].re.p, 0.0, nullptr, c->E1.re.p);
+        launch_axpby(s, ne, 1.0, c->A1.re.p, 1.0, A.re.p, c->E1.im.p);
+        launch_axpby(s, ne, -0.5 * dt, c->E1.im.p, 0.0, nullptr, c->E1.im.p);
+        launch_fill(s, ne, 0.0, U.re.p);
+        launch_fill(s, ne, 0.0, U.im.p);
+        launch_add_identity(s, c->n, c->b, pat_of(c, R_P).d_diag.p, 1.0, U.re.p);
+        const int p = c->opt.taylor_order;
+        if (p >= 1) {
+            launch_axpby(s, ne, 1.0, U.re.p, 1.0, c->E1.re.p, U.re.p);
+            launch_axpby(s, ne, 1.0, U.im.p, 1.0, c->E1.im.p, U.im.p);
+        }
+        const Mat *prev = &c->E1;
+        Mat *bufs[2] = {&c->E2, &c->E3};
+        for (int k = 2; k <= p; ++k) {
+            Mat &next = *bufs[k % 2];
+            product(c, RTDM_PROD_AT, c->E1, *prev, next, 1.0 / k, 0.0, s);   // T_k = P(M T_{k-1}) / k
+            launch_axpby(s, ne, 1.0, U.re.p, 1.0, next.re.p, U.re.p);
+            launch_axpby(s, ne, 1.0, U.im.p, 1.0, next.im.p, U.im.p);
+            prev = &next;
+        }
+        if (use_cm(c)) transpose_into(c, U, c->Uc, s);
+        break;
+    }
+    default: throw Error(RTDM_E_ARG, "unknown propagator");
+    }
+}
+
+// One step on stream s: `passes` propagations of the same K(t) (the first
+// with extrapolated charges, the others corrector passes), then the
+// observables of the new K.  Everything here is a kernel launch (no memset
+// or memcpy), so the same sequence can be captured into a HIP graph and
+// replayed; the trace row and the time come from the device step state.
+void step_body(rtdm_ctx *c, double dt, bool rebuild_u, int passes, hipStream_t s)
+{
+    Mat &U = c->mats[RTDM_MAT_U], &K = c->mats[RTDM_MAT_K], &W = c->mats[RTDM_MAT_W];
+    const Pattern &ps = pat_of(c, R_HS), &pk = pat_of(c, R_K);
+    c->prec = c->opt.precision == RTDM_PREC_FP32 ? RTDM_PREC_FP32 : RTDM_PREC_FP64;
+    const bool sc = passes > 1;
+    Mat &dst = sc ? c->Kt : K;
+    for (int it = 0; it < passes; ++it) {
+        if (rebuild_u) {
+            build_u(c, dt, it > 0, s);
+            c->U_valid = true;
+            c->U_dt = dt;
+        }
+        if (use_cm(c)) {
+            product_cm(c, RTDM_PROD_UK, c->Uc, K, c->Wc, 0, 1, 1.0, s);     // W, column-major
+            product_cm(c, RTDM_PROD_WU, c->Wc, c->Uc, c->Kn, 1, 0, 1.0, s); // B = U^dagger
+            c->W_in_cm = true;
+        } else {
+            product(c, RTDM_PROD_UK, U, K, W, 1.0, 0.0, s);
+            product(c, RTDM_PROD_WU, W, U, c->Kn, 1.0, 0.0, s);
+            c->W_in_cm = false;
+        }
+        launch_hermitize(s, pk.nnzb, c->b, pk.d_trans.p, c->Kn.re.p, c->Kn.im.p, dst.re.p, dst.im.p,
+                         c->partials.p);
+        if (sc)
+            launch_mulliken(s, c->n, c->b, ps.d_rowptr.p, ps.d_trans.p, c->s_to_k.p, c->mats[RTDM_MAT_S].re.p,
+                            dst.re.p, c->q_c.p);
+    }
     reduce_finish(c, s, c->herm_sums.p);
     c->herm_valid = true;
     launch_axpby(s, c->n, 1.0, c->q_cur, 0.0, nullptr, c->q_prev);                 // q(t - dt) <- q(t)
-    launch_mulliken(s, c->n, c->b, ps.d_rowptr.p, ps.d_trans.p, c->s_to_k.p, c->mats[RTDM_MAT_S].re.p, K.re.p,
-                    c->q_cur);
+    if (sc) {
+        copy_mat(c, c->Kt, K, s);
+        launch_axpby(s, c->n, 1.0, c->q_c.p, 0.0, nullptr, c->q_cur);
+    } else {
+        launch_mulliken(s, c->n, c->b, ps.d_rowptr.p, ps.d_trans.p, c->s_to_k.p, c->mats[RTDM_MAT_S].re.p,
+                        K.re.p, c->q_cur);
+    }
     launch_observables_step(s, c->n, c->d_xyz.p, c->q_cur, c->herm_sums.p, c->obs.p, c->step_st.p,
                             c->step_tt.p);
     if (c->n_groups > 1)
@@ -1270,7 +1419,7 @@ int rtdm_step(rtdm_ctx *c, double dt, int64_t n_steps, void *stream)
     }
     launch_step_begin(s, c->step_st.p, c->step_tt.p, c->t_now, dt);
     const double t_start = c->t_now;
-    const bool mull = c->opt.h_model == RTDM_HMODEL_MULLIKEN;
+    const bool vary = h_varies(c);
     auto after_step = [&](int64_t k) {
         c->t_now = t_start + (double)(k + 1) * dt;
         if (c->opt.unit_check_every > 0 && (c->obs_rows + 1) % c->opt.unit_check_every == 0) {
@@ -1278,21 +1427,31 @@ int rtdm_step(rtdm_ctx *c, double dt, int64_t n_steps, void *stream)
             unitarity_sums(c, s);
             launch_unit_to_row(s, c->unit_sums.p, c->s_norm2.p, c->obs.p + 8 * c->obs_rows);
         }
+        if (c->obs_rows == 0) c->trace_dt = dt;
+        else if (dt != c->trace_dt) c->trace_dt_mixed = true;
         c->obs_rows++;
+        c->step_count++;
     };
+    const int sc_passes = 1 + c->opt.sc_iters;
+    auto sc_now = [&]() { return vary && c->opt.sc_iters > 0 && c->step_count < c->opt.sc_steps; };
     int64_t k = 0;
     // a fixed H needs its propagator once: build it in an ordinary step
-    while (k < n_steps && (!mull && (!c->U_valid || c->U_dt != dt))) {
-        step_body(c, dt, true, s);
+    while (k < n_steps && (!vary && (!c->U_valid || c->U_dt != dt))) {
+        step_body(c, dt, true, 1, s);
+        after_step(k++);
+    }
+    // the first steps after a kick with corrector passes run outside the graph
+    while (k < n_steps && sc_now()) {
+        step_body(c, dt, true, sc_passes, s);
         after_step(k++);
     }
     if (k < n_steps && c->opt.use_graph) {
-        if (c->gexec && (c->graph_dt != dt || c->graph_rebuilds_u != mull)) drop_graph(c);
+        if (c->gexec && (c->graph_dt != dt || c->graph_rebuilds_u != vary)) drop_graph(c);
         if (!c->gexec) {
             c->capturing = true;
             RT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             try {
-                step_body(c, dt, mull, s);
+                step_body(c, dt, vary, 1, s);
             } catch (...) {
                 hipGraph_t g = nullptr;
                 (void)hipStreamEndCapture(s, &g);
@@ -1304,7 +1463,7 @@ int rtdm_step(rtdm_ctx *c, double dt, int64_t n_steps, void *stream)
             c->capturing = false;
             RT_HIP(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
             c->graph_dt = dt;
-            c->graph_rebuilds_u = mull;
+            c->graph_rebuilds_u = vary;
         }
         for (; k < n_steps; ++k) {
             RT_HIP(hipGraphLaunch(c->gexec, s));
@@ -1312,9 +1471,55 @@ int rtdm_step(rtdm_ctx *c, double dt, int64_t n_steps, void *stream)
         }
     }
     for (; k < n_steps; ++k) {
-        step_body(c, dt, mull || !c->U_valid || c->U_dt != dt, s);
+        step_body(c, dt, vary || !c->U_valid || c->U_dt != dt, 1, s);
         after_step(k);
     }
+    API_END(c)
+}
+
+int rtdm_set_field(rtdm_ctx *c, const double E0[3], double t0, double sigma)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    RT_CHECK(E0 && std::isfinite(E0[0]) && std::isfinite(E0[1]) && std::isfinite(E0[2]) && std::isfinite(t0) &&
+                 std::isfinite(sigma) && sigma > 0.0,
+             RTDM_E_ARG, "bad field (sigma must be > 0)");
+    for (int k = 0; k < 3; ++k) c->field_E0[k] = E0[k];
+    c->field_t0 = t0;
+    c->field_sigma = sigma;
+    c->field_on = E0[0] != 0.0 || E0[1] != 0.0 || E0[2] != 0.0;
+    c->U_valid = false;
+    drop_graph(c);
+    API_END(c)
+}
+
+int rtdm_spectrum(rtdm_ctx *c, int64_t group, const double P0[3], const double *kappa, double gamma,
+                  int64_t n_omega, const double *omega, double *alpha, double *strength, void *stream)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    RT_CHECK(P0 && n_omega >= 0 && (omega || n_omega == 0) && (alpha || n_omega == 0) && std::isfinite(gamma),
+             RTDM_E_ARG, "bad spectrum arguments");
+    RT_CHECK(group < c->n_groups && (group < 0 || c->n_groups > 1), RTDM_E_ARG, "no such group");
+    RT_CHECK(c->obs_rows >= 1, RTDM_E_STATE, "no steps since the last kick");
+    RT_CHECK(!c->trace_dt_mixed, RTDM_E_STATE, "the trace mixes step lengths");
+    RT_CHECK(kappa || c->field_on, RTDM_E_STATE, "neither a kick nor a field");
+    hipStream_t s = (hipStream_t)stream;
+    if (n_omega == 0) return RTDM_OK;
+    DBuf<double> om, al, st;
+    om.alloc(n_omega);
+    al.alloc(n_omega * 6);
+    st.alloc(n_omega);
+    RT_HIP(hipMemcpyAsync(om.p, omega, om.bytes(), hipMemcpyHostToDevice, s));
+    const double *trace = group < 0 ? c->obs.p : c->obs_g.p;
+    const int64_t stride = group < 0 ? 8 : 4 * c->n_groups;
+    const int64_t off = group < 0 ? 1 : 4 * group;
+    launch_spectrum(s, n_omega, om.p, gamma, c->trace_dt, c->obs_rows, trace, stride, off, P0, kappa ? 1 : 0,
+                    kappa ? kappa : c->field_E0, c->field_t0, c->field_sigma, al.p, st.p);
+    RT_HIP(hipMemcpyAsync(alpha, al.p, al.bytes(), hipMemcpyDeviceToHost, s));
+    if (strength) RT_HIP(hipMemcpyAsync(strength, st.p, st.bytes(), hipMemcpyDeviceToHost, s));
+    RT_HIP(hipStreamSynchronize(s));
     API_END(c)
 }
 
@@ -1342,6 +1547,14 @@ int rtdm_set_groups(rtdm_ctx *c, int64_t n_groups, const int64_t *group_ptr)
     c->d_group.alloc(c->n);
     RT_HIP(hipMemcpy(c->d_gptr.p, group_ptr, c->d_gptr.bytes(), hipMemcpyHostToDevice));
     RT_HIP(hipMemcpy(c->d_group.p, grp.data(), c->d_group.bytes(), hipMemcpyHostToDevice));
+    std::vector<double> cen(3 * n_groups, 0.0);
+    for (int64_t g = 0; g < n_groups; ++g) {
+        for (int64_t i = group_ptr[g]; i < group_ptr[g + 1]; ++i)
+            for (int k = 0; k < 3; ++k) cen[3 * g + k] += c->xyz[3 * i + k];
+        for (int k = 0; k < 3; ++k) cen[3 * g + k] /= (double)(group_ptr[g + 1] - group_ptr[g]);
+    }
+    c->d_centre.alloc(3 * n_groups);
+    RT_HIP(hipMemcpy(c->d_centre.p, cen.data(), c->d_centre.bytes(), hipMemcpyHostToDevice));
     c->obs_g.release();
     c->obs_cap = 0;
     ensure_obs(c, std::max<int64_t>(c->obs_rows, 1024));
@@ -1378,6 +1591,8 @@ int rtdm_apply_kick_groups(rtdm_ctx *c, const double *kappa, void *stream)
     c->obs_rows = 0;
     c->obs_reset_pending = true;
     c->t_now = 0.0;
+    c->step_count = 0;
+    c->trace_dt_mixed = false;
     c->herm_valid = false;
     API_END(c)
 }

@@ -23,6 +23,7 @@ PROD = {"XH": 0, "AT": 1, "UK": 2, "WU": 3, "SX": 4, "UV": 5}
 HMODEL = {"fixed": 0, "mulliken": 1}
 INV_START = {"block_jacobi": 0, "cold": 1, "previous": 2, "learned": 3}
 PRECISION = {"fp64": 0, "fp32": 1, "fp32_taylor": 2}
+PROPAGATOR = {"em": 0, "etrs": 1, "m4": 2}
 
 STATUS = {0: "RTDM_OK", -1: "RTDM_E_ARG", -2: "RTDM_E_STATE", -3: "RTDM_E_OOM", -4: "RTDM_E_HIP",
           -5: "RTDM_E_NOCONV", -6: "RTDM_E_NUMERIC", -7: "RTDM_E_UNSUPPORTED"}
@@ -34,7 +35,8 @@ EXPORTED = ["rtdm_default_options", "rtdm_create", "rtdm_destroy", "rtdm_set_geo
             "rtdm_timing", "rtdm_timing_stats", "rtdm_inverse_info", "rtdm_mlp_params", "rtdm_mlp_init",
             "rtdm_mlp_set_weights", "rtdm_mlp_get_weights", "rtdm_mlp_collect", "rtdm_mlp_clear",
             "rtdm_mlp_train", "rtdm_mlp_loss_grad", "rtdm_mlp_predict", "rtdm_set_groups",
-            "rtdm_apply_kick_groups", "rtdm_group_trace", "rtdm_autotune", "rtdm_last_error"]
+            "rtdm_apply_kick_groups", "rtdm_group_trace", "rtdm_autotune", "rtdm_set_field",
+            "rtdm_spectrum", "rtdm_last_error"]
 
 
 class RtdmError(RuntimeError):
@@ -47,7 +49,8 @@ class Options(ctypes.Structure):
     _fields_ = [("taylor_order", ctypes.c_int), ("unit_check_every", ctypes.c_int),
                 ("precision", ctypes.c_int), ("h_model", ctypes.c_int), ("h_gain", ctypes.c_double),
                 ("inv_start", ctypes.c_int), ("inv_tol", ctypes.c_double),
-                ("inv_max_iter", ctypes.c_int), ("taylor_low_from", ctypes.c_int), ("use_graph", ctypes.c_int)]
+                ("inv_max_iter", ctypes.c_int), ("taylor_low_from", ctypes.c_int), ("use_graph", ctypes.c_int),
+                ("propagator", ctypes.c_int), ("sc_steps", ctypes.c_int), ("sc_iters", ctypes.c_int)]
 
 
 _lib = None
@@ -97,6 +100,8 @@ def load():
         "rtdm_apply_kick_groups": [P, P, P],
         "rtdm_group_trace": [P, P, I64, P],
         "rtdm_autotune": [P, P, P, P],
+        "rtdm_set_field": [P, P, D, D],
+        "rtdm_spectrum": [P, I64, P, P, D, I64, P, P, P, P],
         "rtdm_last_error": [P],
     }
     for name, args in sig.items():
@@ -370,6 +375,23 @@ def rtdm_autotune(ctx, stream=None) -> Tuple[int, int]:
     return w.value, t.value
 
 
+def rtdm_set_field(ctx, E0, t0: float, sigma: float) -> None:
+    e = np.ascontiguousarray(E0, dtype=np.float64)
+    _check(ctx, load().rtdm_set_field(ctx, _p(e), float(t0), float(sigma)))
+
+
+def rtdm_spectrum(ctx, P0, omega, gamma: float, kappa=None, group: int = -1, stream=None):
+    """(alpha (n_w, 3) complex, strength (n_w,)) of the trace since the last kick."""
+    p0 = np.ascontiguousarray(P0, dtype=np.float64)
+    om = np.ascontiguousarray(omega, dtype=np.float64)
+    al = np.zeros((om.size, 3, 2))
+    sw = np.zeros(om.size)
+    kp = None if kappa is None else np.ascontiguousarray(kappa, dtype=np.float64)
+    _check(ctx, load().rtdm_spectrum(ctx, int(group), _p(p0), None if kp is None else _p(kp), float(gamma),
+                                     om.size, _p(om), _p(al), _p(sw), _stream(stream)))
+    return al[..., 0] + 1j * al[..., 1], sw
+
+
 def rtdm_last_error(ctx) -> str:
     m = load().rtdm_last_error(ctx)
     return m.decode() if m else ""
@@ -389,6 +411,8 @@ class Context:
                 v = INV_START[v]
             if k == "precision" and isinstance(v, str):
                 v = PRECISION[v]
+            if k == "propagator" and isinstance(v, str):
+                v = PROPAGATOR[v]
             setattr(o, k, v)
         self.options = o
         self.h = rtdm_create(device, o)
