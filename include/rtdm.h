@@ -102,9 +102,29 @@ typedef enum {
  *               (dt |A|)^n / n!, so their rounding enters U scaled down); the
  *               terms are stored in FP32 and summed into U in FP64;
  *               A = P(X H), U K and W U^dagger stay FP64.
- * FP32 forms need b = 4 or 13.  Storage, reductions, observables, the inverse
- * iteration and the unitarity check always run in FP64. */
-enum { RTDM_PREC_FP64 = 0, RTDM_PREC_FP32 = 1, RTDM_PREC_FP32_TAYLOR = 2 };
+ *   BF16X3      every block product split-precision on the BF16 matrix
+ *               cores: x = hi + lo with hi = bf16(x), lo = bf16(x - hi),
+ *               a b ~ ah bh + ah bl + al bh accumulated in FP32 (three-term
+ *               split of Henry, Tang and Heinecke, 2019);
+ *   FP16X2      every block product split on the FP16 matrix cores with a
+ *               power-of-two scale s per operand matrix (max |x s| in
+ *               [2^13, 2^14)): hi = fp16(x s), lo = fp16((x s - hi) 2^11),
+ *               a b ~ (ah bh + (ah bl + al bh) 2^-11) / (sa sb), FP32
+ *               accumulation (scaled split of Ootomo and Yokota, 2022).
+ *   BF16X3_TAYLOR, FP16X2_TAYLOR  only the Taylor-term products with
+ *               n >= taylor_low_from in that split form (FP64 storage).
+ * Reduced-precision forms need b = 4 or 13.  Storage, reductions,
+ * observables, the inverse iteration and the unitarity check always run in
+ * FP64. */
+enum {
+    RTDM_PREC_FP64 = 0,
+    RTDM_PREC_FP32 = 1,
+    RTDM_PREC_FP32_TAYLOR = 2,
+    RTDM_PREC_BF16X3 = 3,
+    RTDM_PREC_FP16X2 = 4,
+    RTDM_PREC_BF16X3_TAYLOR = 5,
+    RTDM_PREC_FP16X2_TAYLOR = 6
+};
 enum { RTDM_HMODEL_FIXED = 0, RTDM_HMODEL_MULLIKEN = 1 };
 /* Starting guess of the inverse iteration: block-Jacobi blockdiag(S_ii^-1);
  * cold I / (largest absolute row sum of S); the current X; or the learned
@@ -137,7 +157,7 @@ typedef struct {
     int inv_start;         /* starting guess of the inverse iteration (default block-Jacobi) */
     double inv_tol;        /* stop when ||X_{k+1}-X_k||_F / ||X_{k+1}||_F <= tol (default 1e-10) */
     int inv_max_iter;      /* iteration cap (default 50) */
-    int taylor_low_from;   /* RTDM_PREC_FP32_TAYLOR: first Taylor order n computed in FP32 (>= 2, default 3) */
+    int taylor_low_from;   /* *_TAYLOR precisions: first Taylor order n in reduced precision (>= 2, default 3) */
     int use_graph;         /* 1: rtdm_step replays one captured HIP graph per step (default 0) */
     int propagator;        /* RTDM_PROP_* (default EM) */
     int sc_steps;          /* steps after a kick with corrector passes (default 0) */

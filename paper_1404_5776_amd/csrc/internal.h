@@ -90,6 +90,10 @@ struct SpgemmArgs {
     const double *zero = nullptr;    // 256 zero doubles (operand of lanes without data)
     const int32_t *order = nullptr;  // processing order of the output blocks (null: storage order)
     int wpb = 16;                    // waves per workgroup of the step kernels (4, 8, 16)
+    // FP16 split products: [8k .. 8k+3] the reduction of operand k's (A: 0,
+    // B: 1) real plane, [8k+4 .. 8k+7] of its imaginary plane (zeros if
+    // real); the last slot of each holds max |x|.
+    const double *maxabs = nullptr;
 };
 void launch_spgemm(hipStream_t s, const SpgemmArgs &a);
 // Same product with the left operand given as column-major blocks, the right

@@ -184,6 +184,7 @@ struct rtdm_ctx {
     bool field_on = false;
     double field_E0[3] = {0.0, 0.0, 0.0}, field_t0 = 0.0, field_sigma = 1.0;
     DBuf<double> d_centre;
+    DBuf<double> f16_max;       // operand maxima of the FP16 split products
     bool timing = false;
     std::vector<hipEvent_t> events;
     std::vector<TRec> recs;
@@ -419,6 +420,22 @@ void product(rtdm_ctx *c, int prod, const Mat &A, const Mat &B, Mat &C, double a
     RT_CHECK(C.cplx || (!A.cplx && !B.cplx && ali == 0.0), RTDM_E_UNSUPPORTED,
              "complex product into a real matrix");
     a.wpb = c->wpb;
+    if (c->prec == RTDM_PREC_FP16X2) {
+        // per-operand max |x| (both planes) for the power-of-two scales
+        const Mat *ops[2] = {&A, &B};
+        for (int k = 0; k < 2; ++k) {
+            const int64_t ne = elems(c, *ops[k]);
+            launch_red_max(s, ne, ops[k]->re.p, c->partials.p);
+            launch_red_finish(s, c->partials.p, c->f16_max.p + 8 * k);
+            if (ops[k]->cplx) {
+                launch_red_max(s, ne, ops[k]->im.p, c->partials.p);
+                launch_red_finish(s, c->partials.p, c->f16_max.p + 8 * k + 4);
+            } else {
+                launch_fill(s, 4, 0.0, c->f16_max.p + 8 * k + 4);
+            }
+        }
+        a.maxabs = c->f16_max.p;
+    }
     if (c->timing && !c->capturing) {
         const size_t k = 2 * c->recs.size();
         RT_HIP(hipEventRecord(event_at(c, k), s));
@@ -510,6 +527,19 @@ void ensure_s_norm(rtdm_ctx *c, hipStream_t s)
     c->s_norm_valid = true;
 }
 
+// Arithmetic of the step's products under the options' precision: the forms
+// that reduce every product, else FP64 (the *_TAYLOR forms lower only late
+// Taylor terms, inside build_propagator).
+int all_products_prec(rtdm_ctx *c)
+{
+    switch (c->opt.precision) {
+    case RTDM_PREC_FP32:
+    case RTDM_PREC_BF16X3:
+    case RTDM_PREC_FP16X2: return c->opt.precision;
+    default: return RTDM_PREC_FP64;
+    }
+}
+
 // U = sum_{n=0}^{p} (-i)^n tau_n with tau_0 = I, tau_1 = dt A, tau_n = (dt/n) P_P(A tau_{n-1}).
 void build_propagator(rtdm_ctx *c, double dt, hipStream_t s)
 {
@@ -518,8 +548,14 @@ void build_propagator(rtdm_ctx *c, double dt, hipStream_t s)
     const int64_t ne = elems(c, A);
     const int p = c->opt.taylor_order;
     const bool low32 = c->opt.precision == RTDM_PREC_FP32_TAYLOR && c->Ac32.p != nullptr;
-    const int n0 = c->opt.precision == RTDM_PREC_FP64 ? p + 1
-                   : (c->opt.precision == RTDM_PREC_FP32 ? 2 : c->opt.taylor_low_from);
+    int n0 = 2, low = all_products_prec(c);
+    switch (c->opt.precision) {
+    case RTDM_PREC_FP64: n0 = p + 1; break;
+    case RTDM_PREC_FP32_TAYLOR: n0 = c->opt.taylor_low_from; low = RTDM_PREC_FP32; break;
+    case RTDM_PREC_BF16X3_TAYLOR: n0 = c->opt.taylor_low_from; low = RTDM_PREC_BF16X3; break;
+    case RTDM_PREC_FP16X2_TAYLOR: n0 = c->opt.taylor_low_from; low = RTDM_PREC_FP16X2; break;
+    default: break;
+    }
     launch_fill(s, ne, 0.0, U.re.p);   // kernels, not memsets: this code may be captured in a graph
     launch_fill(s, ne, 0.0, U.im.p);
     launch_add_identity(s, c->n, c->b, pat_of(c, R_P).d_diag.p, 1.0, U.re.p);
@@ -566,7 +602,7 @@ void build_propagator(rtdm_ctx *c, double dt, hipStream_t s)
             Mat &src = c->tau[cur];
             Mat &dst = c->tau[1 - cur];
             const int saved = c->prec;
-            if (k >= n0) c->prec = RTDM_PREC_FP32;
+            if (k >= n0) c->prec = low;
             if (use_cm(c)) product_cm(c, RTDM_PROD_AT, c->Ac, src, dst, 0, 0, dt / k, s);
             else product(c, RTDM_PROD_AT, A, src, dst, dt / k, 0.0, s);
             c->prec = saved;
@@ -783,7 +819,7 @@ int rtdm_create(rtdm_ctx **out, int hip_device, const rtdm_options *opt)
     if (opt) c->opt = *opt;
     else rtdm_default_options(&c->opt);
     RT_CHECK(c->opt.taylor_order >= 0 && c->opt.taylor_order <= 32, RTDM_E_ARG, "taylor_order out of range");
-    RT_CHECK(c->opt.precision >= RTDM_PREC_FP64 && c->opt.precision <= RTDM_PREC_FP32_TAYLOR, RTDM_E_ARG,
+    RT_CHECK(c->opt.precision >= RTDM_PREC_FP64 && c->opt.precision <= RTDM_PREC_FP16X2_TAYLOR, RTDM_E_ARG,
              "unknown precision");
     RT_CHECK(c->opt.h_model == RTDM_HMODEL_FIXED || c->opt.h_model == RTDM_HMODEL_MULLIKEN, RTDM_E_ARG,
              "unknown h_model");
@@ -803,6 +839,7 @@ int rtdm_create(rtdm_ctx **out, int hip_device, const rtdm_options *opt)
     c->s_norm2.alloc(4);
     c->hot_sums.alloc(4);
     c->obs_tmp.alloc(8);
+    c->f16_max.alloc(16);
     c->zero.alloc(256);
     RT_HIP(hipMemset(c->zero.p, 0, c->zero.bytes()));
     *out = c;
@@ -1353,7 +1390,7 @@ void step_body(rtdm_ctx *c, double dt, bool rebuild_u, int passes, hipStream_t s
 {
     Mat &U = c->mats[RTDM_MAT_U], &K = c->mats[RTDM_MAT_K], &W = c->mats[RTDM_MAT_W];
     const Pattern &ps = pat_of(c, R_HS), &pk = pat_of(c, R_K);
-    c->prec = c->opt.precision == RTDM_PREC_FP32 ? RTDM_PREC_FP32 : RTDM_PREC_FP64;
+    c->prec = all_products_prec(c);
     const bool sc = passes > 1;
     Mat &dst = sc ? c->Kt : K;
     for (int it = 0; it < passes; ++it) {
@@ -1774,7 +1811,7 @@ int rtdm_multiply(rtdm_ctx *c, rtdm_mat Cm, rtdm_mat Am, rtdm_mat Bm, int op_a, 
     hipStream_t s = (hipStream_t)stream;
     const bool cres = A.cplx || B.cplx || ali != 0.0;
     RT_CHECK(C.cplx || !cres, RTDM_E_UNSUPPORTED, "complex result for a real matrix slot");
-    c->prec = c->opt.precision == RTDM_PREC_FP32 ? RTDM_PREC_FP32 : RTDM_PREC_FP64;
+    c->prec = all_products_prec(c);
     try {
         product(c, prod, A, B, C, alr, ali, s);
     } catch (...) {

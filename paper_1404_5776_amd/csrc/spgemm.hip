@@ -191,6 +191,7 @@ static inline unsigned xcd_grid(int64_t nblocks)
 // FP32 (v_mfma_f32_16x16x4_f32).  Both take A[r][q] / B[q][r] from lane
 // 16*q + r; element e of the result sits in row 4*e + q for FP64 and in row
 // 4*q + e for FP32 (measured on gfx950).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 template <class T> struct Mfma16;
 template <> struct Mfma16<double> {
     typedef double acc_t __attribute__((ext_vector_type(4)));
@@ -522,6 +523,127 @@ static void launch_lds(hipStream_t s, const SpgemmArgs &a)
 //   MFMA block g; A operand A_g[r][q]; B operand B_g[q][r]; D: D_g[q][r].
 // The wave's outputs advance in lock-step over their triple lists; a finished
 // output feeds zeros.
+
+// Split-precision block products (B = 4 or 13, operand layouts as in
+// k_spgemm_kc).  Each FP64 operand element x is split into two 16-bit
+// parts and the product of two elements is taken as three 16-bit products
+// with FP32 accumulation on the matrix cores (v_mfma_f32_16x16x32_*):
+//   MODE 0, BF16 x3 (the three-product split of Henry, Tang and Heinecke,
+//     2019): hi = bf16(x), lo = bf16(x - hi); a b ~ ah bh + ah bl + al bh.
+//   MODE 1, FP16 x2 (the scaled split of Ootomo and Yokota, 2022):
+//     y = x s with s = 2^(13 - floor(log2 max|X|)) per operand matrix,
+//     hi = fp16(y), lo = fp16((y - hi) 2^11);
+//     a b ~ (ah bh + (ah bl + al bh) 2^-11) / (sa sb).
+// The contraction of an output block is concatenated over its triples; a
+// 32-wide MFMA step takes elements 8q..8q+7 of the step from lane group q.
+// The sign of a conjugated operand's imaginary part is applied at the load.
+template <int MODE> struct Split16;
+template <> struct Split16<0> {
+    typedef __bf16 v8 __attribute__((ext_vector_type(8)));
+    static __device__ inline void split(double x, float, __bf16 &hi, __bf16 &lo)
+    {
+        hi = (__bf16)(float)x;
+        lo = (__bf16)(float)(x - (double)(float)hi);
+    }
+    static __device__ inline f32x4 mfma(v8 a, v8 b, f32x4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+    typedef __bf16 e_t;
+};
+template <> struct Split16<1> {
+    typedef _Float16 v8 __attribute__((ext_vector_type(8)));
+    static __device__ inline void split(double x, float sc, _Float16 &hi, _Float16 &lo)
+    {
+        const double y = x * (double)sc;
+        hi = (_Float16)(float)y;
+        lo = (_Float16)(float)((y - (double)(float)hi) * 2048.0);
+    }
+    static __device__ inline f32x4 mfma(v8 a, v8 b, f32x4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+    typedef _Float16 e_t;
+};
+
+// Power-of-two operand scale of the FP16 split from max |X| (both planes).
+__device__ inline float f16_scale(const double *mx, int k)
+{
+    const double m = fmax(mx[8 * k + 3], mx[8 * k + 7]);
+    return m > 0.0 ? ldexpf(1.0f, 13 - ilogb(m)) : 1.0f;
+}
+
+template <int B, bool AC, bool BC, int TA, int TB, int MODE>
+__global__ __launch_bounds__(256) void k_spgemm_split(
+    int64_t nout, const int64_t *__restrict__ off, const int2 *__restrict__ trip,
+    const double *__restrict__ ar, const double *__restrict__ ai, const double *__restrict__ br,
+    const double *__restrict__ bi, double *__restrict__ cr, double *__restrict__ ci, double alr,
+    double ali, const double *__restrict__ maxabs)
+{
+    typedef Split16<MODE> SP;
+    typedef typename SP::v8 v8;
+    constexpr int BB = B * B;
+    const int lane = threadIdx.x & 63;
+    const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= nout) return;                     // uniform across the wave
+    const int r = lane & 15, q = lane >> 4;
+    const bool rv = r < B;
+    const int64_t t0 = off[c];
+    const int nt = (int)(off[c + 1] - t0);
+    const int L = nt * B;
+    const float sa = MODE ? f16_scale(maxabs, 0) : 1.0f;
+    const float sb = MODE ? f16_scale(maxabs, 1) : 1.0f;
+    f32x4 h[4] = {}, m[4] = {};                // rr, ii, ri, ir: hi*hi and the mixed terms
+    for (int u0 = 0; u0 < L; u0 += 32) {
+        v8 ahr, alr8, ahi, ali8, bhr, blr8, bhi, bli8;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const int u = u0 + 8 * q + v;
+            double xar = 0.0, xai = 0.0, xbr = 0.0, xbi = 0.0;
+            if (rv && u < L) {
+                const int tt = u / B, k = u - tt * B;
+                const int2 ab = trip[t0 + tt];
+                const int64_t pa = (int64_t)ab.x * BB + (TA ? k * B + r : r * B + k);
+                const int64_t pb = (int64_t)ab.y * BB + (TB ? r * B + k : k * B + r);
+                xar = ar[pa];
+                xbr = br[pb];
+                if (AC) xai = TA ? -ai[pa] : ai[pa];
+                if (BC) xbi = TB ? -bi[pb] : bi[pb];
+            }
+            typename SP::e_t hi, lo;
+            SP::split(xar, sa, hi, lo); ahr[v] = hi; alr8[v] = lo;
+            SP::split(xbr, sb, hi, lo); bhr[v] = hi; blr8[v] = lo;
+            if (AC) { SP::split(xai, sa, hi, lo); ahi[v] = hi; ali8[v] = lo; }
+            if (BC) { SP::split(xbi, sb, hi, lo); bhi[v] = hi; bli8[v] = lo; }
+        }
+        auto prod3 = [&](int k, const v8 &ah, const v8 &al, const v8 &bh, const v8 &bl) {
+            h[k] = SP::mfma(ah, bh, h[k]);
+            m[k] = SP::mfma(ah, bl, m[k]);
+            m[k] = SP::mfma(al, bh, m[k]);
+        };
+        prod3(0, ahr, alr8, bhr, blr8);
+        if (AC && BC) prod3(1, ahi, ali8, bhi, bli8);
+        if (BC) prod3(2, ahr, alr8, bhi, bli8);
+        if (AC) prod3(3, ahi, ali8, bhr, blr8);
+    }
+    const double inv = 1.0 / ((double)sa * (double)sb);
+    const double ml = MODE ? 1.0 / 2048.0 : 1.0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int row = 4 * q + e, col = r;
+        if (row < B && col < B) {
+            double v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = ((double)h[k][e] + ml * (double)m[k][e]) * inv;
+            const double re = v[0] - v[1];
+            const double im = v[2] + v[3];
+            const int64_t o = c * BB + row * B + col;
+            cr[o] = alr * re - ali * im;
+            if (ci) ci[o] = alr * im + ali * re;
+        }
+    }
+}
+
 template <int SUB, bool AC, bool BC, int OPA, int OPB>
 __global__ __launch_bounds__(256) void k_spgemm_b4(
     int64_t nout, const int64_t *__restrict__ off, const int2 *__restrict__ trip,
@@ -600,12 +722,28 @@ static void launch_b4(hipStream_t s, const SpgemmArgs &a)
                        a.alpha_im);
 }
 
+template <bool AC, bool BC, int OA, int OB>
+static void launch_split(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
+{
+#define RT_SPLIT(B_, M_)                                                                         \
+    hipLaunchKernelGGL((k_spgemm_split<B_, AC, BC, OA, OB, M_>), g, t, 0, s, a.nout, a.off, a.trip, \
+                       a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re, a.alpha_im, a.maxabs)
+    const int mode = a.precision == RTDM_PREC_FP16X2 ? 1 : 0;
+    if (a.b == 13 && mode == 0) RT_SPLIT(13, 0);
+    else if (a.b == 13) RT_SPLIT(13, 1);
+    else if (mode == 0) RT_SPLIT(4, 0);
+    else RT_SPLIT(4, 1);
+#undef RT_SPLIT
+}
+
 template <bool AC, bool BC>
 static void dispatch_ops(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
 {
 #define RT_LAUNCH(OA, OB)                                                                        \
     do {                                                                                         \
-        if (a.precision == RTDM_PREC_FP32 && a.b == 13)                                          \
+        if (a.precision == RTDM_PREC_BF16X3 || a.precision == RTDM_PREC_FP16X2)                  \
+            launch_split<AC, BC, OA, OB>(s, a, g, t);                                            \
+        else if (a.precision == RTDM_PREC_FP32 && a.b == 13)                                     \
             hipLaunchKernelGGL((k_spgemm_kc<13, AC, BC, OA, OB, float>), g, t, 0, s, a.nout,     \
                                a.off, a.trip, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re,    \
                                a.alpha_im);                                                      \
@@ -746,8 +884,9 @@ void launch_spgemm(hipStream_t s, const SpgemmArgs &a)
 {
     if (a.nout == 0) return;
     RT_CHECK(a.b >= 1 && a.b <= 16, RTDM_E_UNSUPPORTED, "block size must be 1..16");
-    RT_CHECK(a.precision == RTDM_PREC_FP64 || (a.precision == RTDM_PREC_FP32 && (a.b == 4 || a.b == 13)),
-             RTDM_E_UNSUPPORTED, "FP32 products need b = 4 or 13");
+    RT_CHECK(a.precision == RTDM_PREC_FP64 || (a.b == 4 || a.b == 13), RTDM_E_UNSUPPORTED,
+             "reduced-precision products need b = 4 or 13");
+    RT_CHECK(a.precision != RTDM_PREC_FP16X2 || a.maxabs, RTDM_E_ARG, "FP16 split products need operand maxima");
     const dim3 g((unsigned)((a.nout + 3) / 4)), t(256);
     const bool ac = a.ai != nullptr, bc = a.bi != nullptr;
     if (ac && bc) dispatch_ops<true, true>(s, a, g, t);

@@ -22,7 +22,8 @@ MAT = {"S": 0, "H0": 1, "H": 2, "X": 3, "A": 4, "U": 5, "K": 6, "W": 7}
 PROD = {"XH": 0, "AT": 1, "UK": 2, "WU": 3, "SX": 4, "UV": 5}
 HMODEL = {"fixed": 0, "mulliken": 1}
 INV_START = {"block_jacobi": 0, "cold": 1, "previous": 2, "learned": 3}
-PRECISION = {"fp64": 0, "fp32": 1, "fp32_taylor": 2}
+PRECISION = {"fp64": 0, "fp32": 1, "fp32_taylor": 2, "bf16x3": 3, "fp16x2": 4, "bf16x3_taylor": 5,
+             "fp16x2_taylor": 6}
 PROPAGATOR = {"em": 0, "etrs": 1, "m4": 2}
 
 STATUS = {0: "RTDM_OK", -1: "RTDM_E_ARG", -2: "RTDM_E_STATE", -3: "RTDM_E_OOM", -4: "RTDM_E_HIP",
