@@ -9,7 +9,11 @@ timed region starts.
 
 Prints ONE JSON line with steps/s, the roofline of the dominant product
 kernel (algorithmic flops per launch over its average HIP-event duration) and
-the oracle's CPU rate on a bounded sample.
+the oracle's CPU rate on a bounded sample.  Beside the FP64 run, on the same
+workload: the reduced-precision forms (late Taylor terms in FP32, split BF16
+or split FP16) with the learned inverse start, their dipole error against the
+FP64 run; the captured-graph step; and a batch leg (clusters of the 64-cluster
+workload with x/y/z kicks in block-diagonal batches, FP64 and FP32).
 """
 
 import argparse
@@ -52,28 +56,32 @@ def make_workload(args):
     return s
 
 
-def gpu_run(s, args, precision="fp64", taylor_low_from=3):
+def gpu_run(s, args, precision="fp64", taylor_low_from=3, use_graph=0, inv_start="block_jacobi",
+            mlp_weights=None):
     import torch  # device memory and streams come from torch's runtime
     from paper_1404_5776_amd import rtdm
 
     torch.cuda.init()
     stream = torch.cuda.current_stream()
     ctx = rtdm.Context(0, h_model=s.h_model, h_gain=s.h_gain, precision=precision,
-                       taylor_low_from=taylor_low_from)
+                       taylor_low_from=taylor_low_from, use_graph=use_graph, inv_start=inv_start)
     t = time.time()
     ctx.load_system(s, stream)
-    log(f"set-up (neighbour lists, schedules, upload) {time.time() - t:.1f} s")
-    t = time.time()
+    log(f"[{precision}] set-up (neighbour lists, schedules, upload) {time.time() - t:.1f} s")
+    if mlp_weights is not None:
+        rtdm.rtdm_mlp_set_weights(ctx.h, mlp_weights)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
     iters, res = rtdm.rtdm_build_inverse(ctx.h, stream)
-    log(f"Hotelling inverse: {iters} iterations, residual {res:.2e}, {time.time() - t:.1f} s")
+    inv_s = time.perf_counter() - t
+    log(f"[{precision}] inverse ({inv_start} start): {iters} iterations, residual {res:.2e}, {inv_s:.2f} s")
     rtdm.rtdm_apply_kick(ctx.h, s.kappa, stream)
     p0 = rtdm.rtdm_observables(ctx.h, stream)[:3]
     sched = {k: rtdm.rtdm_schedule_stats(ctx.h, k) for k in ("XH", "AT", "UK", "WU")}
-    log("triples per product:", {k: v[1] for k, v in sched.items()})
     if args.warmup:
         rtdm.rtdm_step(ctx.h, s.dt, args.warmup, stream)
     torch.cuda.synchronize()
-    rtdm.rtdm_timing(ctx.h, True)
+    rtdm.rtdm_timing(ctx.h, not use_graph)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rtdm.rtdm_step(ctx.h, s.dt, args.steps, stream)
@@ -83,7 +91,89 @@ def gpu_run(s, args, precision="fp64", taylor_low_from=3):
     rtdm.rtdm_timing(ctx.h, False)
     trace = rtdm.rtdm_dipole_trace(ctx.h)
     ctx.close()
-    return t1 - t0, stats, sched, trace, p0
+    return dict(elapsed=t1 - t0, stats=stats, sched=sched, trace=trace, p0=p0, inv_iters=iters, inv_s=inv_s)
+
+
+def train_learned_start(b, seeds=(101, 102, 103), cells=(3, 3, 3)):
+    """Train the inverse-start network on converged inverses of small lattices
+    of the workload's recipe (held-out seeds); returns its weights."""
+    from paper_1404_5776_amd import rtdm, synth
+    ctx = None
+    t = time.time()
+    for k, seed in enumerate(seeds):
+        sysk = synth.diamond_lattice(cells, b, 10.0, 16.0, seed=seed, k0="local", h_model="mulliken")
+        if ctx is None:
+            ctx = rtdm.Context(0, inv_tol=1e-12)
+            ctx.load_system(sysk)
+            rtdm.rtdm_mlp_init(ctx.h, 7)
+        else:
+            ctx.load_system(sysk)
+        rtdm.rtdm_build_inverse(ctx.h)
+        rtdm.rtdm_mlp_collect(ctx.h, 4000, 100 + k)
+    loss = rtdm.rtdm_mlp_train(ctx.h, 60, 256, 2e-3, 11)
+    w = rtdm.rtdm_mlp_get_weights(ctx.h)
+    ctx.close()
+    log(f"learned start: trained on {len(seeds)} lattices of {cells} cells, loss {loss:.2e}, "
+        f"{time.time() - t:.1f} s")
+    return w, loss
+
+
+def batch_leg(args):
+    """The 64-cluster workload: every cluster with x, y and z kicks, packed
+    into block-diagonal batches of equal b, one captured step graph per batch,
+    launch shapes autotuned; FP64 and FP32.  Returns the batch object."""
+    import torch
+    from paper_1404_5776_amd import rtdm, synth
+
+    t = time.time()
+    clusters = []
+    for k in range(args.batch_clusters):
+        clusters.append(synth.config4_cluster(k))
+        log(f"batch: cluster {k}: {clusters[-1].n_atoms} atoms, b={clusters[-1].b} ({time.time() - t:.1f} s)")
+    kicks = [(0.01, 0, 0), (0, 0.01, 0), (0, 0, 0.01)]
+    # pack by b, at most batch_atoms atoms (3 kicks counted) per batch
+    batches = []
+    for b in (4, 13):
+        cur, n = [], 0
+        for c in sorted([c for c in clusters if c.b == b], key=lambda c: -c.n_atoms):
+            if cur and n + 3 * c.n_atoms > args.batch_atoms:
+                batches.append(cur)
+                cur, n = [], 0
+            cur.append(c)
+            n += 3 * c.n_atoms
+        if cur:
+            batches.append(cur)
+    out = {"workload": f"the first {len(clusters)} of the 64 random clusters (log-uniform 50-2000 atoms, "
+                       f"b 4 or 13, R_HS 8, "
+                       f"R_K 12 bohr, fixed H), x/y/z kicks each: {3 * len(clusters)} propagations in "
+                       f"{len(batches)} block-diagonal batches, one captured step graph per batch",
+           "propagations": 3 * len(clusters), "atoms": int(sum(c.n_atoms for c in clusters)),
+           "steps": args.batch_steps}
+    for prec in ("fp64", "fp32"):
+        total_s, shapes = 0.0, []
+        for bt in batches:
+            stream = torch.cuda.current_stream()
+            ctx = rtdm.Context(0, precision=prec, use_graph=1)
+            ctx.load_batch(bt, [kicks] * len(bt), stream)
+            rtdm.rtdm_build_inverse(ctx.h, stream)
+            rtdm.rtdm_apply_kick_groups(ctx.h, ctx.group_kicks, stream)
+            rtdm.rtdm_step(ctx.h, bt[0].dt, 1)              # builds the fixed-H propagator
+            shape = rtdm.rtdm_autotune(ctx.h) if bt[0].b == 13 and prec == "fp64" else None
+            rtdm.rtdm_step(ctx.h, bt[0].dt, 1)              # captures the step graph
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rtdm.rtdm_step(ctx.h, bt[0].dt, args.batch_steps)
+            torch.cuda.synchronize()
+            total_s += time.perf_counter() - t0
+            shapes.append({"b": bt[0].b, "systems": len(bt), "atoms": int(3 * sum(c.n_atoms for c in bt)),
+                           "autotuned_wpb_row_tile": shape})
+            ctx.close()
+        out[prec] = {"propagation_steps_per_s": 3 * len(clusters) * args.batch_steps / total_s,
+                     "seconds_per_step_all_batches": total_s / args.batch_steps}
+        if prec == "fp64":
+            out["batches"] = shapes
+        log(f"batch {prec}: {out[prec]}")
+    return out
 
 
 def cpu_baseline(s, target_s: float):
@@ -123,9 +213,15 @@ def main():
     ap.add_argument("--cells", default="8x8x8", help="diamond conventional cells (8 atoms each)")
     ap.add_argument("--cpu-seconds", type=float, default=16.0, help="oracle sample budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true",
-                    help="skip the reduced-precision run (FP32 Taylor terms) compared against the FP64 run")
-    ap.add_argument("--low-from", type=int, default=3, help="first Taylor order in FP32 for the mixed run")
+    ap.add_argument("--forms", default="fp32_taylor,bf16x3_taylor,fp16x2_taylor",
+                    help="reduced-precision forms run beside FP64 (comma list, empty for none)")
+    ap.add_argument("--no-learned", action="store_true", help="forms use the block-Jacobi inverse start")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--batch-clusters", type=int, default=32,
+                    help="clusters of the batch leg, the first of the 64-cluster list (0: skip)")
+    ap.add_argument("--batch-atoms", type=int, default=24000, help="atoms per batch (kicks counted)")
+    ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--low-from", type=int, default=3, help="first Taylor order in reduced precision in the *_taylor forms")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (read + write) before the workload, "
                          "so hardware byte counters can be scaled against a known size")
@@ -133,8 +229,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU design (spatial "
-                                   "domain decomposition with halo exchange) is described in DESIGN.md",
+        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU path (spatial "
+                                   "domain decomposition with halo exchange) is a design, not built",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
@@ -152,20 +248,48 @@ def main():
     t = time.time()
     s = make_workload(args)
     log(f"workload {s.name}: {s.n_atoms} atoms, b={s.b}, generated in {time.time() - t:.1f} s")
-    elapsed, stats, sched, trace, p0 = gpu_run(s, args)
+    base = gpu_run(s, args)
+    elapsed, stats, sched, trace, p0 = base["elapsed"], base["stats"], base["sched"], base["trace"], base["p0"]
     steps_per_s = args.steps / elapsed
-    mixed = None
-    if not args.no_mixed:
-        el2, stats2, _, trace2, _ = gpu_run(s, args, precision="fp32_taylor", taylor_low_from=args.low_from)
-        n = min(len(trace), len(trace2))
+
+    def compare(run):
+        n = min(len(trace), len(run["trace"]))
         induced = np.abs(trace[:n, 1:4] - p0).max()
-        err = np.abs(trace2[:n, 1:4] - trace[:n, 1:4]).max()
-        mixed = {"mode": f"Taylor terms of order >= {args.low_from} on FP32 matrix cores with FP32 storage; "
-                         f"X H, U K, W U^dagger, reductions and observables FP64",
-                 "steps_per_s": args.steps / el2, "speedup_vs_fp64": elapsed / el2,
-                 "dipole_error_vs_fp64": err / induced, "dipole_error_abs": err,
-                 "compared_steps": int(n), "warmup_steps_before_compare": args.warmup,
-                 "per_product_ms": {k: v[1] / max(v[0], 1) for k, v in stats2.items()}}
+        err = np.abs(run["trace"][:n, 1:4] - trace[:n, 1:4]).max()
+        return err / induced, err, n
+
+    forms = []
+    weights = None
+    if args.forms:
+        if not args.no_learned:
+            weights, loss = train_learned_start(s.b)
+        for form in args.forms.split(","):
+            r = gpu_run(s, args, precision=form, taylor_low_from=args.low_from,
+                        inv_start="learned" if weights is not None else "block_jacobi", mlp_weights=weights)
+            e_rel, e_abs, n = compare(r)
+            forms.append({"precision": form, "taylor_low_from": args.low_from,
+                          "inverse_start": "learned" if weights is not None else "block_jacobi",
+                          "steps_per_s": args.steps / r["elapsed"], "speedup_vs_fp64": elapsed / r["elapsed"],
+                          "dipole_error_vs_fp64": e_rel, "dipole_error_abs": e_abs, "compared_steps": int(n),
+                          "inverse_iterations": r["inv_iters"], "inverse_s": r["inv_s"],
+                          "per_product_ms": {k: v[1] / max(v[0], 1) for k, v in r["stats"].items()}})
+            log(f"form {form}: {forms[-1]['steps_per_s']:.3f} steps/s, dipole error {e_rel:.2e}")
+    graph = None
+    if not args.no_graph:
+        g = gpu_run(s, args, use_graph=1)
+        graph = {"steps_per_s": args.steps / g["elapsed"], "speedup_vs_eager": elapsed / g["elapsed"],
+                 "bit_identical_trace": bool(np.array_equal(g["trace"][:, :6], trace[:, :6]))}
+        log(f"graph: {graph}")
+    learned = None
+    if weights is not None:
+        learned = {"inverse_iterations_block_jacobi": base["inv_iters"],
+                   "inverse_s_block_jacobi": base["inv_s"],
+                   "inverse_iterations_learned": forms[0]["inverse_iterations"] if forms else None,
+                   "inverse_s_learned": forms[0]["inverse_s"] if forms else None,
+                   "training_loss": loss,
+                   "training_data": "converged inverses (residual 1e-12) of three 216-atom lattices of the "
+                                    "same recipe with held-out seeds"}
+    batch = batch_leg(args) if args.batch_clusters > 0 else None
 
     # dominant product kernel: the kind with the most kernel time
     dom = max(stats, key=lambda k: stats[k][1])
@@ -218,7 +342,10 @@ def main():
         "per_product_ms": {k: v[1] / max(v[0], 1) for k, v in stats.items()},
         "trace_last": trace[-1, :6].tolist() if len(trace) else None,
         "cpu_baseline": cpu,
-        "mixed_precision": mixed,
+        "precision_forms": forms,
+        "graph": graph,
+        "learned_start": learned,
+        "batch": batch,
     }
     print(json.dumps(out))
 
