@@ -254,6 +254,22 @@ int rtdm_dipole_trace(rtdm_ctx *ctx, double *out, int64_t max_rows, int64_t *row
  * with D = P_P(U^dagger P_P(S U)) - S over R_P's pattern.  Synchronises. */
 int rtdm_unitarity(rtdm_ctx *ctx, double out[3], void *hip_stream);
 
+/* ---- caller-owned device memory ----
+ * Bytes of device memory that hold every buffer of the context now (256-byte
+ * aligned), plus a reserve of 64 MiB for the temporaries of later calls and
+ * the growth of the observable trace.  Call after set-up (rtdm_set_ranges
+ * and the uploads). */
+int rtdm_workspace_size(rtdm_ctx *ctx, size_t *bytes);
+/* Move every device buffer of the context into the caller's region
+ * [ptr, ptr + bytes) (device memory of the context's device, 256-byte
+ * aligned, e.g. a torch.empty(bytes, dtype=uint8) tensor) and free the
+ * library's own allocations; later allocations of the context are slices of
+ * the region (RTDM_E_OOM when it is exhausted).  The region stays owned by
+ * the caller and must outlive the context.  Afterwards the geometry and
+ * ranges are fixed (RTDM_E_STATE); a captured step graph is rebuilt.  Binding
+ * twice is RTDM_E_STATE.  Synchronises the device. */
+int rtdm_bind_workspace(rtdm_ctx *ctx, void *ptr, size_t bytes);
+
 /* External field of Gaussian time profile (Sec. II.B, linear response):
  * E(t) = E0 exp(-(t - t0)^2 / (2 sigma^2)) enters H(t) as the electrons'
  * energy E(t) . (r - r_c) (external potential -E . r, electron charge -1),

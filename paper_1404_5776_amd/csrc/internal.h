@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <stdexcept>
 #include <string>
+#include <unordered_set>
 #include <utility>
 
 #include "rtdm.h"
@@ -30,38 +31,77 @@ struct Error : std::runtime_error {
         if (!(cond)) throw ::rtdm::Error((code), (msg));  \
     } while (0)
 
+// Device memory of one context.  Every buffer the context allocates is
+// registered here.  Without a bound workspace a buffer owns a hipMalloc
+// allocation; once the caller binds a workspace (rtdm_bind_workspace) every
+// registered buffer is moved into it and later allocations are 256-byte
+// aligned slices of it, taken in order (a released slice is not reused).
+struct DBufBase;
+struct DevMem {
+    std::unordered_set<DBufBase *> bufs;
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+};
+// The context of the API call in progress on this thread (null outside calls).
+extern thread_local DevMem *g_devmem;
+
+struct DBufBase {
+    DevMem *mem = nullptr;   // registry the buffer belongs to (null: unregistered)
+    bool in_ws = false;      // the memory is a slice of a bound workspace
+    size_t nbytes = 0;
+    virtual void *raw() const = 0;
+    virtual void set_raw(void *p) = 0;
+    virtual ~DBufBase() = default;
+};
+void *devmem_alloc(DBufBase *b, size_t bytes);
+void devmem_free(DBufBase *b, void *p);
+void devmem_moved(DBufBase *from, DBufBase *to);
+inline size_t devmem_align(size_t bytes) { return (bytes + 255) & ~(size_t)255; }
+
 // Owning device buffer.
 template <class T>
-struct DBuf {
+struct DBuf : DBufBase {
     T *p = nullptr;
     size_t n = 0;
     DBuf() = default;
     DBuf(const DBuf &) = delete;
     DBuf &operator=(const DBuf &) = delete;
-    DBuf(DBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DBuf(DBuf &&o) noexcept { take(o); }
     DBuf &operator=(DBuf &&o) noexcept {
-        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        if (this != &o) { release(); take(o); }
         return *this;
     }
-    ~DBuf() { release(); }
+    ~DBuf() override { release(); }
     void alloc(size_t count) {
         if (count == n && p) return;
         release();
         if (count == 0) return;
-        hipError_t e = hipMalloc(reinterpret_cast<void **>(&p), count * sizeof(T));
-        if (e != hipSuccess) {
-            p = nullptr;
-            (void)hipGetLastError();
-            throw Error(RTDM_E_OOM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
-        }
+        p = static_cast<T *>(devmem_alloc(this, count * sizeof(T)));
         n = count;
     }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) devmem_free(this, p);
         p = nullptr;
         n = 0;
     }
     size_t bytes() const { return n * sizeof(T); }
+    void *raw() const override { return p; }
+    void set_raw(void *q) override { p = static_cast<T *>(q); }
+
+private:
+    void take(DBuf &o) noexcept {
+        p = o.p;
+        n = o.n;
+        mem = o.mem;
+        in_ws = o.in_ws;
+        nbytes = o.nbytes;
+        devmem_moved(&o, this);
+        o.p = nullptr;
+        o.n = 0;
+        o.mem = nullptr;
+        o.nbytes = 0;
+        o.in_ws = false;
+    }
 };
 
 // ---------------------------------------------------------------- kernels
@@ -127,7 +167,7 @@ void launch_hermitize(hipStream_t s, int64_t nnzb, int b, const int32_t *trans, 
 void launch_mulliken(hipStream_t s, int64_t n_atoms, int b, const int64_t *s_ptr,
                      const int32_t *s_trans, const int32_t *s_to_k, const double *sv,
                      const double *kr, double *q);
-// H[diag] = H0[diag] + gain*(1.5 q_cur - 0.5 q_prev - q_ref) on the diagonal elements.
+// H[diag] += gain*(q_a + theta (q_x - q_y) - q_ref) on the diagonal elements.
 void launch_onsite_shift(hipStream_t s, int64_t n_atoms, int b, const int32_t *diag, double gain,
                          const double *q_a, double theta, const double *q_x, const double *q_y,
                          const double *q_ref, double *h);

@@ -28,6 +28,70 @@
 
 #include "internal.h"
 
+namespace rtdm {
+
+thread_local DevMem *g_devmem = nullptr;
+
+void *devmem_alloc(DBufBase *b, size_t bytes)
+{
+    DevMem *m = g_devmem;
+    void *p = nullptr;
+    if (m && m->base) {
+        const size_t off = devmem_align(m->used);
+        RT_CHECK(off + bytes <= m->cap, RTDM_E_OOM,
+                 "bound workspace exhausted: " + std::to_string(bytes) + " more bytes needed");
+        p = m->base + off;
+        m->used = off + bytes;
+        b->in_ws = true;
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error(RTDM_E_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+        }
+        b->in_ws = false;
+    }
+    b->mem = m;
+    b->nbytes = bytes;
+    if (m) m->bufs.insert(b);
+    return p;
+}
+
+void devmem_free(DBufBase *b, void *p)
+{
+    DevMem *m = b->mem;
+    if (b->in_ws) {
+        // the most recent slice (a temporary of the current call) is given back
+        if (m && static_cast<char *>(p) + b->nbytes == m->base + m->used)
+            m->used = (size_t)(static_cast<char *>(p) - m->base);
+    } else {
+        (void)hipFree(p);
+    }
+    if (m) m->bufs.erase(b);
+    b->mem = nullptr;
+    b->nbytes = 0;
+    b->in_ws = false;
+}
+
+void devmem_moved(DBufBase *from, DBufBase *to)
+{
+    if (!to->mem) return;
+    to->mem->bufs.erase(from);
+    to->mem->bufs.insert(to);
+}
+
+}  // namespace rtdm
+
+namespace {
+// Makes a context's registry the current one for the duration of an API call.
+struct DevMemScope {
+    rtdm::DevMem *saved;
+    explicit DevMemScope(rtdm::DevMem *m) : saved(rtdm::g_devmem) { rtdm::g_devmem = m; }
+    ~DevMemScope() { rtdm::g_devmem = saved; }
+};
+constexpr size_t kWorkspaceReserve = size_t(64) << 20;   // per-call temporaries, trace growth
+}  // namespace
+
 using namespace rtdm;
 
 namespace {
@@ -111,6 +175,7 @@ struct MlpState {
 }  // namespace
 
 struct rtdm_ctx {
+    rtdm::DevMem mem;   // first member: destroyed after every buffer registered in it
     int device = 0;
     rtdm_options opt{};
     std::string err;
@@ -762,7 +827,7 @@ double mlp_loss_grad(rtdm_ctx *c, int64_t n, const int32_t *idx, const float *x,
 
 // ================================================================== ABI
 
-#define API_BEGIN try {
+#define API_BEGIN DevMemScope devmem_scope_((c) ? &(c)->mem : nullptr); try {
 #define API_END(c)                                                \
     }                                                             \
     catch (const rtdm::Error &e) {                                \
@@ -874,6 +939,7 @@ int rtdm_set_geometry(rtdm_ctx *c, int64_t n_atoms, const double *xyz, const int
     API_BEGIN
     set_device(c);
     RT_CHECK(n_atoms >= 1 && n_atoms < (int64_t)INT32_MAX && xyz && nbf, RTDM_E_ARG, "bad geometry arguments");
+    RT_CHECK(!c->mem.base, RTDM_E_STATE, "the geometry is fixed once a workspace is bound");
     const int b = nbf[0];
     for (int64_t i = 0; i < n_atoms; ++i)
         RT_CHECK(nbf[i] == b, RTDM_E_UNSUPPORTED, "atoms with different numbers of functions");
@@ -898,6 +964,7 @@ int rtdm_set_ranges(rtdm_ctx *c, double R_hs, double R_p, double R_k)
 {
     if (!c) return RTDM_E_ARG;
     API_BEGIN
+    RT_CHECK(!c->mem.base, RTDM_E_STATE, "the ranges are fixed once a workspace is bound");
     set_device(c);
     require(c->n > 0, "set_geometry first");
     RT_CHECK(std::isfinite(R_hs) && std::isfinite(R_k) && std::isfinite(R_p) && R_hs >= 0 && R_k >= 0,
@@ -1510,6 +1577,56 @@ int rtdm_step(rtdm_ctx *c, double dt, int64_t n_steps, void *stream)
     for (; k < n_steps; ++k) {
         step_body(c, dt, vary || !c->U_valid || c->U_dt != dt, 1, s);
         after_step(k);
+    }
+    API_END(c)
+}
+
+int rtdm_workspace_size(rtdm_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes) return RTDM_E_ARG;
+    API_BEGIN
+    size_t tot = 0;
+    for (auto *b : c->mem.bufs) tot += devmem_align(b->nbytes);
+    *bytes = tot + kWorkspaceReserve;
+    API_END(c)
+}
+
+int rtdm_bind_workspace(rtdm_ctx *c, void *ptr, size_t bytes)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    RT_CHECK(ptr && (reinterpret_cast<uintptr_t>(ptr) & 255) == 0, RTDM_E_ARG,
+             "the workspace must be a 256-byte aligned device pointer");
+    RT_CHECK(!c->mem.base, RTDM_E_STATE, "a workspace is already bound");
+    hipPointerAttribute_t attr;
+    RT_CHECK(hipPointerGetAttributes(&attr, ptr) == hipSuccess && attr.type == hipMemoryTypeDevice &&
+                 attr.device == c->device,
+             RTDM_E_ARG, "the workspace is not device memory of the context's device");
+    std::vector<DBufBase *> list(c->mem.bufs.begin(), c->mem.bufs.end());
+    std::sort(list.begin(), list.end(), [](DBufBase *a, DBufBase *b) { return a->raw() < b->raw(); });
+    size_t need = 0;
+    for (auto *b : list) need += devmem_align(b->nbytes);
+    RT_CHECK(need <= bytes, RTDM_E_OOM, "workspace too small: " + std::to_string(need) + " bytes needed");
+    RT_HIP(hipDeviceSynchronize());
+    drop_graph(c);
+    const bool cur_a = c->q_cur == c->q_a.p;
+    char *base = static_cast<char *>(ptr);
+    size_t off = 0;
+    for (auto *b : list) {
+        void *np = base + off;
+        RT_HIP(hipMemcpy(np, b->raw(), b->nbytes, hipMemcpyDeviceToDevice));
+        RT_HIP(hipFree(b->raw()));
+        b->set_raw(np);
+        b->in_ws = true;
+        off += devmem_align(b->nbytes);
+    }
+    c->mem.base = base;
+    c->mem.cap = bytes;
+    c->mem.used = off;
+    if (c->q_a.p) {
+        c->q_cur = cur_a ? c->q_a.p : c->q_b.p;
+        c->q_prev = cur_a ? c->q_b.p : c->q_a.p;
     }
     API_END(c)
 }

@@ -37,7 +37,7 @@ EXPORTED = ["rtdm_default_options", "rtdm_create", "rtdm_destroy", "rtdm_set_geo
             "rtdm_mlp_set_weights", "rtdm_mlp_get_weights", "rtdm_mlp_collect", "rtdm_mlp_clear",
             "rtdm_mlp_train", "rtdm_mlp_loss_grad", "rtdm_mlp_predict", "rtdm_set_groups",
             "rtdm_apply_kick_groups", "rtdm_group_trace", "rtdm_autotune", "rtdm_set_field",
-            "rtdm_spectrum", "rtdm_last_error"]
+            "rtdm_spectrum", "rtdm_workspace_size", "rtdm_bind_workspace", "rtdm_last_error"]
 
 
 class RtdmError(RuntimeError):
@@ -103,6 +103,8 @@ def load():
         "rtdm_autotune": [P, P, P, P],
         "rtdm_set_field": [P, P, D, D],
         "rtdm_spectrum": [P, I64, P, P, D, I64, P, P, P, P],
+        "rtdm_workspace_size": [P, P],
+        "rtdm_bind_workspace": [P, P, ctypes.c_size_t],
         "rtdm_last_error": [P],
     }
     for name, args in sig.items():
@@ -393,6 +395,16 @@ def rtdm_spectrum(ctx, P0, omega, gamma: float, kappa=None, group: int = -1, str
     return al[..., 0] + 1j * al[..., 1], sw
 
 
+def rtdm_workspace_size(ctx) -> int:
+    n = ctypes.c_size_t()
+    _check(ctx, load().rtdm_workspace_size(ctx, ctypes.byref(n)))
+    return n.value
+
+
+def rtdm_bind_workspace(ctx, ptr: int, nbytes: int) -> None:
+    _check(ctx, load().rtdm_bind_workspace(ctx, ctypes.c_void_p(ptr), nbytes))
+
+
 def rtdm_last_error(ctx) -> str:
     m = load().rtdm_last_error(ctx)
     return m.decode() if m else ""
@@ -429,6 +441,15 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def bind_workspace(self, device: int = 0):
+        """Move the context's device buffers into one torch allocation (kept
+        alive by this object)."""
+        import torch
+        n = rtdm_workspace_size(self.h)
+        self.workspace = torch.empty(n, dtype=torch.uint8, device=f"cuda:{device}")
+        rtdm_bind_workspace(self.h, self.workspace.data_ptr(), n)
+        return n
 
     def load_batch(self, systems, kicks, stream=None):
         """One geometry holding every (system, kick) pair as its own group.

@@ -1,0 +1,61 @@
+"""Caller-owned device memory: after rtdm_bind_workspace every buffer of the
+context lives in one torch allocation, and the results are bit-identical to
+the same run on the library's own allocations."""
+
+import numpy as np
+import pytest
+
+from paper_1404_5776_amd import rtdm, synth
+from tests._common import gpu_context
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(s, bind, use_graph=0, **opts):
+    ctx = gpu_context(s, h_model=s.h_model, use_graph=use_graph, **opts)
+    n = ctx.bind_workspace() if bind else 0
+    rtdm.rtdm_build_inverse(ctx.h)
+    rtdm.rtdm_apply_kick(ctx.h, s.kappa)
+    rtdm.rtdm_step(ctx.h, s.dt, 3)
+    rtdm.rtdm_step(ctx.h, s.dt, 4)
+    out = (rtdm.rtdm_download(ctx.h, "K", s.b), rtdm.rtdm_dipole_trace(ctx.h), rtdm.rtdm_unitarity(ctx.h))
+    if bind:
+        # the geometry and ranges are fixed now; a second binding is refused
+        with pytest.raises(rtdm.RtdmError):
+            rtdm.rtdm_set_ranges(ctx.h, s.R_HS, s.R_P, s.R_K)
+        with pytest.raises(rtdm.RtdmError):
+            rtdm.rtdm_bind_workspace(ctx.h, ctx.workspace.data_ptr(), n)
+    ctx.close()
+    return out, n
+
+
+@pytest.mark.parametrize("which,use_graph", [("cluster_b4", 0), ("lattice_b13", 1)])
+def test_bound_workspace_gives_identical_results(which, use_graph):
+    s = synth.config1() if which == "cluster_b4" else synth.diamond_lattice(
+        (2, 2, 2), 13, 10.0, 16.0, seed=21, k0="local", h_model="mulliken")
+    (K0, tr0, u0), _ = _run(s, False, use_graph)
+    (K1, tr1, u1), n = _run(s, True, use_graph)
+    print(f"{which}: workspace {n / 2**20:.1f} MiB")
+    assert n > (64 << 20)
+    assert np.array_equal(K0, K1)
+    assert np.array_equal(tr0[:, :6], tr1[:, :6])
+    assert np.array_equal(u0, u1)
+
+
+def test_too_small_or_foreign_workspace_is_refused():
+    import torch
+    s = synth.config1()
+    ctx = gpu_context(s)
+    n = rtdm.rtdm_workspace_size(ctx.h)
+    live = n - (64 << 20)               # the size includes a 64 MiB reserve
+    small = torch.empty(live // 2, dtype=torch.uint8, device="cuda:0")
+    with pytest.raises(rtdm.RtdmError) as e:
+        rtdm.rtdm_bind_workspace(ctx.h, small.data_ptr(), small.numel())
+    assert e.value.code == -3          # RTDM_E_OOM
+    host = torch.empty(n, dtype=torch.uint8, pin_memory=True)
+    with pytest.raises(rtdm.RtdmError):
+        rtdm.rtdm_bind_workspace(ctx.h, host.data_ptr(), n)
+    # the context still works on its own allocations
+    rtdm.rtdm_build_inverse(ctx.h)
+    rtdm.rtdm_step(ctx.h, s.dt, 2)
+    ctx.close()
