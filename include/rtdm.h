@@ -91,7 +91,8 @@ typedef enum {
     RTDM_PROD_WU = 3,   /* K' = P_K(W U^dagger)          (Sec. II.A solution)  */
     RTDM_PROD_SX = 4,   /* P_P(S X), also P_P(S U)       (Sec. V.A, Sec. IV)   */
     RTDM_PROD_UV = 5,   /* P_P(U^dagger V)               (Sec. IV, Eq. s_unit) */
-    RTDM_PROD_COUNT = 6
+    RTDM_PROD_ZX = 6,   /* P_K(Z X), Z on R_P            (ground state, rtdm_ground_state) */
+    RTDM_PROD_COUNT = 7
 } rtdm_prod;
 
 /* Arithmetic of the block products of rtdm_step and rtdm_multiply:
@@ -253,6 +254,22 @@ int rtdm_dipole_trace(rtdm_ctx *ctx, double *out, int64_t max_rows, int64_t *row
  * metric): out[0] = ||D||_F/||S||_F, out[1] = mean |D_ab|, out[2] = max |D_ab|
  * with D = P_P(U^dagger P_P(S U)) - S over R_P's pattern.  Synchronises. */
 int rtdm_unitarity(rtdm_ctx *ctx, double out[3], void *hip_stream);
+
+/* Ground-state density matrix of H0 (the state before the kick; Sec. II.A:
+ * K S K = K, Tr(K S) = n_occ) by trace-correcting purification (Niklasson,
+ * 2002) with truncation, into slot K:
+ *   A = P_P(X H0) with X ~ S^-1 (rtdm_build_inverse first);
+ *   Z_0 = (hi I - A) / (hi - lo), [lo, hi] from the Gershgorin row discs of A;
+ *   per iteration Z^2 = P_P(Z Z); stop when |Tr Z - Tr Z^2| <= tol n_occ, or
+ *   when that measure, already below 1e-4 n_occ, stops falling; otherwise
+ *   Z <- Z^2 if Tr Z > n_occ, else Z <- 2 Z - Z^2;
+ *   K = P_K(Z X), then K <- (K + K^T) / 2.
+ * iters, idempotency (the last |Tr Z - Tr Z^2|) and branches (bit k set:
+ * iteration k took 2 Z - Z^2) may be NULL.  RTDM_E_NOCONV after max_iter
+ * iterations.  Resets the trace and the reference charges like a K upload.
+ * Synchronises (two scalars per iteration). */
+int rtdm_ground_state(rtdm_ctx *ctx, double n_occ, double tol, int max_iter, void *hip_stream, int *iters,
+                      double *idempotency, uint64_t *branches);
 
 /* ---- caller-owned device memory ----
  * Bytes of device memory that hold every buffer of the context now (256-byte

@@ -769,6 +769,60 @@ __global__ __launch_bounds__(kT) void k_red_sumsq(int64_t n, const double *__res
     write_partials(v, partials);
 }
 
+// Sum of the diagonal elements of the diagonal blocks (slot 0).
+__global__ __launch_bounds__(kT) void k_red_trace(int64_t n_atoms, int b, const int32_t *__restrict__ diag,
+                                                  const double *__restrict__ v, double *__restrict__ partials)
+{
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x; e < n_atoms * b; e += (int64_t)kRedBlocks * kT) {
+        const int64_t i = e / b;
+        const int a = (int)(e - i * b);
+        acc[0] += v[(int64_t)diag[i] * b * b + a * (b + 1)];
+    }
+    write_partials(acc, partials);
+}
+
+void launch_red_trace(hipStream_t s, int64_t n_atoms, int b, const int32_t *diag, const double *v,
+                      double *partials)
+{
+    hipLaunchKernelGGL(k_red_trace, dim3(kRedBlocks), dim3(kT), 0, s, n_atoms, b, diag, v, partials);
+    RT_HIP(hipGetLastError());
+}
+
+// Gershgorin row discs of a block-sparse matrix: for element row (i, a),
+// lohi = (c - r, c + r) with c = a_(ia,ia) and r = sum over the row's other
+// elements of |a| (blocks of the row in order, each block's row summed first).
+__global__ void k_gershgorin(int64_t n_atoms, int b, const int64_t *__restrict__ rowptr,
+                             const int32_t *__restrict__ diag, const double *__restrict__ v,
+                             double *__restrict__ lohi)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_atoms * b) return;
+    const int64_t i = e / b;
+    const int a = (int)(e - i * b);
+    const int64_t bb = (int64_t)b * b;
+    double rs = 0.0;
+    for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+        double t = 0.0;
+        for (int c = 0; c < b; ++c) t += fabs(v[p * bb + a * b + c]);
+        rs += t;
+    }
+    const double cen = v[(int64_t)diag[i] * bb + a * (b + 1)];
+    const double rad = rs - fabs(cen);
+    lohi[2 * e] = cen - rad;
+    lohi[2 * e + 1] = cen + rad;
+}
+
+void launch_gershgorin(hipStream_t s, int64_t n_atoms, int b, const int64_t *rowptr, const int32_t *diag,
+                       const double *v, double *lohi)
+{
+    const int64_t n = n_atoms * b;
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_gershgorin, dim3((unsigned)((n + kT - 1) / kT)), dim3(kT), 0, s, n_atoms, b, rowptr, diag,
+                       v, lohi);
+    RT_HIP(hipGetLastError());
+}
+
 void launch_red_sumsq(hipStream_t s, int64_t n, const double *x, double *partials)
 {
     hipLaunchKernelGGL(k_red_sumsq, dim3(kRedBlocks), dim3(kT), 0, s, n, x, partials);

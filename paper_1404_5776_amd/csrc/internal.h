@@ -207,6 +207,10 @@ void launch_red_unitarity(hipStream_t s, int64_t nnzb_p, int b, const int32_t *p
 void launch_red_minus_identity(hipStream_t s, int64_t nnzb, int b, const int32_t *rowof,
                                const int32_t *col, const double *v, double *partials);
 void launch_red_sumsq(hipStream_t s, int64_t n, const double *x, double *partials);
+void launch_red_trace(hipStream_t s, int64_t n_atoms, int b, const int32_t *diag, const double *v,
+                      double *partials);
+void launch_gershgorin(hipStream_t s, int64_t n_atoms, int b, const int64_t *rowptr, const int32_t *diag,
+                       const double *v, double *lohi);
 void launch_red_max(hipStream_t s, int64_t n, const double *x, double *partials);
 void launch_red_finish(hipStream_t s, const double *partials, double *out);
 // unit-row update: row[6] = sqrt(sums[0] / s2)

@@ -154,7 +154,7 @@ struct TRec {
     double flops;
 };
 
-const char *kProdName[RTDM_PROD_COUNT] = {"XH", "AT", "UK", "WU", "SX", "UV"};
+const char *kProdName[RTDM_PROD_COUNT] = {"XH", "AT", "UK", "WU", "SX", "UV", "ZX"};
 
 // Learned starting guess: network parameters, Adam state, training samples.
 struct MlpState {
@@ -408,6 +408,7 @@ std::tuple<int, int, int, int, int> prod_key(rtdm_ctx *c, int prod)
     case RTDM_PROD_WU: return {k, p, k, 0, 1};
     case RTDM_PROD_SX: return {hs, p, p, 0, 0};
     case RTDM_PROD_UV: return {p, p, p, 1, 0};
+    case RTDM_PROD_ZX: return {p, p, k, 0, 0};
     }
     throw Error(RTDM_E_ARG, "unknown product kind");
 }
@@ -1578,6 +1579,78 @@ int rtdm_step(rtdm_ctx *c, double dt, int64_t n_steps, void *stream)
         step_body(c, dt, vary || !c->U_valid || c->U_dt != dt, 1, s);
         after_step(k);
     }
+    API_END(c)
+}
+
+int rtdm_ground_state(rtdm_ctx *c, double n_occ, double tol, int max_iter, void *stream, int *iters_out,
+                      double *idem_out, uint64_t *branches_out)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    require(c->ranges_set && c->X_valid && c->uploaded[RTDM_MAT_H0] && c->uploaded[RTDM_MAT_S],
+            "upload S, H0 and build (or upload) the inverse first");
+    RT_CHECK(n_occ > 0 && std::isfinite(n_occ) && tol > 0 && max_iter >= 1 && max_iter <= 64, RTDM_E_ARG,
+             "bad ground-state arguments (max_iter 1..64)");
+    hipStream_t s = (hipStream_t)stream;
+    c->prec = RTDM_PREC_FP64;
+    Mat &A = c->mats[RTDM_MAT_A], &X = c->mats[RTDM_MAT_X], &K = c->mats[RTDM_MAT_K];
+    const Pattern &pp = pat_of(c, R_P), &pk = pat_of(c, R_K);
+    const int64_t ne = elems(c, A);
+    product(c, RTDM_PROD_XH, X, c->mats[RTDM_MAT_H0], A, 1.0, 0.0, s);
+    // Gershgorin bounds of A: per element row, centre and radius; extremes on the host
+    DBuf<double> lohi;
+    lohi.alloc(2 * c->n * c->b);
+    launch_gershgorin(s, c->n, c->b, pp.d_rowptr.p, pp.d_diag.p, A.re.p, lohi.p);
+    std::vector<double> h(2 * c->n * c->b);
+    RT_HIP(hipMemcpyAsync(h.data(), lohi.p, lohi.bytes(), hipMemcpyDeviceToHost, s));
+    RT_HIP(hipStreamSynchronize(s));
+    double lo = h[0], hi = h[1];
+    for (size_t e = 0; e < h.size(); e += 2) {
+        lo = std::min(lo, h[e]);
+        hi = std::max(hi, h[e + 1]);
+    }
+    RT_CHECK(hi > lo, RTDM_E_NUMERIC, "degenerate spectral bounds");
+    // Z_0 = (hi I - A) / (hi - lo)
+    Mat *Z = &c->tau[0], *Z2 = &c->tau[1];
+    launch_axpby(s, ne, -1.0 / (hi - lo), A.re.p, 0.0, nullptr, Z->re.p);
+    launch_add_identity(s, c->n, c->b, pp.d_diag.p, hi / (hi - lo), Z->re.p);
+    double prev = 0.0, idem = 0.0;
+    uint64_t branches = 0;
+    int it = 0;
+    bool done = false;
+    for (; it < max_iter && !done; ++it) {
+        product(c, RTDM_PROD_AT, *Z, *Z, *Z2, 1.0, 0.0, s);
+        launch_red_trace(s, c->n, c->b, pp.d_diag.p, Z->re.p, c->partials.p);
+        reduce_finish(c, s, c->hot_sums.p);
+        launch_red_trace(s, c->n, c->b, pp.d_diag.p, Z2->re.p, c->partials.p);
+        reduce_finish(c, s, c->obs_tmp.p);
+        double tz, tz2;
+        read_scalars(&tz, c->hot_sums.p, 1, s);
+        read_scalars(&tz2, c->obs_tmp.p, 1, s);
+        idem = std::fabs(tz - tz2);
+        if (idem <= tol * n_occ || (it >= 1 && prev < 1e-4 * n_occ && idem >= prev)) {
+            done = true;
+            break;
+        }
+        prev = idem;
+        if (tz > n_occ) {
+            std::swap(Z, Z2);
+        } else {
+            launch_axpby(s, ne, 2.0, Z->re.p, -1.0, Z2->re.p, Z->re.p);
+            branches |= uint64_t(1) << it;
+        }
+    }
+    if (iters_out) *iters_out = done ? it + 1 : it;
+    if (idem_out) *idem_out = idem;
+    if (branches_out) *branches_out = branches;
+    RT_CHECK(done, RTDM_E_NOCONV, "purification did not reach its idempotency tolerance");
+    // K = (P_K(Z X) + P_K(Z X)^T) / 2
+    product(c, RTDM_PROD_ZX, *Z, X, c->Kn, 1.0, 0.0, s);
+    launch_fill(s, elems(c, c->Kn), 0.0, c->Kn.im.p);
+    launch_hermitize(s, pk.nnzb, c->b, pk.d_trans.p, c->Kn.re.p, c->Kn.im.p, K.re.p, K.im.p, c->partials.p);
+    RT_HIP(hipStreamSynchronize(s));
+    after_upload(c, RTDM_MAT_K);
     API_END(c)
 }
 

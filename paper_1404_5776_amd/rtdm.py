@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librtdm.so")
 
 MAT = {"S": 0, "H0": 1, "H": 2, "X": 3, "A": 4, "U": 5, "K": 6, "W": 7}
-PROD = {"XH": 0, "AT": 1, "UK": 2, "WU": 3, "SX": 4, "UV": 5}
+PROD = {"XH": 0, "AT": 1, "UK": 2, "WU": 3, "SX": 4, "UV": 5, "ZX": 6}
 HMODEL = {"fixed": 0, "mulliken": 1}
 INV_START = {"block_jacobi": 0, "cold": 1, "previous": 2, "learned": 3}
 PRECISION = {"fp64": 0, "fp32": 1, "fp32_taylor": 2, "bf16x3": 3, "fp16x2": 4, "bf16x3_taylor": 5,
@@ -37,7 +37,8 @@ EXPORTED = ["rtdm_default_options", "rtdm_create", "rtdm_destroy", "rtdm_set_geo
             "rtdm_mlp_set_weights", "rtdm_mlp_get_weights", "rtdm_mlp_collect", "rtdm_mlp_clear",
             "rtdm_mlp_train", "rtdm_mlp_loss_grad", "rtdm_mlp_predict", "rtdm_set_groups",
             "rtdm_apply_kick_groups", "rtdm_group_trace", "rtdm_autotune", "rtdm_set_field",
-            "rtdm_spectrum", "rtdm_workspace_size", "rtdm_bind_workspace", "rtdm_last_error"]
+            "rtdm_spectrum", "rtdm_workspace_size", "rtdm_bind_workspace", "rtdm_ground_state",
+            "rtdm_last_error"]
 
 
 class RtdmError(RuntimeError):
@@ -105,6 +106,7 @@ def load():
         "rtdm_spectrum": [P, I64, P, P, D, I64, P, P, P, P],
         "rtdm_workspace_size": [P, P],
         "rtdm_bind_workspace": [P, P, ctypes.c_size_t],
+        "rtdm_ground_state": [P, D, D, ctypes.c_int, P, P, P, P],
         "rtdm_last_error": [P],
     }
     for name, args in sig.items():
@@ -403,6 +405,16 @@ def rtdm_workspace_size(ctx) -> int:
 
 def rtdm_bind_workspace(ctx, ptr: int, nbytes: int) -> None:
     _check(ctx, load().rtdm_bind_workspace(ctx, ctypes.c_void_p(ptr), nbytes))
+
+
+def rtdm_ground_state(ctx, n_occ: float, tol: float = 1e-10, max_iter: int = 64, stream=None):
+    """(iterations, last idempotency measure, branch mask); K <- the ground state of H0."""
+    it = ctypes.c_int()
+    idem = ctypes.c_double()
+    br = ctypes.c_uint64()
+    _check(ctx, load().rtdm_ground_state(ctx, float(n_occ), float(tol), int(max_iter), _stream(stream),
+                                         ctypes.byref(it), ctypes.byref(idem), ctypes.byref(br)))
+    return it.value, idem.value, br.value
 
 
 def rtdm_last_error(ctx) -> str:
