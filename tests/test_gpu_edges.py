@@ -1,0 +1,75 @@
+"""Degenerate and ragged inputs on the GPU against the oracle: one atom, atoms
+with no neighbour in any range, a ragged mix of dense and isolated parts,
+zero steps, a zero kick and a zero time step."""
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1404_5776_amd import rtdm, synth
+from tests._common import TOL, dipole_floor, gpu_context, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _system(xyz, b, R_HS, R_K, seed, **kw):
+    return synth.build_system("edge", np.asarray(xyz, dtype=float), b, R_HS, R_K, seed, k0="exact", **kw)
+
+
+def _ragged(b):
+    rng = np.random.default_rng(40)
+    dense = synth.cluster_positions(24, rng)                        # a dense cluster
+    sparse = np.array([[60.0, 0, 0], [80.0, 5.0, 0], [100.0, 0, 7.0]])  # isolated atoms
+    pair = np.array([[0.0, 60.0, 0], [3.0, 61.0, 0]])                # one close pair
+    return _system(np.vstack([dense, sparse, pair]), b, 6.0, 8.0, 41, h_model="mulliken")
+
+
+CASES = {
+    "one_atom_b4": lambda: _system([[0.0, 0.0, 0.0]], 4, 6.0, 8.0, 42),
+    "isolated_b13": lambda: _system([[0.0, 0, 0], [30.0, 0, 0], [0, 40.0, 0]], 13, 6.0, 8.0, 43),
+    "ragged_b4": lambda: _ragged(4),
+    "ragged_b13": lambda: _ragged(13),
+}
+
+
+@pytest.mark.parametrize("which", sorted(CASES))
+def test_degenerate_systems_match_oracle(which):
+    s = CASES[which]()
+    st = O.setup(s)
+    kappa = (0.05, -0.02, 0.01)
+    ctx = gpu_context(s, h_model=s.h_model)
+    it, _ = rtdm.rtdm_build_inverse(ctx.h)
+    rtdm.rtdm_apply_kick(ctx.h, kappa)
+    rtdm.rtdm_step(ctx.h, s.dt, 0)                                  # zero steps: nothing recorded
+    assert rtdm.rtdm_dipole_trace(ctx.h).shape == (0, 7)
+    rtdm.rtdm_step(ctx.h, s.dt, 6)
+    tr = rtdm.rtdm_dipole_trace(ctx.h)
+    K = rtdm.rtdm_download(ctx.h, "K", s.b)
+    X = rtdm.rtdm_download(ctx.h, "X", s.b)
+    ctx.close()
+    ref = O.propagate(st, 6, s.dt, kappa, h_model=s.h_model)
+    assert it == ref.inverse.iters
+    assert rel(X, ref.X.val) <= TOL
+    assert rel(K, ref.K.val) <= TOL
+    q0 = O.mulliken(O.kick(st.K0, st.xyz, kappa), st.S)
+    P0 = O.dipole(q0, st.xyz)
+    induced = np.abs(ref.rows[:, 1:4] - P0).max()
+    assert np.abs(tr[:, 1:4] - ref.rows[:, 1:4]).max() <= TOL * induced + dipole_floor(q0, st.xyz)
+    assert np.abs(tr[:, 4] - ref.rows[:, 4]).max() <= TOL * abs(ref.rows[0, 4])
+
+
+def test_zero_kick_and_zero_step_leave_k_unchanged():
+    s = synth.config1()
+    ctx = gpu_context(s)
+    rtdm.rtdm_build_inverse(ctx.h)
+    K0 = rtdm.rtdm_download(ctx.h, "K", s.b)
+    obs0 = rtdm.rtdm_observables(ctx.h)
+    rtdm.rtdm_apply_kick(ctx.h, (0.0, 0.0, 0.0))
+    assert np.array_equal(rtdm.rtdm_download(ctx.h, "K", s.b), K0)
+    rtdm.rtdm_step(ctx.h, 0.0, 2)                                   # U = I: K' = K, Hermitised
+    K = rtdm.rtdm_download(ctx.h, "K", s.b)
+    tr = rtdm.rtdm_dipole_trace(ctx.h)
+    ctx.close()
+    st = O.setup(s)
+    assert rel(K, O.hermitize(st.K0).val) <= TOL
+    np.testing.assert_allclose(tr[:, 1:5], np.tile(obs0[:4], (2, 1)), rtol=0, atol=1e-10 * abs(obs0[3]))
