@@ -205,6 +205,65 @@ def cpu_baseline(s, target_s: float):
     return rate, total_rows
 
 
+def study_precision(args):
+    """Reduced-precision forms on the 32,768-atom b = 4 lattice at each K
+    cut-off: dipole and Tr(KS) error against the FP64 run on the same GPU,
+    and steps/s.  Prints one JSON line."""
+    from paper_1404_5776_amd import synth
+    forms = ["fp32", "fp32_taylor", "bf16x3", "bf16x3_taylor", "fp16x2", "fp16x2_taylor"]
+    out = {"study": "precision", "workload": "diamond lattice 32768 atoms x 4 functions, R_HS 10 bohr, "
+                                            "Mulliken on-site H, EM + Taylor p=5, dt 0.05",
+           "steps": args.steps, "warmup": args.warmup, "taylor_low_from": args.low_from, "cutoffs": []}
+    for R_K in (float(x) for x in args.cutoffs.split(",")):
+        t = time.time()
+        s = synth.config3(R_K, n_steps=args.steps)
+        log(f"R_K {R_K}: generated in {time.time() - t:.1f} s")
+        base = gpu_run(s, args)
+        tr0, p0 = base["trace"], base["p0"]
+        n = len(tr0)
+        induced = np.abs(tr0[:, 1:4] - p0).max()
+        row = {"R_K": R_K, "fp64_steps_per_s": args.steps / base["elapsed"],
+               "triples_per_product": {k: v[1] for k, v in base["sched"].items()}, "forms": {}}
+        for form in forms:
+            r = gpu_run(s, args, precision=form, taylor_low_from=args.low_from)
+            tr = r["trace"]
+            row["forms"][form] = {
+                "steps_per_s": args.steps / r["elapsed"],
+                "dipole_error_vs_fp64": float(np.abs(tr[:n, 1:4] - tr0[:n, 1:4]).max() / induced),
+                "trks_error_vs_fp64": float(np.abs(tr[:n, 4] - tr0[:n, 4]).max() / abs(tr0[0, 4]))}
+            log(f"R_K {R_K} {form}: {row['forms'][form]}")
+        out["cutoffs"].append(row)
+    print(json.dumps(out))
+
+
+def study_learned(args):
+    """The 65,536-atom b = 4 lattice (R_K 12): iterations and time of the
+    inverse build from the block-Jacobi and from the learned start (network
+    trained on three held-out 216-atom lattices of the R_K 16 recipe), and
+    steps/s with and without the build at 10 and 100 steps.  One JSON line."""
+    import torch
+    from paper_1404_5776_amd import synth
+    torch.cuda.init()                     # torch's runtime first: it provides the streams
+    t = time.time()
+    s = synth.config5(n_steps=args.steps)
+    log(f"{s.name}: generated in {time.time() - t:.1f} s")
+    w, loss = train_learned_start(s.b)
+    base = gpu_run(s, args)
+    lrn = gpu_run(s, args, inv_start="learned", mlp_weights=w)
+    step_s = base["elapsed"] / args.steps
+    out = {"study": "learned", "workload": "diamond lattice 65536 atoms x 4 functions, R_HS 10, R_K 12 bohr, "
+                                          "Mulliken on-site H, EM + Taylor p=5, dt 0.05",
+           "training_loss": loss, "steps": args.steps,
+           "block_jacobi": {"iterations": base["inv_iters"], "inverse_s": base["inv_s"]},
+           "learned": {"iterations": lrn["inv_iters"], "inverse_s": lrn["inv_s"]},
+           "steps_per_s": args.steps / base["elapsed"],
+           "dipole_trace_identical_within": float(np.abs(lrn["trace"][:, 1:4] - base["trace"][:, 1:4]).max())}
+    for n in (10, 100):
+        out[f"steps_per_s_with_build_n{n}"] = {
+            "block_jacobi": n / (base["inv_s"] + n * step_s), "learned": n / (lrn["inv_s"] + n * step_s)}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -225,6 +284,10 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (read + write) before the workload, "
                          "so hardware byte counters can be scaled against a known size")
+    ap.add_argument("--study", choices=["precision", "learned"], default=None,
+                    help="instead of the benchmark line: the precision sweep on the 32,768-atom lattice, or "
+                         "the learned inverse start on the 65,536-atom lattice (one JSON line each)")
+    ap.add_argument("--cutoffs", default="8,12,16,20", help="K cut-offs of the precision study (bohr)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -233,6 +296,13 @@ def main():
                                    "domain decomposition with halo exchange) is a design, not built",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+
+    if args.study == "precision":
+        study_precision(args)
+        return
+    if args.study == "learned":
+        study_learned(args)
+        return
 
     if args.calibrate_copy:
         import torch
