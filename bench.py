@@ -372,16 +372,31 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
+        from oracle import oracle as O
         t = time.time()
-        rate, rows = cpu_baseline(s, args.cpu_seconds)
-        # oracle seconds per step = sum over the step's products of triples / (triples per second)
+        threads = O.set_threads(0)
         per_step = {"XH": 1, "AT": 4, "UK": 1, "WU": 1}
-        sec = sum(per_step[k] * sched[k][1] / rate[k] for k in per_step)
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        cpu = {"value": 1.0 / sec, "unit": "steps/s", "cores": threads, "kind": "oracle",
+        b3 = float(s.b) ** 3
+        flops_per_trip = {k: 8 * b3 for k in per_step}       # the oracle multiplies complex128 blocks
+
+        def rate_of(seconds):
+            rate, rows = cpu_baseline(s, seconds)
+            sec = sum(per_step[k] * sched[k][1] / rate[k] for k in per_step)
+            gf = sum(per_step[k] * sched[k][1] * flops_per_trip[k] for k in per_step) / sec / 1e9
+            return 1.0 / sec, gf, rows
+
+        v_all, gf_all, rows = rate_of(args.cpu_seconds)
+        O.set_threads(1)
+        v_one, gf_one, rows1 = rate_of(args.cpu_seconds / 8)
+        O.set_threads(threads)
+        cpu = {"value": v_all, "unit": "steps/s", "cores": threads, "kind": "oracle",
                "sample": f"oracle masked block products (complex128) on {rows} output atom rows of the "
                          f"XH, AT, UK and WU products of this workload, triples/s per kind scaled by the "
-                         f"per-step triple counts (1 XH + 4 AT + 1 UK + 1 WU); {time.time() - t:.0f} s wall"}
+                         f"per-step triple counts (1 XH + 4 AT + 1 UK + 1 WU); {time.time() - t:.0f} s wall "
+                         f"with the single-thread sample",
+               "gflops": gf_all, "single_thread": {"value": v_one, "gflops": gf_one, "rows": rows1},
+               "gflops_note": "complex128 flops of the oracle's products (8 b^3 per triple), the GPU's "
+                              "real-specialised count is lower"}
 
     out = {
         "metric": METRIC,

@@ -28,6 +28,7 @@
  * Cut-off patterns are symmetric ((i,j) kept iff (j,i) kept), which the
  * conjugate-transpose lookups below rely on; the Python side asserts it.
  */
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -167,4 +168,12 @@ int64_t oracle_spgemm(int64_t n, int b,
         free(slot);
     }
     return triples;
+}
+
+/* Threads of the OpenMP regions above (timing of the oracle at a fixed
+ * thread count); returns the count in force afterwards. */
+int oracle_set_threads(int n)
+{
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
 }

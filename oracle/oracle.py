@@ -80,8 +80,15 @@ def lib():
         L.oracle_spgemm.argtypes = [i64, ctypes.c_int, P, P, P, ctypes.c_int, P, P, P, ctypes.c_int,
                                     P, P, P, ctypes.c_double, ctypes.c_double, i64, i64]
         L.oracle_spgemm.restype = i64
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_threads.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> int:
+    """OpenMP threads of the compiled oracle (0: keep); returns the count in force."""
+    return int(lib().oracle_set_threads(int(n)))
 
 
 def _ptr(a: np.ndarray):
