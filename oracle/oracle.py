@@ -41,6 +41,20 @@ Where the paper is silent the readings are (each listed in the design notes):
    diagonal block, q_i = Re sum_j tr(K_ij S_ji), q_ref = q(K0) before the kick.
 10. Kick K_ij <- exp(i kappa . (r_i - r_j)) K_ij.
 11. Dipole P = -sum_i (r_i - r_c) q_i with r_c the centroid of the atoms.
+12. ETRS: each half-step exponential is its own truncated Taylor series and
+    their product is truncated to P_U; M4: the commutator is the difference
+    of the two truncated products, exp(M) the complex recursion
+    T_n = P_U(M T_{n-1}) / n.
+13. Charges at a time point t + theta dt: extrapolated from q(t - dt), q(t);
+    in corrector passes interpolated between q(t) and the q(t + dt) of the
+    previous pass.
+14. Field: the electrons carry the energy +E(t).(r - r_c) in the position
+    model <i|r|j> = (r_i + r_j)/2 S_ij; a kick exp(i kappa.r) is then the
+    impulsive field of integral -kappa.
+15. Spectrum: rectangle-rule damped transform over the recorded steps,
+    alpha_jj = F[P_j - P_j(0)] / F[E_j], F[E] = -kappa for a kick.
+16. Ground state: trace-correcting purification of P(S^-1 H) from Gershgorin
+    bounds, K = (P_K(Z S^-1) + transpose) / 2.
 """
 
 from __future__ import annotations

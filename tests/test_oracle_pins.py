@@ -414,3 +414,35 @@ def test_mlp_oracle_gradient_matches_finite_differences():
               mlp.loss_grad(wm, x, t, n_in, n_out, fp16=False)[0]) / (2 * eps)
         assert abs(fd - g[k]) <= 1e-7 * max(1.0, abs(g[k]))
     assert abs(loss - ((mlp.forward(w, x, n_in, n_out, False)[0] - t) ** 2).mean()) < 1e-15
+
+
+def test_mlp_descriptors_swap_symmetry_and_first_order_start():
+    """Descriptor of block (j, i) = (-vector, same length, S_ij^T) of block (i, j);
+    the first-order start 2I - S is the one-term Neumann inverse of S = I + E,
+    so its error against LAPACK's inverse falls like |E|^2."""
+    from oracle import mlp
+    s = _tiny_system(n=12, b=3, R_HS=6.0, R_K=9.0, seed=31)
+    st = O.setup(s)
+    d = mlp.descriptors(st.xyz, st.S, s.R_HS)
+    t = st.S.pat.transpose_index()
+    b = s.b
+    np.testing.assert_array_equal(d[t, :3], -d[:, :3])
+    np.testing.assert_array_equal(d[t, 3], d[:, 3])
+    Sb = d[:, 4:].reshape(-1, b, b)
+    np.testing.assert_array_equal(Sb[t], np.transpose(Sb, (0, 2, 1)))
+    assert np.allclose(np.linalg.norm(d[:, :3], axis=1), d[:, 3])
+    # Neumann: scale the off-identity part of S by h; error of 2I - S vs S^-1 ~ h^2
+    Sd = st.S.to_dense().real
+    E = Sd - np.eye(Sd.shape[0])
+    errs = []
+    for h in (0.2, 0.1, 0.05):
+        Sh = O.BSM(st.S.pat, b, st.S.val.copy())
+        dg = st.S.pat.index(np.arange(st.S.pat.n), np.arange(st.S.pat.n))
+        Sh.val = h * Sh.val
+        Sh.val[dg] += (1 - h) * np.eye(b)
+        X0 = np.zeros_like(Sd)
+        blocks = mlp.first_order_start(Sh)
+        for p, (i, j) in enumerate(zip(Sh.pat.rows(), Sh.pat.col)):
+            X0[i * b:(i + 1) * b, j * b:(j + 1) * b] = blocks[p]
+        errs.append(np.abs(X0 - np.linalg.inv(np.eye(Sd.shape[0]) + h * E)).max())
+    assert 3.0 < errs[0] / errs[1] < 5.0 and 3.0 < errs[1] / errs[2] < 5.0
