@@ -163,6 +163,8 @@ typedef struct {
     int propagator;        /* RTDM_PROP_* (default EM) */
     int sc_steps;          /* steps after a kick with corrector passes (default 0) */
     int sc_iters;          /* corrector passes per such step (default 2) */
+    double unit_tol;       /* > 0: at each unitarity check, stop with RTDM_E_NUMERIC when the relative
+                              unitarity error exceeds it or Tr(KS) is not finite (default 0: record only) */
 } rtdm_options;
 
 /* Fill *opt with the defaults above.  Never fails for a non-NULL opt. */
@@ -241,7 +243,8 @@ int rtdm_step(rtdm_ctx *ctx, double dt, int64_t n_steps, void *hip_stream);
  * out[3] Tr(K S) (Sec. IV), out[4] ||K'-K'^dagger||_F/||K'||_F of the last
  * step's product before Hermitisation, out[5] relative unitarity error
  * ||P_P(U^dagger P_P(S U)) - S||_F / ||S||_F of the current U (Eq. s_unit,
- * computed now).  Synchronises. */
+ * computed now).  RTDM_E_NUMERIC if any of out[0..4] is not finite.
+ * Synchronises. */
 int rtdm_observables(rtdm_ctx *ctx, double out[6], void *hip_stream);
 
 /* Copy the trace recorded since the last kick: row s (s = 0..rows-1) holds
@@ -270,6 +273,17 @@ int rtdm_unitarity(rtdm_ctx *ctx, double out[3], void *hip_stream);
  * Synchronises (two scalars per iteration). */
 int rtdm_ground_state(rtdm_ctx *ctx, double n_occ, double tol, int max_iter, void *hip_stream, int *iters,
                       double *idempotency, uint64_t *branches);
+
+/* ---- checkpoint and resume (for long runs split over processes) ----
+ * The propagation state beside the matrices: state[0] the time since the
+ * kick, state[1] the step count since the kick, then the Mulliken charges
+ * q(t), q(t - dt) and q_ref (n_atoms each): 2 + 3 n_atoms doubles (host).
+ * Resume = upload S, H0, K (rtdm_download of K at the checkpoint), build or
+ * upload the inverse, rtdm_set_state: the following steps then repeat the
+ * uninterrupted run bit for bit.  rtdm_set_state starts a new trace.  Both
+ * synchronise. */
+int rtdm_get_state(rtdm_ctx *ctx, double *state, int64_t n, void *hip_stream);
+int rtdm_set_state(rtdm_ctx *ctx, const double *state, int64_t n, void *hip_stream);
 
 /* ---- caller-owned device memory ----
  * Bytes of device memory that hold every buffer of the context now (256-byte

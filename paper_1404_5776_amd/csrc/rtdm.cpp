@@ -864,6 +864,7 @@ int rtdm_default_options(rtdm_options *opt)
     opt->propagator = RTDM_PROP_EM;
     opt->sc_steps = 0;
     opt->sc_iters = 2;
+    opt->unit_tol = 0.0;
     return RTDM_OK;
 }
 
@@ -898,6 +899,7 @@ int rtdm_create(rtdm_ctx **out, int hip_device, const rtdm_options *opt)
     RT_CHECK(c->opt.propagator == RTDM_PROP_EM || c->opt.precision == RTDM_PREC_FP64, RTDM_E_UNSUPPORTED,
              "ETRS and M4 need RTDM_PREC_FP64");
     RT_CHECK(c->opt.sc_steps >= 0 && c->opt.sc_iters >= 0, RTDM_E_ARG, "sc_steps / sc_iters < 0");
+    RT_CHECK(c->opt.unit_tol >= 0.0, RTDM_E_ARG, "unit_tol < 0");
     set_device(c);
     c->partials.alloc(kRedBlocks * 4);
     c->herm_sums.alloc(4);
@@ -1531,6 +1533,19 @@ int rtdm_step(rtdm_ctx *c, double dt, int64_t n_steps, void *stream)
             c->prec = RTDM_PREC_FP64;               // the unitarity check stays FP64
             unitarity_sums(c, s);
             launch_unit_to_row(s, c->unit_sums.p, c->s_norm2.p, c->obs.p + 8 * c->obs_rows);
+            if (c->opt.unit_tol > 0.0) {             // monitor: one synchronising read per check
+                double row[8];
+                read_scalars(row, c->obs.p + 8 * c->obs_rows, 8, s);
+                const bool bad = !std::isfinite(row[4]) || !std::isfinite(row[6]) || row[6] > c->opt.unit_tol;
+                if (bad) {
+                    c->obs_rows++;
+                    c->step_count++;
+                    throw Error(RTDM_E_NUMERIC, "step " + std::to_string(c->step_count) + ": unitarity error " +
+                                                    std::to_string(row[6]) + " (tolerance " +
+                                                    std::to_string(c->opt.unit_tol) + ") or Tr(KS) " +
+                                                    std::to_string(row[4]));
+                }
+            }
         }
         if (c->obs_rows == 0) c->trace_dt = dt;
         else if (dt != c->trace_dt) c->trace_dt_mixed = true;
@@ -1922,6 +1937,51 @@ int rtdm_observables(rtdm_ctx *c, double out[6], void *stream)
         read_scalars(s2, c->s_norm2.p, 4, s);
         out[5] = std::sqrt(u[0] / s2[0]);
     }
+    for (int k = 0; k < 5; ++k)
+        RT_CHECK(std::isfinite(out[k]), RTDM_E_NUMERIC, "non-finite observable: the propagation has blown up");
+    API_END(c)
+}
+
+int rtdm_get_state(rtdm_ctx *c, double *out, int64_t n, void *stream)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    require(c->ranges_set && c->uploaded[RTDM_MAT_K] && c->uploaded[RTDM_MAT_S], "upload S and K first");
+    RT_CHECK(out && n == 2 + 3 * c->n, RTDM_E_ARG, "the state holds 2 + 3 n_atoms doubles");
+    hipStream_t s = (hipStream_t)stream;
+    ensure_charges(c, s);
+    out[0] = c->t_now;
+    out[1] = (double)c->step_count;
+    RT_HIP(hipMemcpyAsync(out + 2, c->q_cur, c->n * sizeof(double), hipMemcpyDeviceToHost, s));
+    RT_HIP(hipMemcpyAsync(out + 2 + c->n, c->q_prev, c->n * sizeof(double), hipMemcpyDeviceToHost, s));
+    RT_HIP(hipMemcpyAsync(out + 2 + 2 * c->n, c->q_ref.p, c->n * sizeof(double), hipMemcpyDeviceToHost, s));
+    RT_HIP(hipStreamSynchronize(s));
+    API_END(c)
+}
+
+int rtdm_set_state(rtdm_ctx *c, const double *in, int64_t n, void *stream)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    require(c->ranges_set && c->uploaded[RTDM_MAT_K] && c->uploaded[RTDM_MAT_S], "upload S and K first");
+    RT_CHECK(in && n == 2 + 3 * c->n, RTDM_E_ARG, "the state holds 2 + 3 n_atoms doubles");
+    RT_CHECK(std::isfinite(in[0]) && in[1] >= 0 && in[1] == std::floor(in[1]), RTDM_E_ARG, "bad time or step count");
+    hipStream_t s = (hipStream_t)stream;
+    RT_HIP(hipMemcpyAsync(c->q_cur, in + 2, c->n * sizeof(double), hipMemcpyHostToDevice, s));
+    RT_HIP(hipMemcpyAsync(c->q_prev, in + 2 + c->n, c->n * sizeof(double), hipMemcpyHostToDevice, s));
+    RT_HIP(hipMemcpyAsync(c->q_ref.p, in + 2 + 2 * c->n, c->n * sizeof(double), hipMemcpyHostToDevice, s));
+    RT_HIP(hipStreamSynchronize(s));
+    c->t_now = in[0];
+    c->step_count = (int64_t)in[1];
+    c->charges_valid = true;
+    c->q_ref_valid = true;
+    c->obs_rows = 0;
+    c->obs_reset_pending = true;
+    c->trace_dt_mixed = false;
+    c->herm_valid = false;
+    c->U_valid = false;
     API_END(c)
 }
 

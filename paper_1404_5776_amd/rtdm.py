@@ -38,7 +38,7 @@ EXPORTED = ["rtdm_default_options", "rtdm_create", "rtdm_destroy", "rtdm_set_geo
             "rtdm_mlp_train", "rtdm_mlp_loss_grad", "rtdm_mlp_predict", "rtdm_set_groups",
             "rtdm_apply_kick_groups", "rtdm_group_trace", "rtdm_autotune", "rtdm_set_field",
             "rtdm_spectrum", "rtdm_workspace_size", "rtdm_bind_workspace", "rtdm_ground_state",
-            "rtdm_last_error"]
+            "rtdm_get_state", "rtdm_set_state", "rtdm_last_error"]
 
 
 class RtdmError(RuntimeError):
@@ -52,7 +52,8 @@ class Options(ctypes.Structure):
                 ("precision", ctypes.c_int), ("h_model", ctypes.c_int), ("h_gain", ctypes.c_double),
                 ("inv_start", ctypes.c_int), ("inv_tol", ctypes.c_double),
                 ("inv_max_iter", ctypes.c_int), ("taylor_low_from", ctypes.c_int), ("use_graph", ctypes.c_int),
-                ("propagator", ctypes.c_int), ("sc_steps", ctypes.c_int), ("sc_iters", ctypes.c_int)]
+                ("propagator", ctypes.c_int), ("sc_steps", ctypes.c_int), ("sc_iters", ctypes.c_int),
+                ("unit_tol", ctypes.c_double)]
 
 
 _lib = None
@@ -107,6 +108,8 @@ def load():
         "rtdm_workspace_size": [P, P],
         "rtdm_bind_workspace": [P, P, ctypes.c_size_t],
         "rtdm_ground_state": [P, D, D, ctypes.c_int, P, P, P, P],
+        "rtdm_get_state": [P, P, I64, P],
+        "rtdm_set_state": [P, P, I64, P],
         "rtdm_last_error": [P],
     }
     for name, args in sig.items():
@@ -415,6 +418,17 @@ def rtdm_ground_state(ctx, n_occ: float, tol: float = 1e-10, max_iter: int = 64,
     _check(ctx, load().rtdm_ground_state(ctx, float(n_occ), float(tol), int(max_iter), _stream(stream),
                                          ctypes.byref(it), ctypes.byref(idem), ctypes.byref(br)))
     return it.value, idem.value, br.value
+
+
+def rtdm_get_state(ctx, n_atoms: int, stream=None) -> np.ndarray:
+    out = np.zeros(2 + 3 * n_atoms)
+    _check(ctx, load().rtdm_get_state(ctx, _p(out), out.size, _stream(stream)))
+    return out
+
+
+def rtdm_set_state(ctx, state, stream=None) -> None:
+    st = np.ascontiguousarray(state, dtype=np.float64)
+    _check(ctx, load().rtdm_set_state(ctx, _p(st), st.size, _stream(stream)))
 
 
 def rtdm_last_error(ctx) -> str:

@@ -7,6 +7,7 @@ are chosen so that a dropped term, a wrong sign, a transposed operand or an
 off-by-one in the Taylor order fails at least one of them.
 """
 
+import dataclasses
 import math
 
 import numpy as np
@@ -446,3 +447,31 @@ def test_mlp_descriptors_swap_symmetry_and_first_order_start():
             X0[i * b:(i + 1) * b, j * b:(j + 1) * b] = blocks[p]
         errs.append(np.abs(X0 - np.linalg.inv(np.eye(Sd.shape[0]) + h * E)).max())
     assert 3.0 < errs[0] / errs[1] < 5.0 and 3.0 < errs[1] / errs[2] < 5.0
+
+
+def test_atom_relabelling_and_rigid_rotation_invariance():
+    """The physics does not depend on atom labels, and rotating the geometry
+    together with the kick rotates the dipole trace (Mulliken H, truncated)."""
+    s = _tiny_system(n=12, b=3, R_HS=6.0, R_K=9.0, seed=32)
+    kappa = np.array([0.05, -0.03, 0.02])
+    st = O.setup(s)
+    ref = O.propagate(st, 8, 0.05, kappa, h_model="mulliken").rows
+    # relabel: reverse the atom order (blocks follow their atoms)
+    perm = np.arange(s.n_atoms)[::-1]
+    inv = np.argsort(perm)
+
+    def relabel(m):
+        return synth.BlockCOO(inv[m.rows].astype(np.int32), inv[m.cols].astype(np.int32), m.data)
+
+    s2 = dataclasses.replace(s, xyz=s.xyz[perm], S=relabel(s.S), H0=relabel(s.H0), K0=relabel(s.K0))
+    got = O.propagate(O.setup(s2), 8, 0.05, kappa, h_model="mulliken").rows
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+    # rigid rotation about an arbitrary axis, kick rotated with it
+    th = 0.7
+    a = np.array([1.0, 2.0, -1.0]) / math.sqrt(6.0)
+    Kx = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+    Rm = np.eye(3) + math.sin(th) * Kx + (1 - math.cos(th)) * Kx @ Kx
+    s3 = dataclasses.replace(s, xyz=s.xyz @ Rm.T)
+    rot = O.propagate(O.setup(s3), 8, 0.05, Rm @ kappa, h_model="mulliken").rows
+    np.testing.assert_allclose(rot[:, 1:4], ref[:, 1:4] @ Rm.T, rtol=0, atol=1e-10 * np.abs(ref[:, 1:4]).max())
+    np.testing.assert_allclose(rot[:, 4], ref[:, 4], rtol=1e-12)
