@@ -140,6 +140,9 @@ void launch_spgemm(hipStream_t s, const SpgemmArgs &a);
 // operand's op(B)[m][r] at m*B + r (conj_b: conjugated) and the output written
 // column-major if out_col_major.  b = 13, FP64.
 void launch_spgemm_cm(hipStream_t s, const SpgemmArgs &a, int conj_b, int out_col_major);
+// Split-precision (BF16X3 / FP16X2) step product of real operands: column-
+// major left operand, row-major right operand, row-major FP64 output.
+void launch_spgemm_cm_split(hipStream_t s, const SpgemmArgs &a);
 // Real FP32 step product: a32 column-major left operand, b32 row-major right
 // operand, c32 = alpha * P_C(A B) row-major FP32 (b = 13).
 void launch_spgemm_r32(hipStream_t s, const SpgemmArgs &a, const float *a32, const float *b32, float *c32,

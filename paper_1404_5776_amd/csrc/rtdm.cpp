@@ -515,6 +515,8 @@ void product(rtdm_ctx *c, int prod, const Mat &A, const Mat &B, Mat &C, double a
     }
 }
 
+bool is_split(int prec) { return prec == RTDM_PREC_BF16X3 || prec == RTDM_PREC_FP16X2; }
+
 // Step product with the column-major copy Acm of the left operand (see
 // launch_spgemm_cm); same schedule, timing and flop accounting as product().
 void product_cm(rtdm_ctx *c, int prod, const Mat &Acm, const Mat &B, Mat &C, int conj_b, int out_cm,
@@ -539,17 +541,33 @@ void product_cm(rtdm_ctx *c, int prod, const Mat &Acm, const Mat &B, Mat &C, int
     a.zero = c->zero.p;
     a.order = S.order.p;
     a.wpb = c->wpb;
+    a.precision = c->prec;
     RT_CHECK(C.cplx || (!Acm.cplx && !B.cplx), RTDM_E_UNSUPPORTED, "complex product into a real matrix");
+    const bool split = is_split(c->prec);
+    if (c->prec == RTDM_PREC_FP16X2) {
+        // max |x| of both (real) operands for the power-of-two scales
+        const Mat *ops[2] = {&Acm, &B};
+        for (int k = 0; k < 2; ++k) {
+            launch_red_max(s, elems(c, *ops[k]), ops[k]->re.p, c->partials.p);
+            launch_red_finish(s, c->partials.p, c->f16_max.p + 8 * k);
+            launch_fill(s, 4, 0.0, c->f16_max.p + 8 * k + 4);
+        }
+        a.maxabs = c->f16_max.p;
+    }
+    auto go = [&]() {
+        if (split) launch_spgemm_cm_split(s, a);
+        else launch_spgemm_cm(s, a, conj_b, out_cm);
+    };
     if (c->timing && !c->capturing) {
         const size_t k = 2 * c->recs.size();
         RT_HIP(hipEventRecord(event_at(c, k), s));
-        launch_spgemm_cm(s, a, conj_b, out_cm);
+        go();
         RT_HIP(hipEventRecord(event_at(c, k + 1), s));
         const double b3 = (double)c->b * c->b * c->b;
         const double sub = (Acm.cplx ? 2.0 : 1.0) * (B.cplx ? 2.0 : 1.0);
         c->recs.push_back({prod, (int)k, (double)S.ntrip * 2.0 * b3 * sub});
     } else {
-        launch_spgemm_cm(s, a, conj_b, out_cm);
+        go();
     }
 }
 
@@ -561,7 +579,7 @@ void transpose_into(rtdm_ctx *c, const Mat &M, Mat &out, hipStream_t s)
     if (M.cplx) launch_transpose_blocks(s, nb, c->b, M.im.p, out.im.p);
 }
 
-bool use_cm(rtdm_ctx *c) { return c->b == 13 && c->prec == RTDM_PREC_FP64; }
+bool use_cm(rtdm_ctx *c) { return c->b == 13 && (c->prec == RTDM_PREC_FP64 || c->prec == RTDM_PREC_FP32); }
 
 void reduce_finish(rtdm_ctx *c, hipStream_t s, double *out) { launch_red_finish(s, c->partials.p, out); }
 
@@ -669,7 +687,11 @@ void build_propagator(rtdm_ctx *c, double dt, hipStream_t s)
             Mat &dst = c->tau[1 - cur];
             const int saved = c->prec;
             if (k >= n0) c->prec = low;
-            if (use_cm(c)) product_cm(c, RTDM_PROD_AT, c->Ac, src, dst, 0, 0, dt / k, s);
+            // the *_TAYLOR split forms keep the step in FP64, so the column-major A is current
+            const bool split_cm = c->b == 13 && is_split(c->prec) &&
+                                  (c->opt.precision == RTDM_PREC_BF16X3_TAYLOR ||
+                                   c->opt.precision == RTDM_PREC_FP16X2_TAYLOR);
+            if (use_cm(c) || split_cm) product_cm(c, RTDM_PROD_AT, c->Ac, src, dst, 0, 0, dt / k, s);
             else product(c, RTDM_PROD_AT, A, src, dst, dt / k, 0.0, s);
             c->prec = saved;
             add_term(k, dst.re.p, nullptr);

@@ -299,7 +299,10 @@ __global__ __launch_bounds__(256) void k_spgemm_kc(
 // compile-time offset; lanes without data (rows r >= B, or past the last
 // triple) point at a zero block.  Conjugation is a sign applied to the
 // accumulated imaginary products at the end.
-template <int B, bool AC, bool BC, int CJA, int CJB, int LC, int WPB = 4>
+//
+// T = float runs the same dataflow on the FP32 matrix cores (operands rounded
+// to FP32 on load, FP32 accumulation).
+template <int B, bool AC, bool BC, int CJA, int CJB, int LC, int WPB = 4, class T = double>
 __global__ __launch_bounds__(64 * WPB) void k_spgemm_q4(
     int64_t nout, const int64_t *__restrict__ off, const int2 *__restrict__ trip,
     const double *__restrict__ ar, const double *__restrict__ ai, const double *__restrict__ br,
@@ -316,7 +319,7 @@ __global__ __launch_bounds__(64 * WPB) void k_spgemm_q4(
     const bool rv = r < B;
     const int64_t t0 = off[c];
     const int nt = (int)(off[c + 1] - t0);
-    typedef Mfma16<double>::acc_t acc_t;
+    typedef typename Mfma16<T>::acc_t acc_t;
     acc_t rr = {0, 0, 0, 0}, ii = {0, 0, 0, 0}, ri = {0, 0, 0, 0}, ir = {0, 0, 0, 0};
     for (int g = 0; g < nt; g += 4) {
         const double *pa = zero, *pai = zero, *pb = zero, *pbi = zero;
@@ -330,21 +333,21 @@ __global__ __launch_bounds__(64 * WPB) void k_spgemm_q4(
         }
 #pragma unroll
         for (int st = 0; st < B; ++st) {
-            const double xa = pa[st * B], xb = pb[st * B];
-            rr = Mfma16<double>::step(xa, xb, rr);
-            if (AC && BC) ii = Mfma16<double>::step(pai[st * B], pbi[st * B], ii);
-            if (BC) ri = Mfma16<double>::step(xa, pbi[st * B], ri);
-            if (AC) ir = Mfma16<double>::step(pai[st * B], xb, ir);
+            const T xa = (T)pa[st * B], xb = (T)pb[st * B];
+            rr = Mfma16<T>::step(xa, xb, rr);
+            if (AC && BC) ii = Mfma16<T>::step((T)pai[st * B], (T)pbi[st * B], ii);
+            if (BC) ri = Mfma16<T>::step(xa, (T)pbi[st * B], ri);
+            if (AC) ir = Mfma16<T>::step((T)pai[st * B], xb, ir);
         }
     }
     // op(A)_im = sa * A_im, op(B)_im = sb * B_im
     constexpr double sa = CJA ? -1.0 : 1.0, sb = CJB ? -1.0 : 1.0;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        const int row = Mfma16<double>::row(e, q), col = r;
+        const int row = Mfma16<T>::row(e, q), col = r;
         if (row < B && col < B) {
-            const double re = rr[e] - (sa * sb) * ii[e];
-            const double im = sb * ri[e] + sa * ir[e];
+            const double re = (double)rr[e] - (sa * sb) * (double)ii[e];
+            const double im = sb * (double)ri[e] + sa * (double)ir[e];
             const int64_t o = c * BB + (LC ? col * B + row : row * B + col);
             cr[o] = alr * re - ali * im;
             if (ci) ci[o] = alr * im + ali * re;
@@ -542,8 +545,10 @@ template <> struct Split16<0> {
     typedef __bf16 v8 __attribute__((ext_vector_type(8)));
     static __device__ inline void split(double x, float, __bf16 &hi, __bf16 &lo)
     {
-        hi = (__bf16)(float)x;
-        lo = (__bf16)(float)(x - (double)(float)hi);
+        float xf = (float)x;
+        asm volatile("" : "+v"(xf));
+        hi = (__bf16)xf;
+        lo = (__bf16)(xf - (float)hi);
     }
     static __device__ inline f32x4 mfma(v8 a, v8 b, f32x4 c)
     {
@@ -555,9 +560,9 @@ template <> struct Split16<1> {
     typedef _Float16 v8 __attribute__((ext_vector_type(8)));
     static __device__ inline void split(double x, float sc, _Float16 &hi, _Float16 &lo)
     {
-        const double y = x * (double)sc;
-        hi = (_Float16)(float)y;
-        lo = (_Float16)(float)((y - (double)(float)hi) * 2048.0);
+        const float y = (float)x * sc;
+        hi = (_Float16)y;
+        lo = (_Float16)((y - (float)hi) * 2048.0f);
     }
     static __device__ inline f32x4 mfma(v8 a, v8 b, f32x4 c)
     {
@@ -642,6 +647,129 @@ __global__ __launch_bounds__(256) void k_spgemm_split(
             if (ci) ci[o] = alr * im + ali * re;
         }
     }
+}
+
+// Split-precision variant of k_spgemm_q4 for real operands (the Taylor-term
+// products A tau of the *_TAYLOR forms), same four-triple grouping, order and
+// XCD mapping.  Each 16-bit MFMA (v_mfma_f32_16x16x16_{bf16,f16}) step takes
+// four consecutive contraction elements s0..s0+3 of its triple from lane
+// group q, so four steps cover B = 13 (elements 13..15 are zero).  Every
+// FP64 element is split as in k_spgemm_split (BF16 hi/lo, or FP16 hi/lo of
+// the power-of-two scaled value with the low part scaled by 2^11) and each
+// product is taken as hi*hi + hi*lo + lo*hi with FP32 accumulation.
+template <int MODE> struct Split4;
+template <> struct Split4<0> {
+    typedef short v4 __attribute__((ext_vector_type(4)));
+    static __device__ inline void split(double x, float, short &hi, short &lo)
+    {
+        float xf = (float)x;                       // 24 bits hold both 8-bit parts
+        asm volatile("" : "+v"(xf));               // round to FP32 first: keeps the conversions apart
+        const __bf16 h = (__bf16)xf;
+        const __bf16 l = (__bf16)(xf - (float)h);
+        hi = __builtin_bit_cast(short, h);
+        lo = __builtin_bit_cast(short, l);
+    }
+    static __device__ inline f32x4 mfma(v4 a, v4 b, f32x4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+    }
+    typedef short e_t;
+};
+template <> struct Split4<1> {
+    typedef _Float16 v4 __attribute__((ext_vector_type(4)));
+    static __device__ inline void split(double x, float sc, _Float16 &hi, _Float16 &lo)
+    {
+        const float y = (float)x * sc;              // sc a power of two; 24 bits hold both 11-bit parts
+        hi = (_Float16)y;
+        lo = (_Float16)((y - (float)hi) * 2048.0f);
+    }
+    static __device__ inline f32x4 mfma(v4 a, v4 b, f32x4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+    }
+    typedef _Float16 e_t;
+};
+
+template <int B, int MODE, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_spgemm_q4s(
+    int64_t nout, const int64_t *__restrict__ off, const int2 *__restrict__ trip, const double *__restrict__ ar,
+    const double *__restrict__ br, double *__restrict__ cr, double alr, const double *__restrict__ zero,
+    const int32_t *__restrict__ order, const double *__restrict__ maxabs)
+{
+    typedef Split4<MODE> SP;
+    typedef typename SP::v4 v4;
+    constexpr int BB = B * B;
+    const int lane = threadIdx.x & 63;
+    const int64_t w = xcd_block((nout + WPB - 1) / WPB) * WPB + (threadIdx.x >> 6);
+    if (w >= nout) return;                     // uniform across the wave
+    const int64_t c = order ? (int64_t)order[w] : w;
+    const int r = lane & 15, q = lane >> 4;
+    const bool rv = r < B;
+    const int64_t t0 = off[c];
+    const int nt = (int)(off[c + 1] - t0);
+    const float sa = MODE ? f16_scale(maxabs, 0) : 1.0f;
+    const float sb = MODE ? f16_scale(maxabs, 1) : 1.0f;
+    f32x4 h = {0, 0, 0, 0}, m = {0, 0, 0, 0};
+    for (int g = 0; g < nt; g += 4) {
+        const double *pa = zero, *pb = zero;
+        if (rv && g + q < nt) {
+            const int2 ab = trip[t0 + g + q];
+            pa = ar + (int64_t)ab.x * BB + r;
+            pb = br + (int64_t)ab.y * BB + r;
+        }
+#pragma unroll
+        for (int s0 = 0; s0 < B; s0 += 4) {
+            v4 ah, al, bh, bl;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int st = s0 + v;
+                const double xa = st < B ? pa[st * B] : 0.0, xb = st < B ? pb[st * B] : 0.0;
+                typename SP::e_t hi, lo;
+                SP::split(xa, sa, hi, lo);
+                ah[v] = hi;
+                al[v] = lo;
+                SP::split(xb, sb, hi, lo);
+                bh[v] = hi;
+                bl[v] = lo;
+            }
+            h = SP::mfma(ah, bh, h);
+            m = SP::mfma(ah, bl, m);
+            m = SP::mfma(al, bh, m);
+        }
+    }
+    const double inv = 1.0 / ((double)sa * (double)sb);
+    const double ml = MODE ? 1.0 / 2048.0 : 1.0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int row = 4 * q + e, col = r;
+        if (row < B && col < B) cr[c * BB + row * B + col] = alr * (((double)h[e] + ml * (double)m[e]) * inv);
+    }
+}
+
+void launch_spgemm_cm_split(hipStream_t s, const SpgemmArgs &a)
+{
+    if (a.nout == 0) return;
+    RT_CHECK(a.b == 13 && !a.ai && !a.bi && !a.ci &&
+                 (a.precision == RTDM_PREC_BF16X3 || a.precision == RTDM_PREC_FP16X2),
+             RTDM_E_UNSUPPORTED, "split step products need b = 13, real operands and a split precision");
+    RT_CHECK(a.precision != RTDM_PREC_FP16X2 || a.maxabs, RTDM_E_ARG, "FP16 split products need operand maxima");
+    const int wpb = a.wpb;
+    const unsigned grid = xcd_grid((a.nout + wpb - 1) / wpb);
+#define RT_Q4S(M, W)                                                                                      \
+    hipLaunchKernelGGL((k_spgemm_q4s<13, M, W>), dim3(grid), dim3(64 * W), 0, s, a.nout, a.off, a.trip, a.ar, \
+                       a.br, a.cr, a.alpha_re, a.zero, a.order, a.maxabs)
+    const int mode = a.precision == RTDM_PREC_FP16X2 ? 1 : 0;
+    if (mode == 0) {
+        if (wpb == 16) RT_Q4S(0, 16);
+        else if (wpb == 8) RT_Q4S(0, 8);
+        else RT_Q4S(0, 4);
+    } else {
+        if (wpb == 16) RT_Q4S(1, 16);
+        else if (wpb == 8) RT_Q4S(1, 8);
+        else RT_Q4S(1, 4);
+    }
+#undef RT_Q4S
+    RT_HIP(hipGetLastError());
 }
 
 template <int SUB, bool AC, bool BC, int OPA, int OPB>
@@ -791,13 +919,19 @@ static void launch_cm(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
         const int wpb = a.wpb;
         const int remap = getenv("RTDM_NO_XCD") ? 0 : 1;
         const unsigned grid = xcd_grid((a.nout + wpb - 1) / wpb);
-#define RT_Q4(W)                                                                                  \
-    hipLaunchKernelGGL((k_spgemm_q4<13, AC, BC, 0, CJB, LC, W>), dim3(grid), dim3(64 * W), 0, s,    \
+#define RT_Q4(W, T)                                                                               \
+    hipLaunchKernelGGL((k_spgemm_q4<13, AC, BC, 0, CJB, LC, W, T>), dim3(grid), dim3(64 * W), 0, s, \
                        a.nout, a.off, a.trip, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re,       \
                        a.alpha_im, a.zero, a.order, remap)
-        if (wpb == 16) RT_Q4(16);
-        else if (wpb == 8) RT_Q4(8);
-        else RT_Q4(4);
+        if (a.precision == RTDM_PREC_FP32) {
+            if (wpb == 16) RT_Q4(16, float);
+            else if (wpb == 8) RT_Q4(8, float);
+            else RT_Q4(4, float);
+        } else {
+            if (wpb == 16) RT_Q4(16, double);
+            else if (wpb == 8) RT_Q4(8, double);
+            else RT_Q4(4, double);
+        }
 #undef RT_Q4
     }
 }
@@ -805,8 +939,10 @@ static void launch_cm(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
 void launch_spgemm_cm(hipStream_t s, const SpgemmArgs &a, int conj_b, int out_col_major)
 {
     if (a.nout == 0) return;
-    RT_CHECK(a.b == 13 && a.precision == RTDM_PREC_FP64, RTDM_E_UNSUPPORTED,
-             "column-major step products need b = 13 and FP64");
+    RT_CHECK(a.b == 13 && (a.precision == RTDM_PREC_FP64 || a.precision == RTDM_PREC_FP32), RTDM_E_UNSUPPORTED,
+             "column-major step products need b = 13 and FP64 or FP32");
+    RT_CHECK(a.precision == RTDM_PREC_FP64 || kernel_variant() == 0, RTDM_E_UNSUPPORTED,
+             "the measured step-kernel variants are FP64 only");
     const dim3 g((unsigned)((a.nout + 3) / 4)), t(256);
     const bool ac = a.ai != nullptr, bc = a.bi != nullptr;
 #define RT_CM(AC_, BC_)                                                            \

@@ -154,3 +154,24 @@ def test_split_taylor_b13_lattice_error_stated(prec, bound):
     e_dip = np.abs(tr[:, 1:4] - ref.rows[:, 1:4]).max() / induced
     print(f"{prec} (from order 3) b=13 lattice, 10 steps: dipole error {e_dip:.2e} of peak induced")
     assert e_dip <= bound
+
+
+def test_fp32_step_kernels_b13_lattice_error_stated():
+    """Every product of the b = 13 step on the FP32 matrix cores (operands
+    rounded on load): the dipole error is of the order of the FP32 rounding
+    of K relative to the small induced signal, as for the b = 4 cluster."""
+    s = synth.diamond_lattice((2, 2, 2), 13, 10.0, 16.0, seed=21, k0="local", h_model="mulliken")
+    st = O.setup(s)
+    ctx = gpu_context(s, h_model="mulliken", precision="fp32")
+    rtdm.rtdm_build_inverse(ctx.h)
+    rtdm.rtdm_apply_kick(ctx.h, s.kappa)
+    rtdm.rtdm_step(ctx.h, s.dt, 10)
+    tr = rtdm.rtdm_dipole_trace(ctx.h)
+    ctx.close()
+    ref = O.propagate(st, 10, s.dt, s.kappa, h_model="mulliken")
+    P0 = O.dipole(O.mulliken(O.kick(st.K0, st.xyz, s.kappa), st.S), st.xyz)
+    induced = np.abs(ref.rows[:, 1:4] - P0).max()
+    e_dip = np.abs(tr[:, 1:4] - ref.rows[:, 1:4]).max() / induced
+    e_tr = np.abs(tr[:, 4] - ref.rows[:, 4]).max() / abs(ref.rows[0, 4])
+    print(f"fp32 (all products) b=13 lattice, 10 steps: dipole error {e_dip:.2e} of peak induced, Tr(KS) {e_tr:.2e}")
+    assert e_dip <= 0.1 and e_tr <= 1e-5
