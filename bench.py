@@ -94,6 +94,43 @@ def gpu_run(s, args, precision="fp64", taylor_low_from=3, use_graph=0, inv_start
     return dict(elapsed=t1 - t0, stats=stats, sched=sched, trace=trace, p0=p0, inv_iters=iters, inv_s=inv_s)
 
 
+def measured_peaks():
+    """Achievable rates on this GPU for context: FP64 GEMM through torch's BLAS
+    (8192^3, best of 5) and a device copy of 2 GiB (read + write, best of 5)."""
+    import torch
+    n = 8192
+    a = torch.rand(n, n, dtype=torch.float64, device="cuda")
+    b = torch.rand(n, n, dtype=torch.float64, device="cuda")
+    torch.matmul(a, b)
+    best = 1e30
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        torch.matmul(a, b)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    gemm = 2.0 * n ** 3 / best / 1e12
+    del a, b
+    x = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    best = 1e30
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        y.copy_(x)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    bw = 2.0 * x.numel() * 8 / best / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return {"fp64_gemm_tflops": gemm, "copy_gb_per_s": bw,
+            "note": "torch.matmul float64 8192^3 and a 2 GiB device copy, best of 5; context for the "
+                    "published peaks the roofline uses"}
+
+
 def train_learned_start(b, seeds=(101, 102, 103), cells=(3, 3, 3)):
     """Train the inverse-start network on converged inverses of small lattices
     of the workload's recipe (held-out seeds); returns its weights."""
@@ -276,6 +313,7 @@ def main():
                     help="reduced-precision forms run beside FP64 (comma list, empty for none)")
     ap.add_argument("--no-learned", action="store_true", help="forms use the block-Jacobi inverse start")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the GEMM / copy rate measurement")
     ap.add_argument("--batch-clusters", type=int, default=32,
                     help="clusters of the batch leg, the first of the 64-cluster list (0: skip)")
     ap.add_argument("--batch-atoms", type=int, default=24000, help="atoms per batch (kicks counted)")
@@ -360,6 +398,9 @@ def main():
                    "training_data": "converged inverses (residual 1e-12) of three 216-atom lattices of the "
                                     "same recipe with held-out seeds"}
     batch = batch_leg(args) if args.batch_clusters > 0 else None
+    peaks = None if args.no_peaks else measured_peaks()
+    if peaks:
+        log(f"measured peaks: {peaks}")
 
     # dominant product kernel: the kind with the most kernel time
     dom = max(stats, key=lambda k: stats[k][1])
@@ -431,6 +472,7 @@ def main():
         "graph": graph,
         "learned_start": learned,
         "batch": batch,
+        "measured_peaks": peaks,
     }
     print(json.dumps(out))
 
