@@ -136,6 +136,11 @@ struct SpgemmArgs {
     const double *maxabs = nullptr;
 };
 void launch_spgemm(hipStream_t s, const SpgemmArgs &a);
+// b = 4, FP64, op(A) = A: one workgroup per row of C with that row of A
+// staged in LDS (max_row: the longest row of A's pattern, in blocks).
+void launch_spgemm_b4r(hipStream_t s, const SpgemmArgs &a, int64_t n_rows, const int64_t *c_rowptr,
+                       const int64_t *a_rowptr, int64_t max_row);
+void init_kernel_attributes();
 // Same product with the left operand given as column-major blocks, the right
 // operand's op(B)[m][r] at m*B + r (conj_b: conjugated) and the output written
 // column-major if out_col_major.  b = 13, FP64.

@@ -101,6 +101,7 @@ enum Range { R_HS = 0, R_P = 1, R_K = 2 };
 struct Pattern {
     double R = 0.0;
     int64_t n = 0, nnzb = 0;
+    int64_t max_row = -1;      // longest row in blocks (computed on first use)
     std::vector<int64_t> rowptr;
     std::vector<int32_t> col, rowof, trans, diag;
     DBuf<int64_t> d_rowptr;
@@ -238,6 +239,7 @@ struct rtdm_ctx {
     bool graph_rebuilds_u = false;
     // launch shape of the step products
     int wpb = 16, row_tile = 64;
+    int row_stationary4 = 1;    // b = 4: stage each row of the left operand in LDS
     int inv_iters_total = 0, inv_fell_back = 0;
     // ETRS / Magnus work matrices and the self-consistent corrector's state
     Mat E1, E2, E3, A1, Kt;
@@ -459,6 +461,9 @@ hipEvent_t event_at(rtdm_ctx *c, size_t k)
     return c->events[k];
 }
 
+constexpr size_t kB4rMaxLds = 40 * 1024;   // LDS budget of one row-stationary workgroup
+constexpr int64_t kB4rMaxRow = 160;         // longest left-operand row it takes (blocks)
+
 // C = P_C(alpha op(A) op(B)) with the schedule of `prod`.
 void product(rtdm_ctx *c, int prod, const Mat &A, const Mat &B, Mat &C, double alr, double ali,
              hipStream_t s)
@@ -502,16 +507,36 @@ void product(rtdm_ctx *c, int prod, const Mat &A, const Mat &B, Mat &C, double a
         }
         a.maxabs = c->f16_max.p;
     }
+    // b = 4 FP64 with op(A) = A: row-stationary kernel when a row of A fits in LDS
+    const Pattern &PA = *c->pats[A.pat], &PC = *c->pats[C.pat];
+    int64_t max_row = 0;
+    (void)PA;
+    if (c->b == 4 && c->prec == RTDM_PREC_FP64 && a.op_a == 0 && c->row_stationary4) {
+        Pattern &pa = *c->pats[A.pat];
+        if (pa.max_row < 0) {
+            pa.max_row = 0;
+            for (int64_t i = 0; i < pa.n; ++i) pa.max_row = std::max(pa.max_row, pa.rowptr[i + 1] - pa.rowptr[i]);
+        }
+        max_row = pa.max_row;
+        // measured on diamond lattices: the row-stationary kernel wins up to rows of ~150 blocks
+        // (R 8-12 bohr) and loses beyond (R 16), where the per-triple kernel's L2 reuse takes over
+        if (max_row > kB4rMaxRow || (size_t)max_row * 16 * sizeof(double) * (A.cplx ? 2 : 1) > kB4rMaxLds)
+            max_row = 0;
+    }
+    auto go = [&]() {
+        if (max_row > 0) launch_spgemm_b4r(s, a, PC.n, PC.d_rowptr.p, PA.d_rowptr.p, max_row);
+        else launch_spgemm(s, a);
+    };
     if (c->timing && !c->capturing) {
         const size_t k = 2 * c->recs.size();
         RT_HIP(hipEventRecord(event_at(c, k), s));
-        launch_spgemm(s, a);
+        go();
         RT_HIP(hipEventRecord(event_at(c, k + 1), s));
         const double b3 = (double)c->b * c->b * c->b;
         const double sub = (A.cplx ? 2.0 : 1.0) * (B.cplx ? 2.0 : 1.0);
         c->recs.push_back({prod, (int)k, (double)S.ntrip * 2.0 * b3 * sub});
     } else {
-        launch_spgemm(s, a);
+        go();
     }
 }
 
@@ -923,6 +948,7 @@ int rtdm_create(rtdm_ctx **out, int hip_device, const rtdm_options *opt)
     RT_CHECK(c->opt.sc_steps >= 0 && c->opt.sc_iters >= 0, RTDM_E_ARG, "sc_steps / sc_iters < 0");
     RT_CHECK(c->opt.unit_tol >= 0.0, RTDM_E_ARG, "unit_tol < 0");
     set_device(c);
+    init_kernel_attributes();
     c->partials.alloc(kRedBlocks * 4);
     c->herm_sums.alloc(4);
     c->unit_sums.alloc(4);
@@ -1885,12 +1911,23 @@ int rtdm_autotune(rtdm_ctx *c, void *stream, int *wpb_out, int *tile_out)
     hipStream_t s = (hipStream_t)stream;
     if (c->b == 13) {
         const int wpbs[3] = {4, 8, 16}, tiles[3] = {16, 64, 256};
-        hipEvent_t e0, e1;
-        RT_HIP(hipEventCreate(&e0));
-        RT_HIP(hipEventCreate(&e1));
+        // events and the context's timing flag are restored however the sweep ends
+        struct Guard {
+            rtdm_ctx *c;
+            bool timing;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            ~Guard()
+            {
+                c->timing = timing;
+                if (e0) (void)hipEventDestroy(e0);
+                if (e1) (void)hipEventDestroy(e1);
+            }
+        } guard{c, c->timing};
+        RT_HIP(hipEventCreate(&guard.e0));
+        RT_HIP(hipEventCreate(&guard.e1));
+        hipEvent_t e0 = guard.e0, e1 = guard.e1;
         double best = 1e300;
         int bw = c->wpb, bt = c->row_tile;
-        const bool timing = c->timing;
         c->timing = false;
         for (int tile : tiles) {
             c->row_tile = tile;
@@ -1918,9 +1955,6 @@ int rtdm_autotune(rtdm_ctx *c, void *stream, int *wpb_out, int *tile_out)
                 }
             }
         }
-        c->timing = timing;
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
         c->wpb = bw;
         c->row_tile = bt;
         for (auto &kv : c->scheds) {

@@ -840,6 +840,109 @@ __global__ __launch_bounds__(256) void k_spgemm_b4(
     }
 }
 
+
+// Row-stationary product for b = 4 (FP64, op(A) = A): one workgroup per row i
+// of C.  The blocks of row i of A are contiguous in A's storage; the
+// workgroup copies them into LDS once, and every triple of every output
+// (i, j) then takes its A block from LDS, so only the B blocks stream from
+// memory (one block per triple instead of two).  Each wave runs four output
+// blocks at a time as the four blocks of v_mfma_f64_4x4x4_4b, one triple
+// per instruction (lane 16q + 4g + r: A_g[r][q], B_g[q][r], D_g[q][r]).
+template <bool AC, bool BC, int OPB>
+__global__ __launch_bounds__(256) void k_spgemm_b4r(
+    int64_t n_rows, const int64_t *__restrict__ c_rowptr, const int64_t *__restrict__ a_rowptr,
+    const int64_t *__restrict__ off, const int2 *__restrict__ trip, const double *__restrict__ ar,
+    const double *__restrict__ ai, const double *__restrict__ br, const double *__restrict__ bi,
+    double *__restrict__ cr, double *__restrict__ ci, double alr, double ali)
+{
+    extern __shared__ double lds[];            // [plane][block of row i][16]
+    const int64_t i = xcd_block(n_rows);
+    if (i >= n_rows) return;                   // uniform across the workgroup
+    const int64_t a0 = a_rowptr[i], na = a_rowptr[i + 1] - a0;
+    const int tid = threadIdx.x;
+    for (int64_t e = tid; e < na * 16; e += 256) {
+        lds[e] = ar[a0 * 16 + e];
+        if (AC) lds[na * 16 + e] = ai[a0 * 16 + e];
+    }
+    __syncthreads();
+    const int lane = tid & 63, w = tid >> 6;
+    const int g = (lane >> 2) & 3, r = lane & 3, q = lane >> 4;
+    const int ia = r * 4 + q;                          // A[r][q]
+    const int ib = OPB ? (r * 4 + q) : (q * 4 + r);    // op(B)[q][r]
+    const double sb = OPB ? -1.0 : 1.0;                // conjugate of op(B) = B^dagger
+    const int64_t c_beg = c_rowptr[i], c_end = c_rowptr[i + 1];
+    for (int64_t c0 = c_beg + 4 * w; c0 < c_end; c0 += 16) {
+        const int64_t c = c0 + g;
+        const bool live = c < c_end;
+        const int64_t t0 = live ? off[c] : 0;
+        const int nt = live ? (int)(off[c + 1] - t0) : 0;
+        int ntmax = max(nt, __shfl_xor(nt, 4, 64));
+        ntmax = max(ntmax, __shfl_xor(ntmax, 8, 64));
+        double rr = 0.0, ii = 0.0, ri = 0.0, ir = 0.0;
+        for (int t = 0; t < ntmax; ++t) {
+            double xar = 0.0, xai = 0.0, xbr = 0.0, xbi = 0.0;
+            if (t < nt) {
+                const int2 ab = trip[t0 + t];
+                const int64_t la = (int64_t)(ab.x - a0) * 16 + ia;
+                const int64_t pb = (int64_t)ab.y * 16 + ib;
+                xar = lds[la];
+                xbr = br[pb];
+                if (AC) xai = lds[na * 16 + la];
+                if (BC) xbi = sb * bi[pb];
+            }
+            rr = __builtin_amdgcn_mfma_f64_4x4x4f64(xar, xbr, rr, 0, 0, 0);
+            if (AC && BC) ii = __builtin_amdgcn_mfma_f64_4x4x4f64(xai, xbi, ii, 0, 0, 0);
+            if (BC) ri = __builtin_amdgcn_mfma_f64_4x4x4f64(xar, xbi, ri, 0, 0, 0);
+            if (AC) ir = __builtin_amdgcn_mfma_f64_4x4x4f64(xai, xbr, ir, 0, 0, 0);
+        }
+        if (live) {
+            const double re = rr - ii, im = ri + ir;
+            const int64_t o = c * 16 + q * 4 + r;
+            cr[o] = alr * re - ali * im;
+            if (ci) ci[o] = alr * im + ali * re;
+        }
+    }
+}
+
+// Allow the row-stationary kernels the whole LDS of a CU (set once, outside
+// any stream capture).
+void init_kernel_attributes()
+{
+    const int bytes = 160 * 1024;
+    const void *ks[] = {(const void *)k_spgemm_b4r<true, true, 0>,   (const void *)k_spgemm_b4r<true, false, 0>,
+                        (const void *)k_spgemm_b4r<false, true, 0>,  (const void *)k_spgemm_b4r<false, false, 0>,
+                        (const void *)k_spgemm_b4r<true, true, 1>,   (const void *)k_spgemm_b4r<true, false, 1>,
+                        (const void *)k_spgemm_b4r<false, true, 1>,  (const void *)k_spgemm_b4r<false, false, 1>};
+    for (const void *k : ks) RT_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+}
+
+void launch_spgemm_b4r(hipStream_t s, const SpgemmArgs &a, int64_t n_rows, const int64_t *c_rowptr,
+                       const int64_t *a_rowptr, int64_t max_row)
+{
+    if (a.nout == 0) return;
+    RT_CHECK(a.b == 4 && a.precision == RTDM_PREC_FP64 && a.op_a == 0, RTDM_E_UNSUPPORTED,
+             "row-stationary products need b = 4, FP64 and op(A) = A");
+    const bool ac = a.ai != nullptr, bc = a.bi != nullptr;
+    const size_t lds = (size_t)max_row * 16 * sizeof(double) * (ac ? 2 : 1);
+    const dim3 grid(xcd_grid(n_rows)), blk(256);
+#define RT_B4R(AC_, BC_, OB_)                                                                         \
+    hipLaunchKernelGGL((k_spgemm_b4r<AC_, BC_, OB_>), grid, blk, lds, s, n_rows, c_rowptr, a_rowptr, a.off, \
+                       a.trip, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re, a.alpha_im)
+    if (a.op_b) {
+        if (ac && bc) RT_B4R(true, true, 1);
+        else if (ac) RT_B4R(true, false, 1);
+        else if (bc) RT_B4R(false, true, 1);
+        else RT_B4R(false, false, 1);
+    } else {
+        if (ac && bc) RT_B4R(true, true, 0);
+        else if (ac) RT_B4R(true, false, 0);
+        else if (bc) RT_B4R(false, true, 0);
+        else RT_B4R(false, false, 0);
+    }
+#undef RT_B4R
+    RT_HIP(hipGetLastError());
+}
+
 template <int SUB, bool AC, bool BC, int OA, int OB>
 static void launch_b4(hipStream_t s, const SpgemmArgs &a)
 {
