@@ -943,6 +943,136 @@ void launch_spgemm_b4r(hipStream_t s, const SpgemmArgs &a, int64_t n_rows, const
     RT_HIP(hipGetLastError());
 }
 
+
+// Reduced-precision products for b = 4 on the 16-block 4x4 matrix-core
+// instructions (gfx950, measured layout: lane 4 blk + r supplies row r of
+// A_blk and column r of B_blk, and holds D_blk[e][r] in its value e).  A wave
+// runs 16 output blocks, one per MFMA block, one triple of each per step:
+//   MODE 0 FP32   : four v_mfma_f32_4x4x1_16b per block product;
+//   MODE 1 BF16x3 : hi/lo split, three v_mfma_f32_4x4x4_16b_bf16;
+//   MODE 2 FP16x2 : scaled hi/lo split, three v_mfma_f32_4x4x4_16b_f16.
+// Operands are FP64 in memory (op(A) = A; op(B) = B or B^dagger), results
+// FP64; accumulation FP32.
+template <int MODE> struct Small4;
+template <> struct Small4<1> {
+    typedef short v4 __attribute__((ext_vector_type(4)));
+    static __device__ inline f32x4 mfma(v4 a, v4 b, f32x4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline void split(double x, float, short &hi, short &lo) { Split4<0>::split(x, 1.0f, hi, lo); }
+    typedef short e_t;
+};
+template <> struct Small4<2> {
+    typedef _Float16 v4 __attribute__((ext_vector_type(4)));
+    static __device__ inline f32x4 mfma(v4 a, v4 b, f32x4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_4x4x4f16(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline void split(double x, float sc, _Float16 &hi, _Float16 &lo)
+    {
+        Split4<1>::split(x, sc, hi, lo);
+    }
+    typedef _Float16 e_t;
+};
+
+template <bool AC, bool BC, int OPB, int MODE>
+__global__ __launch_bounds__(256) void k_spgemm_b4x(
+    int64_t nout, const int64_t *__restrict__ off, const int2 *__restrict__ trip,
+    const double *__restrict__ ar, const double *__restrict__ ai, const double *__restrict__ br,
+    const double *__restrict__ bi, double *__restrict__ cr, double *__restrict__ ci, double alr, double ali,
+    const double *__restrict__ maxabs)
+{
+    const int lane = threadIdx.x & 63;
+    const int blk = lane >> 2, r = lane & 3;
+    const int64_t c0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+    if (c0 >= nout) return;                    // uniform across the wave
+    const int64_t c = c0 + blk;
+    const bool live = c < nout;
+    const int64_t t0 = live ? off[c] : 0;
+    const int nt = live ? (int)(off[c + 1] - t0) : 0;
+    int ntmax = nt;
+#pragma unroll
+    for (int o = 4; o < 64; o <<= 1) ntmax = max(ntmax, __shfl_xor(ntmax, o, 64));
+    const float sa = MODE == 2 ? f16_scale(maxabs, 0) : 1.0f;
+    const float sb = MODE == 2 ? f16_scale(maxabs, 1) : 1.0f;
+    f32x4 h[4] = {}, m[4] = {};                // rr, ii, ri, ir
+    const double cb = OPB ? -1.0 : 1.0;
+    for (int t = 0; t < ntmax; ++t) {
+        double xa[4] = {0, 0, 0, 0}, xai[4] = {0, 0, 0, 0}, xb[4] = {0, 0, 0, 0}, xbi[4] = {0, 0, 0, 0};
+        if (t < nt) {
+            const int2 ab = trip[t0 + t];
+            const int64_t pa = (int64_t)ab.x * 16 + r * 4, pb = (int64_t)ab.y * 16;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                xa[k] = ar[pa + k];                                    // A[r][k]
+                const int64_t e = OPB ? pb + r * 4 + k : pb + k * 4 + r; // op(B)[k][r]
+                xb[k] = br[e];
+                if (AC) xai[k] = ai[pa + k];
+                if (BC) xbi[k] = cb * bi[e];
+            }
+        }
+        if (MODE == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                h[0] = __builtin_amdgcn_mfma_f32_4x4x1f32((float)xa[k], (float)xb[k], h[0], 0, 0, 0);
+                if (AC && BC) h[1] = __builtin_amdgcn_mfma_f32_4x4x1f32((float)xai[k], (float)xbi[k], h[1], 0, 0, 0);
+                if (BC) h[2] = __builtin_amdgcn_mfma_f32_4x4x1f32((float)xa[k], (float)xbi[k], h[2], 0, 0, 0);
+                if (AC) h[3] = __builtin_amdgcn_mfma_f32_4x4x1f32((float)xai[k], (float)xb[k], h[3], 0, 0, 0);
+            }
+        } else {
+            typedef Small4<MODE == 0 ? 1 : MODE> SP;
+            typedef typename SP::v4 v4;
+            auto prod3 = [&](int u, const double *x, float sx, const double *y, float sy) {
+                v4 xh, xl, yh, yl;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    typename SP::e_t hi, lo;
+                    SP::split(x[k], sx, hi, lo);
+                    xh[k] = hi;
+                    xl[k] = lo;
+                    SP::split(y[k], sy, hi, lo);
+                    yh[k] = hi;
+                    yl[k] = lo;
+                }
+                h[u] = SP::mfma(xh, yh, h[u]);
+                m[u] = SP::mfma(xh, yl, m[u]);
+                m[u] = SP::mfma(xl, yh, m[u]);
+            };
+            prod3(0, xa, sa, xb, sb);
+            if (AC && BC) prod3(1, xai, sa, xbi, sb);
+            if (BC) prod3(2, xa, sa, xbi, sb);
+            if (AC) prod3(3, xai, sa, xb, sb);
+        }
+    }
+    if (!live) return;
+    const double inv = 1.0 / ((double)sa * (double)sb);
+    const double ml = MODE == 2 ? 1.0 / 2048.0 : (MODE == 1 ? 1.0 : 0.0);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = ((double)h[u][e] + ml * (double)m[u][e]) * inv;
+        const double re = v[0] - v[1], im = v[2] + v[3];
+        const int64_t o = c * 16 + e * 4 + r;
+        cr[o] = alr * re - ali * im;
+        if (ci) ci[o] = alr * im + ali * re;
+    }
+}
+
+template <bool AC, bool BC, int OB>
+static void launch_b4x(hipStream_t s, const SpgemmArgs &a)
+{
+    const dim3 g((unsigned)((a.nout + 63) / 64)), t(256);
+#define RT_B4X(M)                                                                                     \
+    hipLaunchKernelGGL((k_spgemm_b4x<AC, BC, OB, M>), g, t, 0, s, a.nout, a.off, a.trip, a.ar, a.ai, a.br, \
+                       a.bi, a.cr, a.ci, a.alpha_re, a.alpha_im, a.maxabs)
+    if (a.precision == RTDM_PREC_FP32) RT_B4X(0);
+    else if (a.precision == RTDM_PREC_BF16X3) RT_B4X(1);
+    else RT_B4X(2);
+#undef RT_B4X
+}
+
 template <int SUB, bool AC, bool BC, int OA, int OB>
 static void launch_b4(hipStream_t s, const SpgemmArgs &a)
 {
@@ -972,7 +1102,9 @@ static void dispatch_ops(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
 {
 #define RT_LAUNCH(OA, OB)                                                                        \
     do {                                                                                         \
-        if (a.precision == RTDM_PREC_BF16X3 || a.precision == RTDM_PREC_FP16X2)                  \
+        if (a.precision != RTDM_PREC_FP64 && a.b == 4 && OA == 0)                                \
+            launch_b4x<AC, BC, OB>(s, a);                                                        \
+        else if (a.precision == RTDM_PREC_BF16X3 || a.precision == RTDM_PREC_FP16X2)             \
             launch_split<AC, BC, OA, OB>(s, a, g, t);                                            \
         else if (a.precision == RTDM_PREC_FP32 && a.b == 13)                                     \
             hipLaunchKernelGGL((k_spgemm_kc<13, AC, BC, OA, OB, float>), g, t, 0, s, a.nout,     \

@@ -116,7 +116,7 @@ def test_split_products_within_stated_tolerance(b, prec, bound):
 
 
 @pytest.mark.parametrize("prec,n0,bound_dip,bound_tr", [
-    ("bf16x3", 2, 2.0, 1e-4), ("fp16x2", 2, 5e-2, 1e-5),
+    ("bf16x3", 2, 2.0, 1e-4), ("fp16x2", 2, 0.1, 1e-5),
     ("bf16x3_taylor", 2, 1e-3, 1e-7), ("bf16x3_taylor", 3, 1e-7, 1e-10),
     ("fp16x2_taylor", 2, 2e-5, 2e-8), ("fp16x2_taylor", 3, 5e-9, 1e-12)])
 def test_split_propagation_error_stated(prec, n0, bound_dip, bound_tr):
