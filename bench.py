@@ -247,7 +247,7 @@ def study_precision(args):
     cut-off: dipole and Tr(KS) error against the FP64 run on the same GPU,
     and steps/s.  Prints one JSON line."""
     from paper_1404_5776_amd import synth
-    forms = ["fp32", "fp32_taylor", "bf16x3", "bf16x3_taylor", "fp16x2", "fp16x2_taylor"]
+    forms = [f for f in args.sweep_forms.split(",") if f]
     out = {"study": "precision", "workload": "diamond lattice 32768 atoms x 4 functions, R_HS 10 bohr, "
                                             "Mulliken on-site H, EM + Taylor p=5, dt 0.05",
            "steps": args.steps, "warmup": args.warmup, "taylor_low_from": args.low_from, "cutoffs": []}
@@ -326,6 +326,8 @@ def main():
                     help="instead of the benchmark line: the precision sweep on the 32,768-atom lattice, or "
                          "the learned inverse start on the 65,536-atom lattice (one JSON line each)")
     ap.add_argument("--cutoffs", default="8,12,16,20", help="K cut-offs of the precision study (bohr)")
+    ap.add_argument("--sweep-forms", default="fp32,fp32_taylor,bf16x3,bf16x3_taylor,fp16x2,fp16x2_taylor",
+                    help="forms of the precision study beside FP64 (comma list)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))

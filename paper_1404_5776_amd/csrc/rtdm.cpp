@@ -239,7 +239,7 @@ struct rtdm_ctx {
     bool graph_rebuilds_u = false;
     // launch shape of the step products
     int wpb = 16, row_tile = 64;
-    int row_stationary4 = 1;    // b = 4: stage each row of the left operand in LDS
+    int row_stationary4 = 0;    // b = 4: stage each row of the left operand in LDS (measured slower than the wide kernel)
     int inv_iters_total = 0, inv_fell_back = 0;
     // ETRS / Magnus work matrices and the self-consistent corrector's state
     Mat E1, E2, E3, A1, Kt;
@@ -949,6 +949,7 @@ int rtdm_create(rtdm_ctx **out, int hip_device, const rtdm_options *opt)
     RT_CHECK(c->opt.unit_tol >= 0.0, RTDM_E_ARG, "unit_tol < 0");
     set_device(c);
     init_kernel_attributes();
+    if (const char *e = getenv("RTDM_B4_ROWSTAT")) c->row_stationary4 = atoi(e);   // measurements
     c->partials.alloc(kRedBlocks * 4);
     c->herm_sums.alloc(4);
     c->unit_sums.alloc(4);

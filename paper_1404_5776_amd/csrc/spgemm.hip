@@ -1073,6 +1073,78 @@ static void launch_b4x(hipStream_t s, const SpgemmArgs &a)
 #undef RT_B4X
 }
 
+
+// FP64 b = 4 product, 16 output blocks per wave: four v_mfma_f64_4x4x4_4b per
+// triple step (instruction j runs outputs c0 + 4j + g in its four blocks), so
+// every lane has eight (real) operand loads in flight per step instead of
+// two.  Same operand bytes per triple as k_spgemm_b4.
+template <bool AC, bool BC, int OPB>
+__global__ __launch_bounds__(256) void k_spgemm_b4w(
+    int64_t nout, const int64_t *__restrict__ off, const int2 *__restrict__ trip,
+    const double *__restrict__ ar, const double *__restrict__ ai, const double *__restrict__ br,
+    const double *__restrict__ bi, double *__restrict__ cr, double *__restrict__ ci, double alr, double ali)
+{
+    const int lane = threadIdx.x & 63;
+    const int g = (lane >> 2) & 3, r = lane & 3, q = lane >> 4;
+    const int64_t c0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+    if (c0 >= nout) return;                    // uniform across the wave
+    const int ia = r * 4 + q;                          // A[r][q]
+    const int ib = OPB ? (r * 4 + q) : (q * 4 + r);    // op(B)[q][r]
+    const double cb = OPB ? -1.0 : 1.0;
+    int64_t t0[4];
+    int nt[4];
+    int ntmax = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t c = c0 + 4 * j + g;
+        t0[j] = c < nout ? off[c] : 0;
+        nt[j] = c < nout ? (int)(off[c + 1] - t0[j]) : 0;
+        ntmax = max(ntmax, nt[j]);
+    }
+    ntmax = max(ntmax, __shfl_xor(ntmax, 4, 64));
+    ntmax = max(ntmax, __shfl_xor(ntmax, 8, 64));
+    double rr[4] = {0, 0, 0, 0}, ii[4] = {0, 0, 0, 0}, ri[4] = {0, 0, 0, 0}, ir[4] = {0, 0, 0, 0};
+    for (int t = 0; t < ntmax; ++t) {
+        double xar[4], xai[4], xbr[4], xbi[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            xar[j] = xai[j] = xbr[j] = xbi[j] = 0.0;
+            if (t < nt[j]) {
+                const int2 ab = trip[t0[j] + t];
+                const int64_t pa = (int64_t)ab.x * 16 + ia, pb = (int64_t)ab.y * 16 + ib;
+                xar[j] = ar[pa];
+                xbr[j] = br[pb];
+                if (AC) xai[j] = ai[pa];
+                if (BC) xbi[j] = cb * bi[pb];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            rr[j] = __builtin_amdgcn_mfma_f64_4x4x4f64(xar[j], xbr[j], rr[j], 0, 0, 0);
+            if (AC && BC) ii[j] = __builtin_amdgcn_mfma_f64_4x4x4f64(xai[j], xbi[j], ii[j], 0, 0, 0);
+            if (BC) ri[j] = __builtin_amdgcn_mfma_f64_4x4x4f64(xar[j], xbi[j], ri[j], 0, 0, 0);
+            if (AC) ir[j] = __builtin_amdgcn_mfma_f64_4x4x4f64(xai[j], xbr[j], ir[j], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t c = c0 + 4 * j + g;
+        if (c < nout) {
+            const double re = rr[j] - ii[j], im = ri[j] + ir[j];
+            const int64_t o = c * 16 + q * 4 + r;
+            cr[o] = alr * re - ali * im;
+            if (ci) ci[o] = alr * im + ali * re;
+        }
+    }
+}
+
+template <bool AC, bool BC, int OB>
+static void launch_b4w(hipStream_t s, const SpgemmArgs &a)
+{
+    hipLaunchKernelGGL((k_spgemm_b4w<AC, BC, OB>), dim3((unsigned)((a.nout + 63) / 64)), dim3(256), 0, s, a.nout,
+                       a.off, a.trip, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re, a.alpha_im);
+}
+
 template <int SUB, bool AC, bool BC, int OA, int OB>
 static void launch_b4(hipStream_t s, const SpgemmArgs &a)
 {
@@ -1097,6 +1169,17 @@ static void launch_split(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
 #undef RT_SPLIT
 }
 
+// FP64 b = 4 per-triple products: 16 outputs per wave (1) or 4 (0); RTDM_B4_WIDE
+// overrides it for measurements.
+static int b4_wide()
+{
+    static int v = [] {
+        const char *e = getenv("RTDM_B4_WIDE");
+        return e ? atoi(e) : 1;
+    }();
+    return v;
+}
+
 template <bool AC, bool BC>
 static void dispatch_ops(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
 {
@@ -1114,6 +1197,8 @@ static void dispatch_ops(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
             hipLaunchKernelGGL((k_spgemm_kc<4, AC, BC, OA, OB, float>), g, t, 0, s, a.nout,      \
                                a.off, a.trip, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re,    \
                                a.alpha_im);                                                      \
+        else if (a.b == 4 && OA == 0 && b4_wide())                                               \
+            launch_b4w<AC, BC, OB>(s, a);                                                        \
         else if (a.b == 4)                                                                       \
             launch_b4<(AC && BC) ? 4 : ((AC || BC) ? 2 : 1), AC, BC, OA, OB>(s, a);              \
         else if (a.b == 13 && kernel_variant() == 1)                                             \
