@@ -134,6 +134,16 @@ struct SpgemmArgs {
     // B: 1) real plane, [8k+4 .. 8k+7] of its imaginary plane (zeros if
     // real); the last slot of each holds max |x|.
     const double *maxabs = nullptr;
+    // Row runs of the b = 13 step products (launch_spgemm_cm when nch > 0):
+    // run c covers the outputs ch_out[c*nj .. c*nj+nj-1] (-1: none) of one row
+    // i of C; its entries ch_off[c] .. ch_off[c+1]-1 are the contraction
+    // indices k used by any of them, entry e naming op(A)_ik (ch_a[e]) and
+    // op(B)_kj of each output (ch_b[e*nj + t], -1 where that output has no
+    // triple with this k).  ch_order: processing order of the runs.
+    int nj = 0;
+    int64_t nch = 0;
+    const int64_t *ch_off = nullptr;
+    const int32_t *ch_a = nullptr, *ch_b = nullptr, *ch_out = nullptr, *ch_order = nullptr;
 };
 void launch_spgemm(hipStream_t s, const SpgemmArgs &a);
 // b = 4, FP64, op(A) = A: one workgroup per row of C with that row of A

@@ -114,11 +114,22 @@ struct Mat {
     DBuf<double> re, im;
 };
 
+// Row runs of one schedule for one run length nj (see build_runs).
+struct Runs {
+    int nj = 0;
+    int64_t nch = 0;
+    DBuf<int64_t> off;
+    DBuf<int32_t> a, b, out, order;
+    std::vector<int32_t> row, col;   // row and first column of each run
+};
+
 struct Sched {
     int64_t nout = 0, ntrip = 0;
     DBuf<int64_t> off;
     DBuf<int2> trip;
     DBuf<int32_t> order;   // processing order of the output blocks (row tiles, then columns)
+    // row runs of the b = 13 step products (SpgemmArgs::ch_*), by run length
+    std::map<int, std::unique_ptr<Runs>> runs;
 };
 
 // Processing order of the output blocks of pattern C: rows are cut into
@@ -148,6 +159,75 @@ std::vector<int32_t> tile_order(const Pattern &C, int tile_i, int tile_j)
 }
 
 
+
+// Processing order of row runs: rows in tiles of `tile_i` atoms; inside a
+// tile by first column, then row (the order of tile_order for single outputs).
+std::vector<int32_t> run_order(const Runs &R, int tile_i)
+{
+    std::vector<int32_t> ord(R.nch);
+    for (int64_t u = 0; u < R.nch; ++u) ord[u] = (int32_t)u;
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
+        const int32_t tx = R.row[x] / tile_i, ty = R.row[y] / tile_i;
+        return tx != ty ? tx < ty : R.col[x] < R.col[y];
+    });
+    return ord;
+}
+
+// Row runs of schedule S (output pattern C): the outputs of each row cut into
+// runs of nj consecutive columns; the entries of a run are the distinct
+// op(A) blocks of its outputs' triples (one per contraction index k), each
+// with the op(B) block of every output of the run (-1: no triple for k).
+void build_runs(Sched &S, const Pattern &C, int nj, int tile_i)
+{
+    if (S.runs.count(nj)) return;
+    auto R = std::make_unique<Runs>();
+    std::vector<int64_t> off(S.nout + 1);
+    std::vector<int2> trip(S.ntrip);
+    RT_HIP(hipMemcpy(off.data(), S.off.p, off.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+    if (S.ntrip) RT_HIP(hipMemcpy(trip.data(), S.trip.p, trip.size() * sizeof(int2), hipMemcpyDeviceToHost));
+    std::vector<int64_t> roff{0};
+    std::vector<int32_t> ra, rb, rout;
+    struct T3 { int32_t a, t, b; };
+    std::vector<T3> buf;
+    for (int64_t i = 0; i < C.n; ++i) {
+        for (int64_t p0 = C.rowptr[i]; p0 < C.rowptr[i + 1]; p0 += nj) {
+            const int64_t p1 = std::min<int64_t>(p0 + nj, C.rowptr[i + 1]);
+            buf.clear();
+            for (int64_t p = p0; p < p1; ++p)
+                for (int64_t e = off[p]; e < off[p + 1]; ++e)
+                    buf.push_back({trip[e].x, (int32_t)(p - p0), trip[e].y});
+            std::sort(buf.begin(), buf.end(),
+                      [](const T3 &x, const T3 &y) { return x.a != y.a ? x.a < y.a : x.t < y.t; });
+            for (size_t u = 0; u < buf.size();) {
+                const int32_t a = buf[u].a;
+                ra.push_back(a);
+                const size_t base = rb.size();
+                rb.resize(base + nj, -1);
+                for (; u < buf.size() && buf[u].a == a; ++u) rb[base + buf[u].t] = buf[u].b;
+            }
+            roff.push_back((int64_t)ra.size());
+            for (int t = 0; t < nj; ++t) rout.push_back(p0 + t < p1 ? (int32_t)(p0 + t) : -1);
+            R->row.push_back((int32_t)i);
+            R->col.push_back(C.col[p0]);
+        }
+    }
+    R->nj = nj;
+    R->nch = (int64_t)R->row.size();
+    R->off.alloc(roff.size());
+    R->a.alloc(std::max<size_t>(ra.size(), 1));
+    R->b.alloc(std::max<size_t>(rb.size(), 1));
+    R->out.alloc(std::max<size_t>(rout.size(), 1));
+    R->order.alloc(std::max<int64_t>(R->nch, 1));
+    RT_HIP(hipMemcpy(R->off.p, roff.data(), roff.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    if (!ra.empty()) RT_HIP(hipMemcpy(R->a.p, ra.data(), ra.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (!rb.empty()) RT_HIP(hipMemcpy(R->b.p, rb.data(), rb.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (!rout.empty())
+        RT_HIP(hipMemcpy(R->out.p, rout.data(), rout.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    const std::vector<int32_t> ord = run_order(*R, tile_i);
+    if (!ord.empty())
+        RT_HIP(hipMemcpy(R->order.p, ord.data(), ord.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    S.runs.emplace(nj, std::move(R));
+}
 
 struct TRec {
     int prod;
@@ -239,6 +319,7 @@ struct rtdm_ctx {
     bool graph_rebuilds_u = false;
     // launch shape of the step products
     int wpb = 16, row_tile = 64;
+    int run_real = 2, run_cplx = 1;   // b = 13 step products: outputs per row run (1: single outputs)
     int row_stationary4 = 0;    // b = 4: stage each row of the left operand in LDS (measured slower than the wide kernel)
     int inv_iters_total = 0, inv_fell_back = 0;
     // ETRS / Magnus work matrices and the self-consistent corrector's state
@@ -418,8 +499,21 @@ std::tuple<int, int, int, int, int> prod_key(rtdm_ctx *c, int prod)
 Sched &schedule(rtdm_ctx *c, int prod)
 {
     auto key = prod_key(c, prod);
+    // b = 13 step products of the column-major path: X H and A tau real,
+    // U K and W U^dagger complex; row runs for the kind's run length
+    const int nj = c->b != 13 ? 1
+                   : (prod == RTDM_PROD_XH || prod == RTDM_PROD_AT) ? c->run_real
+                   : (prod == RTDM_PROD_UK || prod == RTDM_PROD_WU) ? c->run_cplx
+                                                                      : 1;
     auto it = c->scheds.find(key);
-    if (it != c->scheds.end()) return *it->second;
+    if (it != c->scheds.end()) {
+        // a kind sharing its patterns with an earlier one (equal cut-offs)
+        if (nj > 1) {
+            build_runs(*it->second, *c->pats[std::get<2>(key)], nj, c->row_tile);
+            RT_HIP(hipDeviceSynchronize());
+        }
+        return *it->second;
+    }
     auto S = std::make_unique<Sched>();
     const Pattern &A = *c->pats[std::get<0>(key)];
     const Pattern &B = *c->pats[std::get<1>(key)];
@@ -445,6 +539,7 @@ Sched &schedule(rtdm_ctx *c, int prod)
         if (!ord.empty())
             RT_HIP(hipMemcpy(S->order.p, ord.data(), ord.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     }
+    if (nj > 1) build_runs(*S, C, nj, c->row_tile);
     RT_HIP(hipDeviceSynchronize());
     Sched &ref = *S;
     c->scheds.emplace(key, std::move(S));
@@ -567,6 +662,21 @@ void product_cm(rtdm_ctx *c, int prod, const Mat &Acm, const Mat &B, Mat &C, int
     a.order = S.order.p;
     a.wpb = c->wpb;
     a.precision = c->prec;
+    {
+        // row runs of the length chosen for real or complex operands, if built
+        const int nj = (!Acm.cplx && !B.cplx) ? c->run_real : c->run_cplx;
+        auto r = S.runs.find(nj);
+        if (nj > 1 && r != S.runs.end() && r->second->nch > 0) {
+            const Runs &R = *r->second;
+            a.nj = R.nj;
+            a.nch = R.nch;
+            a.ch_off = R.off.p;
+            a.ch_a = R.a.p;
+            a.ch_b = R.b.p;
+            a.ch_out = R.out.p;
+            a.ch_order = R.order.p;
+        }
+    }
     RT_CHECK(C.cplx || (!Acm.cplx && !B.cplx), RTDM_E_UNSUPPORTED, "complex product into a real matrix");
     const bool split = is_split(c->prec);
     if (c->prec == RTDM_PREC_FP16X2) {
@@ -950,6 +1060,11 @@ int rtdm_create(rtdm_ctx **out, int hip_device, const rtdm_options *opt)
     set_device(c);
     init_kernel_attributes();
     if (const char *e = getenv("RTDM_B4_ROWSTAT")) c->row_stationary4 = atoi(e);   // measurements
+    if (const char *e = getenv("RTDM_RUN_REAL")) c->run_real = atoi(e);
+    if (const char *e = getenv("RTDM_RUN_CPLX")) c->run_cplx = atoi(e);
+    RT_CHECK((c->run_real == 1 || c->run_real == 2 || c->run_real == 4 || c->run_real == 8) &&
+                 (c->run_cplx == 1 || c->run_cplx == 2 || c->run_cplx == 4),
+             RTDM_E_ARG, "row runs of 1, 2, 4 (or 8, real products) outputs");
     c->partials.alloc(kRedBlocks * 4);
     c->herm_sums.alloc(4);
     c->unit_sums.alloc(4);
@@ -1903,6 +2018,27 @@ int rtdm_group_trace(rtdm_ctx *c, double *out, int64_t max_rows, int64_t *rows)
     API_END(c)
 }
 
+namespace {
+// Re-derive the processing order of every schedule (outputs and row runs) for
+// row tiles of `tile` atoms.
+void set_row_tile(rtdm_ctx *c, int tile)
+{
+    c->row_tile = tile;
+    for (auto &kv : c->scheds) {
+        Sched &S = *kv.second;
+        const std::vector<int32_t> ord = tile_order(*c->pats[std::get<2>(kv.first)], tile, 1 << 30);
+        if (!ord.empty())
+            RT_HIP(hipMemcpy(S.order.p, ord.data(), ord.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        for (auto &rr : S.runs) {
+            const Runs &R = *rr.second;
+            if (R.nch == 0) continue;
+            const std::vector<int32_t> ro = run_order(R, tile);
+            RT_HIP(hipMemcpy(R.order.p, ro.data(), ro.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        }
+    }
+}
+}  // namespace
+
 int rtdm_autotune(rtdm_ctx *c, void *stream, int *wpb_out, int *tile_out)
 {
     if (!c) return RTDM_E_ARG;
@@ -1931,14 +2067,7 @@ int rtdm_autotune(rtdm_ctx *c, void *stream, int *wpb_out, int *tile_out)
         int bw = c->wpb, bt = c->row_tile;
         c->timing = false;
         for (int tile : tiles) {
-            c->row_tile = tile;
-            for (auto &kv : c->scheds) {
-                // re-derive the processing order of every schedule for this tile
-                const std::vector<int32_t> ord = tile_order(*c->pats[std::get<2>(kv.first)], tile, 1 << 30);
-                if (!ord.empty())
-                    RT_HIP(hipMemcpy(kv.second->order.p, ord.data(), ord.size() * sizeof(int32_t),
-                                     hipMemcpyHostToDevice));
-            }
+            set_row_tile(c, tile);
             for (int w : wpbs) {
                 c->wpb = w;
                 product_cm(c, RTDM_PROD_UK, c->Uc, c->mats[RTDM_MAT_K], c->Wc, 0, 1, 1.0, s);   // warm-up
@@ -1957,13 +2086,7 @@ int rtdm_autotune(rtdm_ctx *c, void *stream, int *wpb_out, int *tile_out)
             }
         }
         c->wpb = bw;
-        c->row_tile = bt;
-        for (auto &kv : c->scheds) {
-            const std::vector<int32_t> ord = tile_order(*c->pats[std::get<2>(kv.first)], bt, 1 << 30);
-            if (!ord.empty())
-                RT_HIP(hipMemcpy(kv.second->order.p, ord.data(), ord.size() * sizeof(int32_t),
-                                 hipMemcpyHostToDevice));
-        }
+        set_row_tile(c, bt);
         c->W_in_cm = true;
         drop_graph(c);
     }

@@ -355,6 +355,95 @@ __global__ __launch_bounds__(64 * WPB) void k_spgemm_q4(
     }
 }
 
+typedef __attribute__((address_space(1))) const double gdouble;
+
+// Row runs of the step products: one wave computes NJ output blocks C_ij of
+// the same row i.  The entries of the run are the contraction indices k used
+// by any of its outputs; lane group q takes entry g + q, loads op(A)_ik once
+// and op(B)_kj of every output (the zero block where that output has no
+// triple with this k), and each loaded A element feeds NJ MFMAs.  The operand
+// blocks of A beyond L2 are then fetched once per run instead of once per
+// output; the price is the absent (zero) products of a run.  Data layout,
+// lane mapping, conjugation and output as in k_spgemm_q4.
+template <int B, bool AC, bool BC, int CJB, int LC, int NJ, class T = double>
+__global__ __launch_bounds__(256) void k_spgemm_q4j(
+    int64_t nch, const int64_t *__restrict__ off, const int32_t *__restrict__ ea,
+    const int32_t *__restrict__ eb, const int32_t *__restrict__ cout,
+    const double *__restrict__ ar, const double *__restrict__ ai, const double *__restrict__ br,
+    const double *__restrict__ bi, double *__restrict__ cr, double *__restrict__ ci, double alr,
+    double ali, const double *__restrict__ zero, const int32_t *__restrict__ order, int remap)
+{
+    static_assert(B >= 4 && B <= 16, "k_spgemm_q4j needs 4 <= B <= 16");
+    constexpr int BB = B * B;
+    const int lane = threadIdx.x & 63;
+    const int64_t w = xcd_block((nch + 3) / 4, remap) * 4 + (threadIdx.x >> 6);
+    if (w >= nch) return;                      // uniform across the wave
+    const int64_t c = order ? (int64_t)order[w] : w;
+    const int r = lane & 15, q = lane >> 4;
+    const bool rv = r < B;
+    const int64_t e0 = off[c];
+    const int ne = (int)(off[c + 1] - e0);
+    typedef typename Mfma16<T>::acc_t acc_t;
+    acc_t rr[NJ], ii[NJ], ri[NJ], ir[NJ];
+#pragma unroll
+    for (int t = 0; t < NJ; ++t) rr[t] = ii[t] = ri[t] = ir[t] = acc_t{0, 0, 0, 0};
+    const gdouble *gz = (const gdouble *)zero;
+    for (int g = 0; g < ne; g += 4) {
+        // global-address-space pointers: the loads stay global loads (flat
+        // loads would make every wait drain the scalar-memory counter too)
+        const gdouble *pa = gz, *pai = gz;
+        const gdouble *pb[NJ], *pbi[NJ];
+#pragma unroll
+        for (int t = 0; t < NJ; ++t) pb[t] = pbi[t] = gz;
+        if (rv && g + q < ne) {
+            const int64_t e = e0 + g + q;
+            const int64_t oa = (int64_t)ea[e] * BB + r;
+            pa = (const gdouble *)(ar + oa);
+            if (AC) pai = (const gdouble *)(ai + oa);
+#pragma unroll
+            for (int t = 0; t < NJ; ++t) {
+                const int kb = eb[e * NJ + t];
+                if (kb >= 0) {
+                    const int64_t ob = (int64_t)kb * BB + r;
+                    pb[t] = (const gdouble *)(br + ob);
+                    if (BC) pbi[t] = (const gdouble *)(bi + ob);
+                }
+            }
+        }
+#pragma unroll
+        for (int st = 0; st < B; ++st) {
+            const T xa = (T)pa[st * B];
+            const T xai = AC ? (T)pai[st * B] : (T)0;
+#pragma unroll
+            for (int t = 0; t < NJ; ++t) {
+                const T xb = (T)pb[t][st * B];
+                const T xbi = BC ? (T)pbi[t][st * B] : (T)0;
+                rr[t] = Mfma16<T>::step(xa, xb, rr[t]);
+                if (AC && BC) ii[t] = Mfma16<T>::step(xai, xbi, ii[t]);
+                if (BC) ri[t] = Mfma16<T>::step(xa, xbi, ri[t]);
+                if (AC) ir[t] = Mfma16<T>::step(xai, xb, ir[t]);
+            }
+        }
+    }
+    constexpr double sb = CJB ? -1.0 : 1.0;
+#pragma unroll
+    for (int t = 0; t < NJ; ++t) {
+        const int p = cout[c * NJ + t];
+        if (p < 0) continue;                   // uniform: a short run
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int row = Mfma16<T>::row(e, q), col = r;
+            if (row < B && col < B) {
+                const double re = (double)rr[t][e] - sb * (double)ii[t][e];
+                const double im = sb * (double)ri[t][e] + (double)ir[t][e];
+                const int64_t o = (int64_t)p * BB + (LC ? col * B + row : row * B + col);
+                cr[o] = alr * re - ali * im;
+                if (ci) ci[o] = alr * im + ali * re;
+            }
+        }
+    }
+}
+
 // k_spgemm_q4 with the operands of the next group of four triples loaded into
 // registers while the matrix cores work on the current group, so the load
 // latency of one group hides behind B*SUB MFMAs of the previous one.
@@ -1256,6 +1345,35 @@ static void launch_cm(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
     }
 }
 
+// Row-run kernel (k_spgemm_q4j): runs of 2 or 4 outputs, or 8 for real operands.
+template <bool AC, bool BC, int CJB, int LC>
+static void launch_cmj(hipStream_t s, const SpgemmArgs &a)
+{
+    const int remap = getenv("RTDM_NO_XCD") ? 0 : 1;
+    const unsigned grid = xcd_grid((a.nch + 3) / 4);
+    const bool f32 = a.precision == RTDM_PREC_FP32;
+#define RT_Q4J(NJ, T)                                                                               \
+    hipLaunchKernelGGL((k_spgemm_q4j<13, AC, BC, CJB, LC, NJ, T>), dim3(grid), dim3(256), 0, s, a.nch, \
+                       a.ch_off, a.ch_a, a.ch_b, a.ch_out, a.ar, a.ai, a.br, a.bi, a.cr, a.ci,        \
+                       a.alpha_re, a.alpha_im, a.zero, a.ch_order, remap)
+    if (a.nj == 2) {
+        if (f32) RT_Q4J(2, float);
+        else RT_Q4J(2, double);
+    } else if (a.nj == 4) {
+        if (f32) RT_Q4J(4, float);
+        else RT_Q4J(4, double);
+    } else {
+        if constexpr (!AC && !BC) {
+            RT_CHECK(a.nj == 8, RTDM_E_ARG, "row runs of 2, 4 or 8 outputs");
+            if (f32) RT_Q4J(8, float);
+            else RT_Q4J(8, double);
+        } else {
+            RT_CHECK(false, RTDM_E_ARG, "row runs of complex products hold 2 or 4 outputs");
+        }
+    }
+#undef RT_Q4J
+}
+
 void launch_spgemm_cm(hipStream_t s, const SpgemmArgs &a, int conj_b, int out_col_major)
 {
     if (a.nout == 0) return;
@@ -1267,7 +1385,12 @@ void launch_spgemm_cm(hipStream_t s, const SpgemmArgs &a, int conj_b, int out_co
     const bool ac = a.ai != nullptr, bc = a.bi != nullptr;
 #define RT_CM(AC_, BC_)                                                            \
     do {                                                                           \
-        if (conj_b && out_col_major) launch_cm<AC_, BC_, 1, 1>(s, a, g, t);        \
+        if (a.nch > 0 && kernel_variant() == 0) {                                  \
+            if (conj_b && out_col_major) launch_cmj<AC_, BC_, 1, 1>(s, a);         \
+            else if (conj_b) launch_cmj<AC_, BC_, 1, 0>(s, a);                     \
+            else if (out_col_major) launch_cmj<AC_, BC_, 0, 1>(s, a);              \
+            else launch_cmj<AC_, BC_, 0, 0>(s, a);                                 \
+        } else if (conj_b && out_col_major) launch_cm<AC_, BC_, 1, 1>(s, a, g, t); \
         else if (conj_b) launch_cm<AC_, BC_, 1, 0>(s, a, g, t);                    \
         else if (out_col_major) launch_cm<AC_, BC_, 0, 1>(s, a, g, t);             \
         else launch_cm<AC_, BC_, 0, 0>(s, a, g, t);                                \

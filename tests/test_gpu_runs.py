@@ -1,0 +1,111 @@
+"""Row runs of the b = 13 step products against the oracle.
+
+The step products (X H, A tau, U K, W U^dagger) at b = 13 can compute several
+output blocks of one row per wave, sharing the left operand's loads; the run
+length is chosen per context (RTDM_RUN_REAL for the real products: 1, 2, 4
+or 8; RTDM_RUN_CPLX for the complex ones: 1, 2 or 4).  Only the order of the
+contraction sums differs, so every run length must meet the FP64 bar against
+the oracle, and agree with the single-output kernel to a few ulps.  The
+systems have rows whose lengths are not multiples of the run length, so
+short runs (absent outputs) are exercised.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1404_5776_amd import rtdm, synth
+from tests._common import TOL, dipole_floor, gpu_context, rel
+
+pytestmark = pytest.mark.gpu
+
+RUNS = [(1, 1), (2, 2), (4, 4), (8, 4), (8, 2)]
+N_STEPS = 4
+
+
+def _lattice():
+    return synth.diamond_lattice((2, 2, 2), 13, 10.0, 16.0, seed=31, k0="local", h_model="mulliken")
+
+
+def _cluster():
+    rng = np.random.default_rng(32)
+    xyz = synth.cluster_positions(37, rng)
+    return synth.build_system("cl37_b13", xyz, 13, 6.0, 8.0, 32, h_model="mulliken")
+
+
+SYSTEMS = {"lattice64_b13": _lattice, "cluster37_b13": _cluster}
+
+
+@pytest.fixture(scope="module", params=sorted(SYSTEMS))
+def reference(request):
+    s = SYSTEMS[request.param]()
+    st = O.setup(s)
+    ref = O.propagate(st, N_STEPS, s.dt, s.kappa, h_model=s.h_model)
+    return s, st, ref
+
+
+def _run(s, run_real, run_cplx, **opts):
+    old = {k: os.environ.get(k) for k in ("RTDM_RUN_REAL", "RTDM_RUN_CPLX")}
+    os.environ["RTDM_RUN_REAL"] = str(run_real)
+    os.environ["RTDM_RUN_CPLX"] = str(run_cplx)
+    try:
+        ctx = gpu_context(s, h_model=s.h_model, **opts)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    try:
+        rtdm.rtdm_build_inverse(ctx.h)
+        rtdm.rtdm_apply_kick(ctx.h, s.kappa)
+        rtdm.rtdm_step(ctx.h, s.dt, N_STEPS)
+        return rtdm.rtdm_download(ctx.h, "K", s.b), rtdm.rtdm_dipole_trace(ctx.h)
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("run_real,run_cplx", RUNS)
+def test_row_runs_match_oracle(reference, run_real, run_cplx):
+    s, st, ref = reference
+    K, tr = _run(s, run_real, run_cplx, use_graph=0)
+    q0 = O.mulliken(O.kick(st.K0, st.xyz, s.kappa), st.S)
+    P0 = O.dipole(q0, st.xyz)
+    induced = np.abs(ref.rows[:, 1:4] - P0).max()
+    err = np.abs(tr[:, 1:4] - ref.rows[:, 1:4]).max()
+    print(f"runs {run_real}/{run_cplx}: K rel {rel(K, ref.K.val):.2e}, dipole err {err:.2e} of {induced:.2e}")
+    assert rel(K, ref.K.val) <= TOL
+    assert err <= TOL * induced + dipole_floor(q0, st.xyz)
+
+
+def test_row_runs_agree_with_single_outputs(reference):
+    s, _, _ = reference
+    K1, tr1 = _run(s, 1, 1)
+    for rr, rc in RUNS[1:]:
+        K, tr = _run(s, rr, rc)
+        # same triples, contraction sums in another order: a few ulps per step
+        assert rel(K, K1) <= 1e-13, (rr, rc)
+        np.testing.assert_allclose(tr[:, 4], tr1[:, 4], rtol=1e-13)
+
+
+def test_row_runs_fp32_products():
+    """FP32 step products run the same row-run dataflow on the FP32 matrix cores."""
+    s = _lattice()
+    K1, _ = _run(s, 1, 1, precision="fp32")
+    K4, _ = _run(s, 4, 4, precision="fp32")
+    K8, _ = _run(s, 8, 2, precision="fp32")
+    # FP32 products with FP32 accumulation in another order: agreement at FP32 rounding
+    assert rel(K4, K1) <= 1e-5
+    assert rel(K8, K1) <= 1e-5
+
+
+def test_bad_run_length_is_refused():
+    s = _cluster()
+    os.environ["RTDM_RUN_REAL"] = "3"
+    try:
+        with pytest.raises(rtdm.RtdmError):
+            gpu_context(s)
+    finally:
+        os.environ.pop("RTDM_RUN_REAL", None)
