@@ -177,9 +177,9 @@ std::vector<int32_t> run_order(const Runs &R, int tile_i)
 // runs of nj consecutive columns; the entries of a run are the distinct
 // op(A) blocks of its outputs' triples (one per contraction index k), each
 // with the op(B) block of every output of the run (-1: no triple for k).
-void build_runs(Sched &S, const Pattern &C, int nj, int tile_i)
+bool build_runs(Sched &S, const Pattern &C, int nj, int tile_i)
 {
-    if (S.runs.count(nj)) return;
+    if (S.runs.count(nj)) return false;
     auto R = std::make_unique<Runs>();
     std::vector<int64_t> off(S.nout + 1);
     std::vector<int2> trip(S.ntrip);
@@ -227,6 +227,7 @@ void build_runs(Sched &S, const Pattern &C, int nj, int tile_i)
     if (!ord.empty())
         RT_HIP(hipMemcpy(R->order.p, ord.data(), ord.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     S.runs.emplace(nj, std::move(R));
+    return true;
 }
 
 struct TRec {
@@ -508,10 +509,9 @@ Sched &schedule(rtdm_ctx *c, int prod)
     auto it = c->scheds.find(key);
     if (it != c->scheds.end()) {
         // a kind sharing its patterns with an earlier one (equal cut-offs)
-        if (nj > 1) {
-            build_runs(*it->second, *c->pats[std::get<2>(key)], nj, c->row_tile);
+        // (every kind is scheduled when the ranges are set, so this never runs during a capture)
+        if (nj > 1 && build_runs(*it->second, *c->pats[std::get<2>(key)], nj, c->row_tile))
             RT_HIP(hipDeviceSynchronize());
-        }
         return *it->second;
     }
     auto S = std::make_unique<Sched>();
@@ -807,6 +807,19 @@ void build_propagator(rtdm_ctx *c, double dt, hipStream_t s)
             a.alpha_re = dt / k;
             a.order = S.order.p;
             a.wpb = c->wpb;
+            if (c->run_real > 1) {
+                auto rr = S.runs.find(c->run_real);
+                if (rr != S.runs.end() && rr->second->nch > 0) {
+                    const Runs &R = *rr->second;
+                    a.nj = R.nj;
+                    a.nch = R.nch;
+                    a.ch_off = R.off.p;
+                    a.ch_a = R.a.p;
+                    a.ch_b = R.b.p;
+                    a.ch_out = R.out.p;
+                    a.ch_order = R.order.p;
+                }
+            }
             const bool rec = c->timing && !c->capturing;
             const size_t ev = 2 * c->recs.size();
             if (rec) RT_HIP(hipEventRecord(event_at(c, ev), s));
@@ -1062,6 +1075,7 @@ int rtdm_create(rtdm_ctx **out, int hip_device, const rtdm_options *opt)
     if (const char *e = getenv("RTDM_B4_ROWSTAT")) c->row_stationary4 = atoi(e);   // measurements
     if (const char *e = getenv("RTDM_RUN_REAL")) c->run_real = atoi(e);
     if (const char *e = getenv("RTDM_RUN_CPLX")) c->run_cplx = atoi(e);
+    if (const char *e = getenv("RTDM_ROW_TILE")) c->row_tile = std::max(1, atoi(e));
     RT_CHECK((c->run_real == 1 || c->run_real == 2 || c->run_real == 4 || c->run_real == 8) &&
                  (c->run_cplx == 1 || c->run_cplx == 2 || c->run_cplx == 4),
              RTDM_E_ARG, "row runs of 1, 2, 4 (or 8, real products) outputs");

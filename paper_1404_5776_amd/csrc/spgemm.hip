@@ -1314,6 +1314,19 @@ static void dispatch_ops(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
 // Step products with a column-major copy of the left operand (op(A)[r][m] at
 // m*B + r) and a right operand whose op(B)[m][r] sits at m*B + r (row-major
 // B, or the column-major copy of a matrix used conjugate-transposed).
+// Unused LDS bytes per workgroup of the b = 13 step kernels, which caps the
+// workgroups per CU (and so the output blocks in flight per L2); 0 by
+// default, RTDM_STEP_LDS sets it for measurements.
+static unsigned occupancy_lds()
+{
+    static const unsigned v = [] {
+        const char *e = getenv("RTDM_STEP_LDS");
+        const long x = e ? atol(e) : 0;
+        return (unsigned)std::min<long>(std::max<long>(x, 0), 160 * 1024);
+    }();
+    return v;
+}
+
 template <bool AC, bool BC, int CJB, int LC>
 static void launch_cm(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
 {
@@ -1328,8 +1341,9 @@ static void launch_cm(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
         const int wpb = a.wpb;
         const int remap = getenv("RTDM_NO_XCD") ? 0 : 1;
         const unsigned grid = xcd_grid((a.nout + wpb - 1) / wpb);
+        const unsigned lds = occupancy_lds();
 #define RT_Q4(W, T)                                                                               \
-    hipLaunchKernelGGL((k_spgemm_q4<13, AC, BC, 0, CJB, LC, W, T>), dim3(grid), dim3(64 * W), 0, s, \
+    hipLaunchKernelGGL((k_spgemm_q4<13, AC, BC, 0, CJB, LC, W, T>), dim3(grid), dim3(64 * W), lds, s, \
                        a.nout, a.off, a.trip, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re,       \
                        a.alpha_im, a.zero, a.order, remap)
         if (a.precision == RTDM_PREC_FP32) {
@@ -1352,8 +1366,9 @@ static void launch_cmj(hipStream_t s, const SpgemmArgs &a)
     const int remap = getenv("RTDM_NO_XCD") ? 0 : 1;
     const unsigned grid = xcd_grid((a.nch + 3) / 4);
     const bool f32 = a.precision == RTDM_PREC_FP32;
+    const unsigned lds = occupancy_lds();
 #define RT_Q4J(NJ, T)                                                                               \
-    hipLaunchKernelGGL((k_spgemm_q4j<13, AC, BC, CJB, LC, NJ, T>), dim3(grid), dim3(256), 0, s, a.nch, \
+    hipLaunchKernelGGL((k_spgemm_q4j<13, AC, BC, CJB, LC, NJ, T>), dim3(grid), dim3(256), lds, s, a.nch, \
                        a.ch_off, a.ch_a, a.ch_b, a.ch_out, a.ar, a.ai, a.br, a.bi, a.cr, a.ci,        \
                        a.alpha_re, a.alpha_im, a.zero, a.ch_order, remap)
     if (a.nj == 2) {
@@ -1442,11 +1457,84 @@ __global__ __launch_bounds__(64 * WPB) void k_spgemm_q4r32(
     }
 }
 
+// Row-run form of k_spgemm_q4r32 (the dataflow of k_spgemm_q4j on FP32
+// storage): NJ outputs of one row per wave, each loaded left-operand element
+// feeding NJ FP32 MFMAs.
+typedef __attribute__((address_space(1))) const float gfloat;
+template <int B, int NJ>
+__global__ __launch_bounds__(256) void k_spgemm_q4jr32(
+    int64_t nch, const int64_t *__restrict__ off, const int32_t *__restrict__ ea,
+    const int32_t *__restrict__ eb, const int32_t *__restrict__ cidx, const float *__restrict__ a,
+    const float *__restrict__ b, float *__restrict__ cout, float alpha, const float *__restrict__ zero,
+    const int32_t *__restrict__ order)
+{
+    constexpr int BB = B * B;
+    const int lane = threadIdx.x & 63;
+    const int64_t w = xcd_block((nch + 3) / 4) * 4 + (threadIdx.x >> 6);
+    if (w >= nch) return;                      // uniform across the wave
+    const int64_t c = order ? (int64_t)order[w] : w;
+    const int r = lane & 15, q = lane >> 4;
+    const bool rv = r < B;
+    const int64_t e0 = off[c];
+    const int ne = (int)(off[c + 1] - e0);
+    typedef Mfma16<float>::acc_t acc_t;
+    acc_t acc[NJ];
+#pragma unroll
+    for (int t = 0; t < NJ; ++t) acc[t] = acc_t{0, 0, 0, 0};
+    const gfloat *gz = (const gfloat *)zero;
+    for (int g = 0; g < ne; g += 4) {
+        const gfloat *pa = gz;
+        const gfloat *pb[NJ];
+#pragma unroll
+        for (int t = 0; t < NJ; ++t) pb[t] = gz;
+        if (rv && g + q < ne) {
+            const int64_t e = e0 + g + q;
+            pa = (const gfloat *)(a + (int64_t)ea[e] * BB + r);
+#pragma unroll
+            for (int t = 0; t < NJ; ++t) {
+                const int kb = eb[e * NJ + t];
+                if (kb >= 0) pb[t] = (const gfloat *)(b + (int64_t)kb * BB + r);
+            }
+        }
+#pragma unroll
+        for (int st = 0; st < B; ++st) {
+            const float xa = pa[st * B];
+#pragma unroll
+            for (int t = 0; t < NJ; ++t) acc[t] = Mfma16<float>::step(xa, pb[t][st * B], acc[t]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NJ; ++t) {
+        const int p = cidx[c * NJ + t];
+        if (p < 0) continue;                   // uniform: a short run
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int row = Mfma16<float>::row(e, q), col = r;
+            if (row < B && col < B) cout[(int64_t)p * BB + row * B + col] = alpha * acc[t][e];
+        }
+    }
+}
+
 void launch_spgemm_r32(hipStream_t s, const SpgemmArgs &a, const float *a32, const float *b32, float *c32,
                        const float *zero32)
 {
     if (a.nout == 0) return;
     RT_CHECK(a.b == 13, RTDM_E_UNSUPPORTED, "FP32 step products need b = 13");
+    if (a.nch > 0) {
+        const unsigned grid = xcd_grid((a.nch + 3) / 4);
+#define RT_R32J(NJ)                                                                                     \
+    hipLaunchKernelGGL((k_spgemm_q4jr32<13, NJ>), dim3(grid), dim3(256), 0, s, a.nch, a.ch_off, a.ch_a, \
+                       a.ch_b, a.ch_out, a32, b32, c32, (float)a.alpha_re, zero32, a.ch_order)
+        if (a.nj == 2) RT_R32J(2);
+        else if (a.nj == 4) RT_R32J(4);
+        else {
+            RT_CHECK(a.nj == 8, RTDM_E_ARG, "row runs of 2, 4 or 8 outputs");
+            RT_R32J(8);
+        }
+#undef RT_R32J
+        RT_HIP(hipGetLastError());
+        return;
+    }
     const int wpb = a.wpb;
     const unsigned grid = xcd_grid((a.nout + wpb - 1) / wpb);
 #define RT_R32(W)                                                                                  \

@@ -109,3 +109,26 @@ def test_bad_run_length_is_refused():
             gpu_context(s)
     finally:
         os.environ.pop("RTDM_RUN_REAL", None)
+
+
+def test_row_runs_under_graph_capture(reference):
+    """A captured step replays the row-run kernels bit for bit (the schedules
+    and their runs are built when the ranges are set, never inside a capture)."""
+    s, _, _ = reference
+    Ke, tre = _run(s, 2, 1, use_graph=0)
+    Kg, trg = _run(s, 2, 1, use_graph=1)
+    assert np.array_equal(Ke, Kg)
+    assert np.array_equal(tre[:, :6], trg[:, :6])
+
+
+def test_row_runs_fp32_taylor_terms():
+    """FP32-storage Taylor terms (fp32_taylor) through the FP32 row-run kernel
+    agree with the single-output FP32 kernel at FP32 rounding of those terms."""
+    s = _lattice()
+    K1, tr1 = _run(s, 1, 1, precision="fp32_taylor")
+    K2, tr2 = _run(s, 2, 1, precision="fp32_taylor")
+    K8, _ = _run(s, 8, 1, precision="fp32_taylor")
+    assert rel(K2, K1) <= 1e-9
+    assert rel(K8, K1) <= 1e-9
+    induced = np.abs(tr1[:, 1:4] - tr1[0, 1:4]).max()
+    assert np.abs(tr2[:, 1:4] - tr1[:, 1:4]).max() <= 1e-7 * max(induced, 1e-300)
