@@ -320,7 +320,7 @@ struct rtdm_ctx {
     bool graph_rebuilds_u = false;
     // launch shape of the step products
     int wpb = 16, row_tile = 64;
-    int run_real = 2, run_cplx = 1;   // b = 13 step products: outputs per row run (1: single outputs)
+    int run_real = 2, run_cplx = 2;   // b = 13 step products: outputs per row run (1: single outputs)
     int row_stationary4 = 0;    // b = 4: stage each row of the left operand in LDS (measured slower than the wide kernel)
     int inv_iters_total = 0, inv_fell_back = 0;
     // ETRS / Magnus work matrices and the self-consistent corrector's state

@@ -365,8 +365,8 @@ typedef __attribute__((address_space(1))) const double gdouble;
 // blocks of A beyond L2 are then fetched once per run instead of once per
 // output; the price is the absent (zero) products of a run.  Data layout,
 // lane mapping, conjugation and output as in k_spgemm_q4.
-template <int B, bool AC, bool BC, int CJB, int LC, int NJ, class T = double>
-__global__ __launch_bounds__(256) void k_spgemm_q4j(
+template <int B, bool AC, bool BC, int CJB, int LC, int NJ, class T = double, int MINW = 1>
+__global__ __launch_bounds__(256, MINW) void k_spgemm_q4j(
     int64_t nch, const int64_t *__restrict__ off, const int32_t *__restrict__ ea,
     const int32_t *__restrict__ eb, const int32_t *__restrict__ cout,
     const double *__restrict__ ar, const double *__restrict__ ai, const double *__restrict__ br,
@@ -384,9 +384,9 @@ __global__ __launch_bounds__(256) void k_spgemm_q4j(
     const int64_t e0 = off[c];
     const int ne = (int)(off[c + 1] - e0);
     typedef typename Mfma16<T>::acc_t acc_t;
-    acc_t rr[NJ], ii[NJ], ri[NJ], ir[NJ];
+    acc_t rr[NJ], ri[NJ], ir[NJ];
 #pragma unroll
-    for (int t = 0; t < NJ; ++t) rr[t] = ii[t] = ri[t] = ir[t] = acc_t{0, 0, 0, 0};
+    for (int t = 0; t < NJ; ++t) rr[t] = ri[t] = ir[t] = acc_t{0, 0, 0, 0};
     const gdouble *gz = (const gdouble *)zero;
     for (int g = 0; g < ne; g += 4) {
         // global-address-space pointers: the loads stay global loads (flat
@@ -414,14 +414,27 @@ __global__ __launch_bounds__(256) void k_spgemm_q4j(
         for (int st = 0; st < B; ++st) {
             const T xa = (T)pa[st * B];
             const T xai = AC ? (T)pai[st * B] : (T)0;
+            if constexpr (AC && BC) {
+                // two accumulators per output: re += a_r b_r + (-s a_i) b_i,
+                // im += (s a_r) b_i + a_i b_r with s = -1 for a conjugated B
+                const T nai = CJB ? xai : -xai, sar = CJB ? -xa : xa;
 #pragma unroll
-            for (int t = 0; t < NJ; ++t) {
-                const T xb = (T)pb[t][st * B];
-                const T xbi = BC ? (T)pbi[t][st * B] : (T)0;
-                rr[t] = Mfma16<T>::step(xa, xb, rr[t]);
-                if (AC && BC) ii[t] = Mfma16<T>::step(xai, xbi, ii[t]);
-                if (BC) ri[t] = Mfma16<T>::step(xa, xbi, ri[t]);
-                if (AC) ir[t] = Mfma16<T>::step(xai, xb, ir[t]);
+                for (int t = 0; t < NJ; ++t) {
+                    const T xb = (T)pb[t][st * B], xbi = (T)pbi[t][st * B];
+                    rr[t] = Mfma16<T>::step(xa, xb, rr[t]);
+                    ri[t] = Mfma16<T>::step(sar, xbi, ri[t]);
+                    rr[t] = Mfma16<T>::step(nai, xbi, rr[t]);
+                    ri[t] = Mfma16<T>::step(xai, xb, ri[t]);
+                }
+            } else {
+#pragma unroll
+                for (int t = 0; t < NJ; ++t) {
+                    const T xb = (T)pb[t][st * B];
+                    const T xbi = BC ? (T)pbi[t][st * B] : (T)0;
+                    rr[t] = Mfma16<T>::step(xa, xb, rr[t]);
+                    if (BC) ri[t] = Mfma16<T>::step(xa, xbi, ri[t]);
+                    if (AC) ir[t] = Mfma16<T>::step(xai, xb, ir[t]);
+                }
             }
         }
     }
@@ -434,8 +447,8 @@ __global__ __launch_bounds__(256) void k_spgemm_q4j(
         for (int e = 0; e < 4; ++e) {
             const int row = Mfma16<T>::row(e, q), col = r;
             if (row < B && col < B) {
-                const double re = (double)rr[t][e] - sb * (double)ii[t][e];
-                const double im = sb * (double)ri[t][e] + (double)ir[t][e];
+                const double re = (double)rr[t][e];
+                const double im = (AC && BC) ? (double)ri[t][e] : sb * (double)ri[t][e] + (double)ir[t][e];
                 const int64_t o = (int64_t)p * BB + (LC ? col * B + row : row * B + col);
                 cr[o] = alr * re - ali * im;
                 if (ci) ci[o] = alr * im + ali * re;
@@ -1367,13 +1380,17 @@ static void launch_cmj(hipStream_t s, const SpgemmArgs &a)
     const unsigned grid = xcd_grid((a.nch + 3) / 4);
     const bool f32 = a.precision == RTDM_PREC_FP32;
     const unsigned lds = occupancy_lds();
-#define RT_Q4J(NJ, T)                                                                               \
-    hipLaunchKernelGGL((k_spgemm_q4j<13, AC, BC, CJB, LC, NJ, T>), dim3(grid), dim3(256), lds, s, a.nch, \
+#define RT_Q4J_W(NJ, T, W)                                                                       \
+    hipLaunchKernelGGL((k_spgemm_q4j<13, AC, BC, CJB, LC, NJ, T, W>), dim3(grid), dim3(256), lds, s,   \
+                       a.nch,                                                                         \
                        a.ch_off, a.ch_a, a.ch_b, a.ch_out, a.ar, a.ai, a.br, a.bi, a.cr, a.ci,        \
                        a.alpha_re, a.alpha_im, a.zero, a.ch_order, remap)
+#define RT_Q4J(NJ, T) RT_Q4J_W(NJ, T, 1)
     if (a.nj == 2) {
+        // complex runs of 2 compiled for at least 4 waves per SIMD (at most 128
+        // registers): 4 % faster than the compiler's 3; real runs lose 12 % so
         if (f32) RT_Q4J(2, float);
-        else RT_Q4J(2, double);
+        else RT_Q4J_W(2, double, (AC && BC) ? 4 : 1);
     } else if (a.nj == 4) {
         if (f32) RT_Q4J(4, float);
         else RT_Q4J(4, double);
@@ -1387,6 +1404,7 @@ static void launch_cmj(hipStream_t s, const SpgemmArgs &a)
         }
     }
 #undef RT_Q4J
+#undef RT_Q4J_W
 }
 
 void launch_spgemm_cm(hipStream_t s, const SpgemmArgs &a, int conj_b, int out_col_major)
