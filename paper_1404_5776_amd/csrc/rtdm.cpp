@@ -173,59 +173,62 @@ std::vector<int32_t> run_order(const Runs &R, int tile_i)
     return ord;
 }
 
-// Row runs of schedule S (output pattern C): the outputs of each row cut into
-// runs of nj consecutive columns; the entries of a run are the distinct
-// op(A) blocks of its outputs' triples (one per contraction index k), each
-// with the op(B) block of every output of the run (-1: no triple for k).
-bool build_runs(Sched &S, const Pattern &C, int nj, int tile_i)
+constexpr size_t kRunReserve = size_t(16) << 30;   // device memory row runs leave free
+
+// Row runs of schedule S for op(A) = A: the outputs of each row of C cut into
+// runs of nj consecutive columns; the entries of a run are the k of row i of
+// A used by any of its outputs, each with op(A)_ik and the op(B)_kj block of
+// every output (-1: no triple for k).  Built on the GPU (k_run_sym); inter4
+// stores the b = 4 kernel's slot order.
+bool build_runs(Sched &S, const Pattern &A, const Pattern &B, const Pattern &C, int op_b, int nj, int inter4,
+                int tile_i)
 {
     if (S.runs.count(nj)) return false;
     auto R = std::make_unique<Runs>();
-    std::vector<int64_t> off(S.nout + 1);
-    std::vector<int2> trip(S.ntrip);
-    RT_HIP(hipMemcpy(off.data(), S.off.p, off.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
-    if (S.ntrip) RT_HIP(hipMemcpy(trip.data(), S.trip.p, trip.size() * sizeof(int2), hipMemcpyDeviceToHost));
-    std::vector<int64_t> roff{0};
-    std::vector<int32_t> ra, rb, rout;
-    struct T3 { int32_t a, t, b; };
-    std::vector<T3> buf;
-    for (int64_t i = 0; i < C.n; ++i) {
+    std::vector<int64_t> p0s;
+    for (int64_t i = 0; i < C.n; ++i)
         for (int64_t p0 = C.rowptr[i]; p0 < C.rowptr[i + 1]; p0 += nj) {
-            const int64_t p1 = std::min<int64_t>(p0 + nj, C.rowptr[i + 1]);
-            buf.clear();
-            for (int64_t p = p0; p < p1; ++p)
-                for (int64_t e = off[p]; e < off[p + 1]; ++e)
-                    buf.push_back({trip[e].x, (int32_t)(p - p0), trip[e].y});
-            std::sort(buf.begin(), buf.end(),
-                      [](const T3 &x, const T3 &y) { return x.a != y.a ? x.a < y.a : x.t < y.t; });
-            for (size_t u = 0; u < buf.size();) {
-                const int32_t a = buf[u].a;
-                ra.push_back(a);
-                const size_t base = rb.size();
-                rb.resize(base + nj, -1);
-                for (; u < buf.size() && buf[u].a == a; ++u) rb[base + buf[u].t] = buf[u].b;
-            }
-            roff.push_back((int64_t)ra.size());
-            for (int t = 0; t < nj; ++t) rout.push_back(p0 + t < p1 ? (int32_t)(p0 + t) : -1);
             R->row.push_back((int32_t)i);
             R->col.push_back(C.col[p0]);
+            p0s.push_back(p0);
         }
-    }
     R->nj = nj;
     R->nch = (int64_t)R->row.size();
-    R->off.alloc(roff.size());
-    R->a.alloc(std::max<size_t>(ra.size(), 1));
-    R->b.alloc(std::max<size_t>(rb.size(), 1));
-    R->out.alloc(std::max<size_t>(rout.size(), 1));
-    R->order.alloc(std::max<int64_t>(R->nch, 1));
-    RT_HIP(hipMemcpy(R->off.p, roff.data(), roff.size() * sizeof(int64_t), hipMemcpyHostToDevice));
-    if (!ra.empty()) RT_HIP(hipMemcpy(R->a.p, ra.data(), ra.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    if (!rb.empty()) RT_HIP(hipMemcpy(R->b.p, rb.data(), rb.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    if (!rout.empty())
-        RT_HIP(hipMemcpy(R->out.p, rout.data(), rout.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    const int64_t nch = R->nch;
+    DBuf<int32_t> d_row;
+    DBuf<int64_t> d_p0, cnt;
+    d_row.alloc(std::max<int64_t>(nch, 1));
+    d_p0.alloc(std::max<int64_t>(nch, 1));
+    cnt.alloc(std::max<int64_t>(nch, 1));
+    std::vector<int64_t> off(nch + 1, 0);
+    if (nch) {
+        RT_HIP(hipMemcpy(d_row.p, R->row.data(), nch * sizeof(int32_t), hipMemcpyHostToDevice));
+        RT_HIP(hipMemcpy(d_p0.p, p0s.data(), nch * sizeof(int64_t), hipMemcpyHostToDevice));
+        launch_run_count(nullptr, nch, d_row.p, d_p0.p, C.d_rowptr.p, C.d_col.p, A.d_rowptr.p, A.d_col.p,
+                         B.d_rowptr.p, B.d_col.p, nj, cnt.p);
+        RT_HIP(hipMemcpy(off.data() + 1, cnt.p, nch * sizeof(int64_t), hipMemcpyDeviceToHost));
+        for (int64_t u = 0; u < nch; ++u) off[u + 1] += off[u];
+    }
+    const int64_t ne = off[nch];
+    {
+        // optional: keep per-output lists where the runs would not leave room
+        size_t free_b = 0, total_b = 0;
+        RT_HIP(hipMemGetInfo(&free_b, &total_b));
+        const double need = (double)ne * 4.0 * (1 + nj) + (double)nch * (8.0 + 4.0 * nj + 4.0);
+        if (need + (double)kRunReserve > (double)free_b) return false;
+    }
+    R->off.alloc(nch + 1);
+    R->a.alloc(std::max<int64_t>(ne, 1));
+    R->b.alloc(std::max<int64_t>(ne * nj, 1));
+    R->out.alloc(std::max<int64_t>(nch * nj, 1));
+    R->order.alloc(std::max<int64_t>(nch, 1));
+    RT_HIP(hipMemcpy(R->off.p, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    launch_run_fill(nullptr, nch, d_row.p, d_p0.p, C.d_rowptr.p, C.d_col.p, A.d_rowptr.p, A.d_col.p, B.d_rowptr.p,
+                    B.d_col.p, B.d_trans.p, op_b, nj, inter4, R->off.p, R->a.p, R->b.p, R->out.p);
     const std::vector<int32_t> ord = run_order(*R, tile_i);
     if (!ord.empty())
         RT_HIP(hipMemcpy(R->order.p, ord.data(), ord.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    RT_HIP(hipDeviceSynchronize());   // the temporaries above are freed on return
     S.runs.emplace(nj, std::move(R));
     return true;
 }
@@ -321,6 +324,7 @@ struct rtdm_ctx {
     // launch shape of the step products
     int wpb = 16, row_tile = 64;
     int run_real = 2, run_cplx = 2;   // b = 13 step products: outputs per row run (1: single outputs)
+    int run_b4 = 16;                  // b = 4 FP64 products: outputs per row run (1: single outputs)
     int row_stationary4 = 0;    // b = 4: stage each row of the left operand in LDS (measured slower than the wide kernel)
     int inv_iters_total = 0, inv_fell_back = 0;
     // ETRS / Magnus work matrices and the self-consistent corrector's state
@@ -500,18 +504,25 @@ std::tuple<int, int, int, int, int> prod_key(rtdm_ctx *c, int prod)
 Sched &schedule(rtdm_ctx *c, int prod)
 {
     auto key = prod_key(c, prod);
-    // b = 13 step products of the column-major path: X H and A tau real,
-    // U K and W U^dagger complex; row runs for the kind's run length
-    const int nj = c->b != 13 ? 1
-                   : (prod == RTDM_PROD_XH || prod == RTDM_PROD_AT) ? c->run_real
-                   : (prod == RTDM_PROD_UK || prod == RTDM_PROD_WU) ? c->run_cplx
-                                                                      : 1;
+    // Row runs: b = 13 step products of the column-major path (X H and A tau
+    // real, U K and W U^dagger complex), b = 4 FP64 products with op(A) = A.
+    const bool cm_kind = prod == RTDM_PROD_XH || prod == RTDM_PROD_AT || prod == RTDM_PROD_UK ||
+                         prod == RTDM_PROD_WU;
+    const int nj = std::get<3>(key) != 0 ? 1
+                   : c->b == 13 ? (!cm_kind ? 1
+                                   : (prod == RTDM_PROD_XH || prod == RTDM_PROD_AT) ? c->run_real
+                                                                                      : c->run_cplx)
+                   : c->b == 4 ? c->run_b4
+                               : 1;
+    auto runs_for = [&](Sched &S) {
+        // (every kind is scheduled when the ranges are set, so this never runs during a capture)
+        if (nj > 1)
+            build_runs(S, *c->pats[std::get<0>(key)], *c->pats[std::get<1>(key)], *c->pats[std::get<2>(key)],
+                       std::get<4>(key), nj, c->b == 4, c->row_tile);
+    };
     auto it = c->scheds.find(key);
     if (it != c->scheds.end()) {
-        // a kind sharing its patterns with an earlier one (equal cut-offs)
-        // (every kind is scheduled when the ranges are set, so this never runs during a capture)
-        if (nj > 1 && build_runs(*it->second, *c->pats[std::get<2>(key)], nj, c->row_tile))
-            RT_HIP(hipDeviceSynchronize());
+        runs_for(*it->second);   // a kind sharing its patterns with an earlier one (equal cut-offs)
         return *it->second;
     }
     auto S = std::make_unique<Sched>();
@@ -539,7 +550,7 @@ Sched &schedule(rtdm_ctx *c, int prod)
         if (!ord.empty())
             RT_HIP(hipMemcpy(S->order.p, ord.data(), ord.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     }
-    if (nj > 1) build_runs(*S, C, nj, c->row_tile);
+    runs_for(*S);
     RT_HIP(hipDeviceSynchronize());
     Sched &ref = *S;
     c->scheds.emplace(key, std::move(S));
@@ -617,6 +628,18 @@ void product(rtdm_ctx *c, int prod, const Mat &A, const Mat &B, Mat &C, double a
         // (R 8-12 bohr) and loses beyond (R 16), where the per-triple kernel's L2 reuse takes over
         if (max_row > kB4rMaxRow || (size_t)max_row * 16 * sizeof(double) * (A.cplx ? 2 : 1) > kB4rMaxLds)
             max_row = 0;
+    }
+    if (c->b == 4 && c->prec == RTDM_PREC_FP64 && a.op_a == 0 && max_row == 0 && c->run_b4 > 1) {
+        auto r = S.runs.find(c->run_b4);
+        if (r != S.runs.end() && r->second->nch > 0) {
+            const Runs &R = *r->second;
+            a.nj = R.nj;
+            a.nch = R.nch;
+            a.ch_off = R.off.p;
+            a.ch_a = R.a.p;
+            a.ch_b = R.b.p;
+            a.ch_out = R.out.p;
+        }
     }
     auto go = [&]() {
         if (max_row > 0) launch_spgemm_b4r(s, a, PC.n, PC.d_rowptr.p, PA.d_rowptr.p, max_row);
@@ -1076,6 +1099,8 @@ int rtdm_create(rtdm_ctx **out, int hip_device, const rtdm_options *opt)
     if (const char *e = getenv("RTDM_RUN_REAL")) c->run_real = atoi(e);
     if (const char *e = getenv("RTDM_RUN_CPLX")) c->run_cplx = atoi(e);
     if (const char *e = getenv("RTDM_ROW_TILE")) c->row_tile = std::max(1, atoi(e));
+    if (const char *e = getenv("RTDM_RUN_B4")) c->run_b4 = atoi(e);
+    RT_CHECK(c->run_b4 == 1 || c->run_b4 == 16, RTDM_E_ARG, "b = 4 row runs hold 1 or 16 outputs");
     RT_CHECK((c->run_real == 1 || c->run_real == 2 || c->run_real == 4 || c->run_real == 8) &&
                  (c->run_cplx == 1 || c->run_cplx == 2 || c->run_cplx == 4),
              RTDM_E_ARG, "row runs of 1, 2, 4 (or 8, real products) outputs");

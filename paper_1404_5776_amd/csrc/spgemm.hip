@@ -73,6 +73,87 @@ __global__ void k_sym_fill(int64_t nout, const int32_t *__restrict__ c_rowof,
     }
 }
 
+// Row runs (see SpgemmArgs::ch_*): one thread per run of up to nj (<= 16)
+// consecutive outputs p0 .. p1-1 of row i of C, op(A) = A.  The thread walks
+// row i of A (ascending k) and, in step, the rows j_t of B's pattern (the
+// patterns are symmetric, so k in row j_t means block (k, j_t) exists); an
+// entry is a k present for at least one output.  Slot of output t in an
+// entry: t, or (t % 4) * 4 + t / 4 with `inter4` (the lane order of the b = 4
+// kernel, whose lane group g reads outputs g, g + 4, g + 8, g + 12).
+constexpr int kMaxRun = 16;
+template <bool FILL>
+__global__ void k_run_sym(int64_t nch, const int32_t *__restrict__ run_row, const int64_t *__restrict__ run_p0,
+                          const int64_t *__restrict__ c_ptr, const int32_t *__restrict__ c_col,
+                          const int64_t *__restrict__ a_ptr, const int32_t *__restrict__ a_col,
+                          const int64_t *__restrict__ b_ptr, const int32_t *__restrict__ b_col,
+                          const int32_t *__restrict__ b_trans, int op_b, int nj, int inter4,
+                          int64_t *__restrict__ cnt, const int64_t *__restrict__ off, int32_t *__restrict__ ea,
+                          int32_t *__restrict__ eb, int32_t *__restrict__ rout)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nch) return;
+    const int i = run_row[c];
+    const int64_t p0 = run_p0[c];
+    const int m = (int)min<int64_t>(nj, c_ptr[i + 1] - p0);
+    int64_t pb[kMaxRun], eb_end[kMaxRun];
+    for (int t = 0; t < m; ++t) {
+        const int j = c_col[p0 + t];
+        pb[t] = b_ptr[j];
+        eb_end[t] = b_ptr[j + 1];
+    }
+    if (FILL)
+        for (int t = 0; t < nj; ++t) rout[c * nj + t] = t < m ? (int32_t)(p0 + t) : -1;
+    int64_t n = 0, o = FILL ? off[c] : 0;
+    for (int64_t pa = a_ptr[i]; pa < a_ptr[i + 1]; ++pa) {
+        const int k = a_col[pa];
+        bool any = false;
+        for (int t = 0; t < m; ++t) {
+            while (pb[t] < eb_end[t] && b_col[pb[t]] < k) ++pb[t];
+            any |= pb[t] < eb_end[t] && b_col[pb[t]] == k;
+        }
+        if (!any) continue;
+        if (FILL) {
+            ea[o] = (int32_t)pa;
+            for (int t = 0; t < nj; ++t) {
+                const int slot = inter4 ? (t & 3) * 4 + (t >> 2) : t;
+                int32_t v = -1;
+                // op(B)_kj: block (k, j) = trans of (j, k), or (j, k) itself for the conjugate transpose
+                if (t < m && pb[t] < eb_end[t] && b_col[pb[t]] == k) v = op_b ? (int32_t)pb[t] : b_trans[pb[t]];
+                eb[o * nj + slot] = v;
+            }
+            ++o;
+        } else {
+            ++n;
+        }
+    }
+    if (!FILL) cnt[c] = n;
+}
+
+void launch_run_count(hipStream_t s, int64_t nch, const int32_t *run_row, const int64_t *run_p0, const int64_t *c_ptr,
+                      const int32_t *c_col, const int64_t *a_ptr, const int32_t *a_col, const int64_t *b_ptr,
+                      const int32_t *b_col, int nj, int64_t *cnt)
+{
+    if (nch == 0) return;
+    RT_CHECK(nj >= 1 && nj <= kMaxRun, RTDM_E_ARG, "row runs hold 1..16 outputs");
+    hipLaunchKernelGGL(k_run_sym<false>, dim3((unsigned)((nch + 127) / 128)), dim3(128), 0, s, nch, run_row, run_p0,
+                       c_ptr, c_col, a_ptr, a_col, b_ptr, b_col, nullptr, 0, nj, 0, cnt, nullptr, nullptr, nullptr,
+                       nullptr);
+    RT_HIP(hipGetLastError());
+}
+
+void launch_run_fill(hipStream_t s, int64_t nch, const int32_t *run_row, const int64_t *run_p0, const int64_t *c_ptr,
+                     const int32_t *c_col, const int64_t *a_ptr, const int32_t *a_col, const int64_t *b_ptr,
+                     const int32_t *b_col, const int32_t *b_trans, int op_b, int nj, int inter4, const int64_t *off,
+                     int32_t *ea, int32_t *eb, int32_t *rout)
+{
+    if (nch == 0) return;
+    RT_CHECK(nj >= 1 && nj <= kMaxRun, RTDM_E_ARG, "row runs hold 1..16 outputs");
+    hipLaunchKernelGGL(k_run_sym<true>, dim3((unsigned)((nch + 127) / 128)), dim3(128), 0, s, nch, run_row, run_p0,
+                       c_ptr, c_col, a_ptr, a_col, b_ptr, b_col, b_trans, op_b, nj, inter4, nullptr, off, ea, eb,
+                       rout);
+    RT_HIP(hipGetLastError());
+}
+
 void launch_sym_count(hipStream_t s, int64_t nout, const int32_t *c_rowof, const int32_t *c_col,
                       const int64_t *a_ptr, const int32_t *a_col, const int64_t *b_ptr,
                       const int32_t *b_col, int64_t *cnt)
@@ -1240,6 +1321,75 @@ __global__ __launch_bounds__(256) void k_spgemm_b4w(
     }
 }
 
+// FP64 b = 4 product over row runs of 16 outputs (SpgemmArgs::ch_*, slots in
+// the lane order below): one wave per run.  Each entry k of the run is one
+// triple step: every lane loads the same op(A)_ik element position (one
+// block for the whole wave) and the op(B)_kj elements of its four outputs
+// (zero where an output has no triple with this k); instruction jj of the
+// four v_mfma_f64_4x4x4_4b runs outputs 4 jj + g in its blocks g.  Against
+// k_spgemm_b4w the left-operand loads fall from one block per output and
+// triple to one per entry; the price is the absent (zero) products.
+template <bool AC, bool BC, int OPB>
+__global__ __launch_bounds__(256) void k_spgemm_b4j(
+    int64_t nch, const int64_t *__restrict__ off, const int32_t *__restrict__ ea,
+    const int32_t *__restrict__ eb, const int32_t *__restrict__ cout, const double *__restrict__ ar,
+    const double *__restrict__ ai, const double *__restrict__ br, const double *__restrict__ bi,
+    double *__restrict__ cr, double *__restrict__ ci, double alr, double ali)
+{
+    const int lane = threadIdx.x & 63;
+    const int g = (lane >> 2) & 3, r = lane & 3, q = lane >> 4;
+    const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= nch) return;                      // uniform across the wave
+    const int ia = r * 4 + q;                          // A[r][q]
+    const int ib = OPB ? (r * 4 + q) : (q * 4 + r);    // op(B)[q][r]
+    const double cb = OPB ? -1.0 : 1.0;
+    const int64_t e0 = off[c], e1 = off[c + 1];
+    double rr[4] = {0, 0, 0, 0}, ii[4] = {0, 0, 0, 0}, ri[4] = {0, 0, 0, 0}, ir[4] = {0, 0, 0, 0};
+    for (int64_t e = e0; e < e1; ++e) {
+        const int64_t pa = (int64_t)ea[e] * 16 + ia;
+        const double xar = ar[pa];
+        const double xai = AC ? ai[pa] : 0.0;
+        const int4 kb4 = *reinterpret_cast<const int4 *>(eb + e * 16 + g * 4);
+        const int kb[4] = {kb4.x, kb4.y, kb4.z, kb4.w};
+        double xbr[4], xbi[4];
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            xbr[jj] = xbi[jj] = 0.0;
+            if (kb[jj] >= 0) {
+                const int64_t pb = (int64_t)kb[jj] * 16 + ib;
+                xbr[jj] = br[pb];
+                if (BC) xbi[jj] = cb * bi[pb];
+            }
+        }
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            rr[jj] = __builtin_amdgcn_mfma_f64_4x4x4f64(xar, xbr[jj], rr[jj], 0, 0, 0);
+            if (AC && BC) ii[jj] = __builtin_amdgcn_mfma_f64_4x4x4f64(xai, xbi[jj], ii[jj], 0, 0, 0);
+            if (BC) ri[jj] = __builtin_amdgcn_mfma_f64_4x4x4f64(xar, xbi[jj], ri[jj], 0, 0, 0);
+            if (AC) ir[jj] = __builtin_amdgcn_mfma_f64_4x4x4f64(xai, xbr[jj], ir[jj], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+        const int p = cout[c * 16 + 4 * jj + g];
+        if (p >= 0) {
+            const double re = rr[jj] - ii[jj], im = ri[jj] + ir[jj];
+            const int64_t o = (int64_t)p * 16 + q * 4 + r;
+            cr[o] = alr * re - ali * im;
+            if (ci) ci[o] = alr * im + ali * re;
+        }
+    }
+}
+
+template <bool AC, bool BC, int OB>
+static void launch_b4j(hipStream_t s, const SpgemmArgs &a)
+{
+    RT_CHECK(a.nj == 16, RTDM_E_ARG, "b = 4 row runs hold 16 outputs");
+    hipLaunchKernelGGL((k_spgemm_b4j<AC, BC, OB>), dim3((unsigned)((a.nch + 3) / 4)), dim3(256), 0, s, a.nch,
+                       a.ch_off, a.ch_a, a.ch_b, a.ch_out, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re,
+                       a.alpha_im);
+}
+
 template <bool AC, bool BC, int OB>
 static void launch_b4w(hipStream_t s, const SpgemmArgs &a)
 {
@@ -1299,6 +1449,8 @@ static void dispatch_ops(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
             hipLaunchKernelGGL((k_spgemm_kc<4, AC, BC, OA, OB, float>), g, t, 0, s, a.nout,      \
                                a.off, a.trip, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re,    \
                                a.alpha_im);                                                      \
+        else if (a.b == 4 && OA == 0 && a.nch > 0)                                               \
+            launch_b4j<AC, BC, OB>(s, a);                                                        \
         else if (a.b == 4 && OA == 0 && b4_wide())                                               \
             launch_b4w<AC, BC, OB>(s, a);                                                        \
         else if (a.b == 4)                                                                       \

@@ -1,4 +1,4 @@
-"""Row runs of the b = 13 step products against the oracle.
+"""Row runs of the block products against the oracle.
 
 The step products (X H, A tau, U K, W U^dagger) at b = 13 can compute several
 output blocks of one row per wave, sharing the left operand's loads; the run
@@ -46,10 +46,11 @@ def reference(request):
     return s, st, ref
 
 
-def _run(s, run_real, run_cplx, **opts):
-    old = {k: os.environ.get(k) for k in ("RTDM_RUN_REAL", "RTDM_RUN_CPLX")}
+def _run(s, run_real, run_cplx, run_b4=16, **opts):
+    old = {k: os.environ.get(k) for k in ("RTDM_RUN_REAL", "RTDM_RUN_CPLX", "RTDM_RUN_B4")}
     os.environ["RTDM_RUN_REAL"] = str(run_real)
     os.environ["RTDM_RUN_CPLX"] = str(run_cplx)
+    os.environ["RTDM_RUN_B4"] = str(run_b4)
     try:
         ctx = gpu_context(s, h_model=s.h_model, **opts)
     finally:
@@ -132,3 +133,32 @@ def test_row_runs_fp32_taylor_terms():
     assert rel(K8, K1) <= 1e-9
     induced = np.abs(tr1[:, 1:4] - tr1[0, 1:4]).max()
     assert np.abs(tr2[:, 1:4] - tr1[:, 1:4]).max() <= 1e-7 * max(induced, 1e-300)
+
+
+def _b4_lattice():
+    return synth.diamond_lattice((3, 3, 3), 4, 10.0, 12.0, seed=33, h_model="mulliken")
+
+
+def test_b4_row_runs_match_oracle_and_single_outputs():
+    """b = 4 FP64 products over runs of 16 outputs of a row (RTDM_RUN_B4=16,
+    the default) against the oracle and against per-output triple lists."""
+    s = _b4_lattice()
+    st = O.setup(s)
+    ref = O.propagate(st, N_STEPS, s.dt, s.kappa, h_model=s.h_model)
+    K16, tr16 = _run(s, 2, 2, run_b4=16)
+    K1, tr1 = _run(s, 2, 2, run_b4=1)
+    q0 = O.mulliken(O.kick(st.K0, st.xyz, s.kappa), st.S)
+    P0 = O.dipole(q0, st.xyz)
+    induced = np.abs(ref.rows[:, 1:4] - P0).max()
+    assert rel(K16, ref.K.val) <= TOL
+    assert np.abs(tr16[:, 1:4] - ref.rows[:, 1:4]).max() <= TOL * induced + dipole_floor(q0, st.xyz)
+    assert rel(K16, K1) <= 1e-13
+    np.testing.assert_allclose(tr16[:, 4], tr1[:, 4], rtol=1e-13)
+
+
+def test_b4_row_runs_under_graph_capture():
+    s = _b4_lattice()
+    Ke, tre = _run(s, 2, 2, run_b4=16, use_graph=0)
+    Kg, trg = _run(s, 2, 2, run_b4=16, use_graph=1)
+    assert np.array_equal(Ke, Kg)
+    assert np.array_equal(tre[:, :6], trg[:, :6])
