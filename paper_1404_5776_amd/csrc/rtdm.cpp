@@ -629,7 +629,9 @@ void product(rtdm_ctx *c, int prod, const Mat &A, const Mat &B, Mat &C, double a
         if (max_row > kB4rMaxRow || (size_t)max_row * 16 * sizeof(double) * (A.cplx ? 2 : 1) > kB4rMaxLds)
             max_row = 0;
     }
-    if (c->b == 4 && c->prec == RTDM_PREC_FP64 && a.op_a == 0 && max_row == 0 && c->run_b4 > 1) {
+    const bool b4_runs_prec = c->prec == RTDM_PREC_FP64 || c->prec == RTDM_PREC_FP32 ||
+                              c->prec == RTDM_PREC_BF16X3 || c->prec == RTDM_PREC_FP16X2;
+    if (c->b == 4 && b4_runs_prec && a.op_a == 0 && max_row == 0 && c->run_b4 > 1) {
         auto r = S.runs.find(c->run_b4);
         if (r != S.runs.end() && r->second->nch > 0) {
             const Runs &R = *r->second;
@@ -814,7 +816,9 @@ void build_propagator(rtdm_ctx *c, double dt, hipStream_t s)
     };
     int cur = 0;          // tau[cur] (FP64) or tau32[cur] (FP32) holds tau_{k-1}
     bool in32 = false;
-    if (low32 && n0 <= p) launch_to_f32(s, pat_of(c, R_P).nnzb, c->b, 0, c->Ac.re.p, c->Ac32.p);
+    // FP32 copy of A: of its column-major copy at b = 13, of A itself (row-major) at b = 4
+    if (low32 && n0 <= p)
+        launch_to_f32(s, pat_of(c, R_P).nnzb, c->b, 0, c->b == 13 ? c->Ac.re.p : A.re.p, c->Ac32.p);
     for (int k = 2; k <= p; ++k) {
         if (low32 && k >= n0) {
             if (!in32) {
@@ -830,8 +834,9 @@ void build_propagator(rtdm_ctx *c, double dt, hipStream_t s)
             a.alpha_re = dt / k;
             a.order = S.order.p;
             a.wpb = c->wpb;
-            if (c->run_real > 1) {
-                auto rr = S.runs.find(c->run_real);
+            const int nj = c->b == 4 ? c->run_b4 : c->run_real;
+            if (nj > 1) {
+                auto rr = S.runs.find(nj);
                 if (rr != S.runs.end() && rr->second->nch > 0) {
                     const Runs &R = *rr->second;
                     a.nj = R.nj;
@@ -1203,7 +1208,7 @@ int rtdm_set_ranges(rtdm_ctx *c, double R_hs, double R_p, double R_k)
     c->Ac32.release();
     c->tau32[0].release();
     c->tau32[1].release();
-    if (c->b == 13 && c->opt.precision == RTDM_PREC_FP32_TAYLOR) {
+    if ((c->b == 13 || c->b == 4) && c->opt.precision == RTDM_PREC_FP32_TAYLOR) {
         const int64_t ne = pat_of(c, R_P).nnzb * (int64_t)c->b * c->b;
         c->Ac32.alloc(ne);
         c->tau32[0].alloc(ne);

@@ -1159,32 +1159,44 @@ template <> struct Small4<2> {
     typedef _Float16 e_t;
 };
 
-template <bool AC, bool BC, int OPB, int MODE>
+//
+// RUNS: the wave computes a row run of 16 outputs (SpgemmArgs::ch_*, b = 4
+// slot order) instead of 16 consecutive outputs: all blocks share the entry's
+// op(A)_ik, and block blk takes the op(B)_kj of output blk (zero if absent).
+template <bool AC, bool BC, int OPB, int MODE, bool RUNS = false>
 __global__ __launch_bounds__(256) void k_spgemm_b4x(
     int64_t nout, const int64_t *__restrict__ off, const int2 *__restrict__ trip,
     const double *__restrict__ ar, const double *__restrict__ ai, const double *__restrict__ br,
     const double *__restrict__ bi, double *__restrict__ cr, double *__restrict__ ci, double alr, double ali,
-    const double *__restrict__ maxabs)
+    const double *__restrict__ maxabs, const int32_t *__restrict__ ea = nullptr,
+    const int32_t *__restrict__ eb = nullptr, const int32_t *__restrict__ rout = nullptr)
 {
     const int lane = threadIdx.x & 63;
     const int blk = lane >> 2, r = lane & 3;
-    const int64_t c0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+    // RUNS: nout is the number of runs, off the entry offsets
+    const int64_t wv = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t c0 = RUNS ? wv : wv * 16;
     if (c0 >= nout) return;                    // uniform across the wave
-    const int64_t c = c0 + blk;
-    const bool live = c < nout;
-    const int64_t t0 = live ? off[c] : 0;
-    const int nt = live ? (int)(off[c + 1] - t0) : 0;
+    const int64_t c = RUNS ? (int64_t)rout[wv * 16 + blk] : c0 + blk;
+    const bool live = RUNS ? c >= 0 : c < nout;
+    const int64_t t0 = RUNS ? off[wv] : (live ? off[c] : 0);
+    const int nt = RUNS ? (int)(off[wv + 1] - t0) : (live ? (int)(off[c + 1] - t0) : 0);
     int ntmax = nt;
+    if (!RUNS) {
 #pragma unroll
-    for (int o = 4; o < 64; o <<= 1) ntmax = max(ntmax, __shfl_xor(ntmax, o, 64));
+        for (int o = 4; o < 64; o <<= 1) ntmax = max(ntmax, __shfl_xor(ntmax, o, 64));
+    }
+    const int slot = (blk & 3) * 4 + (blk >> 2);
     const float sa = MODE == 2 ? f16_scale(maxabs, 0) : 1.0f;
     const float sb = MODE == 2 ? f16_scale(maxabs, 1) : 1.0f;
     f32x4 h[4] = {}, m[4] = {};                // rr, ii, ri, ir
     const double cb = OPB ? -1.0 : 1.0;
     for (int t = 0; t < ntmax; ++t) {
         double xa[4] = {0, 0, 0, 0}, xai[4] = {0, 0, 0, 0}, xb[4] = {0, 0, 0, 0}, xbi[4] = {0, 0, 0, 0};
-        if (t < nt) {
-            const int2 ab = trip[t0 + t];
+        int2 ab = make_int2(0, -1);
+        if (RUNS) ab = make_int2(ea[t0 + t], eb[(t0 + t) * 16 + slot]);
+        else if (t < nt) ab = trip[t0 + t];
+        if (ab.y >= 0) {
             const int64_t pa = (int64_t)ab.x * 16 + r * 4, pb = (int64_t)ab.y * 16;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -1246,6 +1258,18 @@ __global__ __launch_bounds__(256) void k_spgemm_b4x(
 template <bool AC, bool BC, int OB>
 static void launch_b4x(hipStream_t s, const SpgemmArgs &a)
 {
+    if (a.nch > 0) {
+        RT_CHECK(a.nj == 16, RTDM_E_ARG, "b = 4 row runs hold 16 outputs");
+        const dim3 g((unsigned)((a.nch + 3) / 4)), t(256);
+#define RT_B4XJ(M)                                                                                      \
+    hipLaunchKernelGGL((k_spgemm_b4x<AC, BC, OB, M, true>), g, t, 0, s, a.nch, a.ch_off, a.trip, a.ar, a.ai, \
+                       a.br, a.bi, a.cr, a.ci, a.alpha_re, a.alpha_im, a.maxabs, a.ch_a, a.ch_b, a.ch_out)
+        if (a.precision == RTDM_PREC_FP32) RT_B4XJ(0);
+        else if (a.precision == RTDM_PREC_BF16X3) RT_B4XJ(1);
+        else RT_B4XJ(2);
+#undef RT_B4XJ
+        return;
+    }
     const dim3 g((unsigned)((a.nout + 63) / 64)), t(256);
 #define RT_B4X(M)                                                                                     \
     hipLaunchKernelGGL((k_spgemm_b4x<AC, BC, OB, M>), g, t, 0, s, a.nout, a.off, a.trip, a.ar, a.ai, a.br, \
@@ -1685,11 +1709,73 @@ __global__ __launch_bounds__(256) void k_spgemm_q4jr32(
     }
 }
 
+// Real FP32-storage b = 4 product (the late Taylor terms of the fp32_taylor
+// form): FP32 row-major blocks, v_mfma_f32_4x4x1_16b with FP32 accumulation,
+// FP32 output scaled by alpha; lane 4 blk + r holds row r of A_blk and
+// column r of B_blk.  RUNS: one row run of 16 outputs per wave (entries
+// shared by all blocks, b = 4 slot order); otherwise 16 consecutive outputs
+// per wave, each with its own triple list.
+template <bool RUNS>
+__global__ __launch_bounds__(256) void k_spgemm_b4r32(
+    int64_t n, const int64_t *__restrict__ off, const int2 *__restrict__ trip, const int32_t *__restrict__ ea,
+    const int32_t *__restrict__ eb, const int32_t *__restrict__ rout, const float *__restrict__ a,
+    const float *__restrict__ b, float *__restrict__ c32, float alpha)
+{
+    const int lane = threadIdx.x & 63;
+    const int blk = lane >> 2, r = lane & 3;
+    const int64_t wv = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t c0 = RUNS ? wv : wv * 16;
+    if (c0 >= n) return;                       // uniform across the wave
+    const int64_t c = RUNS ? (int64_t)rout[wv * 16 + blk] : c0 + blk;
+    const bool live = RUNS ? c >= 0 : c < n;
+    const int64_t t0 = RUNS ? off[wv] : (live ? off[c] : 0);
+    const int nt = RUNS ? (int)(off[wv + 1] - t0) : (live ? (int)(off[c + 1] - t0) : 0);
+    int ntmax = nt;
+    if (!RUNS) {
+#pragma unroll
+        for (int o = 4; o < 64; o <<= 1) ntmax = max(ntmax, __shfl_xor(ntmax, o, 64));
+    }
+    const int slot = (blk & 3) * 4 + (blk >> 2);
+    f32x4 h = {0, 0, 0, 0};
+    for (int t = 0; t < ntmax; ++t) {
+        int2 ab = make_int2(0, -1);
+        if (RUNS) ab = make_int2(ea[t0 + t], eb[(t0 + t) * 16 + slot]);
+        else if (t < nt) ab = trip[t0 + t];
+        float xa[4] = {0, 0, 0, 0}, xb[4] = {0, 0, 0, 0};
+        if (ab.y >= 0) {
+            const f32x4 ar4 = *reinterpret_cast<const f32x4 *>(a + (int64_t)ab.x * 16 + r * 4);   // A[r][0..3]
+            const int64_t pb = (int64_t)ab.y * 16 + r;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                xa[k] = ar4[k];
+                xb[k] = b[pb + k * 4];                                                         // B[k][r]
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) h = __builtin_amdgcn_mfma_f32_4x4x1f32(xa[k], xb[k], h, 0, 0, 0);
+    }
+    if (!live) return;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) c32[c * 16 + e * 4 + r] = alpha * h[e];
+}
+
 void launch_spgemm_r32(hipStream_t s, const SpgemmArgs &a, const float *a32, const float *b32, float *c32,
                        const float *zero32)
 {
     if (a.nout == 0) return;
-    RT_CHECK(a.b == 13, RTDM_E_UNSUPPORTED, "FP32 step products need b = 13");
+    RT_CHECK(a.b == 13 || a.b == 4, RTDM_E_UNSUPPORTED, "FP32 step products need b = 4 or 13");
+    if (a.b == 4) {
+        if (a.nch > 0) {
+            RT_CHECK(a.nj == 16, RTDM_E_ARG, "b = 4 row runs hold 16 outputs");
+            hipLaunchKernelGGL(k_spgemm_b4r32<true>, dim3((unsigned)((a.nch + 3) / 4)), dim3(256), 0, s, a.nch,
+                               a.ch_off, nullptr, a.ch_a, a.ch_b, a.ch_out, a32, b32, c32, (float)a.alpha_re);
+        } else {
+            hipLaunchKernelGGL(k_spgemm_b4r32<false>, dim3((unsigned)((a.nout + 63) / 64)), dim3(256), 0, s,
+                               a.nout, a.off, a.trip, nullptr, nullptr, nullptr, a32, b32, c32, (float)a.alpha_re);
+        }
+        RT_HIP(hipGetLastError());
+        return;
+    }
     if (a.nch > 0) {
         const unsigned grid = xcd_grid((a.nch + 3) / 4);
 #define RT_R32J(NJ)                                                                                     \

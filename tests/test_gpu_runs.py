@@ -162,3 +162,16 @@ def test_b4_row_runs_under_graph_capture():
     Kg, trg = _run(s, 2, 2, run_b4=16, use_graph=1)
     assert np.array_equal(Ke, Kg)
     assert np.array_equal(tre[:, :6], trg[:, :6])
+
+
+@pytest.mark.parametrize("precision", ["fp32_taylor", "bf16x3_taylor", "fp16x2_taylor", "fp32"])
+def test_b4_row_runs_reduced_precision(precision):
+    """The reduced-precision b = 4 kernel over row runs agrees with its
+    per-output form at the rounding of the reduced terms (late Taylor terms
+    only: 1e-8 of K; every product reduced: 1e-5)."""
+    s = _b4_lattice()
+    K16, _ = _run(s, 2, 2, run_b4=16, precision=precision)
+    K1, _ = _run(s, 2, 2, run_b4=1, precision=precision)
+    bound = 1e-5 if precision == "fp32" else 1e-8
+    print(f"{precision}: runs vs per-output K rel {rel(K16, K1):.2e}")
+    assert rel(K16, K1) <= bound
