@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 (matrix and vector)
 # Identifies the product kernel build whose HBM traffic profiles/traffic.json holds;
 # change it whenever the kernel changes so that a stale figure is not reported.
-KERNEL_TAG = "q4-b13-xcd-tile64-wpb16-v2"
+KERNEL_TAG = "q4j-b13-nj2-xcd-tile64-v1"
 
 
 def measured_traffic(dom):
@@ -462,7 +462,7 @@ def main():
         "spgemm_tflop_per_step": flops_per_step / 1e12,
         "accuracy": "FP64 path; equals the FP64 oracle within 1e-10 relative in the parity tests, "
                     "so its dipole error vs FP64 is at that level",
-        "roofline": {"bound": "mfma", "kernel": f"k_spgemm_q4<13> ({dom} product)", "achieved": achieved,
+        "roofline": {"bound": "mfma", "kernel": f"k_spgemm_q4j<13, NJ=2> ({dom} product)", "achieved": achieved,
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": measured_traffic(dom), "traffic_unit": "bytes per launch",
                      "avg_launch_ms": avg_s * 1e3,
