@@ -3,11 +3,13 @@
 The step products (X H, A tau, U K, W U^dagger) at b = 13 can compute several
 output blocks of one row per wave, sharing the left operand's loads; the run
 length is chosen per context (RTDM_RUN_REAL for the real products: 1, 2, 4
-or 8; RTDM_RUN_CPLX for the complex ones: 1, 2 or 4).  Only the order of the
-contraction sums differs, so every run length must meet the FP64 bar against
-the oracle, and agree with the single-output kernel to a few ulps.  The
-systems have rows whose lengths are not multiples of the run length, so
-short runs (absent outputs) are exercised.
+or 8; RTDM_RUN_CPLX for the complex ones: 1, 2 or 4).  At b = 4 the products
+run over runs of 16 outputs (RTDM_RUN_B4=16) or per-output lists
+(RTDM_RUN_B4=1).  Only the order of the contraction sums differs, so every
+run length must meet the FP64 bar against the oracle, and agree with the
+single-output kernels to a few ulps.  The systems have rows whose lengths
+are not multiples of the run length, so short runs (absent outputs) are
+exercised.
 """
 
 import os
