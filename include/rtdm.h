@@ -171,7 +171,18 @@ typedef struct {
 int rtdm_default_options(rtdm_options *opt);
 
 /* Create a context on HIP device `hip_device` (opt NULL = defaults).
- * *out receives the context; the caller releases it with rtdm_destroy. */
+ * *out receives the context; the caller releases it with rtdm_destroy.
+ * Kernel-shape variables read from the environment at creation (for
+ * measurements; results differ only in the order of the contraction sums):
+ *   RTDM_RUN_REAL   outputs per row run of the real b = 13 step products (1, 2, 4, 8; default 2)
+ *   RTDM_RUN_CPLX   the same for the complex ones (1, 2, 4; default 2)
+ *   RTDM_RUN_B4     b = 4 products over row runs of 16 outputs (16, default) or per-output lists (1)
+ *   RTDM_ROW_TILE   rows per output tile of the b = 13 processing order (default 64)
+ *   RTDM_B4_ROWSTAT b = 4 row-stationary kernel (1; default 0)
+ * and at the first product launch: RTDM_STEP_LDS (unused LDS bytes per workgroup of the b = 13 step
+ * kernels, capping their occupancy), RTDM_NO_XCD (plain workgroup order), RTDM_B4_WIDE (0: the
+ * 4-output b = 4 kernel), RTDM_B13_KERNEL (earlier b = 13 kernel variants 1-3).
+ * A run length outside these values fails with RTDM_E_ARG. */
 int rtdm_create(rtdm_ctx **out, int hip_device, const rtdm_options *opt);
 
 /* Release every host and device resource of ctx (NULL is accepted). */
