@@ -1500,9 +1500,6 @@ static void dispatch_ops(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
 #undef RT_LAUNCH
 }
 
-// Step products with a column-major copy of the left operand (op(A)[r][m] at
-// m*B + r) and a right operand whose op(B)[m][r] sits at m*B + r (row-major
-// B, or the column-major copy of a matrix used conjugate-transposed).
 // Unused LDS bytes per workgroup of the b = 13 step kernels, which caps the
 // workgroups per CU (and so the output blocks in flight per L2); 0 by
 // default, RTDM_STEP_LDS sets it for measurements.
@@ -1516,6 +1513,9 @@ static unsigned occupancy_lds()
     return v;
 }
 
+// Step products with a column-major copy of the left operand (op(A)[r][m] at
+// m*B + r) and a right operand whose op(B)[m][r] sits at m*B + r (row-major
+// B, or the column-major copy of a matrix used conjugate-transposed).
 template <bool AC, bool BC, int CJB, int LC>
 static void launch_cm(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
 {
