@@ -405,7 +405,9 @@ int rtdm_inverse_error(rtdm_ctx *ctx, double out[3], void *hip_stream);
 /* Test entry: C = P_C(alpha op(A) op(B)) on the slots' patterns, where op is
  * the identity (0) or the conjugate transpose (1).  The (range(A), range(B),
  * range(C), op_a, op_b) combination must be one of RTDM_PROD_* (else
- * RTDM_E_UNSUPPORTED).  C becomes complex if A, B or alpha is.  Async. */
+ * RTDM_E_UNSUPPORTED).  C becomes complex if A, B or alpha is.  At b = 13
+ * in FP64 or FP32 the step kinds (X H, A tau, U K, W U^dagger) with a real
+ * alpha run the step's kernels and layouts; the call then synchronises. */
 int rtdm_multiply(rtdm_ctx *ctx, rtdm_mat C, rtdm_mat A, rtdm_mat B, int op_a, int op_b,
                   double alpha_re, double alpha_im, void *hip_stream);
 

@@ -2287,7 +2287,39 @@ int rtdm_multiply(rtdm_ctx *c, rtdm_mat Cm, rtdm_mat Am, rtdm_mat Bm, int op_a, 
     RT_CHECK(C.cplx || !cres, RTDM_E_UNSUPPORTED, "complex result for a real matrix slot");
     c->prec = all_products_prec(c);
     try {
-        product(c, prod, A, B, C, alr, ali, s);
+        // The step products of the b = 13 column-major path run exactly as in a
+        // step: column-major copies of A (and of B when it is conjugate-
+        // transposed), the row-run kernels, and U K written column-major.
+        const bool step_kind = prod == RTDM_PROD_XH || prod == RTDM_PROD_AT || prod == RTDM_PROD_UK ||
+                               prod == RTDM_PROD_WU;
+        if (use_cm(c) && step_kind && op_a == 0 && ali == 0.0) {
+            auto like = [&](Mat &m, const Mat &ref) {
+                m.pat = ref.pat;
+                m.cplx = ref.cplx;
+                const int64_t ne = c->pats[ref.pat]->nnzb * (int64_t)c->b * c->b;
+                m.re.alloc(ne);
+                if (ref.cplx) m.im.alloc(ne);
+            };
+            Mat Acm, Bcm, Ccm;
+            like(Acm, A);
+            transpose_into(c, A, Acm, s);
+            const Mat *Bp = &B;
+            if (op_b) {
+                like(Bcm, B);
+                transpose_into(c, B, Bcm, s);
+                Bp = &Bcm;
+            }
+            if (prod == RTDM_PROD_UK) {
+                like(Ccm, C);
+                product_cm(c, prod, Acm, *Bp, Ccm, op_b, 1, alr, s);
+                transpose_into(c, Ccm, C, s);
+            } else {
+                product_cm(c, prod, Acm, *Bp, C, op_b, 0, alr, s);
+            }
+            RT_HIP(hipStreamSynchronize(s));   // the copies are freed on return
+        } else {
+            product(c, prod, A, B, C, alr, ali, s);
+        }
     } catch (...) {
         c->prec = RTDM_PREC_FP64;
         throw;
