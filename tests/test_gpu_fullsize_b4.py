@@ -1,0 +1,96 @@
+"""Full-size checks on the 65,536-atom b = 4 lattice (R_HS 10, R_K = R_P 12).
+
+The products run through the same kernels and launch configuration as the
+steps on this workload (row runs of 16 outputs, `k_spgemm_b4j`); the oracle
+recomputes sampled output rows one by one (rows at the start, the middle and
+the end of the atom order).  The propagation is checked through properties
+that hold at any size: exact Hermiticity, conservation of Tr(KS) to the
+Taylor and truncation defects, and a small unitarity error.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1404_5776_amd import rtdm, synth
+from tests._common import TOL, gpu_context
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def big4():
+    s = synth.config5(n_steps=2)
+    st = O.setup(s)
+    ctx = gpu_context(s, h_model="mulliken")
+    yield s, st, ctx
+    ctx.close()
+
+
+def _sample_rows(n):
+    return [(0, 3), (n // 2 - 2, n // 2 + 1), (n - 3, n)]
+
+
+@pytest.mark.parametrize("kind", ["XH", "AT", "UK", "WU"])
+def test_fullsize_b4_product_sampled_rows(big4, kind):
+    s, st, ctx = big4
+    b, h = s.b, ctx.h
+    pp, ph, pk = st.pat_p, st.pat_hs, st.pat_k
+    spec = {"XH": ("A", "X", "H", 0, (pp, False), (ph, False), pp, 1.0),
+            "AT": ("U", "A", "X", 0, (pp, False), (pp, False), pp, 0.05 / 3),
+            "UK": ("W", "U", "K", 0, (pp, True), (pk, True), pk, 1.0),
+            "WU": ("K", "W", "U", 1, (pk, True), (pp, True), pk, 1.0)}[kind]
+    Cs, As, Bs, ob, (pa, ca), (pb, cb), pc, alpha = spec
+    a = synth.random_blocks(pa.rows(), pa.col, b, 41, ca)
+    bm = synth.random_blocks(pb.rows(), pb.col, b, 42, cb)
+    rtdm.rtdm_upload(h, As, a)
+    rtdm.rtdm_upload(h, Bs, bm)
+    rtdm.rtdm_multiply(h, Cs, As, Bs, 0, ob, alpha)
+    got = rtdm.rtdm_download(h, Cs, b)
+    A = O.BSM(pa, b, a.astype(np.complex128))
+    B = O.BSM(pb, b, bm.astype(np.complex128))
+    del a, bm
+    r = pc.rows()
+    for lo, hi in _sample_rows(s.n_atoms):
+        want, _ = O.spgemm(A, B, pc, alpha=alpha, op_b=ob, rows=(lo, hi))
+        sel = (r >= lo) & (r < hi)
+        g, w = got[sel], want.val[sel]
+        assert np.linalg.norm(g - w) <= TOL * np.linalg.norm(w), (kind, lo)
+        assert np.abs(g - w).max() <= TOL * np.abs(w).max(), (kind, lo)
+
+
+def test_fullsize_b4_triple_counts(big4):
+    s, st, ctx = big4
+    out = {k: rtdm.rtdm_schedule_stats(ctx.h, k) for k in ("XH", "AT", "UK", "WU")}
+    assert out["XH"][0] == st.pat_p.nnzb and out["UK"][0] == st.pat_k.nnzb
+    # per-row triple counts of the A T product on sampled rows, by brute force
+    pp = st.pat_p
+    rows = {i: set(pp.col[pp.row_ptr[i]:pp.row_ptr[i + 1]].tolist())
+            for i in (0, s.n_atoms // 2, s.n_atoms - 1)}
+    for i, ri in rows.items():
+        cnt = sum(len(ri & set(pp.col[pp.row_ptr[j]:pp.row_ptr[j + 1]].tolist())) for j in ri)
+        Z = O.zeros(pp, s.b)
+        _, t = O.spgemm(Z, Z, pp, rows=(i, i + 1))
+        assert t == cnt
+    # survey sizing for this workload: about 4.1e8 triples for A T and U K
+    assert 3.7e8 < out["AT"][1] < 4.5e8
+    assert 3.7e8 < out["UK"][1] < 4.5e8
+
+
+def test_fullsize_b4_steps_keep_invariants(big4):
+    s, st, ctx = big4
+    h = ctx.h
+    ctx.load_system(s)
+    it, res = rtdm.rtdm_build_inverse(h)
+    assert it <= 10 and res <= 1e-10
+    rtdm.rtdm_apply_kick(h, s.kappa)
+    obs0 = rtdm.rtdm_observables(h)
+    rtdm.rtdm_step(h, s.dt, 2)
+    tr = rtdm.rtdm_dipole_trace(h)
+    assert tr.shape == (2, 7) and np.all(np.isfinite(tr[:, :6]))
+    assert np.abs(tr[:, 4] - obs0[3]).max() <= 1e-6 * abs(obs0[3])
+    u = rtdm.rtdm_unitarity(h)
+    assert u[0] < 1e-5
+    K = rtdm.rtdm_download(h, "K", s.b)
+    t = st.pat_k.transpose_index()
+    assert np.array_equal(K, np.conj(np.transpose(K[t], (0, 2, 1))))
