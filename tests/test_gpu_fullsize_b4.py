@@ -94,3 +94,40 @@ def test_fullsize_b4_steps_keep_invariants(big4):
     K = rtdm.rtdm_download(h, "K", s.b)
     t = st.pat_k.transpose_index()
     assert np.array_equal(K, np.conj(np.transpose(K[t], (0, 2, 1))))
+
+
+@pytest.fixture(scope="module")
+def big4_r20():
+    """The largest cut-off of the 32,768-atom sweep (R_K = R_P 20 bohr: about
+    4.2e9 triples per product)."""
+    s = synth.config3(20.0, n_steps=2)
+    st = O.setup(s)
+    ctx = gpu_context(s, h_model="mulliken")
+    yield s, st, ctx
+    ctx.close()
+
+
+@pytest.mark.parametrize("kind", ["AT", "WU"])
+def test_fullsize_b4_r20_product_sampled_rows(big4_r20, kind):
+    s, st, ctx = big4_r20
+    b, h = s.b, ctx.h
+    pp, pk = st.pat_p, st.pat_k
+    spec = {"AT": ("U", "A", "X", 0, (pp, False), (pp, False), pp, 0.05 / 3),
+            "WU": ("K", "W", "U", 1, (pk, True), (pp, True), pk, 1.0)}[kind]
+    Cs, As, Bs, ob, (pa, ca), (pb, cb), pc, alpha = spec
+    a = synth.random_blocks(pa.rows(), pa.col, b, 51, ca)
+    bm = synth.random_blocks(pb.rows(), pb.col, b, 52, cb)
+    rtdm.rtdm_upload(h, As, a)
+    rtdm.rtdm_upload(h, Bs, bm)
+    rtdm.rtdm_multiply(h, Cs, As, Bs, 0, ob, alpha)
+    got = rtdm.rtdm_download(h, Cs, b)
+    A = O.BSM(pa, b, a.astype(np.complex128))
+    B = O.BSM(pb, b, bm.astype(np.complex128))
+    del a, bm
+    r = pc.rows()
+    for lo, hi in _sample_rows(s.n_atoms):
+        want, _ = O.spgemm(A, B, pc, alpha=alpha, op_b=ob, rows=(lo, hi))
+        sel = (r >= lo) & (r < hi)
+        g, w = got[sel], want.val[sel]
+        assert np.linalg.norm(g - w) <= TOL * np.linalg.norm(w), (kind, lo)
+        assert np.abs(g - w).max() <= TOL * np.abs(w).max(), (kind, lo)
