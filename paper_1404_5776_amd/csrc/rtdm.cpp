@@ -1106,9 +1106,10 @@ int rtdm_create(rtdm_ctx **out, int hip_device, const rtdm_options *opt)
     if (const char *e = getenv("RTDM_ROW_TILE")) c->row_tile = std::max(1, atoi(e));
     if (const char *e = getenv("RTDM_RUN_B4")) c->run_b4 = atoi(e);
     RT_CHECK(c->run_b4 == 1 || c->run_b4 == 16, RTDM_E_ARG, "b = 4 row runs hold 1 or 16 outputs");
-    RT_CHECK((c->run_real == 1 || c->run_real == 2 || c->run_real == 4 || c->run_real == 8) &&
-                 (c->run_cplx == 1 || c->run_cplx == 2 || c->run_cplx == 4),
-             RTDM_E_ARG, "row runs of 1, 2, 4 (or 8, real products) outputs");
+    RT_CHECK((c->run_real >= 1 && c->run_real <= 4) || c->run_real == 8, RTDM_E_ARG,
+             "row runs of 1 to 4 or 8 outputs for real products");
+    RT_CHECK(c->run_cplx >= 1 && c->run_cplx <= 4, RTDM_E_ARG,
+             "row runs of 1 to 4 outputs for complex products");
     c->partials.alloc(kRedBlocks * 4);
     c->herm_sums.alloc(4);
     c->unit_sums.alloc(4);

@@ -1548,7 +1548,7 @@ static void launch_cm(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
     }
 }
 
-// Row-run kernel (k_spgemm_q4j): runs of 2 or 4 outputs, or 8 for real operands.
+// Row-run kernel (k_spgemm_q4j): runs of 2, 3 or 4 outputs, or 8 for real operands.
 template <bool AC, bool BC, int CJB, int LC>
 static void launch_cmj(hipStream_t s, const SpgemmArgs &a)
 {
@@ -1567,16 +1567,19 @@ static void launch_cmj(hipStream_t s, const SpgemmArgs &a)
         // registers): 4 % faster than the compiler's 3; real runs lose 12 % so
         if (f32) RT_Q4J(2, float);
         else RT_Q4J_W(2, double, (AC && BC) ? 4 : 1);
+    } else if (a.nj == 3) {
+        if (f32) RT_Q4J(3, float);
+        else RT_Q4J_W(3, double, (AC && BC) ? 4 : 1);
     } else if (a.nj == 4) {
         if (f32) RT_Q4J(4, float);
         else RT_Q4J(4, double);
     } else {
         if constexpr (!AC && !BC) {
-            RT_CHECK(a.nj == 8, RTDM_E_ARG, "row runs of 2, 4 or 8 outputs");
+            RT_CHECK(a.nj == 8, RTDM_E_ARG, "row runs of 2, 3, 4 or 8 outputs");
             if (f32) RT_Q4J(8, float);
             else RT_Q4J(8, double);
         } else {
-            RT_CHECK(false, RTDM_E_ARG, "row runs of complex products hold 2 or 4 outputs");
+            RT_CHECK(false, RTDM_E_ARG, "row runs of complex products hold 2, 3 or 4 outputs");
         }
     }
 #undef RT_Q4J
@@ -1782,6 +1785,7 @@ void launch_spgemm_r32(hipStream_t s, const SpgemmArgs &a, const float *a32, con
     hipLaunchKernelGGL((k_spgemm_q4jr32<13, NJ>), dim3(grid), dim3(256), 0, s, a.nch, a.ch_off, a.ch_a, \
                        a.ch_b, a.ch_out, a32, b32, c32, (float)a.alpha_re, zero32, a.ch_order)
         if (a.nj == 2) RT_R32J(2);
+        else if (a.nj == 3) RT_R32J(3);
         else if (a.nj == 4) RT_R32J(4);
         else {
             RT_CHECK(a.nj == 8, RTDM_E_ARG, "row runs of 2, 4 or 8 outputs");

@@ -2,8 +2,8 @@
 
 The step products (X H, A tau, U K, W U^dagger) at b = 13 can compute several
 output blocks of one row per wave, sharing the left operand's loads; the run
-length is chosen per context (RTDM_RUN_REAL for the real products: 1, 2, 4
-or 8; RTDM_RUN_CPLX for the complex ones: 1, 2 or 4).  At b = 4 the products
+length is chosen per context (RTDM_RUN_REAL for the real products: 1 to 4
+or 8; RTDM_RUN_CPLX for the complex ones: 1 to 4).  At b = 4 the products
 run over runs of 16 outputs (RTDM_RUN_B4=16) or per-output lists
 (RTDM_RUN_B4=1).  Only the order of the contraction sums differs, so every
 run length must meet the FP64 bar against the oracle, and agree with the
@@ -23,7 +23,7 @@ from tests._common import TOL, dipole_floor, gpu_context, rel
 
 pytestmark = pytest.mark.gpu
 
-RUNS = [(1, 1), (2, 2), (4, 4), (8, 4), (8, 2)]
+RUNS = [(1, 1), (2, 2), (3, 3), (4, 4), (8, 4), (8, 2)]
 N_STEPS = 4
 
 
@@ -106,7 +106,7 @@ def test_row_runs_fp32_products():
 
 def test_bad_run_length_is_refused():
     s = _cluster()
-    os.environ["RTDM_RUN_REAL"] = "3"
+    os.environ["RTDM_RUN_REAL"] = "5"
     try:
         with pytest.raises(rtdm.RtdmError):
             gpu_context(s)
