@@ -174,8 +174,8 @@ int rtdm_default_options(rtdm_options *opt);
  * *out receives the context; the caller releases it with rtdm_destroy.
  * Kernel-shape variables read from the environment at creation (for
  * measurements; results differ only in the order of the contraction sums):
- *   RTDM_RUN_REAL   outputs per row run of the real b = 13 step products (1, 2, 4, 8; default 2)
- *   RTDM_RUN_CPLX   the same for the complex ones (1, 2, 4; default 2)
+ *   RTDM_RUN_REAL   outputs per row run of the real b = 13 step products (1 to 4, or 8; default 2)
+ *   RTDM_RUN_CPLX   the same for the complex ones (1 to 4; default 2)
  *   RTDM_RUN_B4     b = 4 products over row runs of 16 outputs (16, default) or per-output lists (1)
  *   RTDM_ROW_TILE   rows per output tile of the b = 13 processing order (default 64)
  *   RTDM_B4_ROWSTAT b = 4 row-stationary kernel (1; default 0)
