@@ -256,16 +256,55 @@ static int kernel_variant()
 // range [x*per, (x+1)*per) of logical blocks: neighbouring output blocks, which
 // share operand blocks, then meet in the same L2.  The grid is launched with
 // 8*per blocks; logical indices >= the real count exit.
+//
+// remap > 1 deals chunks of `remap` consecutive logical blocks to the XCDs
+// round-robin instead (chunk m to XCD m % 8), so that the XCDs work on
+// neighbouring chunks at the same time; the grid is then a multiple of
+// 8*remap (xcd_grid with the same remap).
 constexpr int kXcds = 8;
 __device__ inline int64_t xcd_block(int64_t nblocks, int remap = 1)
 {
     if (!remap) return blockIdx.x;
+    const int64_t x = blockIdx.x % kXcds, i = blockIdx.x / kXcds;
+    if (remap > 1) return ((i / remap) * kXcds + x) * remap + i % remap;
     const int64_t per = (nblocks + kXcds - 1) / kXcds;
-    return (int64_t)(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+    return x * per + i;
 }
-static inline unsigned xcd_grid(int64_t nblocks)
+static inline unsigned xcd_grid(int64_t nblocks, int remap = 1)
 {
-    return (unsigned)(((nblocks + kXcds - 1) / kXcds) * kXcds);
+    const int64_t unit = remap > 1 ? (int64_t)kXcds * remap : kXcds;
+    return (unsigned)(((nblocks + unit - 1) / unit) * unit);
+}
+
+// XCD mapping of the row-run kernels: the chunk size of the round-robin deal
+// (128 by default: the XCDs then stream neighbouring outputs, whose operand
+// blocks meet in the shared last-level cache; contiguous eighths, 1, measured
+// 11 % slower at b = 13).  RTDM_XCD_CHUNK sets it for measurements.
+static int xcd_chunk()
+{
+    static const int v = [] {
+        const char *e = getenv("RTDM_XCD_CHUNK");
+        const int x = e ? atoi(e) : 128;
+        return x > 1 ? x : 1;
+    }();
+    return v;
+}
+// The same deal in chunks of about as many output blocks (1,024 by default)
+// for a kernel with `per_wg` output blocks per workgroup.
+static int xcd_chunk_wg(int per_wg)
+{
+    const int c = xcd_chunk();
+    return c > 1 ? std::max(2, c * 8 / std::max(per_wg, 1)) : 1;
+}
+// Same for the b = 4 run kernels (RTDM_B4_CHUNK; 0 keeps the hardware order).
+static int b4_chunk()
+{
+    static const int v = [] {
+        const char *e = getenv("RTDM_B4_CHUNK");
+        const int x = e ? atoi(e) : 0;
+        return x > 1 ? x : (x == 1 ? 1 : 0);
+    }();
+    return v;
 }
 
 // Matrix-core step on one 16x16 tile: FP64 (v_mfma_f64_16x16x4_f64) or
@@ -877,13 +916,13 @@ template <int B, int MODE, int WPB>
 __global__ __launch_bounds__(64 * WPB) void k_spgemm_q4s(
     int64_t nout, const int64_t *__restrict__ off, const int2 *__restrict__ trip, const double *__restrict__ ar,
     const double *__restrict__ br, double *__restrict__ cr, double alr, const double *__restrict__ zero,
-    const int32_t *__restrict__ order, const double *__restrict__ maxabs)
+    const int32_t *__restrict__ order, const double *__restrict__ maxabs, int remap)
 {
     typedef Split4<MODE> SP;
     typedef typename SP::v4 v4;
     constexpr int BB = B * B;
     const int lane = threadIdx.x & 63;
-    const int64_t w = xcd_block((nout + WPB - 1) / WPB) * WPB + (threadIdx.x >> 6);
+    const int64_t w = xcd_block((nout + WPB - 1) / WPB, remap) * WPB + (threadIdx.x >> 6);
     if (w >= nout) return;                     // uniform across the wave
     const int64_t c = order ? (int64_t)order[w] : w;
     const int r = lane & 15, q = lane >> 4;
@@ -937,10 +976,11 @@ void launch_spgemm_cm_split(hipStream_t s, const SpgemmArgs &a)
              RTDM_E_UNSUPPORTED, "split step products need b = 13, real operands and a split precision");
     RT_CHECK(a.precision != RTDM_PREC_FP16X2 || a.maxabs, RTDM_E_ARG, "FP16 split products need operand maxima");
     const int wpb = a.wpb;
-    const unsigned grid = xcd_grid((a.nout + wpb - 1) / wpb);
+    const int remap = xcd_chunk_wg(wpb);
+    const unsigned grid = xcd_grid((a.nout + wpb - 1) / wpb, remap);
 #define RT_Q4S(M, W)                                                                                      \
     hipLaunchKernelGGL((k_spgemm_q4s<13, M, W>), dim3(grid), dim3(64 * W), 0, s, a.nout, a.off, a.trip, a.ar, \
-                       a.br, a.cr, a.alpha_re, a.zero, a.order, a.maxabs)
+                       a.br, a.cr, a.alpha_re, a.zero, a.order, a.maxabs, remap)
     const int mode = a.precision == RTDM_PREC_FP16X2 ? 1 : 0;
     if (mode == 0) {
         if (wpb == 16) RT_Q4S(0, 16);
@@ -1358,11 +1398,11 @@ __global__ __launch_bounds__(256) void k_spgemm_b4j(
     int64_t nch, const int64_t *__restrict__ off, const int32_t *__restrict__ ea,
     const int32_t *__restrict__ eb, const int32_t *__restrict__ cout, const double *__restrict__ ar,
     const double *__restrict__ ai, const double *__restrict__ br, const double *__restrict__ bi,
-    double *__restrict__ cr, double *__restrict__ ci, double alr, double ali)
+    double *__restrict__ cr, double *__restrict__ ci, double alr, double ali, int remap)
 {
     const int lane = threadIdx.x & 63;
     const int g = (lane >> 2) & 3, r = lane & 3, q = lane >> 4;
-    const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t c = xcd_block((nch + 3) / 4, remap) * 4 + (threadIdx.x >> 6);
     if (c >= nch) return;                      // uniform across the wave
     const int ia = r * 4 + q;                          // A[r][q]
     const int ib = OPB ? (r * 4 + q) : (q * 4 + r);    // op(B)[q][r]
@@ -1409,9 +1449,10 @@ template <bool AC, bool BC, int OB>
 static void launch_b4j(hipStream_t s, const SpgemmArgs &a)
 {
     RT_CHECK(a.nj == 16, RTDM_E_ARG, "b = 4 row runs hold 16 outputs");
-    hipLaunchKernelGGL((k_spgemm_b4j<AC, BC, OB>), dim3((unsigned)((a.nch + 3) / 4)), dim3(256), 0, s, a.nch,
-                       a.ch_off, a.ch_a, a.ch_b, a.ch_out, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re,
-                       a.alpha_im);
+    const int remap = b4_chunk();
+    hipLaunchKernelGGL((k_spgemm_b4j<AC, BC, OB>), dim3(xcd_grid((a.nch + 3) / 4, remap)), dim3(256), 0, s,
+                       a.nch, a.ch_off, a.ch_a, a.ch_b, a.ch_out, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re,
+                       a.alpha_im, remap);
 }
 
 template <bool AC, bool BC, int OB>
@@ -1528,8 +1569,8 @@ static void launch_cm(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
                            a.zero, a.order);
     else {
         const int wpb = a.wpb;
-        const int remap = getenv("RTDM_NO_XCD") ? 0 : 1;
-        const unsigned grid = xcd_grid((a.nout + wpb - 1) / wpb);
+        const int remap = getenv("RTDM_NO_XCD") ? 0 : xcd_chunk_wg(wpb);
+        const unsigned grid = xcd_grid((a.nout + wpb - 1) / wpb, remap);
         const unsigned lds = occupancy_lds();
 #define RT_Q4(W, T)                                                                               \
     hipLaunchKernelGGL((k_spgemm_q4<13, AC, BC, 0, CJB, LC, W, T>), dim3(grid), dim3(64 * W), lds, s, \
@@ -1552,8 +1593,8 @@ static void launch_cm(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
 template <bool AC, bool BC, int CJB, int LC>
 static void launch_cmj(hipStream_t s, const SpgemmArgs &a)
 {
-    const int remap = getenv("RTDM_NO_XCD") ? 0 : 1;
-    const unsigned grid = xcd_grid((a.nch + 3) / 4);
+    const int remap = getenv("RTDM_NO_XCD") ? 0 : xcd_chunk();
+    const unsigned grid = xcd_grid((a.nch + 3) / 4, remap);
     const bool f32 = a.precision == RTDM_PREC_FP32;
     const unsigned lds = occupancy_lds();
 #define RT_Q4J_W(NJ, T, W)                                                                       \
@@ -1663,11 +1704,11 @@ __global__ __launch_bounds__(256) void k_spgemm_q4jr32(
     int64_t nch, const int64_t *__restrict__ off, const int32_t *__restrict__ ea,
     const int32_t *__restrict__ eb, const int32_t *__restrict__ cidx, const float *__restrict__ a,
     const float *__restrict__ b, float *__restrict__ cout, float alpha, const float *__restrict__ zero,
-    const int32_t *__restrict__ order)
+    const int32_t *__restrict__ order, int remap)
 {
     constexpr int BB = B * B;
     const int lane = threadIdx.x & 63;
-    const int64_t w = xcd_block((nch + 3) / 4) * 4 + (threadIdx.x >> 6);
+    const int64_t w = xcd_block((nch + 3) / 4, remap) * 4 + (threadIdx.x >> 6);
     if (w >= nch) return;                      // uniform across the wave
     const int64_t c = order ? (int64_t)order[w] : w;
     const int r = lane & 15, q = lane >> 4;
@@ -1780,10 +1821,11 @@ void launch_spgemm_r32(hipStream_t s, const SpgemmArgs &a, const float *a32, con
         return;
     }
     if (a.nch > 0) {
-        const unsigned grid = xcd_grid((a.nch + 3) / 4);
+        const int remap = xcd_chunk();
+        const unsigned grid = xcd_grid((a.nch + 3) / 4, remap);
 #define RT_R32J(NJ)                                                                                     \
     hipLaunchKernelGGL((k_spgemm_q4jr32<13, NJ>), dim3(grid), dim3(256), 0, s, a.nch, a.ch_off, a.ch_a, \
-                       a.ch_b, a.ch_out, a32, b32, c32, (float)a.alpha_re, zero32, a.ch_order)
+                       a.ch_b, a.ch_out, a32, b32, c32, (float)a.alpha_re, zero32, a.ch_order, remap)
         if (a.nj == 2) RT_R32J(2);
         else if (a.nj == 3) RT_R32J(3);
         else if (a.nj == 4) RT_R32J(4);
