@@ -322,7 +322,7 @@ struct rtdm_ctx {
     double graph_dt = 0.0;
     bool graph_rebuilds_u = false;
     // launch shape of the step products
-    int wpb = 16, row_tile = 64;
+    int wpb = 16, row_tile = 256;   // row tile of the b = 13 processing order (measured best with the XCD deal)
     int run_real = 2, run_cplx = 2;   // b = 13 step products: outputs per row run (1: single outputs)
     int run_b4 = 16;                  // b = 4 FP64 products: outputs per row run (1: single outputs)
     int row_stationary4 = 0;    // b = 4: stage each row of the left operand in LDS (measured slower than the wide kernel)
