@@ -351,9 +351,9 @@ int rtdm_apply_kick_groups(rtdm_ctx *ctx, const double *kappa, void *hip_stream)
 int rtdm_group_trace(rtdm_ctx *ctx, double *out, int64_t max_rows, int64_t *rows);
 
 /* Time candidate launch shapes of the step's block products (workgroups of
- * 4, 8 or 16 waves; output tiles of 16, 64 or 256 atom rows) on the current
- * matrices and keep the fastest; b = 13 only (other block sizes have one
- * shape).  Overwrites W and the Taylor-term work buffers.  *wpb, *row_tile
+ * 4, 8 or 16 waves for the single-output kernels; output tiles of 64, 256 or
+ * 1024 atom rows) on the current matrices and keep the fastest; b = 13 only
+ * (other block sizes have one shape).  Overwrites W and the Taylor-term work buffers.  *wpb, *row_tile
  * (may be NULL) receive the choice.  Synchronises. */
 int rtdm_autotune(rtdm_ctx *ctx, void *hip_stream, int *wpb, int *row_tile);
 

@@ -2092,7 +2092,7 @@ int rtdm_autotune(rtdm_ctx *c, void *stream, int *wpb_out, int *tile_out)
     require(c->ranges_set, "set_ranges first");
     hipStream_t s = (hipStream_t)stream;
     if (c->b == 13) {
-        const int wpbs[3] = {4, 8, 16}, tiles[3] = {16, 64, 256};
+        const int wpbs[3] = {4, 8, 16}, tiles[3] = {64, 256, 1024};
         // events and the context's timing flag are restored however the sweep ends
         struct Guard {
             rtdm_ctx *c;
