@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 (matrix and vector)
 # Identifies the product kernel build whose HBM traffic profiles/traffic.json holds;
 # change it whenever the kernel changes so that a stale figure is not reported.
-KERNEL_TAG = "q4j-b13-nj2-xcdchunk128-tile256-v1"
+KERNEL_TAG = "q4j-b13-nj2seg-xcdchunk128-tile256-v1"
 
 
 def measured_traffic(dom):

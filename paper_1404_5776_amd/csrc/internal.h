@@ -144,17 +144,21 @@ struct SpgemmArgs {
     int64_t nch = 0;
     const int64_t *ch_off = nullptr;
     const int32_t *ch_a = nullptr, *ch_b = nullptr, *ch_out = nullptr, *ch_order = nullptr;
+    const int32_t *ch_seg = nullptr;   // runs of 2: per run the entries feeding both outputs, then only the first
 };
 void launch_spgemm(hipStream_t s, const SpgemmArgs &a);
 // Row runs, op(A) = A: entry counts per run, then the entries (SpgemmArgs::ch_*;
 // inter4: the b = 4 kernel's slot order) and the output map of every run.
+// seg (count pass, runs of 2, nullable): per run the sizes of the segments
+// of entries feeding both outputs and only the first; `segmented` (fill
+// pass): store the entries in that segment order.
 void launch_run_count(hipStream_t s, int64_t nch, const int32_t *run_row, const int64_t *run_p0, const int64_t *c_ptr,
                       const int32_t *c_col, const int64_t *a_ptr, const int32_t *a_col, const int64_t *b_ptr,
-                      const int32_t *b_col, int nj, int64_t *cnt);
+                      const int32_t *b_col, int nj, int64_t *cnt, int32_t *seg);
 void launch_run_fill(hipStream_t s, int64_t nch, const int32_t *run_row, const int64_t *run_p0, const int64_t *c_ptr,
                      const int32_t *c_col, const int64_t *a_ptr, const int32_t *a_col, const int64_t *b_ptr,
                      const int32_t *b_col, const int32_t *b_trans, int op_b, int nj, int inter4, const int64_t *off,
-                     int32_t *ea, int32_t *eb, int32_t *rout);
+                     int32_t *ea, int32_t *eb, int32_t *rout, int segmented);
 // b = 4, FP64, op(A) = A: one workgroup per row of C with that row of A
 // staged in LDS (max_row: the longest row of A's pattern, in blocks).
 void launch_spgemm_b4r(hipStream_t s, const SpgemmArgs &a, int64_t n_rows, const int64_t *c_rowptr,

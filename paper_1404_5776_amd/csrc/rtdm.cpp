@@ -120,6 +120,7 @@ struct Runs {
     int64_t nch = 0;
     DBuf<int64_t> off;
     DBuf<int32_t> a, b, out, order;
+    DBuf<int32_t> seg;               // runs of 2 at b = 13: segment sizes (SpgemmArgs::ch_seg)
     std::vector<int32_t> row, col;   // row and first column of each run
 };
 
@@ -200,12 +201,15 @@ bool build_runs(Sched &S, const Pattern &A, const Pattern &B, const Pattern &C, 
     d_row.alloc(std::max<int64_t>(nch, 1));
     d_p0.alloc(std::max<int64_t>(nch, 1));
     cnt.alloc(std::max<int64_t>(nch, 1));
+    // runs of 2 (b = 13) are stored in segments: entries feeding both outputs, then one
+    const bool segmented = nj == 2 && !inter4;
+    if (segmented) R->seg.alloc(std::max<int64_t>(2 * nch, 2));
     std::vector<int64_t> off(nch + 1, 0);
     if (nch) {
         RT_HIP(hipMemcpy(d_row.p, R->row.data(), nch * sizeof(int32_t), hipMemcpyHostToDevice));
         RT_HIP(hipMemcpy(d_p0.p, p0s.data(), nch * sizeof(int64_t), hipMemcpyHostToDevice));
         launch_run_count(nullptr, nch, d_row.p, d_p0.p, C.d_rowptr.p, C.d_col.p, A.d_rowptr.p, A.d_col.p,
-                         B.d_rowptr.p, B.d_col.p, nj, cnt.p);
+                         B.d_rowptr.p, B.d_col.p, nj, cnt.p, segmented ? R->seg.p : nullptr);
         RT_HIP(hipMemcpy(off.data() + 1, cnt.p, nch * sizeof(int64_t), hipMemcpyDeviceToHost));
         for (int64_t u = 0; u < nch; ++u) off[u + 1] += off[u];
     }
@@ -224,7 +228,7 @@ bool build_runs(Sched &S, const Pattern &A, const Pattern &B, const Pattern &C, 
     R->order.alloc(std::max<int64_t>(nch, 1));
     RT_HIP(hipMemcpy(R->off.p, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice));
     launch_run_fill(nullptr, nch, d_row.p, d_p0.p, C.d_rowptr.p, C.d_col.p, A.d_rowptr.p, A.d_col.p, B.d_rowptr.p,
-                    B.d_col.p, B.d_trans.p, op_b, nj, inter4, R->off.p, R->a.p, R->b.p, R->out.p);
+                    B.d_col.p, B.d_trans.p, op_b, nj, inter4, R->off.p, R->a.p, R->b.p, R->out.p, segmented);
     const std::vector<int32_t> ord = run_order(*R, tile_i);
     if (!ord.empty())
         RT_HIP(hipMemcpy(R->order.p, ord.data(), ord.size() * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -700,6 +704,7 @@ void product_cm(rtdm_ctx *c, int prod, const Mat &Acm, const Mat &B, Mat &C, int
             a.ch_b = R.b.p;
             a.ch_out = R.out.p;
             a.ch_order = R.order.p;
+            a.ch_seg = R.seg.p;
         }
     }
     RT_CHECK(C.cplx || (!Acm.cplx && !B.cplx), RTDM_E_UNSUPPORTED, "complex product into a real matrix");

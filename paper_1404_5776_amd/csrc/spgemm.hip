@@ -19,6 +19,7 @@
 // product is four real tile products (re*re, im*im, re*im, im*re) sharing the
 // operand loads; a real operand skips the products it does not need.
 #include <cstdlib>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -88,7 +89,7 @@ __global__ void k_run_sym(int64_t nch, const int32_t *__restrict__ run_row, cons
                           const int64_t *__restrict__ b_ptr, const int32_t *__restrict__ b_col,
                           const int32_t *__restrict__ b_trans, int op_b, int nj, int inter4,
                           int64_t *__restrict__ cnt, const int64_t *__restrict__ off, int32_t *__restrict__ ea,
-                          int32_t *__restrict__ eb, int32_t *__restrict__ rout)
+                          int32_t *__restrict__ eb, int32_t *__restrict__ rout, int segd, int32_t *__restrict__ seg)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nch) return;
@@ -103,54 +104,72 @@ __global__ void k_run_sym(int64_t nch, const int32_t *__restrict__ run_row, cons
     }
     if (FILL)
         for (int t = 0; t < nj; ++t) rout[c * nj + t] = t < m ? (int32_t)(p0 + t) : -1;
+    // With `seg` (runs of 2): the entries feeding both outputs first, then
+    // those feeding only the first, then only the second (each in ascending
+    // k); the count pass records the sizes of the first two segments.
+    const int passes = segd ? 3 : 1;
+    const int want[3] = {3, 1, 2};
     int64_t n = 0, o = FILL ? off[c] : 0;
-    for (int64_t pa = a_ptr[i]; pa < a_ptr[i + 1]; ++pa) {
-        const int k = a_col[pa];
-        bool any = false;
-        for (int t = 0; t < m; ++t) {
-            while (pb[t] < eb_end[t] && b_col[pb[t]] < k) ++pb[t];
-            any |= pb[t] < eb_end[t] && b_col[pb[t]] == k;
-        }
-        if (!any) continue;
-        if (FILL) {
-            ea[o] = (int32_t)pa;
-            for (int t = 0; t < nj; ++t) {
-                const int slot = inter4 ? (t & 3) * 4 + (t >> 2) : t;
-                int32_t v = -1;
-                // op(B)_kj: block (k, j) = trans of (j, k), or (j, k) itself for the conjugate transpose
-                if (t < m && pb[t] < eb_end[t] && b_col[pb[t]] == k) v = op_b ? (int32_t)pb[t] : b_trans[pb[t]];
-                eb[o * nj + slot] = v;
+    int64_t nseg[3] = {0, 0, 0};
+    for (int pass = 0; pass < passes; ++pass) {
+        for (int t = 0; t < m; ++t) pb[t] = b_ptr[c_col[p0 + t]];
+        for (int64_t pa = a_ptr[i]; pa < a_ptr[i + 1]; ++pa) {
+            const int k = a_col[pa];
+            int mask = 0;
+            for (int t = 0; t < m; ++t) {
+                while (pb[t] < eb_end[t] && b_col[pb[t]] < k) ++pb[t];
+                if (pb[t] < eb_end[t] && b_col[pb[t]] == k) mask |= 1 << t;
             }
-            ++o;
-        } else {
-            ++n;
+            if (!mask || (segd && mask != want[pass])) continue;
+            ++nseg[pass];
+            if (FILL) {
+                ea[o] = (int32_t)pa;
+                for (int t = 0; t < nj; ++t) {
+                    const int slot = inter4 ? (t & 3) * 4 + (t >> 2) : t;
+                    int32_t v = -1;
+                    // op(B)_kj: block (k, j) = trans of (j, k), or (j, k) itself for the conjugate transpose
+                    if ((mask >> t) & 1) v = op_b ? (int32_t)pb[t] : b_trans[pb[t]];
+                    eb[o * nj + slot] = v;
+                }
+                ++o;
+            } else {
+                ++n;
+            }
         }
     }
-    if (!FILL) cnt[c] = n;
+    if (!FILL) {
+        cnt[c] = n;
+        if (seg) {
+            seg[2 * c] = (int32_t)nseg[0];
+            seg[2 * c + 1] = (int32_t)nseg[1];
+        }
+    }
 }
 
 void launch_run_count(hipStream_t s, int64_t nch, const int32_t *run_row, const int64_t *run_p0, const int64_t *c_ptr,
                       const int32_t *c_col, const int64_t *a_ptr, const int32_t *a_col, const int64_t *b_ptr,
-                      const int32_t *b_col, int nj, int64_t *cnt)
+                      const int32_t *b_col, int nj, int64_t *cnt, int32_t *seg)
 {
     if (nch == 0) return;
     RT_CHECK(nj >= 1 && nj <= kMaxRun, RTDM_E_ARG, "row runs hold 1..16 outputs");
+    RT_CHECK(!seg || nj == 2, RTDM_E_ARG, "segmented row runs hold 2 outputs");
     hipLaunchKernelGGL(k_run_sym<false>, dim3((unsigned)((nch + 127) / 128)), dim3(128), 0, s, nch, run_row, run_p0,
                        c_ptr, c_col, a_ptr, a_col, b_ptr, b_col, nullptr, 0, nj, 0, cnt, nullptr, nullptr, nullptr,
-                       nullptr);
+                       nullptr, seg ? 1 : 0, seg);
     RT_HIP(hipGetLastError());
 }
 
 void launch_run_fill(hipStream_t s, int64_t nch, const int32_t *run_row, const int64_t *run_p0, const int64_t *c_ptr,
                      const int32_t *c_col, const int64_t *a_ptr, const int32_t *a_col, const int64_t *b_ptr,
                      const int32_t *b_col, const int32_t *b_trans, int op_b, int nj, int inter4, const int64_t *off,
-                     int32_t *ea, int32_t *eb, int32_t *rout)
+                     int32_t *ea, int32_t *eb, int32_t *rout, int segmented)
 {
     if (nch == 0) return;
     RT_CHECK(nj >= 1 && nj <= kMaxRun, RTDM_E_ARG, "row runs hold 1..16 outputs");
+    RT_CHECK(!segmented || (nj == 2 && !inter4), RTDM_E_ARG, "segmented row runs hold 2 outputs");
     hipLaunchKernelGGL(k_run_sym<true>, dim3((unsigned)((nch + 127) / 128)), dim3(128), 0, s, nch, run_row, run_p0,
                        c_ptr, c_col, a_ptr, a_col, b_ptr, b_col, b_trans, op_b, nj, inter4, nullptr, off, ea, eb,
-                       rout);
+                       rout, segmented ? 1 : 0, nullptr);
     RT_HIP(hipGetLastError());
 }
 
@@ -485,13 +504,18 @@ typedef __attribute__((address_space(1))) const double gdouble;
 // blocks of A beyond L2 are then fetched once per run instead of once per
 // output; the price is the absent (zero) products of a run.  Data layout,
 // lane mapping, conjugation and output as in k_spgemm_q4.
+// seg (runs of 2, optional): per run the number of entries that feed both
+// outputs (seg[2c]) and only the first (seg[2c+1]); the entries are stored in
+// that order, the rest feed only the second.  Each segment then runs with
+// only its outputs' products, so no matrix work goes to absent entries.
 template <int B, bool AC, bool BC, int CJB, int LC, int NJ, class T = double, int MINW = 1>
 __global__ __launch_bounds__(256, MINW) void k_spgemm_q4j(
     int64_t nch, const int64_t *__restrict__ off, const int32_t *__restrict__ ea,
     const int32_t *__restrict__ eb, const int32_t *__restrict__ cout,
     const double *__restrict__ ar, const double *__restrict__ ai, const double *__restrict__ br,
     const double *__restrict__ bi, double *__restrict__ cr, double *__restrict__ ci, double alr,
-    double ali, const double *__restrict__ zero, const int32_t *__restrict__ order, int remap)
+    double ali, const double *__restrict__ zero, const int32_t *__restrict__ order, int remap,
+    const int32_t *__restrict__ seg)
 {
     static_assert(B >= 4 && B <= 16, "k_spgemm_q4j needs 4 <= B <= 16");
     constexpr int BB = B * B;
@@ -508,55 +532,75 @@ __global__ __launch_bounds__(256, MINW) void k_spgemm_q4j(
 #pragma unroll
     for (int t = 0; t < NJ; ++t) rr[t] = ri[t] = ir[t] = acc_t{0, 0, 0, 0};
     const gdouble *gz = (const gdouble *)zero;
-    for (int g = 0; g < ne; g += 4) {
-        // global-address-space pointers: the loads stay global loads (flat
-        // loads would make every wait drain the scalar-memory counter too)
-        const gdouble *pa = gz, *pai = gz;
-        const gdouble *pb[NJ], *pbi[NJ];
+    // entries [gb, ge) of the run; output t's products only where bit t of ACT is set
+    auto groups = [&](int gb, int ge, auto act) {
+        constexpr int ACT = decltype(act)::value;
+        for (int g = gb; g < ge; g += 4) {
+            // global-address-space pointers: the loads stay global loads (flat
+            // loads would make every wait drain the scalar-memory counter too)
+            const gdouble *pa = gz, *pai = gz;
+            const gdouble *pb[NJ], *pbi[NJ];
 #pragma unroll
-        for (int t = 0; t < NJ; ++t) pb[t] = pbi[t] = gz;
-        if (rv && g + q < ne) {
-            const int64_t e = e0 + g + q;
-            const int64_t oa = (int64_t)ea[e] * BB + r;
-            pa = (const gdouble *)(ar + oa);
-            if (AC) pai = (const gdouble *)(ai + oa);
+            for (int t = 0; t < NJ; ++t) pb[t] = pbi[t] = gz;
+            if (rv && g + q < ge) {
+                const int64_t e = e0 + g + q;
+                const int64_t oa = (int64_t)ea[e] * BB + r;
+                pa = (const gdouble *)(ar + oa);
+                if (AC) pai = (const gdouble *)(ai + oa);
 #pragma unroll
-            for (int t = 0; t < NJ; ++t) {
-                const int kb = eb[e * NJ + t];
-                if (kb >= 0) {
-                    const int64_t ob = (int64_t)kb * BB + r;
-                    pb[t] = (const gdouble *)(br + ob);
-                    if (BC) pbi[t] = (const gdouble *)(bi + ob);
+                for (int t = 0; t < NJ; ++t) {
+                    if (!((ACT >> t) & 1)) continue;
+                    const int kb = eb[e * NJ + t];
+                    if (kb >= 0) {
+                        const int64_t ob = (int64_t)kb * BB + r;
+                        pb[t] = (const gdouble *)(br + ob);
+                        if (BC) pbi[t] = (const gdouble *)(bi + ob);
+                    }
+                }
+            }
+#pragma unroll
+            for (int st = 0; st < B; ++st) {
+                const T xa = (T)pa[st * B];
+                const T xai = AC ? (T)pai[st * B] : (T)0;
+                if constexpr (AC && BC) {
+                    // two accumulators per output: re += a_r b_r + (-s a_i) b_i,
+                    // im += (s a_r) b_i + a_i b_r with s = -1 for a conjugated B
+                    const T nai = CJB ? xai : -xai, sar = CJB ? -xa : xa;
+#pragma unroll
+                    for (int t = 0; t < NJ; ++t) {
+                        if (!((ACT >> t) & 1)) continue;
+                        const T xb = (T)pb[t][st * B], xbi = (T)pbi[t][st * B];
+                        rr[t] = Mfma16<T>::step(xa, xb, rr[t]);
+                        ri[t] = Mfma16<T>::step(sar, xbi, ri[t]);
+                        rr[t] = Mfma16<T>::step(nai, xbi, rr[t]);
+                        ri[t] = Mfma16<T>::step(xai, xb, ri[t]);
+                    }
+                } else {
+#pragma unroll
+                    for (int t = 0; t < NJ; ++t) {
+                        if (!((ACT >> t) & 1)) continue;
+                        const T xb = (T)pb[t][st * B];
+                        const T xbi = BC ? (T)pbi[t][st * B] : (T)0;
+                        rr[t] = Mfma16<T>::step(xa, xb, rr[t]);
+                        if (BC) ri[t] = Mfma16<T>::step(xa, xbi, ri[t]);
+                        if (AC) ir[t] = Mfma16<T>::step(xai, xb, ir[t]);
+                    }
                 }
             }
         }
-#pragma unroll
-        for (int st = 0; st < B; ++st) {
-            const T xa = (T)pa[st * B];
-            const T xai = AC ? (T)pai[st * B] : (T)0;
-            if constexpr (AC && BC) {
-                // two accumulators per output: re += a_r b_r + (-s a_i) b_i,
-                // im += (s a_r) b_i + a_i b_r with s = -1 for a conjugated B
-                const T nai = CJB ? xai : -xai, sar = CJB ? -xa : xa;
-#pragma unroll
-                for (int t = 0; t < NJ; ++t) {
-                    const T xb = (T)pb[t][st * B], xbi = (T)pbi[t][st * B];
-                    rr[t] = Mfma16<T>::step(xa, xb, rr[t]);
-                    ri[t] = Mfma16<T>::step(sar, xbi, ri[t]);
-                    rr[t] = Mfma16<T>::step(nai, xbi, rr[t]);
-                    ri[t] = Mfma16<T>::step(xai, xb, ri[t]);
-                }
-            } else {
-#pragma unroll
-                for (int t = 0; t < NJ; ++t) {
-                    const T xb = (T)pb[t][st * B];
-                    const T xbi = BC ? (T)pbi[t][st * B] : (T)0;
-                    rr[t] = Mfma16<T>::step(xa, xb, rr[t]);
-                    if (BC) ri[t] = Mfma16<T>::step(xa, xbi, ri[t]);
-                    if (AC) ir[t] = Mfma16<T>::step(xai, xb, ir[t]);
-                }
-            }
+    };
+    constexpr int ALL = (1 << NJ) - 1;
+    if constexpr (NJ == 2) {
+        if (seg) {
+            const int nf = seg[2 * c], n0 = seg[2 * c + 1];   // uniform across the wave
+            groups(0, nf, std::integral_constant<int, 3>());
+            groups(nf, nf + n0, std::integral_constant<int, 1>());
+            groups(nf + n0, ne, std::integral_constant<int, 2>());
+        } else {
+            groups(0, ne, std::integral_constant<int, ALL>());
         }
+    } else {
+        groups(0, ne, std::integral_constant<int, ALL>());
     }
     constexpr double sb = CJB ? -1.0 : 1.0;
 #pragma unroll
@@ -1601,7 +1645,7 @@ static void launch_cmj(hipStream_t s, const SpgemmArgs &a)
     hipLaunchKernelGGL((k_spgemm_q4j<13, AC, BC, CJB, LC, NJ, T, W>), dim3(grid), dim3(256), lds, s,   \
                        a.nch,                                                                         \
                        a.ch_off, a.ch_a, a.ch_b, a.ch_out, a.ar, a.ai, a.br, a.bi, a.cr, a.ci,        \
-                       a.alpha_re, a.alpha_im, a.zero, a.ch_order, remap)
+                       a.alpha_re, a.alpha_im, a.zero, a.ch_order, remap, a.ch_seg)
 #define RT_Q4J(NJ, T) RT_Q4J_W(NJ, T, 1)
     if (a.nj == 2) {
         // complex runs of 2 compiled for at least 4 waves per SIMD (at most 128
