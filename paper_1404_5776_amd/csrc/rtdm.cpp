@@ -466,6 +466,17 @@ Pattern &pat_of(rtdm_ctx *c, int range) { return *c->pats[c->range_pat[range]]; 
 
 int64_t elems(rtdm_ctx *c, const Mat &m) { return c->pats[m.pat]->nnzb * (int64_t)c->b * c->b; }
 
+// Uninitialised matrix on the pattern (and with the planes) of `ref`.
+void alloc_like(rtdm_ctx *c, Mat &m, const Mat &ref)
+{
+    m.pat = ref.pat;
+    m.cplx = ref.cplx;
+    const int64_t ne = c->pats[ref.pat]->nnzb * (int64_t)c->b * c->b;
+    m.re.alloc(ne);
+    if (ref.cplx) m.im.alloc(ne);
+    else m.im.release();
+}
+
 void alloc_mat(rtdm_ctx *c, Mat &m, int range, bool cplx)
 {
     m.pat = c->range_pat[range];
@@ -508,14 +519,14 @@ std::tuple<int, int, int, int, int> prod_key(rtdm_ctx *c, int prod)
 Sched &schedule(rtdm_ctx *c, int prod)
 {
     auto key = prod_key(c, prod);
-    // Row runs: b = 13 step products of the column-major path (X H and A tau
-    // real, U K and W U^dagger complex), b = 4 FP64 products with op(A) = A.
+    // Row runs: b = 13 products of the column-major path (X H, A tau and the
+    // inverse's S X real, U K and W U^dagger complex), b = 4 products with op(A) = A.
     const bool cm_kind = prod == RTDM_PROD_XH || prod == RTDM_PROD_AT || prod == RTDM_PROD_UK ||
-                         prod == RTDM_PROD_WU;
+                         prod == RTDM_PROD_WU || prod == RTDM_PROD_SX;
     const int nj = std::get<3>(key) != 0 ? 1
                    : c->b == 13 ? (!cm_kind ? 1
-                                   : (prod == RTDM_PROD_XH || prod == RTDM_PROD_AT) ? c->run_real
-                                                                                      : c->run_cplx)
+                                   : (prod == RTDM_PROD_UK || prod == RTDM_PROD_WU) ? c->run_cplx
+                                                                                      : c->run_real)
                    : c->b == 4 ? c->run_b4
                                : 1;
     auto runs_for = [&](Sched &S) {
@@ -1486,12 +1497,26 @@ int rtdm_build_inverse(rtdm_ctx *c, void *stream, int *iters, double *residual)
         RT_HIP(hipMemsetAsync(X.re.p, 0, X.re.bytes(), s));
         launch_add_identity(s, c->n, c->b, pp.d_diag.p, 1.0 / h[3], X.re.p);
     };
+    // On the b = 13 column-major path both products run on the step kernels:
+    // a column-major copy of S for the whole iteration, of X per iteration.
+    const bool cm = use_cm(c);
+    Mat Sc;
+    if (cm) {
+        alloc_like(c, Sc, S);
+        transpose_into(c, S, Sc, s);
+    }
     // Returns 1 converged, 0 diverged, -1 hit the cap.
     auto run = [&](int &k_out, double &r_out) -> int {
         std::vector<double> res;
         for (int k = 0; k < c->opt.inv_max_iter; ++k) {
-            product(c, RTDM_PROD_SX, S, X, c->Wh, 1.0, 0.0, s);          // W = P_P(S X)
-            product(c, RTDM_PROD_AT, X, c->Wh, c->Xn, 1.0, 0.0, s);      // P_P(X W)
+            if (cm) {
+                product_cm(c, RTDM_PROD_SX, Sc, X, c->Wh, 0, 0, 1.0, s);  // W = P_P(S X)
+                transpose_into(c, X, c->Xc, s);
+                product_cm(c, RTDM_PROD_AT, c->Xc, c->Wh, c->Xn, 0, 0, 1.0, s);   // P_P(X W)
+            } else {
+                product(c, RTDM_PROD_SX, S, X, c->Wh, 1.0, 0.0, s);       // W = P_P(S X)
+                product(c, RTDM_PROD_AT, X, c->Wh, c->Xn, 1.0, 0.0, s);   // P_P(X W)
+            }
             launch_axpby(s, ne, 2.0, X.re.p, -1.0, c->Xn.re.p, c->Xn.re.p);  // X' = 2X - XW
             launch_red_diff2(s, ne, c->Xn.re.p, X.re.p, c->partials.p);
             reduce_finish(c, s, c->hot_sums.p);
@@ -2299,13 +2324,7 @@ int rtdm_multiply(rtdm_ctx *c, rtdm_mat Cm, rtdm_mat Am, rtdm_mat Bm, int op_a, 
         const bool step_kind = prod == RTDM_PROD_XH || prod == RTDM_PROD_AT || prod == RTDM_PROD_UK ||
                                prod == RTDM_PROD_WU;
         if (use_cm(c) && step_kind && op_a == 0 && ali == 0.0) {
-            auto like = [&](Mat &m, const Mat &ref) {
-                m.pat = ref.pat;
-                m.cplx = ref.cplx;
-                const int64_t ne = c->pats[ref.pat]->nnzb * (int64_t)c->b * c->b;
-                m.re.alloc(ne);
-                if (ref.cplx) m.im.alloc(ne);
-            };
+            auto like = [&](Mat &m, const Mat &ref) { alloc_like(c, m, ref); };
             Mat Acm, Bcm, Ccm;
             like(Acm, A);
             transpose_into(c, A, Acm, s);
