@@ -862,6 +862,7 @@ void build_propagator(rtdm_ctx *c, double dt, hipStream_t s)
                     a.ch_b = R.b.p;
                     a.ch_out = R.out.p;
                     a.ch_order = R.order.p;
+                    a.ch_seg = R.seg.p;
                 }
             }
             const bool rec = c->timing && !c->capturing;

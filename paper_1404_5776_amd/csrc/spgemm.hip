@@ -1748,7 +1748,7 @@ __global__ __launch_bounds__(256) void k_spgemm_q4jr32(
     int64_t nch, const int64_t *__restrict__ off, const int32_t *__restrict__ ea,
     const int32_t *__restrict__ eb, const int32_t *__restrict__ cidx, const float *__restrict__ a,
     const float *__restrict__ b, float *__restrict__ cout, float alpha, const float *__restrict__ zero,
-    const int32_t *__restrict__ order, int remap)
+    const int32_t *__restrict__ order, int remap, const int32_t *__restrict__ seg)
 {
     constexpr int BB = B * B;
     const int lane = threadIdx.x & 63;
@@ -1764,26 +1764,45 @@ __global__ __launch_bounds__(256) void k_spgemm_q4jr32(
 #pragma unroll
     for (int t = 0; t < NJ; ++t) acc[t] = acc_t{0, 0, 0, 0};
     const gfloat *gz = (const gfloat *)zero;
-    for (int g = 0; g < ne; g += 4) {
-        const gfloat *pa = gz;
-        const gfloat *pb[NJ];
+    // entries [gb, ge); output t's products only where bit t of ACT is set (segments as in k_spgemm_q4j)
+    auto groups = [&](int gb, int ge, auto act) {
+        constexpr int ACT = decltype(act)::value;
+        for (int g = gb; g < ge; g += 4) {
+            const gfloat *pa = gz;
+            const gfloat *pb[NJ];
 #pragma unroll
-        for (int t = 0; t < NJ; ++t) pb[t] = gz;
-        if (rv && g + q < ne) {
-            const int64_t e = e0 + g + q;
-            pa = (const gfloat *)(a + (int64_t)ea[e] * BB + r);
+            for (int t = 0; t < NJ; ++t) pb[t] = gz;
+            if (rv && g + q < ge) {
+                const int64_t e = e0 + g + q;
+                pa = (const gfloat *)(a + (int64_t)ea[e] * BB + r);
 #pragma unroll
-            for (int t = 0; t < NJ; ++t) {
-                const int kb = eb[e * NJ + t];
-                if (kb >= 0) pb[t] = (const gfloat *)(b + (int64_t)kb * BB + r);
+                for (int t = 0; t < NJ; ++t) {
+                    if (!((ACT >> t) & 1)) continue;
+                    const int kb = eb[e * NJ + t];
+                    if (kb >= 0) pb[t] = (const gfloat *)(b + (int64_t)kb * BB + r);
+                }
+            }
+#pragma unroll
+            for (int st = 0; st < B; ++st) {
+                const float xa = pa[st * B];
+#pragma unroll
+                for (int t = 0; t < NJ; ++t)
+                    if ((ACT >> t) & 1) acc[t] = Mfma16<float>::step(xa, pb[t][st * B], acc[t]);
             }
         }
-#pragma unroll
-        for (int st = 0; st < B; ++st) {
-            const float xa = pa[st * B];
-#pragma unroll
-            for (int t = 0; t < NJ; ++t) acc[t] = Mfma16<float>::step(xa, pb[t][st * B], acc[t]);
+    };
+    constexpr int ALL = (1 << NJ) - 1;
+    if constexpr (NJ == 2) {
+        if (seg) {
+            const int nf = seg[2 * c], n0 = seg[2 * c + 1];   // uniform across the wave
+            groups(0, nf, std::integral_constant<int, 3>());
+            groups(nf, nf + n0, std::integral_constant<int, 1>());
+            groups(nf + n0, ne, std::integral_constant<int, 2>());
+        } else {
+            groups(0, ne, std::integral_constant<int, ALL>());
         }
+    } else {
+        groups(0, ne, std::integral_constant<int, ALL>());
     }
 #pragma unroll
     for (int t = 0; t < NJ; ++t) {
@@ -1869,7 +1888,7 @@ void launch_spgemm_r32(hipStream_t s, const SpgemmArgs &a, const float *a32, con
         const unsigned grid = xcd_grid((a.nch + 3) / 4, remap);
 #define RT_R32J(NJ)                                                                                     \
     hipLaunchKernelGGL((k_spgemm_q4jr32<13, NJ>), dim3(grid), dim3(256), 0, s, a.nch, a.ch_off, a.ch_a, \
-                       a.ch_b, a.ch_out, a32, b32, c32, (float)a.alpha_re, zero32, a.ch_order, remap)
+                       a.ch_b, a.ch_out, a32, b32, c32, (float)a.alpha_re, zero32, a.ch_order, remap, a.ch_seg)
         if (a.nj == 2) RT_R32J(2);
         else if (a.nj == 3) RT_R32J(3);
         else if (a.nj == 4) RT_R32J(4);
