@@ -271,10 +271,10 @@ static int kernel_variant()
 }
 
 // Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by
-// block index.  xcd_block() renumbers them so that XCD x runs the contiguous
-// range [x*per, (x+1)*per) of logical blocks: neighbouring output blocks, which
-// share operand blocks, then meet in the same L2.  The grid is launched with
-// 8*per blocks; logical indices >= the real count exit.
+// block index.  xcd_block() with remap = 1 renumbers them so that XCD x runs
+// the contiguous range [x*per, (x+1)*per) of logical blocks: neighbouring
+// output blocks, which share operand blocks, then meet in the same L2.  The
+// grid is launched with 8*per blocks; logical indices >= the real count exit.
 //
 // remap > 1 deals chunks of `remap` consecutive logical blocks to the XCDs
 // round-robin instead (chunk m to XCD m % 8), so that the XCDs work on
