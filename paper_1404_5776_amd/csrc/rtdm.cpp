@@ -129,7 +129,7 @@ struct Sched {
     DBuf<int64_t> off;
     DBuf<int2> trip;
     DBuf<int32_t> order;   // processing order of the output blocks (row tiles, then columns)
-    // row runs of the b = 13 step products (SpgemmArgs::ch_*), by run length
+    // row runs of this schedule (SpgemmArgs::ch_*), by run length
     std::map<int, std::unique_ptr<Runs>> runs;
 };
 
