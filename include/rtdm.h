@@ -178,10 +178,6 @@ int rtdm_default_options(rtdm_options *opt);
  *   RTDM_RUN_CPLX   the same for the complex ones (1 to 4; default 2)
  *   RTDM_RUN_B4     b = 4 products over row runs of 16 outputs (16, default) or per-output lists (1)
  *   RTDM_ROW_TILE   rows per output tile of the b = 13 processing order (default 256)
- *   RTDM_B4_ROWSTAT b = 4 row-stationary kernel (1; default 0)
- * and at the first product launch: RTDM_STEP_LDS (unused LDS bytes per workgroup of the b = 13 step
- * kernels, capping their occupancy), RTDM_NO_XCD (plain workgroup order), RTDM_B4_WIDE (0: the
- * 4-output b = 4 kernel), RTDM_B13_KERNEL (earlier b = 13 kernel variants 1-3).
  * A run length outside these values fails with RTDM_E_ARG. */
 int rtdm_create(rtdm_ctx **out, int hip_device, const rtdm_options *opt);
 

@@ -159,11 +159,6 @@ void launch_run_fill(hipStream_t s, int64_t nch, const int32_t *run_row, const i
                      const int32_t *c_col, const int64_t *a_ptr, const int32_t *a_col, const int64_t *b_ptr,
                      const int32_t *b_col, const int32_t *b_trans, int op_b, int nj, int inter4, const int64_t *off,
                      int32_t *ea, int32_t *eb, int32_t *rout, int segmented);
-// b = 4, FP64, op(A) = A: one workgroup per row of C with that row of A
-// staged in LDS (max_row: the longest row of A's pattern, in blocks).
-void launch_spgemm_b4r(hipStream_t s, const SpgemmArgs &a, int64_t n_rows, const int64_t *c_rowptr,
-                       const int64_t *a_rowptr, int64_t max_row);
-void init_kernel_attributes();
 // Same product with the left operand given as column-major blocks, the right
 // operand's op(B)[m][r] at m*B + r (conj_b: conjugated) and the output written
 // column-major if out_col_major.  b = 13, FP64.

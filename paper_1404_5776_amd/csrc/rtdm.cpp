@@ -101,7 +101,6 @@ enum Range { R_HS = 0, R_P = 1, R_K = 2 };
 struct Pattern {
     double R = 0.0;
     int64_t n = 0, nnzb = 0;
-    int64_t max_row = -1;      // longest row in blocks (computed on first use)
     std::vector<int64_t> rowptr;
     std::vector<int32_t> col, rowof, trans, diag;
     DBuf<int64_t> d_rowptr;
@@ -329,7 +328,6 @@ struct rtdm_ctx {
     int wpb = 16, row_tile = 256;   // row tile of the b = 13 processing order (measured best with the XCD deal)
     int run_real = 2, run_cplx = 2;   // b = 13 step products: outputs per row run (1: single outputs)
     int run_b4 = 16;                  // b = 4 FP64 products: outputs per row run (1: single outputs)
-    int row_stationary4 = 0;    // b = 4: stage each row of the left operand in LDS (measured slower than the wide kernel)
     int inv_iters_total = 0, inv_fell_back = 0;
     // ETRS / Magnus work matrices and the self-consistent corrector's state
     Mat E1, E2, E3, A1, Kt;
@@ -582,8 +580,6 @@ hipEvent_t event_at(rtdm_ctx *c, size_t k)
     return c->events[k];
 }
 
-constexpr size_t kB4rMaxLds = 40 * 1024;   // LDS budget of one row-stationary workgroup
-constexpr int64_t kB4rMaxRow = 160;         // longest left-operand row it takes (blocks)
 
 // C = P_C(alpha op(A) op(B)) with the schedule of `prod`.
 void product(rtdm_ctx *c, int prod, const Mat &A, const Mat &B, Mat &C, double alr, double ali,
@@ -628,25 +624,9 @@ void product(rtdm_ctx *c, int prod, const Mat &A, const Mat &B, Mat &C, double a
         }
         a.maxabs = c->f16_max.p;
     }
-    // b = 4 FP64 with op(A) = A: row-stationary kernel when a row of A fits in LDS
-    const Pattern &PA = *c->pats[A.pat], &PC = *c->pats[C.pat];
-    int64_t max_row = 0;
-    (void)PA;
-    if (c->b == 4 && c->prec == RTDM_PREC_FP64 && a.op_a == 0 && c->row_stationary4) {
-        Pattern &pa = *c->pats[A.pat];
-        if (pa.max_row < 0) {
-            pa.max_row = 0;
-            for (int64_t i = 0; i < pa.n; ++i) pa.max_row = std::max(pa.max_row, pa.rowptr[i + 1] - pa.rowptr[i]);
-        }
-        max_row = pa.max_row;
-        // measured on diamond lattices: the row-stationary kernel wins up to rows of ~150 blocks
-        // (R 8-12 bohr) and loses beyond (R 16), where the per-triple kernel's L2 reuse takes over
-        if (max_row > kB4rMaxRow || (size_t)max_row * 16 * sizeof(double) * (A.cplx ? 2 : 1) > kB4rMaxLds)
-            max_row = 0;
-    }
     const bool b4_runs_prec = c->prec == RTDM_PREC_FP64 || c->prec == RTDM_PREC_FP32 ||
                               c->prec == RTDM_PREC_BF16X3 || c->prec == RTDM_PREC_FP16X2;
-    if (c->b == 4 && b4_runs_prec && a.op_a == 0 && max_row == 0 && c->run_b4 > 1) {
+    if (c->b == 4 && b4_runs_prec && a.op_a == 0 && c->run_b4 > 1) {
         auto r = S.runs.find(c->run_b4);
         if (r != S.runs.end() && r->second->nch > 0) {
             const Runs &R = *r->second;
@@ -659,8 +639,7 @@ void product(rtdm_ctx *c, int prod, const Mat &A, const Mat &B, Mat &C, double a
         }
     }
     auto go = [&]() {
-        if (max_row > 0) launch_spgemm_b4r(s, a, PC.n, PC.d_rowptr.p, PA.d_rowptr.p, max_row);
-        else launch_spgemm(s, a);
+        launch_spgemm(s, a);
     };
     if (c->timing && !c->capturing) {
         const size_t k = 2 * c->recs.size();
@@ -1116,8 +1095,6 @@ int rtdm_create(rtdm_ctx **out, int hip_device, const rtdm_options *opt)
     RT_CHECK(c->opt.sc_steps >= 0 && c->opt.sc_iters >= 0, RTDM_E_ARG, "sc_steps / sc_iters < 0");
     RT_CHECK(c->opt.unit_tol >= 0.0, RTDM_E_ARG, "unit_tol < 0");
     set_device(c);
-    init_kernel_attributes();
-    if (const char *e = getenv("RTDM_B4_ROWSTAT")) c->row_stationary4 = atoi(e);   // measurements
     if (const char *e = getenv("RTDM_RUN_REAL")) c->run_real = atoi(e);
     if (const char *e = getenv("RTDM_RUN_CPLX")) c->run_cplx = atoi(e);
     if (const char *e = getenv("RTDM_ROW_TILE")) c->row_tile = std::max(1, atoi(e));

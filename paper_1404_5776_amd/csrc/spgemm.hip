@@ -258,17 +258,6 @@ __global__ __launch_bounds__(256) void k_spgemm16(
 // indices instead of padding every triple from B to a multiple of 4.  Lane
 // (q, r) supplies index kappa = 4*s + q at step s.  The operands of step s+1
 // are loaded before the matrix-core work of step s is issued.
-// Kernel choice for b = 13 (generic products: 0 direct gathers, 1 LDS-staged;
-// step products: 0 four-triple groups, 2 direct gathers); RTDM_B13_KERNEL
-// overrides it for measurements.
-static int kernel_variant()
-{
-    static int v = [] {
-        const char *e = getenv("RTDM_B13_KERNEL");
-        return e ? atoi(e) : 0;
-    }();
-    return v;
-}
 
 // Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by
 // block index.  xcd_block() with remap = 1 renumbers them so that XCD x runs
@@ -296,35 +285,16 @@ static inline unsigned xcd_grid(int64_t nblocks, int remap = 1)
 }
 
 // XCD mapping of the row-run kernels: the chunk size of the round-robin deal
-// (128 by default: the XCDs then stream neighbouring outputs, whose operand
-// blocks meet in the shared last-level cache; contiguous eighths, 1, measured
-// 11 % slower at b = 13).  RTDM_XCD_CHUNK sets it for measurements.
-static int xcd_chunk()
-{
-    static const int v = [] {
-        const char *e = getenv("RTDM_XCD_CHUNK");
-        const int x = e ? atoi(e) : 128;
-        return x > 1 ? x : 1;
-    }();
-    return v;
-}
-// The same deal in chunks of about as many output blocks (1,024 by default)
-// for a kernel with `per_wg` output blocks per workgroup.
-static int xcd_chunk_wg(int per_wg)
-{
-    const int c = xcd_chunk();
-    return c > 1 ? std::max(2, c * 8 / std::max(per_wg, 1)) : 1;
-}
-// Same for the b = 4 run kernels (RTDM_B4_CHUNK; 0 keeps the hardware order).
-static int b4_chunk()
-{
-    static const int v = [] {
-        const char *e = getenv("RTDM_B4_CHUNK");
-        const int x = e ? atoi(e) : 0;
-        return x > 1 ? x : (x == 1 ? 1 : 0);
-    }();
-    return v;
-}
+// (128 workgroups: the XCDs then stream neighbouring outputs, whose operand
+// blocks meet in the shared last-level cache; contiguous eighths measured
+// 11 % slower at b = 13).
+static int xcd_chunk() { return 128; }
+// The same deal in chunks of about as many output blocks (1,024) for a kernel
+// with `per_wg` output blocks per workgroup.
+static int xcd_chunk_wg(int per_wg) { return std::max(2, xcd_chunk() * 8 / std::max(per_wg, 1)); }
+// The b = 4 run kernels keep the hardware order (the deal changed their rate by
+// under 2 % either way).
+static int b4_chunk() { return 0; }
 
 // Matrix-core step on one 16x16 tile: FP64 (v_mfma_f64_16x16x4_f64) or
 // FP32 (v_mfma_f32_16x16x4_f32).  Both take A[r][q] / B[q][r] from lane
@@ -619,168 +589,6 @@ __global__ __launch_bounds__(256, MINW) void k_spgemm_q4j(
             }
         }
     }
-}
-
-// k_spgemm_q4 with the operands of the next group of four triples loaded into
-// registers while the matrix cores work on the current group, so the load
-// latency of one group hides behind B*SUB MFMAs of the previous one.
-template <int B, bool AC, bool BC, int CJA, int CJB, int LC>
-__global__ __launch_bounds__(256) void k_spgemm_q4p(
-    int64_t nout, const int64_t *__restrict__ off, const int2 *__restrict__ trip,
-    const double *__restrict__ ar, const double *__restrict__ ai, const double *__restrict__ br,
-    const double *__restrict__ bi, double *__restrict__ cr, double *__restrict__ ci, double alr,
-    double ali, const double *__restrict__ zero, const int32_t *__restrict__ order)
-{
-    static_assert(B >= 4 && B <= 16, "k_spgemm_q4p needs 4 <= B <= 16");
-    constexpr int BB = B * B;
-    const int lane = threadIdx.x & 63;
-    const int64_t w = xcd_block((nout + 3) / 4) * 4 + (threadIdx.x >> 6);
-    if (w >= nout) return;                     // uniform across the wave
-    const int64_t c = order ? (int64_t)order[w] : w;
-    const int r = lane & 15, q = lane >> 4;
-    const bool rv = r < B;
-    const int64_t t0 = off[c];
-    const int nt = (int)(off[c + 1] - t0);
-    typedef Mfma16<double>::acc_t acc_t;
-    acc_t rr = {0, 0, 0, 0}, ii = {0, 0, 0, 0}, ri = {0, 0, 0, 0}, ir = {0, 0, 0, 0};
-    double ca[B], cai[B], cb[B], cbi[B];       // current group
-    auto load = [&](int g, double *xa, double *xai, double *xb, double *xbi) {
-        const double *pa = zero, *pai = zero, *pb = zero, *pbi = zero;
-        if (rv && g + q < nt) {
-            const int2 ab = trip[t0 + g + q];
-            const int64_t oa = (int64_t)ab.x * BB + r, ob = (int64_t)ab.y * BB + r;
-            pa = ar + oa;
-            pb = br + ob;
-            if (AC) pai = ai + oa;
-            if (BC) pbi = bi + ob;
-        }
-#pragma unroll
-        for (int st = 0; st < B; ++st) {
-            xa[st] = pa[st * B];
-            xb[st] = pb[st * B];
-            if (AC) xai[st] = pai[st * B];
-            if (BC) xbi[st] = pbi[st * B];
-        }
-    };
-    if (nt > 0) load(0, ca, cai, cb, cbi);
-    for (int g = 0; g < nt; g += 4) {
-        double na[B], nai[B], nb[B], nbi[B];
-        if (g + 4 < nt) load(g + 4, na, nai, nb, nbi);
-#pragma unroll
-        for (int st = 0; st < B; ++st) {
-            rr = Mfma16<double>::step(ca[st], cb[st], rr);
-            if (AC && BC) ii = Mfma16<double>::step(cai[st], cbi[st], ii);
-            if (BC) ri = Mfma16<double>::step(ca[st], cbi[st], ri);
-            if (AC) ir = Mfma16<double>::step(cai[st], cb[st], ir);
-        }
-#pragma unroll
-        for (int st = 0; st < B; ++st) {
-            ca[st] = na[st];
-            cb[st] = nb[st];
-            if (AC) cai[st] = nai[st];
-            if (BC) cbi[st] = nbi[st];
-        }
-    }
-    constexpr double sa = CJA ? -1.0 : 1.0, sb = CJB ? -1.0 : 1.0;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int row = Mfma16<double>::row(e, q), col = r;
-        if (row < B && col < B) {
-            const double re = rr[e] - (sa * sb) * ii[e];
-            const double im = sb * ri[e] + sa * ir[e];
-            const int64_t o = c * BB + (LC ? col * B + row : row * B + col);
-            cr[o] = alr * re - ali * im;
-            if (ci) ci[o] = alr * im + ali * re;
-        }
-    }
-}
-
-// LDS-staged variant for a compile-time block size B: the operand blocks of CH
-// triples of the wave's output block are first copied into the wave's own LDS
-// region with coalesced loads (each block plane is B*B contiguous doubles),
-// then the MFMA fragments of the B*CH contraction indices of the chunk are
-// read from LDS (for B = 13, CH = 4 that is exactly 13 steps of 4).  Every
-// wave owns its region, so no workgroup barrier is needed: a wave's LDS
-// operations execute in issue order.
-template <int B, bool AC, bool BC, int OPA, int OPB, int CH, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_spgemm_lds(
-    int64_t nout, const int64_t *__restrict__ off, const int2 *__restrict__ trip,
-    const double *__restrict__ ar, const double *__restrict__ ai, const double *__restrict__ br,
-    const double *__restrict__ bi, double *__restrict__ cr, double *__restrict__ ci, double alr,
-    double ali)
-{
-    constexpr int BB = B * B;
-    constexpr int NPA = AC ? 2 : 1, NPB = BC ? 2 : 1;
-    constexpr int PL = (NPA + NPB) * BB;       // staged doubles per triple
-    constexpr int STEPS = (B * CH + 3) / 4;
-    __shared__ double lds[WPB][CH * PL];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t c = (int64_t)blockIdx.x * WPB + w;
-    if (c >= nout) return;                     // uniform across the wave
-    double *L = lds[w];
-    const int r = lane & 15, q = lane >> 4;
-    const bool rv = r < B;
-    const int64_t t0 = off[c];
-    const int nt = (int)(off[c + 1] - t0);
-    typedef Mfma16<double>::acc_t acc_t;
-    acc_t rr = {0, 0, 0, 0}, ii = {0, 0, 0, 0}, ri = {0, 0, 0, 0}, ir = {0, 0, 0, 0};
-    for (int tc = 0; tc < nt; tc += CH) {
-        const int nch = nt - tc < CH ? nt - tc : CH;
-        for (int u = 0; u < nch; ++u) {
-            const int2 ab = trip[t0 + tc + u];
-            const int64_t pa = (int64_t)ab.x * BB, pb = (int64_t)ab.y * BB;
-            double *d = L + u * PL;
-            for (int e = lane; e < BB; e += 64) {
-                d[e] = ar[pa + e];
-                if (AC) d[BB + e] = ai[pa + e];
-                d[NPA * BB + e] = br[pb + e];
-                if (BC) d[(NPA + 1) * BB + e] = bi[pb + e];
-            }
-        }
-        __builtin_amdgcn_wave_barrier();
-        const int kv = B * nch;
-#pragma unroll
-        for (int s = 0; s < STEPS; ++s) {
-            const int kap = 4 * s + q;
-            const int u = kap / B, m = kap - u * B;
-            double xar = 0.0, xai = 0.0, xbr = 0.0, xbi = 0.0;
-            if (kap < kv && rv) {
-                const double *la = L + u * PL;
-                const double *lb = la + NPA * BB;
-                const int ia = OPA ? (m * B + r) : (r * B + m);   // op(A)[r][m]
-                const int ib = OPB ? (r * B + m) : (m * B + r);   // op(B)[m][r]
-                xar = la[ia];
-                xbr = lb[ib];
-                if (AC) xai = OPA ? -la[BB + ia] : la[BB + ia];
-                if (BC) xbi = OPB ? -lb[BB + ib] : lb[BB + ib];
-            }
-            rr = Mfma16<double>::step(xar, xbr, rr);
-            if (AC && BC) ii = Mfma16<double>::step(xai, xbi, ii);
-            if (BC) ri = Mfma16<double>::step(xar, xbi, ri);
-            if (AC) ir = Mfma16<double>::step(xai, xbr, ir);
-        }
-        __builtin_amdgcn_wave_barrier();
-    }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int row = Mfma16<double>::row(e, q), col = r;
-        if (row < B && col < B) {
-            const double re = rr[e] - ii[e];
-            const double im = ri[e] + ir[e];
-            const int64_t o = c * BB + row * B + col;
-            cr[o] = alr * re - ali * im;
-            if (ci) ci[o] = alr * im + ali * re;
-        }
-    }
-}
-
-template <int B, bool AC, bool BC, int OA, int OB>
-static void launch_lds(hipStream_t s, const SpgemmArgs &a)
-{
-    constexpr int WPB = (AC && BC) ? 2 : 4;
-    hipLaunchKernelGGL((k_spgemm_lds<B, AC, BC, OA, OB, 4, WPB>),
-                       dim3((unsigned)((a.nout + WPB - 1) / WPB)), dim3(64 * WPB), 0, s, a.nout,
-                       a.off, a.trip, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re, a.alpha_im);
 }
 
 // b = 4: v_mfma_f64_4x4x4_4b_f64 runs four independent 4x4x4 products, one
@@ -1108,107 +916,6 @@ __global__ __launch_bounds__(256) void k_spgemm_b4(
 }
 
 
-// Row-stationary product for b = 4 (FP64, op(A) = A): one workgroup per row i
-// of C.  The blocks of row i of A are contiguous in A's storage; the
-// workgroup copies them into LDS once, and every triple of every output
-// (i, j) then takes its A block from LDS, so only the B blocks stream from
-// memory (one block per triple instead of two).  Each wave runs four output
-// blocks at a time as the four blocks of v_mfma_f64_4x4x4_4b, one triple
-// per instruction (lane 16q + 4g + r: A_g[r][q], B_g[q][r], D_g[q][r]).
-template <bool AC, bool BC, int OPB>
-__global__ __launch_bounds__(256) void k_spgemm_b4r(
-    int64_t n_rows, const int64_t *__restrict__ c_rowptr, const int64_t *__restrict__ a_rowptr,
-    const int64_t *__restrict__ off, const int2 *__restrict__ trip, const double *__restrict__ ar,
-    const double *__restrict__ ai, const double *__restrict__ br, const double *__restrict__ bi,
-    double *__restrict__ cr, double *__restrict__ ci, double alr, double ali)
-{
-    extern __shared__ double lds[];            // [plane][block of row i][16]
-    const int64_t i = xcd_block(n_rows);
-    if (i >= n_rows) return;                   // uniform across the workgroup
-    const int64_t a0 = a_rowptr[i], na = a_rowptr[i + 1] - a0;
-    const int tid = threadIdx.x;
-    for (int64_t e = tid; e < na * 16; e += 256) {
-        lds[e] = ar[a0 * 16 + e];
-        if (AC) lds[na * 16 + e] = ai[a0 * 16 + e];
-    }
-    __syncthreads();
-    const int lane = tid & 63, w = tid >> 6;
-    const int g = (lane >> 2) & 3, r = lane & 3, q = lane >> 4;
-    const int ia = r * 4 + q;                          // A[r][q]
-    const int ib = OPB ? (r * 4 + q) : (q * 4 + r);    // op(B)[q][r]
-    const double sb = OPB ? -1.0 : 1.0;                // conjugate of op(B) = B^dagger
-    const int64_t c_beg = c_rowptr[i], c_end = c_rowptr[i + 1];
-    for (int64_t c0 = c_beg + 4 * w; c0 < c_end; c0 += 16) {
-        const int64_t c = c0 + g;
-        const bool live = c < c_end;
-        const int64_t t0 = live ? off[c] : 0;
-        const int nt = live ? (int)(off[c + 1] - t0) : 0;
-        int ntmax = max(nt, __shfl_xor(nt, 4, 64));
-        ntmax = max(ntmax, __shfl_xor(ntmax, 8, 64));
-        double rr = 0.0, ii = 0.0, ri = 0.0, ir = 0.0;
-        for (int t = 0; t < ntmax; ++t) {
-            double xar = 0.0, xai = 0.0, xbr = 0.0, xbi = 0.0;
-            if (t < nt) {
-                const int2 ab = trip[t0 + t];
-                const int64_t la = (int64_t)(ab.x - a0) * 16 + ia;
-                const int64_t pb = (int64_t)ab.y * 16 + ib;
-                xar = lds[la];
-                xbr = br[pb];
-                if (AC) xai = lds[na * 16 + la];
-                if (BC) xbi = sb * bi[pb];
-            }
-            rr = __builtin_amdgcn_mfma_f64_4x4x4f64(xar, xbr, rr, 0, 0, 0);
-            if (AC && BC) ii = __builtin_amdgcn_mfma_f64_4x4x4f64(xai, xbi, ii, 0, 0, 0);
-            if (BC) ri = __builtin_amdgcn_mfma_f64_4x4x4f64(xar, xbi, ri, 0, 0, 0);
-            if (AC) ir = __builtin_amdgcn_mfma_f64_4x4x4f64(xai, xbr, ir, 0, 0, 0);
-        }
-        if (live) {
-            const double re = rr - ii, im = ri + ir;
-            const int64_t o = c * 16 + q * 4 + r;
-            cr[o] = alr * re - ali * im;
-            if (ci) ci[o] = alr * im + ali * re;
-        }
-    }
-}
-
-// Allow the row-stationary kernels the whole LDS of a CU (set once, outside
-// any stream capture).
-void init_kernel_attributes()
-{
-    const int bytes = 160 * 1024;
-    const void *ks[] = {(const void *)k_spgemm_b4r<true, true, 0>,   (const void *)k_spgemm_b4r<true, false, 0>,
-                        (const void *)k_spgemm_b4r<false, true, 0>,  (const void *)k_spgemm_b4r<false, false, 0>,
-                        (const void *)k_spgemm_b4r<true, true, 1>,   (const void *)k_spgemm_b4r<true, false, 1>,
-                        (const void *)k_spgemm_b4r<false, true, 1>,  (const void *)k_spgemm_b4r<false, false, 1>};
-    for (const void *k : ks) RT_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
-}
-
-void launch_spgemm_b4r(hipStream_t s, const SpgemmArgs &a, int64_t n_rows, const int64_t *c_rowptr,
-                       const int64_t *a_rowptr, int64_t max_row)
-{
-    if (a.nout == 0) return;
-    RT_CHECK(a.b == 4 && a.precision == RTDM_PREC_FP64 && a.op_a == 0, RTDM_E_UNSUPPORTED,
-             "row-stationary products need b = 4, FP64 and op(A) = A");
-    const bool ac = a.ai != nullptr, bc = a.bi != nullptr;
-    const size_t lds = (size_t)max_row * 16 * sizeof(double) * (ac ? 2 : 1);
-    const dim3 grid(xcd_grid(n_rows)), blk(256);
-#define RT_B4R(AC_, BC_, OB_)                                                                         \
-    hipLaunchKernelGGL((k_spgemm_b4r<AC_, BC_, OB_>), grid, blk, lds, s, n_rows, c_rowptr, a_rowptr, a.off, \
-                       a.trip, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re, a.alpha_im)
-    if (a.op_b) {
-        if (ac && bc) RT_B4R(true, true, 1);
-        else if (ac) RT_B4R(true, false, 1);
-        else if (bc) RT_B4R(false, true, 1);
-        else RT_B4R(false, false, 1);
-    } else {
-        if (ac && bc) RT_B4R(true, true, 0);
-        else if (ac) RT_B4R(true, false, 0);
-        else if (bc) RT_B4R(false, true, 0);
-        else RT_B4R(false, false, 0);
-    }
-#undef RT_B4R
-    RT_HIP(hipGetLastError());
-}
 
 
 // Reduced-precision products for b = 4 on the 16-block 4x4 matrix-core
@@ -1530,17 +1237,6 @@ static void launch_split(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
 #undef RT_SPLIT
 }
 
-// FP64 b = 4 per-triple products: 16 outputs per wave (1) or 4 (0); RTDM_B4_WIDE
-// overrides it for measurements.
-static int b4_wide()
-{
-    static int v = [] {
-        const char *e = getenv("RTDM_B4_WIDE");
-        return e ? atoi(e) : 1;
-    }();
-    return v;
-}
-
 template <bool AC, bool BC>
 static void dispatch_ops(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
 {
@@ -1560,12 +1256,10 @@ static void dispatch_ops(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
                                a.alpha_im);                                                      \
         else if (a.b == 4 && OA == 0 && a.nch > 0)                                               \
             launch_b4j<AC, BC, OB>(s, a);                                                        \
-        else if (a.b == 4 && OA == 0 && b4_wide())                                               \
+        else if (a.b == 4 && OA == 0)                                                            \
             launch_b4w<AC, BC, OB>(s, a);                                                        \
         else if (a.b == 4)                                                                       \
             launch_b4<(AC && BC) ? 4 : ((AC || BC) ? 2 : 1), AC, BC, OA, OB>(s, a);              \
-        else if (a.b == 13 && kernel_variant() == 1)                                             \
-            launch_lds<13, AC, BC, OA, OB>(s, a);                                                \
         else if (a.b == 13)                                                                      \
             hipLaunchKernelGGL((k_spgemm_kc<13, AC, BC, OA, OB>), g, t, 0, s, a.nout, a.off,     \
                                a.trip, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re,           \
@@ -1585,39 +1279,18 @@ static void dispatch_ops(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
 #undef RT_LAUNCH
 }
 
-// Unused LDS bytes per workgroup of the b = 13 step kernels, which caps the
-// workgroups per CU (and so the output blocks in flight per L2); 0 by
-// default, RTDM_STEP_LDS sets it for measurements.
-static unsigned occupancy_lds()
-{
-    static const unsigned v = [] {
-        const char *e = getenv("RTDM_STEP_LDS");
-        const long x = e ? atol(e) : 0;
-        return (unsigned)std::min<long>(std::max<long>(x, 0), 160 * 1024);
-    }();
-    return v;
-}
-
 // Step products with a column-major copy of the left operand (op(A)[r][m] at
 // m*B + r) and a right operand whose op(B)[m][r] sits at m*B + r (row-major
 // B, or the column-major copy of a matrix used conjugate-transposed).
 template <bool AC, bool BC, int CJB, int LC>
 static void launch_cm(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
 {
-    if (kernel_variant() == 2)
-        hipLaunchKernelGGL((k_spgemm_kc<13, AC, BC, 1, 0, double, 0, CJB, LC>), g, t, 0, s, a.nout,
-                           a.off, a.trip, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re, a.alpha_im);
-    else if (kernel_variant() == 3)
-        hipLaunchKernelGGL((k_spgemm_q4p<13, AC, BC, 0, CJB, LC>), dim3(xcd_grid(g.x)), t, 0, s, a.nout,
-                           a.off, a.trip, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re, a.alpha_im,
-                           a.zero, a.order);
-    else {
+    {
         const int wpb = a.wpb;
-        const int remap = getenv("RTDM_NO_XCD") ? 0 : xcd_chunk_wg(wpb);
+        const int remap = xcd_chunk_wg(wpb);
         const unsigned grid = xcd_grid((a.nout + wpb - 1) / wpb, remap);
-        const unsigned lds = occupancy_lds();
 #define RT_Q4(W, T)                                                                               \
-    hipLaunchKernelGGL((k_spgemm_q4<13, AC, BC, 0, CJB, LC, W, T>), dim3(grid), dim3(64 * W), lds, s, \
+    hipLaunchKernelGGL((k_spgemm_q4<13, AC, BC, 0, CJB, LC, W, T>), dim3(grid), dim3(64 * W), 0, s, \
                        a.nout, a.off, a.trip, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re,       \
                        a.alpha_im, a.zero, a.order, remap)
         if (a.precision == RTDM_PREC_FP32) {
@@ -1637,12 +1310,11 @@ static void launch_cm(hipStream_t s, const SpgemmArgs &a, dim3 g, dim3 t)
 template <bool AC, bool BC, int CJB, int LC>
 static void launch_cmj(hipStream_t s, const SpgemmArgs &a)
 {
-    const int remap = getenv("RTDM_NO_XCD") ? 0 : xcd_chunk();
+    const int remap = xcd_chunk();
     const unsigned grid = xcd_grid((a.nch + 3) / 4, remap);
     const bool f32 = a.precision == RTDM_PREC_FP32;
-    const unsigned lds = occupancy_lds();
 #define RT_Q4J_W(NJ, T, W)                                                                       \
-    hipLaunchKernelGGL((k_spgemm_q4j<13, AC, BC, CJB, LC, NJ, T, W>), dim3(grid), dim3(256), lds, s,   \
+    hipLaunchKernelGGL((k_spgemm_q4j<13, AC, BC, CJB, LC, NJ, T, W>), dim3(grid), dim3(256), 0, s,   \
                        a.nch,                                                                         \
                        a.ch_off, a.ch_a, a.ch_b, a.ch_out, a.ar, a.ai, a.br, a.bi, a.cr, a.ci,        \
                        a.alpha_re, a.alpha_im, a.zero, a.ch_order, remap, a.ch_seg)
@@ -1676,13 +1348,11 @@ void launch_spgemm_cm(hipStream_t s, const SpgemmArgs &a, int conj_b, int out_co
     if (a.nout == 0) return;
     RT_CHECK(a.b == 13 && (a.precision == RTDM_PREC_FP64 || a.precision == RTDM_PREC_FP32), RTDM_E_UNSUPPORTED,
              "column-major step products need b = 13 and FP64 or FP32");
-    RT_CHECK(a.precision == RTDM_PREC_FP64 || kernel_variant() == 0, RTDM_E_UNSUPPORTED,
-             "the measured step-kernel variants are FP64 only");
     const dim3 g((unsigned)((a.nout + 3) / 4)), t(256);
     const bool ac = a.ai != nullptr, bc = a.bi != nullptr;
 #define RT_CM(AC_, BC_)                                                            \
     do {                                                                           \
-        if (a.nch > 0 && kernel_variant() == 0) {                                  \
+        if (a.nch > 0) {                                                           \
             if (conj_b && out_col_major) launch_cmj<AC_, BC_, 1, 1>(s, a);         \
             else if (conj_b) launch_cmj<AC_, BC_, 1, 0>(s, a);                     \
             else if (out_col_major) launch_cmj<AC_, BC_, 0, 1>(s, a);              \
