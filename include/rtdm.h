@@ -390,6 +390,13 @@ int rtdm_mlp_train(rtdm_ctx *ctx, int epochs, int batch, double lr, uint64_t see
  * n x out), without updating; and the forward pass for n host descriptors. */
 int rtdm_mlp_loss_grad(rtdm_ctx *ctx, int64_t n, const float *desc, const float *target, double *loss,
                        float *grad);
+/* Test entry: one Adam step (Kingma and Ba 2015; beta1 0.9, beta2 0.999,
+ * eps 1e-8, the constants of rtdm_mlp_train) on the gradient of the loss of
+ * n host samples (desc n x in, target n x out, copied) at learning rate lr;
+ * the step counter and moments continue from the previous steps and restart
+ * at rtdm_mlp_init / rtdm_mlp_set_weights.  *loss receives the loss before
+ * the step.  Synchronises. */
+int rtdm_mlp_step(rtdm_ctx *ctx, int64_t n, const float *desc, const float *target, double lr, double *loss);
 int rtdm_mlp_predict(rtdm_ctx *ctx, int64_t n, const float *desc, float *y);
 
 /* Truncation error of the inverse (Sec. V.A, the paper's measure of the

@@ -59,6 +59,19 @@ def loss_grad(w, x, t, n_in, n_out, fp16=True):
     return loss, np.concatenate([dW1.ravel(), db1, dW2.ravel(), db2])
 
 
+def adam(w, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """Step t (1, 2, ...) of Adam (Kingma and Ba, 2015, Algorithm 1): the
+    moments m <- beta1 m + (1 - beta1) g and v <- beta2 v + (1 - beta2) g^2,
+    their bias-corrected values m / (1 - beta1^t) and v / (1 - beta2^t), and
+    w <- w - lr m_hat / (sqrt(v_hat) + eps).  Returns (w, m, v)."""
+    g = np.asarray(g, np.float64)
+    m = beta1 * np.asarray(m, np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, np.float64) + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** t)
+    v_hat = v / (1.0 - beta2 ** t)
+    return np.asarray(w, np.float64) - lr * m_hat / (np.sqrt(v_hat) + eps), m, v
+
+
 def descriptors(xyz, S, R):
     """d for every block of S (oracle BSM on S's pattern), in S's block order."""
     r = S.pat.rows()

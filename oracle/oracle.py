@@ -61,6 +61,7 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
+import math
 import os
 import subprocess
 from typing import List, Optional, Sequence, Tuple
@@ -349,9 +350,16 @@ def mulliken(K: BSM, S: BSM) -> np.ndarray:
     return q
 
 
+def centroid(xyz: np.ndarray) -> np.ndarray:
+    """r_c = (sum_i r_i) / n, each coordinate sum rounded once (math.fsum is
+    exactly rounded), so r_c does not depend on the order of the atoms."""
+    n = xyz.shape[0]
+    return np.array([math.fsum(xyz[:, k]) for k in range(3)]) / n
+
+
 def dipole(q: np.ndarray, xyz: np.ndarray) -> np.ndarray:
     """P = -sum_i (r_i - r_c) q_i (electron charge -1, r_c = centroid)."""
-    rc = xyz.mean(axis=0)
+    rc = centroid(xyz)
     return -((xyz - rc) * q[:, None]).sum(axis=0)
 
 
@@ -437,7 +445,7 @@ def field_term(S: BSM, xyz: np.ndarray, E: np.ndarray) -> BSM:
     """Matrix of the electrons' energy E . (r - r_c) on the support functions, in
     the position model of the dipole reading: <i|r|j> = (r_i + r_j)/2 S_ij,
     r_c the atom centroid."""
-    rc = xyz.mean(axis=0)
+    rc = centroid(xyz)
     r = S.pat.rows()
     c = S.pat.col.astype(np.int64)
     mid = 0.5 * ((xyz[r] - rc) + (xyz[c] - rc))          # (nnzb, 3)

@@ -345,21 +345,14 @@ void launch_spectrum(hipStream_t s, int64_t n_omega, const double *omega, double
 // (st[1] + 1) * tt[1], and both counters advance; without one (st null) the
 // row is `out` and the time `t`.
 __global__ __launch_bounds__(kT) void k_observables(int64_t n, const double *__restrict__ xyz,
+                                                    const double *__restrict__ centre,
                                                     const double *__restrict__ q,
                                                     const double *__restrict__ herm_sums, double t,
                                                     double *__restrict__ out, int64_t *st,
                                                     const double *__restrict__ tt)
 {
     __shared__ double sh[4 * kT];
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t i = threadIdx.x; i < n; i += kT) {
-        v[0] += xyz[3 * i];
-        v[1] += xyz[3 * i + 1];
-        v[2] += xyz[3 * i + 2];
-    }
-    block_reduce4(v, sh);
-    const double cx = v[0] / (double)n, cy = v[1] / (double)n, cz = v[2] / (double)n;
-    __syncthreads();
+    const double cx = centre[0], cy = centre[1], cz = centre[2];
     double w[4] = {0.0, 0.0, 0.0, 0.0};
     double tr = 0.0;
     for (int64_t i = threadIdx.x; i < n; i += kT) {
@@ -387,10 +380,10 @@ __global__ __launch_bounds__(kT) void k_observables(int64_t n, const double *__r
     }
 }
 
-void launch_observables(hipStream_t s, int64_t n_atoms, const double *xyz, const double *q,
+void launch_observables(hipStream_t s, int64_t n_atoms, const double *xyz, const double *centre, const double *q,
                         const double *herm_sums, double t, double *row)
 {
-    hipLaunchKernelGGL(k_observables, dim3(1), dim3(kT), 0, s, n_atoms, xyz, q, herm_sums, t, row,
+    hipLaunchKernelGGL(k_observables, dim3(1), dim3(kT), 0, s, n_atoms, xyz, centre, q, herm_sums, t, row,
                        (int64_t *)nullptr, (const double *)nullptr);
     RT_HIP(hipGetLastError());
 }
@@ -404,10 +397,11 @@ __global__ void k_step_end(int64_t *st)
     }
 }
 
-void launch_observables_step(hipStream_t s, int64_t n_atoms, const double *xyz, const double *q,
-                             const double *herm_sums, double *obs, int64_t *st, const double *tt)
+void launch_observables_step(hipStream_t s, int64_t n_atoms, const double *xyz, const double *centre,
+                             const double *q, const double *herm_sums, double *obs, int64_t *st, const double *tt)
 {
-    hipLaunchKernelGGL(k_observables, dim3(1), dim3(kT), 0, s, n_atoms, xyz, q, herm_sums, 0.0, obs, st, tt);
+    hipLaunchKernelGGL(k_observables, dim3(1), dim3(kT), 0, s, n_atoms, xyz, centre, q, herm_sums, 0.0, obs, st,
+                       tt);
     RT_HIP(hipGetLastError());
 }
 
@@ -592,6 +586,7 @@ void launch_step_begin(hipStream_t s, int64_t *st, double *tt, double t0, double
 // to out[row][g][0..3] with row = st[0].
 __global__ __launch_bounds__(kT) void k_group_obs(const int64_t *__restrict__ gptr,
                                                   const double *__restrict__ xyz,
+                                                  const double *__restrict__ centre,
                                                   const double *__restrict__ q,
                                                   const int64_t *__restrict__ st, int64_t n_groups,
                                                   double *__restrict__ out)
@@ -599,16 +594,7 @@ __global__ __launch_bounds__(kT) void k_group_obs(const int64_t *__restrict__ gp
     __shared__ double sh[4 * kT];
     const int64_t g = blockIdx.x;
     const int64_t a0 = gptr[g], a1 = gptr[g + 1];
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t i = a0 + threadIdx.x; i < a1; i += kT) {
-        v[0] += xyz[3 * i];
-        v[1] += xyz[3 * i + 1];
-        v[2] += xyz[3 * i + 2];
-    }
-    block_reduce4(v, sh);
-    const double na = (double)(a1 - a0);
-    const double cx = v[0] / na, cy = v[1] / na, cz = v[2] / na;
-    __syncthreads();
+    const double cx = centre[3 * g], cy = centre[3 * g + 1], cz = centre[3 * g + 2];
     double w[4] = {0.0, 0.0, 0.0, 0.0};
     double tr = 0.0;
     for (int64_t i = a0 + threadIdx.x; i < a1; i += kT) {
@@ -631,11 +617,12 @@ __global__ __launch_bounds__(kT) void k_group_obs(const int64_t *__restrict__ gp
     }
 }
 
-void launch_group_obs(hipStream_t s, int64_t n_groups, const int64_t *gptr, const double *xyz, const double *q,
-                      const int64_t *st, double *out)
+void launch_group_obs(hipStream_t s, int64_t n_groups, const int64_t *gptr, const double *xyz, const double *centre,
+                      const double *q, const int64_t *st, double *out)
 {
     if (n_groups == 0) return;
-    hipLaunchKernelGGL(k_group_obs, dim3((unsigned)n_groups), dim3(kT), 0, s, gptr, xyz, q, st, n_groups, out);
+    hipLaunchKernelGGL(k_group_obs, dim3((unsigned)n_groups), dim3(kT), 0, s, gptr, xyz, centre, q, st, n_groups,
+                       out);
     RT_HIP(hipGetLastError());
 }
 

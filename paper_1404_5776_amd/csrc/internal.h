@@ -205,16 +205,17 @@ void launch_spectrum(hipStream_t s, int64_t n_omega, const double *omega, double
                      const double *trace, int64_t stride, int64_t off, const double P0[3], int kick,
                      const double E0[3], double t0, double sigma, double *alpha, double *strength);
 // Observable row: t, P(3), Tr(KS), herm_err from (partials -> sums), unit_err = NaN.
-void launch_observables(hipStream_t s, int64_t n_atoms, const double *xyz, const double *q,
+// centre: the atoms' centroid (3 doubles, computed on the host with an exactly rounded sum).
+void launch_observables(hipStream_t s, int64_t n_atoms, const double *xyz, const double *centre, const double *q,
                         const double *herm_sums, double t, double *row);
 // The same observables written to obs + 8 * st[0] at time tt[0] + (st[1] + 1) * tt[1].
-void launch_observables_step(hipStream_t s, int64_t n_atoms, const double *xyz, const double *q,
-                             const double *herm_sums, double *obs, int64_t *st, const double *tt);
+void launch_observables_step(hipStream_t s, int64_t n_atoms, const double *xyz, const double *centre,
+                             const double *q, const double *herm_sums, double *obs, int64_t *st, const double *tt);
 void launch_step_begin(hipStream_t s, int64_t *st, double *tt, double t0, double dt);
 void launch_step_end(hipStream_t s, int64_t *st);
 void launch_fill(hipStream_t s, int64_t n, double v, double *out);
-void launch_group_obs(hipStream_t s, int64_t n_groups, const int64_t *gptr, const double *xyz, const double *q,
-                      const int64_t *st, double *out);
+void launch_group_obs(hipStream_t s, int64_t n_groups, const int64_t *gptr, const double *xyz, const double *centre,
+                      const double *q, const int64_t *st, double *out);
 void launch_kick_groups(hipStream_t s, int64_t nnzb, int b, const int32_t *rowof, const int32_t *col,
                         const double *xyz, const int32_t *group, const double *kappa, double *kr, double *ki);
 // X_ii = S_ii^{-1} (Gauss-Jordan, partial pivoting); other blocks untouched.
@@ -261,7 +262,7 @@ void launch_mlp_delta(hipStream_t s, int64_t n, int out, const int32_t *idx, con
 void launch_mlp_grad(hipStream_t s, int64_t n, int in, int out, const int32_t *idx, const float *x,
                      const float *hid, const float *dy, const float *dh, float *grad);
 void launch_adam(hipStream_t s, int64_t np, int64_t nw1, int64_t nb1, int64_t nw2, const float *grad, float *w,
-                 float *m, float *v, float lr, float beta1, float beta2, float eps, int step, __half *w1h,
+                 float *m, float *v, float lr, double beta1, double beta2, float eps, int step, __half *w1h,
                  __half *w2h);
 void launch_to_half(hipStream_t s, int64_t n, const float *x, __half *y);
 void launch_mlp_apply(hipStream_t s, int64_t n, int b, const int32_t *blk, const int32_t *x_of,

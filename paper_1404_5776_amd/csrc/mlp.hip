@@ -8,6 +8,8 @@
 // deterministic (fixed partition, fixed order).
 #include <hip/hip_fp16.h>
 
+#include <cmath>
+
 #include "internal.h"
 
 namespace rtdm {
@@ -222,16 +224,19 @@ void launch_mlp_grad(hipStream_t s, int64_t n, int in, int out, const int32_t *i
 
 // Adam (Kingma & Ba 2015) on the FP32 master weights, then the FP16 copies
 // used by the forward pass.  t is the 1-based step count.
+// omb1 = 1 - beta1, omb2 = 1 - beta2, c1 = 1 - beta1^t, c2 = 1 - beta2^t are
+// formed in double on the host and rounded once (1 - 0.999f^t in single
+// precision would lose three digits to cancellation).
 __global__ void k_adam(int64_t np, int64_t nw1, int64_t nb1, int64_t nw2, const float *__restrict__ grad,
                        float *__restrict__ w, float *__restrict__ m, float *__restrict__ v, float lr,
-                       float beta1, float beta2, float eps, float c1, float c2, __half *__restrict__ w1h,
-                       __half *__restrict__ w2h)
+                       float beta1, float beta2, float omb1, float omb2, float eps, float c1, float c2,
+                       __half *__restrict__ w1h, __half *__restrict__ w2h)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
     const float g = grad[p];
-    const float mi = beta1 * m[p] + (1.0f - beta1) * g;
-    const float vi = beta2 * v[p] + (1.0f - beta2) * g * g;
+    const float mi = beta1 * m[p] + omb1 * g;
+    const float vi = beta2 * v[p] + omb2 * g * g;
     m[p] = mi;
     v[p] = vi;
     const float wi = w[p] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
@@ -241,12 +246,13 @@ __global__ void k_adam(int64_t np, int64_t nw1, int64_t nb1, int64_t nw2, const 
 }
 
 void launch_adam(hipStream_t s, int64_t np, int64_t nw1, int64_t nb1, int64_t nw2, const float *grad, float *w,
-                 float *m, float *v, float lr, float beta1, float beta2, float eps, int step, __half *w1h,
+                 float *m, float *v, float lr, double beta1, double beta2, float eps, int step, __half *w1h,
                  __half *w2h)
 {
-    const float c1 = 1.0f - powf(beta1, (float)step), c2 = 1.0f - powf(beta2, (float)step);
+    const double b1 = beta1, b2 = beta2;
+    const float c1 = (float)(1.0 - std::pow(b1, step)), c2 = (float)(1.0 - std::pow(b2, step));
     hipLaunchKernelGGL(k_adam, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, np, nw1, nb1, nw2, grad, w,
-                       m, v, lr, beta1, beta2, eps, c1, c2, w1h, w2h);
+                       m, v, lr, (float)beta1, (float)beta2, (float)(1.0 - b1), (float)(1.0 - b2), eps, c1, c2, w1h, w2h);
     RT_HIP(hipGetLastError());
 }
 

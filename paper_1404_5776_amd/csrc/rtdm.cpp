@@ -280,8 +280,9 @@ struct rtdm_ctx {
 
     Mat mats[RTDM_MAT_COUNT];
     Mat tau[2], Kn, Xn, Wh, V, Z;
-    // column-major block copies of the step's left operands (b = 13, FP64)
-    Mat Xc, Ac, Uc, Wc;
+    // column-major block copies of the step's left operands (b = 13, FP64) and
+    // of S for the inverse iteration
+    Mat Xc, Ac, Uc, Wc, Sc;
     bool Xc_valid = false, W_in_cm = false;
     // FP32 copies for the reduced-precision Taylor terms (b = 13)
     DBuf<float> Ac32, tau32[2], zero32;
@@ -338,7 +339,7 @@ struct rtdm_ctx {
     // external field E0 exp(-(t - t0)^2 / (2 sigma^2)); centres of the groups
     bool field_on = false;
     double field_E0[3] = {0.0, 0.0, 0.0}, field_t0 = 0.0, field_sigma = 1.0;
-    DBuf<double> d_centre;
+    DBuf<double> d_centre, d_centre_all;   // centres of the groups, of all atoms
     DBuf<double> f16_max;       // operand maxima of the FP16 split products
     bool timing = false;
     std::vector<hipEvent_t> events;
@@ -348,6 +349,24 @@ struct rtdm_ctx {
 namespace {
 
 void set_device(rtdm_ctx *c) { RT_HIP(hipSetDevice(c->device)); }
+
+// Centroid of atoms i0 .. i1-1: each coordinate sum accumulated without
+// rounding error (Knuth's two-sum, the error terms carried in a second
+// double), rounded once, then divided by the count.  Every implementation
+// that rounds the exact sum once gets the same centroid, so the dipole
+// about it does not depend on the summation order of the positions.
+void exact_centre(const std::vector<double> &xyz, int64_t i0, int64_t i1, double out[3])
+{
+    for (int k = 0; k < 3; ++k) {
+        double hi = 0.0, lo = 0.0;
+        for (int64_t i = i0; i < i1; ++i) {
+            const double x = xyz[3 * i + k], s = hi + x, bp = s - hi;
+            lo += (hi - (s - bp)) + (x - bp);
+            hi = s;
+        }
+        out[k] = (hi + lo) / (double)(i1 - i0);
+    }
+}
 
 int slot_range(int m)
 {
@@ -1216,6 +1235,7 @@ int rtdm_set_ranges(rtdm_ctx *c, double R_hs, double R_p, double R_k)
         alloc_mat(c, c->Ac, R_P, false);
         alloc_mat(c, c->Uc, R_P, true);
         alloc_mat(c, c->Wc, R_K, true);
+        alloc_mat(c, c->Sc, R_HS, false);
     }
     c->Xc_valid = false;
     c->W_in_cm = false;
@@ -1264,12 +1284,12 @@ int rtdm_set_ranges(rtdm_ctx *c, double R_hs, double R_p, double R_k)
     c->gptr.clear();
     c->obs_g.release();
     {
-        double cen[3] = {0.0, 0.0, 0.0};
-        for (int64_t i = 0; i < c->n; ++i)
-            for (int k = 0; k < 3; ++k) cen[k] += c->xyz[3 * i + k];
-        for (int k = 0; k < 3; ++k) cen[k] /= (double)c->n;
+        double cen[3];
+        exact_centre(c->xyz, 0, c->n, cen);
         c->d_centre.alloc(3);
+        c->d_centre_all.alloc(3);
         RT_HIP(hipMemcpy(c->d_centre.p, cen, sizeof(cen), hipMemcpyHostToDevice));
+        RT_HIP(hipMemcpy(c->d_centre_all.p, cen, sizeof(cen), hipMemcpyHostToDevice));
     }
     c->step_count = 0;
     c->trace_dt_mixed = false;
@@ -1476,13 +1496,14 @@ int rtdm_build_inverse(rtdm_ctx *c, void *stream, int *iters, double *residual)
         launch_add_identity(s, c->n, c->b, pp.d_diag.p, 1.0 / h[3], X.re.p);
     };
     // On the b = 13 column-major path both products run on the step kernels:
-    // a column-major copy of S for the whole iteration, of X per iteration.
+    // a column-major copy of S (a context buffer, so the iteration allocates
+    // nothing) for the whole iteration, of X per iteration.
     const bool cm = use_cm(c);
-    Mat Sc;
-    if (cm) {
-        alloc_like(c, Sc, S);
-        transpose_into(c, S, Sc, s);
-    }
+    Mat &Sc = c->Sc;
+    if (cm) transpose_into(c, S, Sc, s);
+    // X moves between buffers below and Xc is used as scratch: a captured step
+    // that reads either must be captured again
+    drop_graph(c);
     // Returns 1 converged, 0 diverged, -1 hit the cap.
     auto run = [&](int &k_out, double &r_out) -> int {
         std::vector<double> res;
@@ -1549,6 +1570,10 @@ int rtdm_build_inverse(rtdm_ctx *c, void *stream, int *iters, double *residual)
     if (residual) *residual = r;
     c->X_valid = (st == 1);
     c->Xc_valid = false;
+    if (cm && st == 1) {
+        transpose_into(c, X, c->Xc, s);   // the column-major copy of the converged X
+        c->Xc_valid = true;
+    }
     c->U_valid = false;
     RT_CHECK(st == 1, RTDM_E_NOCONV,
              "Hotelling iteration " + std::string(st == 0 ? "diverged" : "hit the iteration cap") +
@@ -1711,10 +1736,10 @@ void step_body(rtdm_ctx *c, double dt, bool rebuild_u, int passes, hipStream_t s
         launch_mulliken(s, c->n, c->b, ps.d_rowptr.p, ps.d_trans.p, c->s_to_k.p, c->mats[RTDM_MAT_S].re.p,
                         K.re.p, c->q_cur);
     }
-    launch_observables_step(s, c->n, c->d_xyz.p, c->q_cur, c->herm_sums.p, c->obs.p, c->step_st.p,
+    launch_observables_step(s, c->n, c->d_xyz.p, c->d_centre_all.p, c->q_cur, c->herm_sums.p, c->obs.p, c->step_st.p,
                             c->step_tt.p);
     if (c->n_groups > 1)
-        launch_group_obs(s, c->n_groups, c->d_gptr.p, c->d_xyz.p, c->q_cur, c->step_st.p, c->obs_g.p);
+        launch_group_obs(s, c->n_groups, c->d_gptr.p, c->d_xyz.p, c->d_centre.p, c->q_cur, c->step_st.p, c->obs_g.p);
     launch_step_end(s, c->step_st.p);
     c->prec = RTDM_PREC_FP64;
 }
@@ -2007,11 +2032,7 @@ int rtdm_set_groups(rtdm_ctx *c, int64_t n_groups, const int64_t *group_ptr)
     RT_HIP(hipMemcpy(c->d_gptr.p, group_ptr, c->d_gptr.bytes(), hipMemcpyHostToDevice));
     RT_HIP(hipMemcpy(c->d_group.p, grp.data(), c->d_group.bytes(), hipMemcpyHostToDevice));
     std::vector<double> cen(3 * n_groups, 0.0);
-    for (int64_t g = 0; g < n_groups; ++g) {
-        for (int64_t i = group_ptr[g]; i < group_ptr[g + 1]; ++i)
-            for (int k = 0; k < 3; ++k) cen[3 * g + k] += c->xyz[3 * i + k];
-        for (int k = 0; k < 3; ++k) cen[3 * g + k] /= (double)(group_ptr[g + 1] - group_ptr[g]);
-    }
+    for (int64_t g = 0; g < n_groups; ++g) exact_centre(c->xyz, group_ptr[g], group_ptr[g + 1], &cen[3 * g]);
     c->d_centre.alloc(3 * n_groups);
     RT_HIP(hipMemcpy(c->d_centre.p, cen.data(), c->d_centre.bytes(), hipMemcpyHostToDevice));
     c->obs_g.release();
@@ -2157,7 +2178,7 @@ int rtdm_observables(rtdm_ctx *c, double out[6], void *stream)
     RT_CHECK(out, RTDM_E_ARG, "null output");
     hipStream_t s = (hipStream_t)stream;
     ensure_charges(c, s);
-    launch_observables(s, c->n, c->d_xyz.p, c->q_cur, c->herm_valid ? c->herm_sums.p : nullptr, c->t_now,
+    launch_observables(s, c->n, c->d_xyz.p, c->d_centre_all.p, c->q_cur, c->herm_valid ? c->herm_sums.p : nullptr, c->t_now,
                        c->obs_tmp.p);
     double row[8];
     read_scalars(row, c->obs_tmp.p, 8, s);
@@ -2543,8 +2564,8 @@ int rtdm_mlp_train(rtdm_ctx *c, int epochs, int batch, double lr, uint64_t seed,
         int64_t cnt = 0;
         for (int64_t b0 = 0; b0 + bs <= M.ns; b0 += bs) {
             const double l = mlp_loss_grad(c, bs, M.idx.p + b0, M.ds_x.p, M.ds_t.p, nullptr);
-            launch_adam(nullptr, M.np, M.nw1, M.nb1, M.nw2, M.grad.p, M.w.p, M.m.p, M.v.p, (float)lr, 0.9f,
-                        0.999f, 1e-8f, ++M.step, M.w1h.p, M.w2h.p);
+            launch_adam(nullptr, M.np, M.nw1, M.nb1, M.nw2, M.grad.p, M.w.p, M.m.p, M.v.p, (float)lr, 0.9,
+                        0.999, 1e-8f, ++M.step, M.w1h.p, M.w2h.p);
             sum += l * bs;
             cnt += bs;
         }
@@ -2572,6 +2593,27 @@ int rtdm_mlp_loss_grad(rtdm_ctx *c, int64_t n, const float *desc, const float *t
     const double l = mlp_loss_grad(c, n, nullptr, M.tx.p, M.tt.p, nullptr);
     if (loss) *loss = l;
     if (grad) RT_HIP(hipMemcpy(grad, M.grad.p, M.grad.bytes(), hipMemcpyDeviceToHost));
+    API_END(c)
+}
+
+int rtdm_mlp_step(rtdm_ctx *c, int64_t n, const float *desc, const float *target, double lr, double *loss)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    mlp_configure(c);
+    MlpState &M = c->mlp;
+    require(M.ready, "initialise the network first");
+    RT_CHECK(n >= 1 && desc && target && lr > 0 && std::isfinite(lr), RTDM_E_ARG, "bad samples or learning rate");
+    M.tx.alloc((size_t)n * M.in);
+    M.tt.alloc((size_t)n * M.out);
+    RT_HIP(hipMemcpy(M.tx.p, desc, M.tx.bytes(), hipMemcpyHostToDevice));
+    RT_HIP(hipMemcpy(M.tt.p, target, M.tt.bytes(), hipMemcpyHostToDevice));
+    const double l = mlp_loss_grad(c, n, nullptr, M.tx.p, M.tt.p, nullptr);
+    launch_adam(nullptr, M.np, M.nw1, M.nb1, M.nw2, M.grad.p, M.w.p, M.m.p, M.v.p, (float)lr, 0.9, 0.999, 1e-8f,
+                ++M.step, M.w1h.p, M.w2h.p);
+    RT_HIP(hipDeviceSynchronize());
+    if (loss) *loss = l;
     API_END(c)
 }
 

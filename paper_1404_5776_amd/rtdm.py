@@ -35,7 +35,7 @@ EXPORTED = ["rtdm_default_options", "rtdm_create", "rtdm_destroy", "rtdm_set_geo
             "rtdm_dipole_trace", "rtdm_unitarity", "rtdm_inverse_error", "rtdm_multiply", "rtdm_schedule_stats",
             "rtdm_timing", "rtdm_timing_stats", "rtdm_inverse_info", "rtdm_mlp_params", "rtdm_mlp_init",
             "rtdm_mlp_set_weights", "rtdm_mlp_get_weights", "rtdm_mlp_collect", "rtdm_mlp_clear",
-            "rtdm_mlp_train", "rtdm_mlp_loss_grad", "rtdm_mlp_predict", "rtdm_set_groups",
+            "rtdm_mlp_train", "rtdm_mlp_loss_grad", "rtdm_mlp_step", "rtdm_mlp_predict", "rtdm_set_groups",
             "rtdm_apply_kick_groups", "rtdm_group_trace", "rtdm_autotune", "rtdm_set_field",
             "rtdm_spectrum", "rtdm_workspace_size", "rtdm_bind_workspace", "rtdm_ground_state",
             "rtdm_get_state", "rtdm_set_state", "rtdm_last_error"]
@@ -98,6 +98,7 @@ def load():
         "rtdm_mlp_clear": [P],
         "rtdm_mlp_train": [P, I, I, D, ctypes.c_uint64, P],
         "rtdm_mlp_loss_grad": [P, I64, P, P, P, P],
+        "rtdm_mlp_step": [P, I64, P, P, D, P],
         "rtdm_mlp_predict": [P, I64, P, P],
         "rtdm_set_groups": [P, I64, P],
         "rtdm_apply_kick_groups": [P, P, P],
@@ -347,6 +348,14 @@ def rtdm_mlp_loss_grad(ctx, desc, target) -> Tuple[float, np.ndarray]:
     l = ctypes.c_double()
     _check(ctx, load().rtdm_mlp_loss_grad(ctx, d.shape[0], _p(d), _p(t), ctypes.byref(l), _p(g)))
     return l.value, g
+
+
+def rtdm_mlp_step(ctx, desc, target, lr: float) -> float:
+    d = np.ascontiguousarray(desc, dtype=np.float32)
+    t = np.ascontiguousarray(target, dtype=np.float32)
+    l = ctypes.c_double()
+    _check(ctx, load().rtdm_mlp_step(ctx, d.shape[0], _p(d), _p(t), lr, ctypes.byref(l)))
+    return l.value
 
 
 def rtdm_mlp_predict(ctx, desc) -> np.ndarray:

@@ -26,12 +26,34 @@ def assert_same_pattern(ctx, slot, pat: O.Pattern):
     np.testing.assert_array_equal(col, pat.col)
 
 
-def dipole_floor(q: np.ndarray, xyz: np.ndarray) -> float:
-    """Rounding floor of P = -sum_i (r_i - r_c) q_i: the sum nearly cancels, so
-    two FP64 implementations summing in different orders agree only to about
-    log2(n) * eps * sum_i |r_i - r_c| |q_i| (forward error of a tree-order sum).
-    The centroid r_c is itself a sum with error up to log2(n) * eps * |r_c|,
-    and that error is multiplied by the total charge sum_i q_i."""
-    rc = xyz.mean(axis=0)
-    S = np.abs((xyz - rc) * q[:, None]).sum(axis=0) + np.abs(rc) * abs(q.sum())
-    return 2.0 * np.log2(max(len(q), 2)) * np.finfo(float).eps * S.max()
+def dipole_floor(q: np.ndarray, xyz: np.ndarray, dq: float = 0.0) -> float:
+    """Rounding floor of P = -sum_i (r_i - r_c) q_i between two FP64 codes.
+
+    The sum nearly cancels, so two implementations summing in different
+    orders agree only to about log2(n) * eps * sum_i |r_i - r_c| |q_i| (forward
+    error of a tree-order sum).  The centroid r_c is the same number in both
+    (each coordinate sum rounded once), so it adds no term.  The charges
+    themselves differ by rounding (dq = max_i |q_i - q_ref_i|, measured by
+    assert_charges on the last step and doubled for the steps before it),
+    which moves P by at most dq * sum_i |r_i - r_c|."""
+    rc = O.centroid(xyz)
+    d = np.abs(xyz - rc)
+    S = np.abs(d * q[:, None]).sum(axis=0)
+    return 2.0 * np.log2(max(len(q), 2)) * np.finfo(float).eps * S.max() + 2.0 * dq * d.sum(axis=0).max()
+
+
+def gpu_charges(ctx, n_atoms: int) -> np.ndarray:
+    """The context's current Mulliken charges q_i (rtdm_get_state)."""
+    return rtdm.rtdm_get_state(ctx.h, n_atoms)[2:2 + n_atoms]
+
+
+def assert_charges(q: np.ndarray, K_ref: "O.BSM", S: "O.BSM") -> float:
+    """Per-atom charges against the oracle's q_i = Re sum_j tr(K_ij S_ji) of its
+    K: max |q - q_ref| <= TOL * max |q_ref| (the charges do not cancel, so
+    this bar has no rounding floor).  Returns max |q - q_ref|."""
+    want = O.mulliken(K_ref, S)
+    dq = float(np.abs(q - want).max())
+    err = dq / float(np.abs(want).max())
+    print(f"charges: max rel error {err:.2e}")
+    assert err <= TOL, err
+    return dq

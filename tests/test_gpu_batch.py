@@ -14,36 +14,39 @@ import pytest
 
 from oracle import oracle as O
 from paper_1404_5776_amd import rtdm, synth
-from tests._common import TOL, dipole_floor, gpu_context, rel
+from tests._common import TOL, assert_charges, dipole_floor, gpu_charges, gpu_context, rel
 
 pytestmark = pytest.mark.gpu
 
 
-def _clusters():
+def _clusters(b):
+    """Three b = 4 clusters (ranges 8 / 12 bohr) or two b = 13 clusters (6 / 8 bohr)."""
     out = []
-    for k, n in enumerate((30, 55, 41)):
+    sizes, ranges = ((30, 55, 41), (8.0, 12.0)) if b == 4 else ((24, 37), (6.0, 8.0))
+    for k, n in enumerate(sizes):
         xyz = synth.cluster_positions(n, np.random.default_rng(91 + k))
-        out.append(synth.build_system(f"c{n}", xyz, 4, 8.0, 12.0, 95 + k, k0="exact"))
+        out.append(synth.build_system(f"c{n}_b{b}", xyz, b, ranges[0], ranges[1], 95 + k, k0="exact"))
     return out
 
 
-@pytest.mark.parametrize("h_model", ["fixed", "mulliken"])
-def test_batch_of_clusters_with_xyz_kicks_matches_oracle(h_model):
-    systems = _clusters()
+@pytest.mark.parametrize("h_model,b", [("fixed", 4), ("mulliken", 4), ("fixed", 13), ("mulliken", 13)])
+def test_batch_of_clusters_with_xyz_kicks_matches_oracle(h_model, b):
+    systems = _clusters(b)
     kicks = [[(0.01, 0, 0), (0, 0.01, 0), (0, 0, 0.01)]] * len(systems)
-    print(f"[gpu] batch of {len(systems)} clusters x 3 kicks, h_model={h_model}", flush=True)
+    print(f"[gpu] batch of {len(systems)} b={b} clusters x 3 kicks, h_model={h_model}", flush=True)
     ctx = rtdm.Context(0, h_model=h_model)
     gptr = ctx.load_batch(systems, kicks)
     G = len(gptr) - 1
-    assert G == 9
+    assert G == 3 * len(systems)
     rtdm.rtdm_build_inverse(ctx.h)
     rtdm.rtdm_apply_kick_groups(ctx.h, ctx.group_kicks)
     n_steps = 12
     rtdm.rtdm_step(ctx.h, 0.05, n_steps)
     gtr = rtdm.rtdm_group_trace(ctx.h, G)
-    K = rtdm.rtdm_download(ctx.h, "K", 4)
+    K = rtdm.rtdm_download(ctx.h, "K", b)
     rp, col = rtdm.rtdm_pattern(ctx.h, "K")
     xyz = ctx.batch_xyz
+    q_all = gpu_charges(ctx, xyz.shape[0])
     ctx.close()
     rows = np.repeat(np.arange(rp.size - 1), np.diff(rp))
     g = 0
@@ -57,11 +60,12 @@ def test_batch_of_clusters_with_xyz_kicks_matches_oracle(h_model):
             sel = (rows >= a0) & (rows < gptr[g + 1])
             # this group's K blocks, in the oracle's pattern order (same relative order)
             assert rel(K[sel], ref.K.val) <= TOL
+            dq = assert_charges(q_all[a0:gptr[g + 1]], ref.K, st.S)
             q0 = O.mulliken(O.kick(st.K0, st.xyz, kap), st.S)
             P0 = O.dipole(q0, st.xyz)
             induced = np.abs(ref.rows[:, 1:4] - P0).max()
             err = np.abs(gtr[:, g, :3] - ref.rows[:, 1:4]).max()
-            assert err <= TOL * induced + dipole_floor(q0, st.xyz)
+            assert err <= TOL * induced + dipole_floor(q0, st.xyz, dq)
             assert np.abs(gtr[:, g, 3] - ref.rows[:, 4]).max() <= TOL * abs(ref.rows[0, 4])
             g += 1
 
@@ -110,3 +114,27 @@ def test_autotune_keeps_results_bit_identical():
     ctx.close()
     assert np.array_equal(K, K_ref)
     assert np.array_equal(tr[:, :6], tr_ref[:, :6])
+
+
+def test_graph_recaptured_after_a_new_inverse():
+    """step (graph) -> build_inverse -> step (graph) in one context repeats the
+    eager sequence bit for bit: the inverse moves X between buffers and
+    refreshes its column-major copy, so the captured step must be captured
+    again rather than replayed."""
+    s = synth.diamond_lattice((2, 2, 2), 13, 10.0, 16.0, seed=24, k0="local", h_model="mulliken")
+
+    def run(use_graph):
+        ctx = gpu_context(s, h_model="mulliken", use_graph=use_graph)
+        rtdm.rtdm_build_inverse(ctx.h)
+        rtdm.rtdm_apply_kick(ctx.h, s.kappa)
+        rtdm.rtdm_step(ctx.h, s.dt, 3)
+        rtdm.rtdm_build_inverse(ctx.h)
+        rtdm.rtdm_step(ctx.h, s.dt, 3)
+        out = (rtdm.rtdm_download(ctx.h, "K", s.b), rtdm.rtdm_dipole_trace(ctx.h))
+        ctx.close()
+        return out
+
+    K_e, tr_e = run(0)
+    K_g, tr_g = run(1)
+    assert np.array_equal(K_e, K_g)
+    assert np.array_equal(tr_e[:, :6], tr_g[:, :6])

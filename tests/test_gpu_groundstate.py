@@ -9,7 +9,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_1404_5776_amd import rtdm, synth
-from tests._common import TOL, dipole_floor, gpu_context, rel
+from tests._common import TOL, assert_charges, dipole_floor, gpu_charges, gpu_context, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -55,6 +55,7 @@ def test_propagation_from_the_gpu_ground_state():
     rtdm.rtdm_step(ctx.h, s.dt, 10)
     tr = rtdm.rtdm_dipole_trace(ctx.h)
     K = rtdm.rtdm_download(ctx.h, "K", s.b)
+    q = gpu_charges(ctx, s.n_atoms)
     ctx.close()
     st = O.setup(s)
     X = O.hotelling(st.S, st.pat_p)
@@ -67,7 +68,8 @@ def test_propagation_from_the_gpu_ground_state():
     err = np.abs(tr[:, 1:4] - ref.rows[:, 1:4]).max()
     print(f"dipole err {err:.2e} of induced {induced:.2e}; K rel {rel(K, ref.K.val):.2e}")
     assert rel(K, ref.K.val) <= TOL
-    assert err <= TOL * induced + dipole_floor(q0, st.xyz)
+    dq = assert_charges(q, ref.K, st.S)
+    assert err <= TOL * induced + dipole_floor(q0, st.xyz, dq)
 
 
 def test_ground_state_arguments_are_checked():

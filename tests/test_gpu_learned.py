@@ -49,6 +49,39 @@ def test_forward_and_gradient_match_oracle():
     ctx.close()
 
 
+def test_adam_steps_match_oracle():
+    """Two training steps (rtdm_mlp_step) against the oracle's Adam applied to
+    the GPU's own gradients at the same weights, so only the update kernel is
+    compared: FP32 moments and weights on the GPU, FP64 in the oracle, so they
+    agree to a few FP32 roundings of |w| + lr.  The FP16 copies used by the
+    forward pass follow the updated weights (the second gradient is taken at
+    w1 and equals loss_grad there)."""
+    s = _lattice(65)
+    ctx = gpu_context(s)
+    n, n_in, _, n_out = rtdm.rtdm_mlp_params(ctx.h)
+    w0 = _seeded_weights(n_in, n_out, 66)
+    rtdm.rtdm_mlp_set_weights(ctx.h, w0)
+    rng = np.random.default_rng(67)
+    batches = [(rng.normal(size=(200, n_in)).astype(np.float32), rng.normal(size=(200, n_out)).astype(np.float32))
+               for _ in range(2)]
+    lr = 3e-3
+    w_ref, m, v = w0.astype(np.float64), np.zeros(n), np.zeros(n)
+    for t, (x, y) in enumerate(batches, start=1):
+        w_before = rtdm.rtdm_mlp_get_weights(ctx.h)
+        _, g = rtdm.rtdm_mlp_loss_grad(ctx.h, x, y)
+        loss = rtdm.rtdm_mlp_step(ctx.h, x, y, lr)
+        w_gpu = rtdm.rtdm_mlp_get_weights(ctx.h)
+        w_ref, m, v = OM.adam(w_ref, g.astype(np.float64), m, v, t, lr)
+        lo, _ = OM.loss_grad(w_before.astype(np.float64), x, y, n_in, n_out)
+        assert abs(loss - lo) <= 1e-5 * lo
+        bound = 8 * np.finfo(np.float32).eps * (np.abs(w_ref) + lr)
+        err = np.abs(w_gpu - w_ref)
+        print(f"step {t}: max |w_gpu - w_ref| / bound {float((err / bound).max()):.2e}")
+        assert np.all(err <= bound), t
+        assert np.abs(w_gpu - w_before).max() > 0.5 * lr       # the step moved the weights
+    ctx.close()
+
+
 @pytest.mark.parametrize("zero_net", [True, False])
 def test_learned_start_matches_oracle(zero_net):
     """The start 2 delta I - S + y(d) and the iteration from it, against the oracle."""

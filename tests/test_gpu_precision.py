@@ -3,16 +3,21 @@
 FP32 matrix-core products keep FP64 storage, reductions and observables.
 Stated tolerances: one product within 1e-6 relative (Frobenius) of the oracle
 (FP32 rounding of the operands and of each accumulation step, ~2^-24 times a
-modest growth factor).  Over 100 steps of the 64-atom cluster the measured
-errors are stated by the test output and bounded as follows: all products in
-FP32, dipole error <= 0.1 of the peak induced dipole, Tr(KS) <= 1e-5 relative;
-Taylor terms only, dipole <= 1e-2, Tr(KS) <= 1e-7.
+modest growth factor).  Propagation errors (dipole error relative to the
+peak induced dipole, Tr(KS) relative) are printed by each test and bounded at
+about 3x the measured values, so that a form that gets worse fails:
+all products in FP32 lose 3.4e-2 of the kick's signal in 100 steps of the
+64-atom cluster; FP32 Taylor terms from order 2 / 3 keep 1.1e-5 / 7.4e-9.
 
 Split 16-bit forms (FP64 storage, FP32 accumulation): one product within
 3e-5 relative for BF16 x3 (two 8-bit parts: the dropped lo*lo term and the
 rounding of lo are each ~2^-16 of |a||b|) and within 5e-7 for FP16 x2 (two
 11-bit parts, ~2^-22 each, plus FP32 accumulation).  Propagation errors are
-stated by the test output and bounded per form below.
+bounded per form below at about 3x the measured values.  Every product in a
+split form does not meet the 1e-6 dipole target: BF16 x3 loses the whole
+induced signal (error 1.3 of its peak) and FP16 x2 4e-2 of it; only the forms
+that confine the split to late Taylor terms keep the dipole error below 1e-6
+(4e-8 and 3e-9 from order 3).
 """
 
 import numpy as np
@@ -49,8 +54,8 @@ def test_fp32_products_within_stated_tolerance(b):
     ctx.close()
 
 
-@pytest.mark.parametrize("prec,n0,bound_dip,bound_tr", [("fp32", 3, 0.1, 1e-5), ("fp32_taylor", 2, 1e-4, 1e-8),
-                                                        ("fp32_taylor", 3, 1e-5, 1e-9)])
+@pytest.mark.parametrize("prec,n0,bound_dip,bound_tr", [("fp32", 3, 0.1, 2e-5), ("fp32_taylor", 2, 3e-5, 4e-9),
+                                                        ("fp32_taylor", 3, 2e-8, 2.5e-13)])
 def test_fp32_propagation_error_stated(prec, n0, bound_dip, bound_tr):
     s = synth.config1()
     st = O.setup(s)
@@ -70,7 +75,7 @@ def test_fp32_propagation_error_stated(prec, n0, bound_dip, bound_tr):
     assert e_dip <= bound_dip and e_tr <= bound_tr
 
 
-@pytest.mark.parametrize("n0,bound_dip", [(2, 1e-4), (3, 1e-5)])
+@pytest.mark.parametrize("n0,bound_dip", [(2, 1e-5), (3, 8e-9)])
 def test_fp32_taylor_b13_lattice_error_stated(n0, bound_dip):
     """The b = 13 FP32 step kernel (FP32 storage of the Taylor terms) on a 64-atom lattice."""
     s = synth.diamond_lattice((2, 2, 2), 13, 10.0, 16.0, seed=21, k0="local", h_model="mulliken")
@@ -116,9 +121,9 @@ def test_split_products_within_stated_tolerance(b, prec, bound):
 
 
 @pytest.mark.parametrize("prec,n0,bound_dip,bound_tr", [
-    ("bf16x3", 2, 2.0, 1e-4), ("fp16x2", 2, 0.1, 1e-5),
-    ("bf16x3_taylor", 2, 1e-3, 1e-7), ("bf16x3_taylor", 3, 1e-7, 1e-10),
-    ("fp16x2_taylor", 2, 2e-5, 2e-8), ("fp16x2_taylor", 3, 5e-9, 1e-12)])
+    ("bf16x3", 2, 2.0, 6e-5), ("fp16x2", 2, 0.1, 2e-6),
+    ("bf16x3_taylor", 2, 1.2e-3, 9e-8), ("bf16x3_taylor", 3, 1.2e-7, 1.5e-11),
+    ("fp16x2_taylor", 2, 3e-5, 5e-9), ("fp16x2_taylor", 3, 9e-9, 3e-13)])
 def test_split_propagation_error_stated(prec, n0, bound_dip, bound_tr):
     s = synth.config1()
     st = O.setup(s)
@@ -138,7 +143,7 @@ def test_split_propagation_error_stated(prec, n0, bound_dip, bound_tr):
     assert e_dip <= bound_dip and e_tr <= bound_tr
 
 
-@pytest.mark.parametrize("prec,bound", [("bf16x3_taylor", 3e-8), ("fp16x2_taylor", 5e-9)])
+@pytest.mark.parametrize("prec,bound", [("bf16x3_taylor", 2e-8), ("fp16x2_taylor", 5e-9)])
 def test_split_taylor_b13_lattice_error_stated(prec, bound):
     s = synth.diamond_lattice((2, 2, 2), 13, 10.0, 16.0, seed=21, k0="local", h_model="mulliken")
     st = O.setup(s)
@@ -174,4 +179,4 @@ def test_fp32_step_kernels_b13_lattice_error_stated():
     e_dip = np.abs(tr[:, 1:4] - ref.rows[:, 1:4]).max() / induced
     e_tr = np.abs(tr[:, 4] - ref.rows[:, 4]).max() / abs(ref.rows[0, 4])
     print(f"fp32 (all products) b=13 lattice, 10 steps: dipole error {e_dip:.2e} of peak induced, Tr(KS) {e_tr:.2e}")
-    assert e_dip <= 0.1 and e_tr <= 1e-5
+    assert e_dip <= 2e-2 and e_tr <= 1e-6

@@ -15,7 +15,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_1404_5776_amd import rtdm, synth
-from tests._common import TOL, dipole_floor, gpu_context, rel
+from tests._common import TOL, assert_charges, dipole_floor, gpu_charges, gpu_context, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -42,7 +42,7 @@ def _run_gpu(s, n_steps, kappa, field=None, chunks=None, **opts):
     for n in (chunks or (n_steps,)):
         rtdm.rtdm_step(ctx.h, s.dt, n)
     out = dict(trace=rtdm.rtdm_dipole_trace(ctx.h), K=rtdm.rtdm_download(ctx.h, "K", s.b),
-               U=rtdm.rtdm_download(ctx.h, "U", s.b), p0=p0, ctx=ctx)
+               U=rtdm.rtdm_download(ctx.h, "U", s.b), q=gpu_charges(ctx, s.n_atoms), p0=p0, ctx=ctx)
     return out
 
 
@@ -55,7 +55,8 @@ def _compare(s, g, ref, st, kappa):
           f"dipole err {err:.2e} of induced {induced:.2e}")
     assert rel(g["K"], ref.K.val) <= TOL
     assert rel(g["U"], ref.U.val) <= TOL
-    assert err <= TOL * induced + dipole_floor(q0, st.xyz)
+    dq = assert_charges(g["q"], ref.K, st.S)
+    assert err <= TOL * induced + dipole_floor(q0, st.xyz, dq)
     assert np.abs(g["trace"][:, 4] - ref.rows[:, 4]).max() <= TOL * np.abs(ref.rows[:, 4]).max()
 
 

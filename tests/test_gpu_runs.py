@@ -19,7 +19,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_1404_5776_amd import rtdm, synth
-from tests._common import TOL, dipole_floor, gpu_context, rel
+from tests._common import TOL, assert_charges, dipole_floor, gpu_charges, gpu_context, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -65,7 +65,7 @@ def _run(s, run_real, run_cplx, run_b4=16, **opts):
         rtdm.rtdm_build_inverse(ctx.h)
         rtdm.rtdm_apply_kick(ctx.h, s.kappa)
         rtdm.rtdm_step(ctx.h, s.dt, N_STEPS)
-        return rtdm.rtdm_download(ctx.h, "K", s.b), rtdm.rtdm_dipole_trace(ctx.h)
+        return rtdm.rtdm_download(ctx.h, "K", s.b), rtdm.rtdm_dipole_trace(ctx.h), gpu_charges(ctx, s.n_atoms)
     finally:
         ctx.close()
 
@@ -73,21 +73,22 @@ def _run(s, run_real, run_cplx, run_b4=16, **opts):
 @pytest.mark.parametrize("run_real,run_cplx", RUNS)
 def test_row_runs_match_oracle(reference, run_real, run_cplx):
     s, st, ref = reference
-    K, tr = _run(s, run_real, run_cplx, use_graph=0)
+    K, tr, q = _run(s, run_real, run_cplx, use_graph=0)
     q0 = O.mulliken(O.kick(st.K0, st.xyz, s.kappa), st.S)
     P0 = O.dipole(q0, st.xyz)
     induced = np.abs(ref.rows[:, 1:4] - P0).max()
     err = np.abs(tr[:, 1:4] - ref.rows[:, 1:4]).max()
     print(f"runs {run_real}/{run_cplx}: K rel {rel(K, ref.K.val):.2e}, dipole err {err:.2e} of {induced:.2e}")
     assert rel(K, ref.K.val) <= TOL
-    assert err <= TOL * induced + dipole_floor(q0, st.xyz)
+    dq = assert_charges(q, ref.K, st.S)
+    assert err <= TOL * induced + dipole_floor(q0, st.xyz, dq)
 
 
 def test_row_runs_agree_with_single_outputs(reference):
     s, _, _ = reference
-    K1, tr1 = _run(s, 1, 1)
+    K1, tr1, _ = _run(s, 1, 1)
     for rr, rc in RUNS[1:]:
-        K, tr = _run(s, rr, rc)
+        K, tr, _ = _run(s, rr, rc)
         # same triples, contraction sums in another order: a few ulps per step
         assert rel(K, K1) <= 1e-13, (rr, rc)
         np.testing.assert_allclose(tr[:, 4], tr1[:, 4], rtol=1e-13)
@@ -96,9 +97,9 @@ def test_row_runs_agree_with_single_outputs(reference):
 def test_row_runs_fp32_products():
     """FP32 step products run the same row-run dataflow on the FP32 matrix cores."""
     s = _lattice()
-    K1, _ = _run(s, 1, 1, precision="fp32")
-    K4, _ = _run(s, 4, 4, precision="fp32")
-    K8, _ = _run(s, 8, 2, precision="fp32")
+    K1, _, _ = _run(s, 1, 1, precision="fp32")
+    K4, _, _ = _run(s, 4, 4, precision="fp32")
+    K8, _, _ = _run(s, 8, 2, precision="fp32")
     # FP32 products with FP32 accumulation in another order: agreement at FP32 rounding
     assert rel(K4, K1) <= 1e-5
     assert rel(K8, K1) <= 1e-5
@@ -118,8 +119,8 @@ def test_row_runs_under_graph_capture(reference):
     """A captured step replays the row-run kernels bit for bit (the schedules
     and their runs are built when the ranges are set, never inside a capture)."""
     s, _, _ = reference
-    Ke, tre = _run(s, 2, 1, use_graph=0)
-    Kg, trg = _run(s, 2, 1, use_graph=1)
+    Ke, tre, _ = _run(s, 2, 1, use_graph=0)
+    Kg, trg, _ = _run(s, 2, 1, use_graph=1)
     assert np.array_equal(Ke, Kg)
     assert np.array_equal(tre[:, :6], trg[:, :6])
 
@@ -128,9 +129,9 @@ def test_row_runs_fp32_taylor_terms():
     """FP32-storage Taylor terms (fp32_taylor) through the FP32 row-run kernel
     agree with the single-output FP32 kernel at FP32 rounding of those terms."""
     s = _lattice()
-    K1, tr1 = _run(s, 1, 1, precision="fp32_taylor")
-    K2, tr2 = _run(s, 2, 1, precision="fp32_taylor")
-    K8, _ = _run(s, 8, 1, precision="fp32_taylor")
+    K1, tr1, _ = _run(s, 1, 1, precision="fp32_taylor")
+    K2, tr2, _ = _run(s, 2, 1, precision="fp32_taylor")
+    K8, _, _ = _run(s, 8, 1, precision="fp32_taylor")
     assert rel(K2, K1) <= 1e-9
     assert rel(K8, K1) <= 1e-9
     induced = np.abs(tr1[:, 1:4] - tr1[0, 1:4]).max()
@@ -147,8 +148,8 @@ def test_b4_row_runs_match_oracle_and_single_outputs():
     s = _b4_lattice()
     st = O.setup(s)
     ref = O.propagate(st, N_STEPS, s.dt, s.kappa, h_model=s.h_model)
-    K16, tr16 = _run(s, 2, 2, run_b4=16)
-    K1, tr1 = _run(s, 2, 2, run_b4=1)
+    K16, tr16, _ = _run(s, 2, 2, run_b4=16)
+    K1, tr1, _ = _run(s, 2, 2, run_b4=1)
     q0 = O.mulliken(O.kick(st.K0, st.xyz, s.kappa), st.S)
     P0 = O.dipole(q0, st.xyz)
     induced = np.abs(ref.rows[:, 1:4] - P0).max()
@@ -160,8 +161,8 @@ def test_b4_row_runs_match_oracle_and_single_outputs():
 
 def test_b4_row_runs_under_graph_capture():
     s = _b4_lattice()
-    Ke, tre = _run(s, 2, 2, run_b4=16, use_graph=0)
-    Kg, trg = _run(s, 2, 2, run_b4=16, use_graph=1)
+    Ke, tre, _ = _run(s, 2, 2, run_b4=16, use_graph=0)
+    Kg, trg, _ = _run(s, 2, 2, run_b4=16, use_graph=1)
     assert np.array_equal(Ke, Kg)
     assert np.array_equal(tre[:, :6], trg[:, :6])
 
@@ -172,8 +173,8 @@ def test_b4_row_runs_reduced_precision(precision):
     per-output form at the rounding of the reduced terms (late Taylor terms
     only: 1e-8 of K; every product reduced: 1e-5)."""
     s = _b4_lattice()
-    K16, _ = _run(s, 2, 2, run_b4=16, precision=precision)
-    K1, _ = _run(s, 2, 2, run_b4=1, precision=precision)
+    K16, _, _ = _run(s, 2, 2, run_b4=16, precision=precision)
+    K1, _, _ = _run(s, 2, 2, run_b4=1, precision=precision)
     bound = 1e-5 if precision == "fp32" else 1e-8
     print(f"{precision}: runs vs per-output K rel {rel(K16, K1):.2e}")
     assert rel(K16, K1) <= bound

@@ -59,3 +59,23 @@ def test_too_small_or_foreign_workspace_is_refused():
     rtdm.rtdm_build_inverse(ctx.h)
     rtdm.rtdm_step(ctx.h, s.dt, 2)
     ctx.close()
+
+
+def test_workspace_without_reserve_suffices_for_inverse_and_steps():
+    """A workspace of exactly the context's buffers (no reserve for
+    temporaries): the inverse (whose b = 13 iteration keeps its column-major
+    copy of S in a context buffer) and the steps allocate nothing more."""
+    import torch
+    s = synth.diamond_lattice((2, 2, 2), 13, 10.0, 16.0, seed=25, k0="local", h_model="mulliken")
+    ref, _ = _run(s, False)
+    ctx = gpu_context(s, h_model="mulliken")
+    live = rtdm.rtdm_workspace_size(ctx.h) - (64 << 20)
+    ws = torch.empty(live, dtype=torch.uint8, device="cuda:0")
+    rtdm.rtdm_bind_workspace(ctx.h, ws.data_ptr(), live)
+    rtdm.rtdm_build_inverse(ctx.h)
+    rtdm.rtdm_apply_kick(ctx.h, s.kappa)
+    rtdm.rtdm_step(ctx.h, s.dt, 3)
+    rtdm.rtdm_step(ctx.h, s.dt, 4)
+    K = rtdm.rtdm_download(ctx.h, "K", s.b)
+    ctx.close()
+    assert np.array_equal(K, ref[0])

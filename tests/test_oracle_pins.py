@@ -417,6 +417,35 @@ def test_mlp_oracle_gradient_matches_finite_differences():
     assert abs(loss - ((mlp.forward(w, x, n_in, n_out, False)[0] - t) ** 2).mean()) < 1e-15
 
 
+def test_mlp_oracle_adam_two_steps_by_hand():
+    """Two Adam steps of one parameter worked out by hand in exact fractions
+    (lr 1/10, beta1 9/10, beta2 999/1000, eps 1e-8; w0 = 1, g1 = 1/2, g2 = -1/4):
+      m1 = g1/10 = 1/20,  v1 = g1^2/1000 = 1/4000,
+      m_hat1 = m1 / (1/10) = 1/2,  v_hat1 = v1 / (1/1000) = 1/4,
+      w1 = 1 - (1/10)(1/2) / (1/2 + eps);
+      m2 = (9/10)(1/20) - (1/10)(1/4) = 1/50,
+      v2 = (999/1000)(1/4000) + (1/1000)(1/16) = 1249/4000000,
+      1 - beta1^2 = 19/100, 1 - beta2^2 = 1999/1000000,
+      m_hat2 = (1/50)/(19/100) = 2/19,  v_hat2 = (1249/4000000)/(1999/1000000) = 1249/7996,
+      w2 = w1 - (1/10)(2/19) / (sqrt(1249/7996) + eps).
+    A dropped bias correction, eps under the root, the moment weights swapped
+    or the step counter starting at 0 each change w1 or w2 by far more than
+    rounding; the moments must come back exactly as derived."""
+    from oracle import mlp
+    w1, m, v = mlp.adam(np.array([1.0]), np.array([0.5]), np.zeros(1), np.zeros(1), 1, 0.1)
+    np.testing.assert_allclose(m, [1 / 20], rtol=1e-15)
+    np.testing.assert_allclose(v, [1 / 4000], rtol=1e-15)
+    np.testing.assert_allclose(w1, [1.0 - 0.1 * 0.5 / (0.5 + 1e-8)], rtol=1e-15)
+    w2, m, v = mlp.adam(w1, np.array([-0.25]), m, v, 2, 0.1)
+    np.testing.assert_allclose(m, [1 / 50], rtol=1e-14)
+    np.testing.assert_allclose(v, [1249 / 4000000], rtol=1e-14)
+    np.testing.assert_allclose(w2, w1 - 0.1 * (2 / 19) / (np.sqrt(1249 / 7996) + 1e-8), rtol=1e-15)
+    # the first step of Adam moves every parameter by lr in the direction of -g (|g| >> eps)
+    g = np.array([3.0, -0.02, 7e-4])
+    w, _, _ = mlp.adam(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, 0.01)
+    np.testing.assert_allclose(w, -0.01 * np.sign(g), rtol=1e-4)
+
+
 def test_mlp_descriptors_swap_symmetry_and_first_order_start():
     """Descriptor of block (j, i) = (-vector, same length, S_ij^T) of block (i, j);
     the first-order start 2I - S is the one-term Neumann inverse of S = I + E,
