@@ -414,6 +414,22 @@ int rtdm_inverse_error(rtdm_ctx *ctx, double out[3], void *hip_stream);
 int rtdm_multiply(rtdm_ctx *ctx, rtdm_mat C, rtdm_mat A, rtdm_mat B, int op_a, int op_b,
                   double alpha_re, double alpha_im, void *hip_stream);
 
+/* For callers that cannot allocate device memory during the call (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * rtdm_multiply with the same arguments and results, whose b = 13
+ * column-major operand copies live in a static device array of
+ * 128 MiB per GPU (held from the library's first use on that GPU until the
+ * process ends) instead of fresh allocations.  It calls no hipMalloc or
+ * hipFree and does not synchronise (it is asynchronous on hip_stream).
+ * Errors: RTDM_E_ARG when the copies (the planes of A, of B if op_b = 1, of
+ * C for the U K kind) exceed 128 MiB; RTDM_E_STATE when the product kind has
+ * no schedule yet (the five step kinds are scheduled by rtdm_set_ranges;
+ * another kind needs one rtdm_multiply first).  Every call on a GPU, from any
+ * context, shares that GPU's array and overwrites it: calls that overlap on
+ * one GPU (two streams, two host threads) race. */
+int rtdm_multiply_noalloc(rtdm_ctx *ctx, rtdm_mat C, rtdm_mat A, rtdm_mat B, int op_a, int op_b,
+                          double alpha_re, double alpha_im, void *hip_stream);
+
 /* Symbolic sizes of a product: number of output blocks and of (i,k,j) block
  * triples that survive all three cut-offs (the algorithmic unit of work,
  * 2 b^3 flops per real block product). */

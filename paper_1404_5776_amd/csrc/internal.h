@@ -247,6 +247,13 @@ void launch_unit_to_row(hipStream_t s, const double *unit_sums, const double *s_
 void launch_split(hipStream_t s, int64_t n, const double *inter, double *re, double *im);
 void launch_interleave(hipStream_t s, int64_t n, const double *re, const double *im, double *inter);
 
+// ---------------------------------------------------------------- static scratch
+// Size of the file-scope device array behind rtdm_multiply_noalloc (per GPU).
+constexpr size_t kStaticScratchBytes = size_t(128) << 20;
+// Device address of that array on `device`, which must be current; looked up
+// (hipGetSymbolAddress) on the first call per device.
+double *static_scratch(int device);
+
 // ---------------------------------------------------------------- learned start
 constexpr int kMlpHidden = 128;
 void launch_mlp_desc(hipStream_t s, int64_t n, int b, const int32_t *blk, const int32_t *rowof,

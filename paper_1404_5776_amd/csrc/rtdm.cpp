@@ -1114,6 +1114,7 @@ int rtdm_create(rtdm_ctx **out, int hip_device, const rtdm_options *opt)
     RT_CHECK(c->opt.sc_steps >= 0 && c->opt.sc_iters >= 0, RTDM_E_ARG, "sc_steps / sc_iters < 0");
     RT_CHECK(c->opt.unit_tol >= 0.0, RTDM_E_ARG, "unit_tol < 0");
     set_device(c);
+    (void)static_scratch(c->device);   // device address of rtdm_multiply_noalloc's scratch on this GPU
     if (const char *e = getenv("RTDM_RUN_REAL")) c->run_real = atoi(e);
     if (const char *e = getenv("RTDM_RUN_CPLX")) c->run_cplx = atoi(e);
     if (const char *e = getenv("RTDM_ROW_TILE")) c->row_tile = std::max(1, atoi(e));
@@ -2295,12 +2296,35 @@ int rtdm_inverse_error(rtdm_ctx *c, double out[3], void *stream)
     API_END(c)
 }
 
-int rtdm_multiply(rtdm_ctx *c, rtdm_mat Cm, rtdm_mat Am, rtdm_mat Bm, int op_a, int op_b, double alr,
-                  double ali, void *stream)
+namespace {
+
+// A Mat whose planes are borrowed device memory (the static scratch): the
+// pointers are detached before the DBufs are destroyed, so nothing is freed.
+struct BorrowedMat {
+    Mat m;
+    BorrowedMat(int pat, bool cplx, double *re, double *im, size_t n)
+    {
+        m.pat = pat;
+        m.cplx = cplx;
+        m.re.p = re;
+        m.re.n = n;
+        m.im.p = cplx ? im : nullptr;
+        m.im.n = cplx ? n : 0;
+    }
+    ~BorrowedMat()
+    {
+        m.re.p = m.im.p = nullptr;
+        m.re.n = m.im.n = 0;
+    }
+};
+
+// rtdm_multiply's body.  scratch null: the b = 13 column-major copies are
+// allocated (and the call waits for the stream before freeing them);
+// otherwise they are cut from scratch (cap bytes), nothing is allocated and
+// the call returns without waiting.
+void multiply(rtdm_ctx *c, rtdm_mat Cm, rtdm_mat Am, rtdm_mat Bm, int op_a, int op_b, double alr, double ali,
+              hipStream_t s, double *scratch, size_t cap)
 {
-    if (!c) return RTDM_E_ARG;
-    API_BEGIN
-    set_device(c);
     require(c->ranges_set, "set_ranges first");
     RT_CHECK(Am >= 0 && Am < RTDM_MAT_COUNT && Bm >= 0 && Bm < RTDM_MAT_COUNT && Cm >= 0 &&
                  Cm < RTDM_MAT_COUNT && (op_a == 0 || op_a == 1) && (op_b == 0 || op_b == 1),
@@ -2312,7 +2336,8 @@ int rtdm_multiply(rtdm_ctx *c, rtdm_mat Cm, rtdm_mat Am, rtdm_mat Bm, int op_a, 
     for (int q = 0; q < RTDM_PROD_COUNT; ++q)
         if (prod_key(c, q) == want) { prod = q; break; }
     RT_CHECK(prod >= 0, RTDM_E_UNSUPPORTED, "no product kind with these ranges and operations");
-    hipStream_t s = (hipStream_t)stream;
+    RT_CHECK(!scratch || c->scheds.count(want), RTDM_E_STATE,
+             "no schedule of this product kind yet (the allocation-free call builds none): call rtdm_multiply once");
     const bool cres = A.cplx || B.cplx || ali != 0.0;
     RT_CHECK(C.cplx || !cres, RTDM_E_UNSUPPORTED, "complex result for a real matrix slot");
     c->prec = all_products_prec(c);
@@ -2323,24 +2348,55 @@ int rtdm_multiply(rtdm_ctx *c, rtdm_mat Cm, rtdm_mat Am, rtdm_mat Bm, int op_a, 
         const bool step_kind = prod == RTDM_PROD_XH || prod == RTDM_PROD_AT || prod == RTDM_PROD_UK ||
                                prod == RTDM_PROD_WU;
         if (use_cm(c) && step_kind && op_a == 0 && ali == 0.0) {
-            auto like = [&](Mat &m, const Mat &ref) { alloc_like(c, m, ref); };
+            const size_t bb = (size_t)c->b * c->b;
+            const size_t na = c->pats[A.pat]->nnzb * bb, nbm = c->pats[B.pat]->nnzb * bb,
+                         nc = c->pats[C.pat]->nnzb * bb;
+            const bool ccm = prod == RTDM_PROD_UK;
+            auto planes = [](const Mat &m) { return m.cplx ? 2 : 1; };
+            // scratch layout: A's planes, then B's (conjugate-transposed B), then C's (U K), each 256-byte aligned
+            const size_t al = 256 / sizeof(double);
+            auto up = [&](size_t n) { return (n + al - 1) / al * al; };
+            const size_t need = planes(A) * up(na) + (op_b ? planes(B) * up(nbm) : 0) + (ccm ? planes(C) * up(nc) : 0);
+            std::unique_ptr<BorrowedMat> va, vb, vc;
             Mat Acm, Bcm, Ccm;
-            like(Acm, A);
-            transpose_into(c, A, Acm, s);
+            Mat *pa = &Acm, *pb = &Bcm, *pc = &Ccm;
+            if (scratch) {
+                RT_CHECK(need * sizeof(double) <= cap, RTDM_E_ARG,
+                         "operands too large for the static scratch: " + std::to_string(need * sizeof(double)) +
+                             " bytes needed, " + std::to_string(cap) + " available");
+                double *p = scratch;
+                auto take = [&](size_t n) { double *q = p; p += up(n); return q; };
+                double *ar = take(na), *ai = A.cplx ? take(na) : nullptr;
+                va = std::make_unique<BorrowedMat>(A.pat, A.cplx, ar, ai, na);
+                pa = &va->m;
+                if (op_b) {
+                    double *br = take(nbm), *bi = B.cplx ? take(nbm) : nullptr;
+                    vb = std::make_unique<BorrowedMat>(B.pat, B.cplx, br, bi, nbm);
+                    pb = &vb->m;
+                }
+                if (ccm) {
+                    double *cr = take(nc), *ci = C.cplx ? take(nc) : nullptr;
+                    vc = std::make_unique<BorrowedMat>(C.pat, C.cplx, cr, ci, nc);
+                    pc = &vc->m;
+                }
+            } else {
+                alloc_like(c, Acm, A);
+                if (op_b) alloc_like(c, Bcm, B);
+                if (ccm) alloc_like(c, Ccm, C);
+            }
+            transpose_into(c, A, *pa, s);
             const Mat *Bp = &B;
             if (op_b) {
-                like(Bcm, B);
-                transpose_into(c, B, Bcm, s);
-                Bp = &Bcm;
+                transpose_into(c, B, *pb, s);
+                Bp = pb;
             }
-            if (prod == RTDM_PROD_UK) {
-                like(Ccm, C);
-                product_cm(c, prod, Acm, *Bp, Ccm, op_b, 1, alr, s);
-                transpose_into(c, Ccm, C, s);
+            if (ccm) {
+                product_cm(c, prod, *pa, *Bp, *pc, op_b, 1, alr, s);
+                transpose_into(c, *pc, C, s);
             } else {
-                product_cm(c, prod, Acm, *Bp, C, op_b, 0, alr, s);
+                product_cm(c, prod, *pa, *Bp, C, op_b, 0, alr, s);
             }
-            RT_HIP(hipStreamSynchronize(s));   // the copies are freed on return
+            if (!scratch) RT_HIP(hipStreamSynchronize(s));   // the copies are freed on return
         } else {
             product(c, prod, A, B, C, alr, ali, s);
         }
@@ -2350,6 +2406,28 @@ int rtdm_multiply(rtdm_ctx *c, rtdm_mat Cm, rtdm_mat Am, rtdm_mat Bm, int op_a, 
     }
     c->prec = RTDM_PREC_FP64;
     after_upload(c, Cm);
+}
+
+}  // namespace
+
+int rtdm_multiply(rtdm_ctx *c, rtdm_mat Cm, rtdm_mat Am, rtdm_mat Bm, int op_a, int op_b, double alr,
+                  double ali, void *stream)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    multiply(c, Cm, Am, Bm, op_a, op_b, alr, ali, (hipStream_t)stream, nullptr, 0);
+    API_END(c)
+}
+
+int rtdm_multiply_noalloc(rtdm_ctx *c, rtdm_mat Cm, rtdm_mat Am, rtdm_mat Bm, int op_a, int op_b, double alr,
+                          double ali, void *stream)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    multiply(c, Cm, Am, Bm, op_a, op_b, alr, ali, (hipStream_t)stream, static_scratch(c->device),
+             kStaticScratchBytes);
     API_END(c)
 }
 

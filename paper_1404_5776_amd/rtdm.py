@@ -32,7 +32,8 @@ STATUS = {0: "RTDM_OK", -1: "RTDM_E_ARG", -2: "RTDM_E_STATE", -3: "RTDM_E_OOM", 
 EXPORTED = ["rtdm_default_options", "rtdm_create", "rtdm_destroy", "rtdm_set_geometry",
             "rtdm_set_ranges", "rtdm_pattern", "rtdm_upload", "rtdm_upload_coo", "rtdm_download",
             "rtdm_apply_kick", "rtdm_build_inverse", "rtdm_step", "rtdm_observables",
-            "rtdm_dipole_trace", "rtdm_unitarity", "rtdm_inverse_error", "rtdm_multiply", "rtdm_schedule_stats",
+            "rtdm_dipole_trace", "rtdm_unitarity", "rtdm_inverse_error", "rtdm_multiply", "rtdm_multiply_noalloc",
+            "rtdm_schedule_stats",
             "rtdm_timing", "rtdm_timing_stats", "rtdm_inverse_info", "rtdm_mlp_params", "rtdm_mlp_init",
             "rtdm_mlp_set_weights", "rtdm_mlp_get_weights", "rtdm_mlp_collect", "rtdm_mlp_clear",
             "rtdm_mlp_train", "rtdm_mlp_loss_grad", "rtdm_mlp_step", "rtdm_mlp_predict", "rtdm_set_groups",
@@ -86,6 +87,7 @@ def load():
         "rtdm_unitarity": [P, P, P],
         "rtdm_inverse_error": [P, P, P],
         "rtdm_multiply": [P, I, I, I, I, I, D, D, P],
+        "rtdm_multiply_noalloc": [P, I, I, I, I, I, D, D, P],
         "rtdm_schedule_stats": [P, I, P, P],
         "rtdm_timing": [P, I],
         "rtdm_timing_stats": [P, I, P, P, P],
@@ -274,6 +276,12 @@ def rtdm_multiply(ctx, C, A, B, op_a: int = 0, op_b: int = 0, alpha: complex = 1
     a = complex(alpha)
     _check(ctx, load().rtdm_multiply(ctx, _mat(C), _mat(A), _mat(B), int(op_a), int(op_b), a.real, a.imag,
                                      _stream(stream)))
+
+
+def rtdm_multiply_noalloc(ctx, C, A, B, op_a: int = 0, op_b: int = 0, alpha: complex = 1.0, stream=None) -> None:
+    alpha = complex(alpha)
+    _check(ctx, load().rtdm_multiply_noalloc(ctx, _mat(C), _mat(A), _mat(B), op_a, op_b, alpha.real, alpha.imag,
+                                             _stream(stream)))
 
 
 def rtdm_schedule_stats(ctx, prod) -> Tuple[int, int]:
