@@ -159,12 +159,15 @@ typedef struct {
     double inv_tol;        /* stop when ||X_{k+1}-X_k||_F / ||X_{k+1}||_F <= tol (default 1e-10) */
     int inv_max_iter;      /* iteration cap (default 50) */
     int taylor_low_from;   /* *_TAYLOR precisions: first Taylor order n in reduced precision (>= 2, default 3) */
-    int use_graph;         /* 1: rtdm_step replays one captured HIP graph per step (default 0) */
+    int use_graph;         /* 1: rtdm_step replays captured HIP graphs of its steps (default 0) */
     int propagator;        /* RTDM_PROP_* (default EM) */
     int sc_steps;          /* steps after a kick with corrector passes (default 0) */
     int sc_iters;          /* corrector passes per such step (default 2) */
     double unit_tol;       /* > 0: at each unitarity check, stop with RTDM_E_NUMERIC when the relative
                               unitarity error exceeds it or Tr(KS) is not finite (default 0: record only) */
+    int graph_steps;       /* use_graph: steps captured per graph (1..1024, default 16); a call replays
+                              one graph per whole group of graph_steps steps and the one-step graph for
+                              the rest (always the one-step graph while unit_check_every > 0) */
 } rtdm_options;
 
 /* Fill *opt with the defaults above.  Never fails for a non-NULL opt. */

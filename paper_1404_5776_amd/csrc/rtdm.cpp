@@ -320,8 +320,8 @@ struct rtdm_ctx {
     DBuf<double> obs_g, kick_g;
     // captured step
     hipStream_t gstream = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr, graph_multi = nullptr;            // one step; opt.graph_steps steps
+    hipGraphExec_t gexec = nullptr, gexec_multi = nullptr;
     bool capturing = false;
     double graph_dt = 0.0;
     bool graph_rebuilds_u = false;
@@ -908,8 +908,12 @@ void drop_graph(rtdm_ctx *c)
 {
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->gexec_multi) (void)hipGraphExecDestroy(c->gexec_multi);
+    if (c->graph_multi) (void)hipGraphDestroy(c->graph_multi);
     c->gexec = nullptr;
     c->graph = nullptr;
+    c->gexec_multi = nullptr;
+    c->graph_multi = nullptr;
 }
 
 void ensure_obs(rtdm_ctx *c, int64_t rows)
@@ -1078,6 +1082,7 @@ int rtdm_default_options(rtdm_options *opt)
     opt->sc_steps = 0;
     opt->sc_iters = 2;
     opt->unit_tol = 0.0;
+    opt->graph_steps = 16;
     return RTDM_OK;
 }
 
@@ -1113,6 +1118,7 @@ int rtdm_create(rtdm_ctx **out, int hip_device, const rtdm_options *opt)
              "ETRS and M4 need RTDM_PREC_FP64");
     RT_CHECK(c->opt.sc_steps >= 0 && c->opt.sc_iters >= 0, RTDM_E_ARG, "sc_steps / sc_iters < 0");
     RT_CHECK(c->opt.unit_tol >= 0.0, RTDM_E_ARG, "unit_tol < 0");
+    RT_CHECK(c->opt.graph_steps >= 1 && c->opt.graph_steps <= 1024, RTDM_E_ARG, "graph_steps outside 1..1024");
     set_device(c);
     (void)static_scratch(c->device);   // device address of rtdm_multiply_noalloc's scratch on this GPU
     if (const char *e = getenv("RTDM_RUN_REAL")) c->run_real = atoi(e);
@@ -1810,11 +1816,12 @@ int rtdm_step(rtdm_ctx *c, double dt, int64_t n_steps, void *stream)
     }
     if (k < n_steps && c->opt.use_graph) {
         if (c->gexec && (c->graph_dt != dt || c->graph_rebuilds_u != vary)) drop_graph(c);
-        if (!c->gexec) {
+        // capture `count` consecutive steps into one graph
+        auto capture = [&](int count, hipGraph_t &graph, hipGraphExec_t &exec) {
             c->capturing = true;
             RT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             try {
-                step_body(c, dt, vary, 1, s);
+                for (int j = 0; j < count; ++j) step_body(c, dt, vary, 1, s);
             } catch (...) {
                 hipGraph_t g = nullptr;
                 (void)hipStreamEndCapture(s, &g);
@@ -1822,11 +1829,26 @@ int rtdm_step(rtdm_ctx *c, double dt, int64_t n_steps, void *stream)
                 c->capturing = false;
                 throw;
             }
-            RT_HIP(hipStreamEndCapture(s, &c->graph));
+            RT_HIP(hipStreamEndCapture(s, &graph));
             c->capturing = false;
-            RT_HIP(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+            RT_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        };
+        if (!c->gexec) {
+            capture(1, c->graph, c->gexec);
             c->graph_dt = dt;
             c->graph_rebuilds_u = vary;
+        }
+        // whole groups of graph_steps steps replay one multi-step graph (the
+        // step state lives on the device, so the steps of one graph follow
+        // each other as eager steps do); the unitarity monitor needs the host
+        // between steps, so it keeps single-step replays
+        const int G = c->opt.graph_steps;
+        if (G > 1 && c->opt.unit_check_every == 0) {
+            while (n_steps - k >= G) {
+                if (!c->gexec_multi) capture(G, c->graph_multi, c->gexec_multi);
+                RT_HIP(hipGraphLaunch(c->gexec_multi, s));
+                for (int j = 0; j < G; ++j) after_step(k++);
+            }
         }
         for (; k < n_steps; ++k) {
             RT_HIP(hipGraphLaunch(c->gexec, s));

@@ -83,14 +83,18 @@ def _run(s, steps_chunks, use_graph, **opts):
 
 
 @pytest.mark.parametrize("which", ["fixed_b4", "mulliken_b4", "mulliken_b13"])
-def test_graph_replays_equal_eager_steps(which):
+@pytest.mark.parametrize("graph_steps", [1, 4])
+def test_graph_replays_equal_eager_steps(which, graph_steps):
+    """Steps replayed from captured graphs (one step per graph, or four: the
+    calls of 4, 5 and 9 steps replay 4-step graphs and the one-step graph for
+    the rest) repeat the eager steps bit for bit."""
     s = {"fixed_b4": synth.config1,
          "mulliken_b4": lambda: synth.diamond_lattice((3, 3, 3), 4, 10.0, 12.0, seed=22, h_model="mulliken"),
          "mulliken_b13": lambda: synth.diamond_lattice((2, 2, 2), 13, 10.0, 16.0, seed=21, k0="local",
                                                        h_model="mulliken")}[which]()
-    chunks = (3, 4, 5)
+    chunks = (3, 4, 5, 9)
     K_e, tr_e = _run(s, chunks, False, h_model=s.h_model)
-    K_g, tr_g = _run(s, chunks, True, h_model=s.h_model)
+    K_g, tr_g = _run(s, chunks, True, h_model=s.h_model, graph_steps=graph_steps)
     assert tr_e.shape == tr_g.shape == (sum(chunks), 7)
     for r in range(tr_e.shape[0]):                      # every replayed step
         assert np.array_equal(tr_e[r, :6], tr_g[r, :6]), r
@@ -136,5 +140,15 @@ def test_graph_recaptured_after_a_new_inverse():
 
     K_e, tr_e = run(0)
     K_g, tr_g = run(1)
+    assert np.array_equal(K_e, K_g)
+    assert np.array_equal(tr_e[:, :6], tr_g[:, :6])
+
+
+def test_sixteen_step_graphs_equal_eager_steps_over_a_long_run():
+    """The default 16 steps per graph over 100 steps of the 64-atom cluster
+    (6 replays of the 16-step graph and 4 one-step replays)."""
+    s = synth.config1()
+    K_e, tr_e = _run(s, (100,), False)
+    K_g, tr_g = _run(s, (100,), True)
     assert np.array_equal(K_e, K_g)
     assert np.array_equal(tr_e[:, :6], tr_g[:, :6])
