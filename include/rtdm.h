@@ -168,6 +168,9 @@ typedef struct {
     int graph_steps;       /* use_graph: steps captured per graph (1..1024, default 16); a call replays
                               one graph per whole group of graph_steps steps and the one-step graph for
                               the rest (always the one-step graph while unit_check_every > 0) */
+    int n_kicks;           /* kick sets (1..8, default 1): K matrices propagated side by side with one
+                              shared propagator per step (rtdm_apply_kicks, rtdm_select_kick); more than
+                              one needs h_model FIXED and sc_steps 0, since U must not depend on K */
 } rtdm_options;
 
 /* Fill *opt with the defaults above.  Never fails for a non-NULL opt. */
@@ -344,6 +347,19 @@ int rtdm_set_groups(rtdm_ctx *ctx, int64_t n_groups, const int64_t *group_ptr);
 /* K_ij <- exp(i kappa_g . (r_i - r_j)) K_ij with kappa_g = kappa[3g..3g+2]
  * the kick of the group of atoms i and j; otherwise as rtdm_apply_kick. */
 int rtdm_apply_kick_groups(rtdm_ctx *ctx, const double *kappa, void *hip_stream);
+/* Kick sets (opt.n_kicks > 1, Sec. II.B: the polarisability needs a kick along
+ * each axis).  Every set holds its own K (all start from the uploaded K) and
+ * shares S, H, X and the step's propagator U, so a step builds U once and
+ * updates every K with it.  rtdm_apply_kicks applies kick k (kappa[3k ..
+ * 3k+2], bohr^-1, the atom-centred phase of rtdm_apply_kick) to set k, in
+ * every group alike; rtdm_apply_kick and rtdm_apply_kick_groups apply their
+ * kicks to every set.  rtdm_select_kick chooses the set that rtdm_download
+ * (of K), rtdm_observables, rtdm_dipole_trace, rtdm_group_trace,
+ * rtdm_spectrum and rtdm_get_state report (default 0); rtdm_set_state
+ * needs n_kicks = 1. */
+int rtdm_apply_kicks(rtdm_ctx *ctx, const double *kappa, void *hip_stream);
+int rtdm_select_kick(rtdm_ctx *ctx, int k);
+
 /* Per-group trace since the last kick: out[(s * n_groups + g) * 4 + 0..3] =
  * (Px, Py, Pz, Tr(KS)) of group g after step s+1, the dipole taken about the
  * group's centroid.  Synchronises. */

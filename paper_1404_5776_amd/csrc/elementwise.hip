@@ -342,7 +342,7 @@ void launch_spectrum(hipStream_t s, int64_t n_omega, const double *omega, double
 
 // Single workgroup: centroid, dipole P = -sum (r_i - r_c) q_i, Tr(KS) = sum q_i.
 // With a step state st/tt the row is out + 8 * st[0], the time tt[0] +
-// (st[1] + 1) * tt[1], and both counters advance; without one (st null) the
+// (st[1] + 1) * tt[1] (k_step_end advances both counters); without one (st null) the
 // row is `out` and the time `t`.
 __global__ __launch_bounds__(kT) void k_observables(int64_t n, const double *__restrict__ xyz,
                                                     const double *__restrict__ centre,

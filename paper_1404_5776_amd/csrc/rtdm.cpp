@@ -292,7 +292,11 @@ struct rtdm_ctx {
 
     DBuf<int32_t> s_to_k, p_to_hs;
     DBuf<double> q_ref, q_a, q_b;
-    double *q_cur = nullptr, *q_prev = nullptr;
+    double *q_cur = nullptr, *q_prev = nullptr;   // [n_kicks][n]: kick k's charges at + k n
+    // kick sets (opt.n_kicks > 1): K of kick k is mats[K] (k = 0) or Kx[k - 1];
+    // every kick shares S, H, X and U; the API reads kick kick_sel
+    std::vector<Mat> Kx;
+    int kick_sel = 0;
     bool q_ref_valid = false, charges_valid = false;
 
     bool uploaded[RTDM_MAT_COUNT] = {};
@@ -367,6 +371,14 @@ void exact_centre(const std::vector<double> &xyz, int64_t i0, int64_t i1, double
         out[k] = (hi + lo) / (double)(i1 - i0);
     }
 }
+
+int n_kicks(const rtdm_ctx *c) { return c->opt.n_kicks; }
+Mat &kmat(rtdm_ctx *c, int k) { return k == 0 ? c->mats[RTDM_MAT_K] : c->Kx[k - 1]; }
+double *qcur(rtdm_ctx *c, int k) { return c->q_cur + (int64_t)k * c->n; }
+double *qprev(rtdm_ctx *c, int k) { return c->q_prev + (int64_t)k * c->n; }
+double *herm_of(rtdm_ctx *c, int k) { return c->herm_sums.p + 4 * k; }
+double *obs_of(rtdm_ctx *c, int k) { return c->obs.p + (int64_t)k * c->obs_cap * 8; }
+double *obs_g_of(rtdm_ctx *c, int k) { return c->obs_g.p + (int64_t)k * c->obs_cap * c->n_groups * 4; }
 
 int slot_range(int m)
 {
@@ -767,9 +779,10 @@ void ensure_charges(rtdm_ctx *c, hipStream_t s)
 {
     if (c->charges_valid) return;
     Pattern &ps = pat_of(c, R_HS);
-    launch_mulliken(s, c->n, c->b, ps.d_rowptr.p, ps.d_trans.p, c->s_to_k.p, c->mats[RTDM_MAT_S].re.p,
-                    c->mats[RTDM_MAT_K].re.p, c->q_cur);
-    RT_HIP(hipMemcpyAsync(c->q_prev, c->q_cur, c->n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    for (int k = 0; k < n_kicks(c); ++k)
+        launch_mulliken(s, c->n, c->b, ps.d_rowptr.p, ps.d_trans.p, c->s_to_k.p, c->mats[RTDM_MAT_S].re.p,
+                        kmat(c, k).re.p, qcur(c, k));
+    RT_HIP(hipMemcpyAsync(c->q_prev, c->q_cur, n_kicks(c) * c->n * sizeof(double), hipMemcpyDeviceToDevice, s));
     if (!c->q_ref_valid) {
         RT_HIP(hipMemcpyAsync(c->q_ref.p, c->q_cur, c->n * sizeof(double), hipMemcpyDeviceToDevice, s));
         c->q_ref_valid = true;
@@ -919,21 +932,29 @@ void drop_graph(rtdm_ctx *c)
 void ensure_obs(rtdm_ctx *c, int64_t rows)
 {
     const int64_t G = c->n_groups > 1 ? c->n_groups : 0;
-    if (rows <= c->obs_cap && (G == 0 || (int64_t)c->obs_g.n >= c->obs_cap * G * 4)) return;
+    const int NK = n_kicks(c);
+    if (rows <= c->obs_cap && (int64_t)c->obs.n >= c->obs_cap * 8 * NK &&
+        (G == 0 || (int64_t)c->obs_g.n >= c->obs_cap * G * 4 * NK))
+        return;
     int64_t cap = std::max<int64_t>(2 * c->obs_cap, 1024);
     while (cap < rows) cap *= 2;
+    // one trace of cap rows per kick, each kick's rows contiguous
     DBuf<double> nb;
-    nb.alloc(cap * 8);
-    if (c->obs_rows > 0)
-        RT_HIP(hipMemcpy(nb.p, c->obs.p, c->obs_rows * 8 * sizeof(double), hipMemcpyDeviceToDevice));
-    c->obs = std::move(nb);
+    nb.alloc(cap * 8 * NK);
+    if (c->obs_rows > 0 && c->obs.p)
+        for (int k = 0; k < NK; ++k)
+            RT_HIP(hipMemcpy(nb.p + k * cap * 8, obs_of(c, k), c->obs_rows * 8 * sizeof(double),
+                             hipMemcpyDeviceToDevice));
     if (G > 0) {
         DBuf<double> ng;
-        ng.alloc(cap * G * 4);
+        ng.alloc(cap * G * 4 * NK);
         if (c->obs_rows > 0 && c->obs_g.p)
-            RT_HIP(hipMemcpy(ng.p, c->obs_g.p, c->obs_rows * G * 4 * sizeof(double), hipMemcpyDeviceToDevice));
+            for (int k = 0; k < NK; ++k)
+                RT_HIP(hipMemcpy(ng.p + k * cap * G * 4, obs_g_of(c, k), c->obs_rows * G * 4 * sizeof(double),
+                                 hipMemcpyDeviceToDevice));
         c->obs_g = std::move(ng);
     }
+    c->obs = std::move(nb);
     c->obs_cap = cap;
     drop_graph(c);   // the captured step refers to the trace buffers
 }
@@ -966,6 +987,13 @@ void after_upload(rtdm_ctx *c, int m)
     case RTDM_MAT_H0: c->U_valid = false; break;
     case RTDM_MAT_X: c->X_valid = true; c->U_valid = false; c->Xc_valid = false; break;
     case RTDM_MAT_K:
+        for (int k = 1; k < n_kicks(c); ++k) {   // every kick starts from the uploaded K
+            const int64_t ne = elems(c, c->mats[RTDM_MAT_K]);
+            RT_HIP(hipMemcpy(c->Kx[k - 1].re.p, c->mats[RTDM_MAT_K].re.p, ne * sizeof(double),
+                             hipMemcpyDeviceToDevice));
+            RT_HIP(hipMemcpy(c->Kx[k - 1].im.p, c->mats[RTDM_MAT_K].im.p, ne * sizeof(double),
+                             hipMemcpyDeviceToDevice));
+        }
         c->charges_valid = false;
         c->q_ref_valid = false;
         c->obs_reset_pending = true;
@@ -1083,6 +1111,7 @@ int rtdm_default_options(rtdm_options *opt)
     opt->sc_iters = 2;
     opt->unit_tol = 0.0;
     opt->graph_steps = 16;
+    opt->n_kicks = 1;
     return RTDM_OK;
 }
 
@@ -1119,6 +1148,9 @@ int rtdm_create(rtdm_ctx **out, int hip_device, const rtdm_options *opt)
     RT_CHECK(c->opt.sc_steps >= 0 && c->opt.sc_iters >= 0, RTDM_E_ARG, "sc_steps / sc_iters < 0");
     RT_CHECK(c->opt.unit_tol >= 0.0, RTDM_E_ARG, "unit_tol < 0");
     RT_CHECK(c->opt.graph_steps >= 1 && c->opt.graph_steps <= 1024, RTDM_E_ARG, "graph_steps outside 1..1024");
+    RT_CHECK(c->opt.n_kicks >= 1 && c->opt.n_kicks <= 8, RTDM_E_ARG, "n_kicks outside 1..8");
+    RT_CHECK(c->opt.n_kicks == 1 || (c->opt.h_model == RTDM_HMODEL_FIXED && c->opt.sc_steps == 0),
+             RTDM_E_UNSUPPORTED, "several kicks share one propagator: they need a fixed H and no corrector");
     set_device(c);
     (void)static_scratch(c->device);   // device address of rtdm_multiply_noalloc's scratch on this GPU
     if (const char *e = getenv("RTDM_RUN_REAL")) c->run_real = atoi(e);
@@ -1131,7 +1163,7 @@ int rtdm_create(rtdm_ctx **out, int hip_device, const rtdm_options *opt)
     RT_CHECK(c->run_cplx >= 1 && c->run_cplx <= 4, RTDM_E_ARG,
              "row runs of 1 to 4 outputs for complex products");
     c->partials.alloc(kRedBlocks * 4);
-    c->herm_sums.alloc(4);
+    c->herm_sums.alloc(4 * c->opt.n_kicks);
     c->unit_sums.alloc(4);
     c->s_norm2.alloc(4);
     c->hot_sums.alloc(4);
@@ -1280,10 +1312,14 @@ int rtdm_set_ranges(rtdm_ctx *c, double R_hs, double R_p, double R_k)
     RT_HIP(hipMemcpy(c->s_to_k.p, s2k.data(), c->s_to_k.bytes(), hipMemcpyHostToDevice));
     RT_HIP(hipMemcpy(c->p_to_hs.p, p2s.data(), c->p_to_hs.bytes(), hipMemcpyHostToDevice));
     c->q_ref.alloc(c->n);
-    c->q_a.alloc(c->n);
-    c->q_b.alloc(c->n);
+    c->q_a.alloc(c->n * n_kicks(c));
+    c->q_b.alloc(c->n * n_kicks(c));
     c->q_cur = c->q_a.p;
     c->q_prev = c->q_b.p;
+    c->Kx.clear();
+    c->Kx.resize(n_kicks(c) - 1);
+    for (auto &Km : c->Kx) alloc_mat(c, Km, R_K, true);
+    c->kick_sel = 0;
     c->atom_max.alloc(c->n);
     c->scratch.alloc((size_t)c->n * c->b * 2 * c->b);
     drop_graph(c);
@@ -1426,7 +1462,7 @@ int rtdm_download(rtdm_ctx *c, rtdm_mat mat, void *dst, int is_device, void *str
     require(c->ranges_set, "set_ranges first");
     RT_CHECK(mat >= 0 && mat < RTDM_MAT_COUNT && dst, RTDM_E_ARG, "bad download arguments");
     hipStream_t s = (hipStream_t)stream;
-    Mat &M = c->mats[mat];
+    Mat &M = mat == RTDM_MAT_K ? kmat(c, c->kick_sel) : c->mats[mat];
     const int64_t ne = elems(c, M);
     if (mat == RTDM_MAT_W && c->W_in_cm) {             // the step keeps W column-major
         transpose_into(c, c->Wc, M, s);
@@ -1462,10 +1498,10 @@ int rtdm_apply_kick(rtdm_ctx *c, const double kappa[3], void *stream)
         c->charges_valid = false;
         ensure_charges(c, s);
     }
-    Mat &K = c->mats[RTDM_MAT_K];
     const Pattern &P = pat_of(c, R_K);
-    launch_kick(s, P.nnzb, c->b, P.d_rowof.p, P.d_col.p, c->d_xyz.p, kappa[0], kappa[1], kappa[2], K.re.p,
-                K.im.p);
+    for (int k = 0; k < n_kicks(c); ++k)
+        launch_kick(s, P.nnzb, c->b, P.d_rowof.p, P.d_col.p, c->d_xyz.p, kappa[0], kappa[1], kappa[2],
+                    kmat(c, k).re.p, kmat(c, k).im.p);
     c->charges_valid = false;
     c->obs_rows = 0;
     c->obs_reset_pending = true;
@@ -1707,46 +1743,54 @@ void build_u(rtdm_ctx *c, double dt, bool corr, hipStream_t s)
 // replayed; the trace row and the time come from the device step state.
 void step_body(rtdm_ctx *c, double dt, bool rebuild_u, int passes, hipStream_t s)
 {
-    Mat &U = c->mats[RTDM_MAT_U], &K = c->mats[RTDM_MAT_K], &W = c->mats[RTDM_MAT_W];
+    Mat &U = c->mats[RTDM_MAT_U], &W = c->mats[RTDM_MAT_W];
     const Pattern &ps = pat_of(c, R_HS), &pk = pat_of(c, R_K);
+    const int NK = n_kicks(c);                   // several kicks: fixed H, no corrector (checked at creation)
     c->prec = all_products_prec(c);
     const bool sc = passes > 1;
-    Mat &dst = sc ? c->Kt : K;
-    for (int it = 0; it < passes; ++it) {
-        if (rebuild_u) {
-            build_u(c, dt, it > 0, s);
-            c->U_valid = true;
-            c->U_dt = dt;
+    for (int kk = 0; kk < NK; ++kk) {
+        Mat &K = kmat(c, kk);
+        Mat &dst = sc ? c->Kt : K;
+        for (int it = 0; it < passes; ++it) {
+            if (rebuild_u && kk == 0) {          // every kick shares the step's propagator
+                build_u(c, dt, it > 0, s);
+                c->U_valid = true;
+                c->U_dt = dt;
+            }
+            if (use_cm(c)) {
+                product_cm(c, RTDM_PROD_UK, c->Uc, K, c->Wc, 0, 1, 1.0, s);     // W, column-major
+                product_cm(c, RTDM_PROD_WU, c->Wc, c->Uc, c->Kn, 1, 0, 1.0, s); // B = U^dagger
+                c->W_in_cm = true;
+            } else {
+                product(c, RTDM_PROD_UK, U, K, W, 1.0, 0.0, s);
+                product(c, RTDM_PROD_WU, W, U, c->Kn, 1.0, 0.0, s);
+                c->W_in_cm = false;
+            }
+            launch_hermitize(s, pk.nnzb, c->b, pk.d_trans.p, c->Kn.re.p, c->Kn.im.p, dst.re.p, dst.im.p,
+                             c->partials.p);
+            if (sc)
+                launch_mulliken(s, c->n, c->b, ps.d_rowptr.p, ps.d_trans.p, c->s_to_k.p,
+                                c->mats[RTDM_MAT_S].re.p, dst.re.p, c->q_c.p);
         }
-        if (use_cm(c)) {
-            product_cm(c, RTDM_PROD_UK, c->Uc, K, c->Wc, 0, 1, 1.0, s);     // W, column-major
-            product_cm(c, RTDM_PROD_WU, c->Wc, c->Uc, c->Kn, 1, 0, 1.0, s); // B = U^dagger
-            c->W_in_cm = true;
-        } else {
-            product(c, RTDM_PROD_UK, U, K, W, 1.0, 0.0, s);
-            product(c, RTDM_PROD_WU, W, U, c->Kn, 1.0, 0.0, s);
-            c->W_in_cm = false;
-        }
-        launch_hermitize(s, pk.nnzb, c->b, pk.d_trans.p, c->Kn.re.p, c->Kn.im.p, dst.re.p, dst.im.p,
-                         c->partials.p);
-        if (sc)
-            launch_mulliken(s, c->n, c->b, ps.d_rowptr.p, ps.d_trans.p, c->s_to_k.p, c->mats[RTDM_MAT_S].re.p,
-                            dst.re.p, c->q_c.p);
+        reduce_finish(c, s, herm_of(c, kk));
     }
-    reduce_finish(c, s, c->herm_sums.p);
     c->herm_valid = true;
-    launch_axpby(s, c->n, 1.0, c->q_cur, 0.0, nullptr, c->q_prev);                 // q(t - dt) <- q(t)
+    launch_axpby(s, c->n * NK, 1.0, c->q_cur, 0.0, nullptr, c->q_prev);            // q(t - dt) <- q(t)
     if (sc) {
-        copy_mat(c, c->Kt, K, s);
+        copy_mat(c, c->Kt, c->mats[RTDM_MAT_K], s);
         launch_axpby(s, c->n, 1.0, c->q_c.p, 0.0, nullptr, c->q_cur);
     } else {
-        launch_mulliken(s, c->n, c->b, ps.d_rowptr.p, ps.d_trans.p, c->s_to_k.p, c->mats[RTDM_MAT_S].re.p,
-                        K.re.p, c->q_cur);
+        for (int kk = 0; kk < NK; ++kk)
+            launch_mulliken(s, c->n, c->b, ps.d_rowptr.p, ps.d_trans.p, c->s_to_k.p, c->mats[RTDM_MAT_S].re.p,
+                            kmat(c, kk).re.p, qcur(c, kk));
     }
-    launch_observables_step(s, c->n, c->d_xyz.p, c->d_centre_all.p, c->q_cur, c->herm_sums.p, c->obs.p, c->step_st.p,
-                            c->step_tt.p);
-    if (c->n_groups > 1)
-        launch_group_obs(s, c->n_groups, c->d_gptr.p, c->d_xyz.p, c->d_centre.p, c->q_cur, c->step_st.p, c->obs_g.p);
+    for (int kk = 0; kk < NK; ++kk) {
+        launch_observables_step(s, c->n, c->d_xyz.p, c->d_centre_all.p, qcur(c, kk), herm_of(c, kk), obs_of(c, kk),
+                                c->step_st.p, c->step_tt.p);
+        if (c->n_groups > 1)
+            launch_group_obs(s, c->n_groups, c->d_gptr.p, c->d_xyz.p, c->d_centre.p, qcur(c, kk), c->step_st.p,
+                             obs_g_of(c, kk));
+    }
     launch_step_end(s, c->step_st.p);
     c->prec = RTDM_PREC_FP64;
 }
@@ -1781,7 +1825,8 @@ int rtdm_step(rtdm_ctx *c, double dt, int64_t n_steps, void *stream)
         if (c->opt.unit_check_every > 0 && (c->obs_rows + 1) % c->opt.unit_check_every == 0) {
             c->prec = RTDM_PREC_FP64;               // the unitarity check stays FP64
             unitarity_sums(c, s);
-            launch_unit_to_row(s, c->unit_sums.p, c->s_norm2.p, c->obs.p + 8 * c->obs_rows);
+            for (int kk = 0; kk < n_kicks(c); ++kk)   // U is shared: the same value in every kick's trace
+                launch_unit_to_row(s, c->unit_sums.p, c->s_norm2.p, obs_of(c, kk) + 8 * c->obs_rows);
             if (c->opt.unit_tol > 0.0) {             // monitor: one synchronising read per check
                 double row[8];
                 read_scalars(row, c->obs.p + 8 * c->obs_rows, 8, s);
@@ -2019,7 +2064,7 @@ int rtdm_spectrum(rtdm_ctx *c, int64_t group, const double P0[3], const double *
     al.alloc(n_omega * 6);
     st.alloc(n_omega);
     RT_HIP(hipMemcpyAsync(om.p, omega, om.bytes(), hipMemcpyHostToDevice, s));
-    const double *trace = group < 0 ? c->obs.p : c->obs_g.p;
+    const double *trace = group < 0 ? obs_of(c, c->kick_sel) : obs_g_of(c, c->kick_sel);
     const int64_t stride = group < 0 ? 8 : 4 * c->n_groups;
     const int64_t off = group < 0 ? 1 : 4 * group;
     launch_spectrum(s, n_omega, om.p, gamma, c->trace_dt, c->obs_rows, trace, stride, off, P0, kappa ? 1 : 0,
@@ -2078,16 +2123,17 @@ int rtdm_apply_kick_groups(rtdm_ctx *c, const double *kappa, void *stream)
         c->charges_valid = false;
         ensure_charges(c, s);
     }
+    const Pattern &P = pat_of(c, R_K);
     if (c->n_groups == 1) {
-        const Pattern &P = pat_of(c, R_K);
-        launch_kick(s, P.nnzb, c->b, P.d_rowof.p, P.d_col.p, c->d_xyz.p, kappa[0], kappa[1], kappa[2],
-                    c->mats[RTDM_MAT_K].re.p, c->mats[RTDM_MAT_K].im.p);
+        for (int k = 0; k < n_kicks(c); ++k)
+            launch_kick(s, P.nnzb, c->b, P.d_rowof.p, P.d_col.p, c->d_xyz.p, kappa[0], kappa[1], kappa[2],
+                        kmat(c, k).re.p, kmat(c, k).im.p);
     } else {
         c->kick_g.alloc(3 * c->n_groups);
         RT_HIP(hipMemcpyAsync(c->kick_g.p, kappa, c->kick_g.bytes(), hipMemcpyHostToDevice, s));
-        const Pattern &P = pat_of(c, R_K);
-        launch_kick_groups(s, P.nnzb, c->b, P.d_rowof.p, P.d_col.p, c->d_xyz.p, c->d_group.p, c->kick_g.p,
-                           c->mats[RTDM_MAT_K].re.p, c->mats[RTDM_MAT_K].im.p);
+        for (int k = 0; k < n_kicks(c); ++k)
+            launch_kick_groups(s, P.nnzb, c->b, P.d_rowof.p, P.d_col.p, c->d_xyz.p, c->d_group.p, c->kick_g.p,
+                               kmat(c, k).re.p, kmat(c, k).im.p);
         RT_HIP(hipStreamSynchronize(s));
     }
     c->charges_valid = false;
@@ -2097,6 +2143,42 @@ int rtdm_apply_kick_groups(rtdm_ctx *c, const double *kappa, void *stream)
     c->step_count = 0;
     c->trace_dt_mixed = false;
     c->herm_valid = false;
+    API_END(c)
+}
+
+int rtdm_apply_kicks(rtdm_ctx *c, const double *kappa, void *stream)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    require(c->ranges_set && c->uploaded[RTDM_MAT_K] && c->uploaded[RTDM_MAT_S], "upload S and K first");
+    RT_CHECK(kappa, RTDM_E_ARG, "null kicks");
+    for (int e = 0; e < 3 * n_kicks(c); ++e) RT_CHECK(std::isfinite(kappa[e]), RTDM_E_ARG, "bad kick");
+    hipStream_t s = (hipStream_t)stream;
+    if (!c->q_ref_valid) {
+        c->charges_valid = false;
+        ensure_charges(c, s);
+    }
+    const Pattern &P = pat_of(c, R_K);
+    for (int k = 0; k < n_kicks(c); ++k)
+        launch_kick(s, P.nnzb, c->b, P.d_rowof.p, P.d_col.p, c->d_xyz.p, kappa[3 * k], kappa[3 * k + 1],
+                    kappa[3 * k + 2], kmat(c, k).re.p, kmat(c, k).im.p);
+    c->charges_valid = false;
+    c->obs_rows = 0;
+    c->obs_reset_pending = true;
+    c->t_now = 0.0;
+    c->step_count = 0;
+    c->trace_dt_mixed = false;
+    c->herm_valid = false;
+    API_END(c)
+}
+
+int rtdm_select_kick(rtdm_ctx *c, int k)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    RT_CHECK(k >= 0 && k < n_kicks(c), RTDM_E_ARG, "no such kick set");
+    c->kick_sel = k;
     API_END(c)
 }
 
@@ -2111,7 +2193,8 @@ int rtdm_group_trace(rtdm_ctx *c, double *out, int64_t max_rows, int64_t *rows)
     const int64_t nr = std::min(max_rows, c->obs_rows);
     if (rows) *rows = c->obs_rows;
     if (nr > 0)
-        RT_HIP(hipMemcpy(out, c->obs_g.p, nr * c->n_groups * 4 * sizeof(double), hipMemcpyDeviceToHost));
+        RT_HIP(hipMemcpy(out, obs_g_of(c, c->kick_sel), nr * c->n_groups * 4 * sizeof(double),
+                         hipMemcpyDeviceToHost));
     API_END(c)
 }
 
@@ -2201,8 +2284,8 @@ int rtdm_observables(rtdm_ctx *c, double out[6], void *stream)
     RT_CHECK(out, RTDM_E_ARG, "null output");
     hipStream_t s = (hipStream_t)stream;
     ensure_charges(c, s);
-    launch_observables(s, c->n, c->d_xyz.p, c->d_centre_all.p, c->q_cur, c->herm_valid ? c->herm_sums.p : nullptr, c->t_now,
-                       c->obs_tmp.p);
+    launch_observables(s, c->n, c->d_xyz.p, c->d_centre_all.p, qcur(c, c->kick_sel),
+                       c->herm_valid ? herm_of(c, c->kick_sel) : nullptr, c->t_now, c->obs_tmp.p);
     double row[8];
     read_scalars(row, c->obs_tmp.p, 8, s);
     for (int k = 0; k < 5; ++k) out[k] = row[k + 1];
@@ -2230,8 +2313,8 @@ int rtdm_get_state(rtdm_ctx *c, double *out, int64_t n, void *stream)
     ensure_charges(c, s);
     out[0] = c->t_now;
     out[1] = (double)c->step_count;
-    RT_HIP(hipMemcpyAsync(out + 2, c->q_cur, c->n * sizeof(double), hipMemcpyDeviceToHost, s));
-    RT_HIP(hipMemcpyAsync(out + 2 + c->n, c->q_prev, c->n * sizeof(double), hipMemcpyDeviceToHost, s));
+    RT_HIP(hipMemcpyAsync(out + 2, qcur(c, c->kick_sel), c->n * sizeof(double), hipMemcpyDeviceToHost, s));
+    RT_HIP(hipMemcpyAsync(out + 2 + c->n, qprev(c, c->kick_sel), c->n * sizeof(double), hipMemcpyDeviceToHost, s));
     RT_HIP(hipMemcpyAsync(out + 2 + 2 * c->n, c->q_ref.p, c->n * sizeof(double), hipMemcpyDeviceToHost, s));
     RT_HIP(hipStreamSynchronize(s));
     API_END(c)
@@ -2246,6 +2329,7 @@ int rtdm_set_state(rtdm_ctx *c, const double *in, int64_t n, void *stream)
     RT_CHECK(in && n == 2 + 3 * c->n, RTDM_E_ARG, "the state holds 2 + 3 n_atoms doubles");
     RT_CHECK(std::isfinite(in[0]) && in[1] >= 0 && in[1] == std::floor(in[1]), RTDM_E_ARG, "bad time or step count");
     hipStream_t s = (hipStream_t)stream;
+    RT_CHECK(n_kicks(c) == 1, RTDM_E_UNSUPPORTED, "set_state restores a single kick");
     RT_HIP(hipMemcpyAsync(c->q_cur, in + 2, c->n * sizeof(double), hipMemcpyHostToDevice, s));
     RT_HIP(hipMemcpyAsync(c->q_prev, in + 2 + c->n, c->n * sizeof(double), hipMemcpyHostToDevice, s));
     RT_HIP(hipMemcpyAsync(c->q_ref.p, in + 2 + 2 * c->n, c->n * sizeof(double), hipMemcpyHostToDevice, s));
@@ -2273,7 +2357,7 @@ int rtdm_dipole_trace(rtdm_ctx *c, double *out, int64_t max_rows, int64_t *rows)
     if (rows) *rows = c->obs_rows;
     if (nr > 0) {
         std::vector<double> tmp(nr * 8);
-        RT_HIP(hipMemcpy(tmp.data(), c->obs.p, tmp.size() * sizeof(double), hipMemcpyDeviceToHost));
+        RT_HIP(hipMemcpy(tmp.data(), obs_of(c, c->kick_sel), tmp.size() * sizeof(double), hipMemcpyDeviceToHost));
         for (int64_t r = 0; r < nr; ++r)
             for (int k = 0; k < 7; ++k) out[7 * r + k] = tmp[8 * r + k];
     }

@@ -37,7 +37,7 @@ EXPORTED = ["rtdm_default_options", "rtdm_create", "rtdm_destroy", "rtdm_set_geo
             "rtdm_timing", "rtdm_timing_stats", "rtdm_inverse_info", "rtdm_mlp_params", "rtdm_mlp_init",
             "rtdm_mlp_set_weights", "rtdm_mlp_get_weights", "rtdm_mlp_collect", "rtdm_mlp_clear",
             "rtdm_mlp_train", "rtdm_mlp_loss_grad", "rtdm_mlp_step", "rtdm_mlp_predict", "rtdm_set_groups",
-            "rtdm_apply_kick_groups", "rtdm_group_trace", "rtdm_autotune", "rtdm_set_field",
+            "rtdm_apply_kick_groups", "rtdm_group_trace", "rtdm_apply_kicks", "rtdm_select_kick", "rtdm_autotune", "rtdm_set_field",
             "rtdm_spectrum", "rtdm_workspace_size", "rtdm_bind_workspace", "rtdm_ground_state",
             "rtdm_get_state", "rtdm_set_state", "rtdm_last_error"]
 
@@ -54,7 +54,7 @@ class Options(ctypes.Structure):
                 ("inv_start", ctypes.c_int), ("inv_tol", ctypes.c_double),
                 ("inv_max_iter", ctypes.c_int), ("taylor_low_from", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("propagator", ctypes.c_int), ("sc_steps", ctypes.c_int), ("sc_iters", ctypes.c_int),
-                ("unit_tol", ctypes.c_double), ("graph_steps", ctypes.c_int)]
+                ("unit_tol", ctypes.c_double), ("graph_steps", ctypes.c_int), ("n_kicks", ctypes.c_int)]
 
 
 _lib = None
@@ -105,6 +105,8 @@ def load():
         "rtdm_set_groups": [P, I64, P],
         "rtdm_apply_kick_groups": [P, P, P],
         "rtdm_group_trace": [P, P, I64, P],
+        "rtdm_apply_kicks": [P, P, P],
+        "rtdm_select_kick": [P, I],
         "rtdm_autotune": [P, P, P, P],
         "rtdm_set_field": [P, P, D, D],
         "rtdm_spectrum": [P, I64, P, P, D, I64, P, P, P, P],
@@ -384,6 +386,15 @@ def rtdm_apply_kick_groups(ctx, kappa, stream=None) -> None:
     _check(ctx, load().rtdm_apply_kick_groups(ctx, _p(k), _stream(stream)))
 
 
+def rtdm_apply_kicks(ctx, kappas, stream=None) -> None:
+    k = np.ascontiguousarray(kappas, dtype=np.float64).reshape(-1)
+    _check(ctx, load().rtdm_apply_kicks(ctx, _p(k), _stream(stream)))
+
+
+def rtdm_select_kick(ctx, k: int) -> None:
+    _check(ctx, load().rtdm_select_kick(ctx, int(k)))
+
+
 def rtdm_group_trace(ctx, n_groups: int, max_rows: int = 1 << 20) -> np.ndarray:
     rows = ctypes.c_int64()
     _check(ctx, load().rtdm_group_trace(ctx, None, 0, ctypes.byref(rows)))
@@ -534,6 +545,17 @@ class Context:
         self.group_ptr = np.asarray(gptr)
         self.group_kicks = np.asarray(kap, dtype=np.float64)
         return self.group_ptr
+
+    def load_kick_sets(self, systems, kicks, stream=None):
+        """One geometry holding each system once as its own group, for a context
+        created with n_kicks = len(kicks): kick set k propagates every system
+        after the kick kicks[k] (applied by rtdm_apply_kicks with
+        self.kick_vectors), all sets sharing one propagator per step.
+        Returns the group pointer."""
+        assert self.options.n_kicks == len(kicks)
+        gptr = self.load_batch(systems, [[(0.0, 0.0, 0.0)]] * len(systems), stream)
+        self.kick_vectors = np.asarray(kicks, dtype=np.float64)
+        return gptr
 
     def load_system(self, sys_, stream=None):
         self.b = sys_.b

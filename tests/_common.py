@@ -3,7 +3,7 @@
 import numpy as np
 
 from oracle import oracle as O
-from paper_1404_5776_amd import rtdm
+from paper_1404_5776_amd import rtdm, synth
 
 # FP64 parity bar: relative Frobenius error of every compared matrix and
 # max-norm error of every trace relative to its scale.
@@ -57,3 +57,13 @@ def assert_charges(q: np.ndarray, K_ref: "O.BSM", S: "O.BSM") -> float:
     print(f"charges: max rel error {err:.2e}")
     assert err <= TOL, err
     return dq
+
+
+def small_clusters(b):
+    """Three b = 4 clusters (ranges 8 / 12 bohr) or two b = 13 clusters (6 / 8 bohr)."""
+    out = []
+    sizes, ranges = ((30, 55, 41), (8.0, 12.0)) if b == 4 else ((24, 37), (6.0, 8.0))
+    for k, n in enumerate(sizes):
+        xyz = synth.cluster_positions(n, np.random.default_rng(91 + k))
+        out.append(synth.build_system(f"c{n}_b{b}", xyz, b, ranges[0], ranges[1], 95 + k, k0="exact"))
+    return out

@@ -14,24 +14,14 @@ import pytest
 
 from oracle import oracle as O
 from paper_1404_5776_amd import rtdm, synth
-from tests._common import TOL, assert_charges, dipole_floor, gpu_charges, gpu_context, rel
+from tests._common import TOL, assert_charges, dipole_floor, gpu_charges, gpu_context, rel, small_clusters
 
 pytestmark = pytest.mark.gpu
 
 
-def _clusters(b):
-    """Three b = 4 clusters (ranges 8 / 12 bohr) or two b = 13 clusters (6 / 8 bohr)."""
-    out = []
-    sizes, ranges = ((30, 55, 41), (8.0, 12.0)) if b == 4 else ((24, 37), (6.0, 8.0))
-    for k, n in enumerate(sizes):
-        xyz = synth.cluster_positions(n, np.random.default_rng(91 + k))
-        out.append(synth.build_system(f"c{n}_b{b}", xyz, b, ranges[0], ranges[1], 95 + k, k0="exact"))
-    return out
-
-
 @pytest.mark.parametrize("h_model,b", [("fixed", 4), ("mulliken", 4), ("fixed", 13), ("mulliken", 13)])
 def test_batch_of_clusters_with_xyz_kicks_matches_oracle(h_model, b):
-    systems = _clusters(b)
+    systems = small_clusters(b)
     kicks = [[(0.01, 0, 0), (0, 0.01, 0), (0, 0, 0.01)]] * len(systems)
     print(f"[gpu] batch of {len(systems)} b={b} clusters x 3 kicks, h_model={h_model}", flush=True)
     ctx = rtdm.Context(0, h_model=h_model)
