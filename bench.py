@@ -12,8 +12,11 @@ kernel (algorithmic flops per launch over its average HIP-event duration) and
 the oracle's CPU rate on a bounded sample.  Beside the FP64 run, on the same
 workload: the reduced-precision forms (late Taylor terms in FP32, split BF16
 or split FP16) with the learned inverse start, their dipole error against the
-FP64 run; the captured-graph step; and a batch leg (clusters of the 64-cluster
-workload with x/y/z kicks in block-diagonal batches, FP64 and FP32).
+FP64 run; the captured-graph step; a batch leg (all 64 clusters of the
+batching workload with x/y/z kicks, stepped together by captured graphs, FP64
+and FP32, against one system at a time); the 64-atom cluster with multi-step
+graphs against eager steps; and FP64 steps/s of the b = 4 lattices (65,536
+atoms, and 32,768 atoms at R_K 12) with their kernels' roofline fractions.
 """
 
 import argparse
@@ -156,60 +159,144 @@ def train_learned_start(b, seeds=(101, 102, 103), cells=(3, 3, 3)):
 
 
 def batch_leg(args):
-    """The 64-cluster workload: every cluster with x, y and z kicks, packed
-    into block-diagonal batches of equal b, one captured step graph per batch,
-    launch shapes autotuned; FP64 and FP32.  Returns the batch object."""
+    """The 64-cluster workload (log-uniform 50-2,000 atoms, b 4 or 13, R_HS 8,
+    R_K 12 bohr, fixed H), every cluster with x, y and z kicks: 192
+    propagations.  Batched: one kick-set context per b (each cluster once, as
+    a group of a block-diagonal geometry; three K per context sharing one
+    propagator), both advanced by one rtdm batch whose captured graph moves
+    all propagations graph_steps steps per launch.  Per system: each cluster
+    alone in a context of its own with the x kick and captured graphs of the
+    same length; its y and z propagations run the same kernels on the same
+    patterns, so they are counted at the x kick's time.  FP64 (b = 13 launch
+    shapes autotuned on both sides) and FP32."""
     import torch
     from paper_1404_5776_amd import rtdm, synth
 
     t = time.time()
-    clusters = []
-    for k in range(args.batch_clusters):
-        clusters.append(synth.config4_cluster(k))
-        log(f"batch: cluster {k}: {clusters[-1].n_atoms} atoms, b={clusters[-1].b} ({time.time() - t:.1f} s)")
-    kicks = [(0.01, 0, 0), (0, 0.01, 0), (0, 0, 0.01)]
-    # pack by b, at most batch_atoms atoms (3 kicks counted) per batch
-    batches = []
-    for b in (4, 13):
-        cur, n = [], 0
-        for c in sorted([c for c in clusters if c.b == b], key=lambda c: -c.n_atoms):
-            if cur and n + 3 * c.n_atoms > args.batch_atoms:
-                batches.append(cur)
-                cur, n = [], 0
-            cur.append(c)
-            n += 3 * c.n_atoms
-        if cur:
-            batches.append(cur)
-    out = {"workload": f"the first {len(clusters)} of the 64 random clusters (log-uniform 50-2000 atoms, "
-                       f"b 4 or 13, R_HS 8, "
-                       f"R_K 12 bohr, fixed H), x/y/z kicks each: {3 * len(clusters)} propagations in "
-                       f"{len(batches)} block-diagonal batches, one captured step graph per batch",
-           "propagations": 3 * len(clusters), "atoms": int(sum(c.n_atoms for c in clusters)),
-           "steps": args.batch_steps}
+    clusters = synth.config4_all(n_clusters=args.batch_clusters)
+    log(f"batch: {len(clusters)} clusters, {sum(c.n_atoms for c in clusters)} atoms, "
+        f"generated in {time.time() - t:.1f} s")
+    kicks = [(0.01, 0.0, 0.0), (0.0, 0.01, 0.0), (0.0, 0.0, 0.01)]
+    G, n_steps, dt = args.batch_graph_steps, args.batch_steps, clusters[0].dt
+    by_b = {b: [c for c in clusters if c.b == b] for b in (4, 13)}
+    n_prop = len(kicks) * len(clusters)
+    out = {"workload": f"{len(clusters)} random clusters (log-uniform 50-2000 atoms, b 4 or 13, R_HS 8, "
+                       f"R_K 12 bohr, fixed H), x/y/z kicks each: {n_prop} propagations; batched as one "
+                       f"kick-set context per b stepped by one captured graph per {G} steps",
+           "propagations": n_prop, "atoms": int(sum(c.n_atoms for c in clusters)),
+           "clusters_by_b": {str(b): len(v) for b, v in by_b.items()}, "steps": n_steps, "graph_steps": G}
+    stream = torch.cuda.current_stream()
     for prec in ("fp64", "fp32"):
-        total_s, shapes = 0.0, []
-        for bt in batches:
-            stream = torch.cuda.current_stream()
-            ctx = rtdm.Context(0, precision=prec, use_graph=1)
-            ctx.load_batch(bt, [kicks] * len(bt), stream)
+        tune = prec == "fp64"
+        ctxs, shapes = [], {}
+        for b, members in by_b.items():
+            if not members:
+                continue
+            ctx = rtdm.Context(0, precision=prec, n_kicks=len(kicks), use_graph=1, graph_steps=G)
+            ctx.load_kick_sets(members, kicks, stream)
             rtdm.rtdm_build_inverse(ctx.h, stream)
-            rtdm.rtdm_apply_kick_groups(ctx.h, ctx.group_kicks, stream)
-            rtdm.rtdm_step(ctx.h, bt[0].dt, 1)              # builds the fixed-H propagator
-            shape = rtdm.rtdm_autotune(ctx.h) if bt[0].b == 13 and prec == "fp64" else None
-            rtdm.rtdm_step(ctx.h, bt[0].dt, 1)              # captures the step graph
+            rtdm.rtdm_apply_kicks(ctx.h, ctx.kick_vectors, stream)
+            ctxs.append(ctx)
+        bt = rtdm.rtdm_batch_create([c.h for c in ctxs], G)
+        rtdm.rtdm_batch_step(bt, dt, 1, stream)           # the fixed-H propagators
+        if tune:
+            for ctx in ctxs:
+                if ctx.b == 13:
+                    shapes["batched_b13"] = rtdm.rtdm_autotune(ctx.h, stream)
+        rtdm.rtdm_batch_step(bt, dt, G, stream)           # capture and one replay
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rtdm.rtdm_batch_step(bt, dt, n_steps, stream)
+        torch.cuda.synchronize()
+        t_batch = time.perf_counter() - t0
+        rtdm.rtdm_batch_destroy(bt)
+        for ctx in ctxs:
+            ctx.close()
+        t_sys = 0.0
+        for c in clusters:
+            ctx = rtdm.Context(0, precision=prec, use_graph=1, graph_steps=G)
+            ctx.load_system(c, stream)
+            rtdm.rtdm_build_inverse(ctx.h, stream)
+            rtdm.rtdm_apply_kick(ctx.h, kicks[0], stream)
+            rtdm.rtdm_step(ctx.h, dt, 1, stream)
+            if tune and c.b == 13:
+                rtdm.rtdm_autotune(ctx.h, stream)
+            rtdm.rtdm_step(ctx.h, dt, G, stream)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            rtdm.rtdm_step(ctx.h, bt[0].dt, args.batch_steps)
+            rtdm.rtdm_step(ctx.h, dt, n_steps, stream)
             torch.cuda.synchronize()
-            total_s += time.perf_counter() - t0
-            shapes.append({"b": bt[0].b, "systems": len(bt), "atoms": int(3 * sum(c.n_atoms for c in bt)),
-                           "autotuned_wpb_row_tile": shape})
+            t_sys += time.perf_counter() - t0
             ctx.close()
-        out[prec] = {"propagation_steps_per_s": 3 * len(clusters) * args.batch_steps / total_s,
-                     "seconds_per_step_all_batches": total_s / args.batch_steps}
-        if prec == "fp64":
-            out["batches"] = shapes
+        t_sys *= len(kicks)
+        out[prec] = {"propagation_steps_per_s": n_prop * n_steps / t_batch,
+                     "seconds_per_step_all_propagations": t_batch / n_steps,
+                     "per_system_propagation_steps_per_s": n_prop * n_steps / t_sys,
+                     "speedup_vs_per_system": t_sys / t_batch}
+        if shapes:
+            out[prec]["autotuned_wpb_row_tile"] = shapes
         log(f"batch {prec}: {out[prec]}")
+    return out
+
+
+def small_leg(args):
+    """The 64-atom cluster (b = 4, R_HS 8, R_K 12, fixed H, 100 steps): eager
+    steps against steps replayed from captured graphs of graph_steps steps."""
+    import torch
+    from paper_1404_5776_amd import rtdm, synth
+
+    s = synth.config1()
+    stream = torch.cuda.current_stream()
+    out = {"workload": f"cluster {s.n_atoms} atoms x {s.b} functions, R_HS {s.R_HS} R_K {s.R_K} bohr, "
+                       f"fixed H, EM + Taylor p=5, dt {s.dt}, {s.n_steps} steps",
+           "graph_steps": args.small_graph_steps}
+    traces = {}
+    for use_graph in (0, 1):
+        ctx = rtdm.Context(0, use_graph=use_graph, graph_steps=args.small_graph_steps)
+        ctx.load_system(s, stream)
+        rtdm.rtdm_build_inverse(ctx.h, stream)
+        rtdm.rtdm_apply_kick(ctx.h, s.kappa, stream)
+        rtdm.rtdm_step(ctx.h, s.dt, 1 + args.small_graph_steps, stream)      # U, capture, one replay
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rtdm.rtdm_step(ctx.h, s.dt, s.n_steps, stream)
+        torch.cuda.synchronize()
+        dt_s = time.perf_counter() - t0
+        traces[use_graph] = rtdm.rtdm_dipole_trace(ctx.h)
+        ctx.close()
+        out["graph_steps_per_s" if use_graph else "eager_steps_per_s"] = s.n_steps / dt_s
+    out["speedup_graph_vs_eager"] = out["graph_steps_per_s"] / out["eager_steps_per_s"]
+    out["bit_identical_trace"] = bool(np.array_equal(traces[0][:, :6], traces[1][:, :6]))
+    log(f"small system: {out}")
+    return out
+
+
+def b4_leg(args):
+    """FP64 steps/s of the b = 4 lattices, with the roofline fraction of their
+    dominant product kernel: the 65,536-atom lattice (R_K 12) and the
+    32,768-atom lattice at R_K 12, both with the Mulliken on-site H."""
+    from paper_1404_5776_amd import synth
+
+    sub = argparse.Namespace(**vars(args))
+    sub.steps, sub.warmup = args.b4_steps, 2
+    out = {}
+    for key, make in (("lattice65536_rk12", lambda: synth.config5(n_steps=sub.steps)),
+                      ("lattice32768_rk12", lambda: synth.config3(12.0, n_steps=sub.steps))):
+        t = time.time()
+        s = make()
+        log(f"b4 {key}: generated in {time.time() - t:.1f} s")
+        r = gpu_run(s, sub)
+        stats = r["stats"]
+        dom = max(stats, key=lambda k: stats[k][1])
+        n_l, ms, fl = stats[dom]
+        ach = fl / n_l / (ms / 1e3 / n_l) / 1e12
+        out[key] = {"atoms": s.n_atoms, "b": s.b, "R_HS": s.R_HS, "R_K": s.R_K, "steps": sub.steps,
+                    "steps_per_s": sub.steps / r["elapsed"],
+                    "per_product_ms": {k: v[1] / max(v[0], 1) for k, v in stats.items()},
+                    "roofline": {"bound": "mfma", "kernel": f"k_spgemm_b4j ({dom} product)", "achieved": ach,
+                                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS,
+                                 "avg_launch_ms": ms / n_l, "flops_per_launch": fl / n_l}}
+        log(f"b4 {key}: {out[key]['steps_per_s']:.2f} steps/s, {dom} {out[key]['roofline']['frac']:.3f} of peak")
     return out
 
 
@@ -314,10 +401,13 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="forms use the block-Jacobi inverse start")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-peaks", action="store_true", help="skip the GEMM / copy rate measurement")
-    ap.add_argument("--batch-clusters", type=int, default=32,
+    ap.add_argument("--batch-clusters", type=int, default=64,
                     help="clusters of the batch leg, the first of the 64-cluster list (0: skip)")
-    ap.add_argument("--batch-atoms", type=int, default=24000, help="atoms per batch (kicks counted)")
-    ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--batch-steps", type=int, default=32, help="timed steps of the batch leg")
+    ap.add_argument("--batch-graph-steps", type=int, default=16, help="steps per captured graph, batch leg")
+    ap.add_argument("--small-graph-steps", type=int, default=16,
+                    help="steps per captured graph, 64-atom cluster leg (0: skip the leg)")
+    ap.add_argument("--b4-steps", type=int, default=10, help="timed steps of the b = 4 lattices (0: skip)")
     ap.add_argument("--low-from", type=int, default=3, help="first Taylor order in reduced precision in the *_taylor forms")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (read + write) before the workload, "
@@ -400,6 +490,8 @@ def main():
                    "training_data": "converged inverses (residual 1e-12) of three 216-atom lattices of the "
                                     "same recipe with held-out seeds"}
     batch = batch_leg(args) if args.batch_clusters > 0 else None
+    small = small_leg(args) if args.small_graph_steps > 0 else None
+    b4 = b4_leg(args) if args.b4_steps > 0 else None
     peaks = None if args.no_peaks else measured_peaks()
     if peaks:
         log(f"measured peaks: {peaks}")
@@ -474,6 +566,8 @@ def main():
         "graph": graph,
         "learned_start": learned,
         "batch": batch,
+        "small_system": small,
+        "b4": b4,
         "measured_peaks": peaks,
     }
     print(json.dumps(out))

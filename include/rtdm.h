@@ -251,6 +251,29 @@ int rtdm_build_inverse(rtdm_ctx *ctx, void *hip_stream, int *iters, double *resi
  * the first step is reused.  Asynchronous on hip_stream. */
 int rtdm_step(rtdm_ctx *ctx, double dt, int64_t n_steps, void *hip_stream);
 
+/* Batches of contexts (Sec. II.B: independent propagations, e.g. many systems
+ * and their x/y/z kicks, advanced together).  A batch steps every member
+ * context n_steps times per rtdm_batch_step call with the same dt: whole
+ * groups of graph_steps steps replay one captured HIP graph in which every
+ * context's steps run on a capture branch of their own (so the contexts'
+ * kernels may overlap), launched on hip_stream (when NULL, on a stream of
+ * the batch's that is ordered with the null stream); steps that a captured step cannot repeat (a fixed H's first
+ * step, corrector passes after a kick) and the remainder of n_steps run
+ * eagerly.  Every context then holds what n_steps calls of rtdm_step would
+ * have left (tested bit for bit).  The graph is captured again when dt
+ * changes or a member's own captured steps turn stale.
+ *   create: ctxs = 1..64 distinct contexts of one device (the batch keeps the
+ *           pointers; destroy the batch before them), graph_steps 1..1024.
+ *   step:   every member must be ready to step and have unit_check_every = 0
+ *           (RTDM_E_UNSUPPORTED otherwise: the check needs the host between
+ *           steps).  Returns before the device finishes.  Errors are reported
+ *           by rtdm_batch_last_error, not by the members' rtdm_last_error. */
+typedef struct rtdm_batch rtdm_batch;
+int rtdm_batch_create(rtdm_batch **out, rtdm_ctx *const *ctxs, int n_ctx, int graph_steps);
+int rtdm_batch_step(rtdm_batch *batch, double dt, int64_t n_steps, void *hip_stream);
+const char *rtdm_batch_last_error(const rtdm_batch *batch);
+int rtdm_batch_destroy(rtdm_batch *batch);
+
 /* Observables of the current K: out[0..2] dipole P = -sum_i (r_i - r_c) q_i
  * (Sec. II.B, Mulliken charges q_i = Re sum_j tr(K_ij S_ji), r_c the centroid),
  * out[3] Tr(K S) (Sec. IV), out[4] ||K'-K'^dagger||_F/||K'||_F of the last

@@ -56,8 +56,12 @@ def build_library(verbose: bool = False) -> str:
         cmds.append([hipcc, *compile_flags, "-c", "-I", os.path.join(ROOT, "include"), src, "-o", obj])
     with ThreadPoolExecutor(max_workers=min(8, len(cmds))) as ex:
         list(ex.map(run, cmds))
+    # export the C ABI (rtdm_*) only; every other symbol stays local
+    vscript = os.path.join(objdir, "exports.map")
+    with open(vscript, "w") as f:
+        f.write("{\n  global: rtdm_*;\n  local: *;\n};\n")
     tmp = LIB + ".tmp"
-    run([hipcc, *HIPCC_FLAGS, *objs, "-o", tmp])
+    run([hipcc, *HIPCC_FLAGS, *objs, f"-Wl,--version-script={vscript}", "-o", tmp])
     os.replace(tmp, LIB)
     return LIB
 

@@ -327,6 +327,7 @@ struct rtdm_ctx {
     hipGraph_t graph = nullptr, graph_multi = nullptr;            // one step; opt.graph_steps steps
     hipGraphExec_t gexec = nullptr, gexec_multi = nullptr;
     bool capturing = false;
+    uint64_t graph_epoch = 0;   // advances whenever captured steps of this context turn stale
     double graph_dt = 0.0;
     bool graph_rebuilds_u = false;
     // launch shape of the step products
@@ -919,6 +920,7 @@ void unitarity_sums(rtdm_ctx *c, hipStream_t s)
 
 void drop_graph(rtdm_ctx *c)
 {
+    c->graph_epoch++;
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->gexec_multi) (void)hipGraphExecDestroy(c->gexec_multi);
@@ -1797,20 +1799,30 @@ void step_body(rtdm_ctx *c, double dt, bool rebuild_u, int passes, hipStream_t s
 
 }  // namespace
 
-int rtdm_step(rtdm_ctx *c, double dt, int64_t n_steps, void *stream)
+namespace {
+
+// Host side of one rtdm_step (or rtdm_batch_step) call on one context.
+struct StepCall {
+    rtdm_ctx *c;
+    double dt;
+    int64_t n_steps;
+    hipStream_t s;
+    double t_start;
+    bool vary;
+    int64_t k = 0;   // steps done in this call
+};
+
+void step_ready(rtdm_ctx *c, double dt, int64_t n_steps)
 {
-    if (!c) return RTDM_E_ARG;
-    API_BEGIN
-    set_device(c);
     require(c->ranges_set && c->X_valid && c->uploaded[RTDM_MAT_K] && c->uploaded[RTDM_MAT_H0] &&
                 c->uploaded[RTDM_MAT_S],
             "upload S, H0, K and build (or upload) the inverse first");
     RT_CHECK(std::isfinite(dt) && n_steps >= 0, RTDM_E_ARG, "bad step arguments");
-    hipStream_t s = (hipStream_t)stream;
-    if (c->opt.use_graph && !s) {
-        if (!c->gstream) RT_HIP(hipStreamCreate(&c->gstream));
-        s = c->gstream;
-    }
+}
+
+// Trace room, charges and the device step state for n_steps more steps.
+StepCall step_begin(rtdm_ctx *c, double dt, int64_t n_steps, hipStream_t s)
+{
     ensure_obs(c, c->obs_rows + n_steps);
     ensure_charges(c, s);
     if (c->obs_reset_pending) {
@@ -1818,70 +1830,116 @@ int rtdm_step(rtdm_ctx *c, double dt, int64_t n_steps, void *stream)
         c->obs_reset_pending = false;
     }
     launch_step_begin(s, c->step_st.p, c->step_tt.p, c->t_now, dt);
-    const double t_start = c->t_now;
-    const bool vary = h_varies(c);
-    auto after_step = [&](int64_t k) {
-        c->t_now = t_start + (double)(k + 1) * dt;
-        if (c->opt.unit_check_every > 0 && (c->obs_rows + 1) % c->opt.unit_check_every == 0) {
-            c->prec = RTDM_PREC_FP64;               // the unitarity check stays FP64
-            unitarity_sums(c, s);
-            for (int kk = 0; kk < n_kicks(c); ++kk)   // U is shared: the same value in every kick's trace
-                launch_unit_to_row(s, c->unit_sums.p, c->s_norm2.p, obs_of(c, kk) + 8 * c->obs_rows);
-            if (c->opt.unit_tol > 0.0) {             // monitor: one synchronising read per check
-                double row[8];
-                read_scalars(row, c->obs.p + 8 * c->obs_rows, 8, s);
-                const bool bad = !std::isfinite(row[4]) || !std::isfinite(row[6]) || row[6] > c->opt.unit_tol;
-                if (bad) {
-                    c->obs_rows++;
-                    c->step_count++;
-                    throw Error(RTDM_E_NUMERIC, "step " + std::to_string(c->step_count) + ": unitarity error " +
-                                                    std::to_string(row[6]) + " (tolerance " +
-                                                    std::to_string(c->opt.unit_tol) + ") or Tr(KS) " +
-                                                    std::to_string(row[4]));
-                }
+    return StepCall{c, dt, n_steps, s, c->t_now, h_varies(c)};
+}
+
+// Host bookkeeping after the step k of the call (and the unitarity check or
+// monitor when one is due).
+void after_step(StepCall &sc)
+{
+    rtdm_ctx *c = sc.c;
+    hipStream_t s = sc.s;
+    c->t_now = sc.t_start + (double)(sc.k + 1) * sc.dt;
+    if (c->opt.unit_check_every > 0 && (c->obs_rows + 1) % c->opt.unit_check_every == 0) {
+        c->prec = RTDM_PREC_FP64;               // the unitarity check stays FP64
+        unitarity_sums(c, s);
+        for (int kk = 0; kk < n_kicks(c); ++kk)   // U is shared: the same value in every kick's trace
+            launch_unit_to_row(s, c->unit_sums.p, c->s_norm2.p, obs_of(c, kk) + 8 * c->obs_rows);
+        if (c->opt.unit_tol > 0.0) {             // monitor: one synchronising read per check
+            double row[8];
+            read_scalars(row, c->obs.p + 8 * c->obs_rows, 8, s);
+            const bool bad = !std::isfinite(row[4]) || !std::isfinite(row[6]) || row[6] > c->opt.unit_tol;
+            if (bad) {
+                c->obs_rows++;
+                c->step_count++;
+                throw Error(RTDM_E_NUMERIC, "step " + std::to_string(c->step_count) + ": unitarity error " +
+                                                std::to_string(row[6]) + " (tolerance " +
+                                                std::to_string(c->opt.unit_tol) + ") or Tr(KS) " +
+                                                std::to_string(row[4]));
             }
         }
-        if (c->obs_rows == 0) c->trace_dt = dt;
-        else if (dt != c->trace_dt) c->trace_dt_mixed = true;
-        c->obs_rows++;
-        c->step_count++;
-    };
-    const int sc_passes = 1 + c->opt.sc_iters;
-    auto sc_now = [&]() { return vary && c->opt.sc_iters > 0 && c->step_count < c->opt.sc_steps; };
-    int64_t k = 0;
-    // a fixed H needs its propagator once: build it in an ordinary step
-    while (k < n_steps && (!vary && (!c->U_valid || c->U_dt != dt))) {
-        step_body(c, dt, true, 1, s);
-        after_step(k++);
     }
-    // the first steps after a kick with corrector passes run outside the graph
-    while (k < n_steps && sc_now()) {
-        step_body(c, dt, true, sc_passes, s);
-        after_step(k++);
-    }
-    if (k < n_steps && c->opt.use_graph) {
-        if (c->gexec && (c->graph_dt != dt || c->graph_rebuilds_u != vary)) drop_graph(c);
-        // capture `count` consecutive steps into one graph
-        auto capture = [&](int count, hipGraph_t &graph, hipGraphExec_t &exec) {
-            c->capturing = true;
-            RT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            try {
-                for (int j = 0; j < count; ++j) step_body(c, dt, vary, 1, s);
-            } catch (...) {
-                hipGraph_t g = nullptr;
-                (void)hipStreamEndCapture(s, &g);
-                if (g) (void)hipGraphDestroy(g);
-                c->capturing = false;
-                throw;
+    if (c->obs_rows == 0) c->trace_dt = sc.dt;
+    else if (sc.dt != c->trace_dt) c->trace_dt_mixed = true;
+    c->obs_rows++;
+    c->step_count++;
+    sc.k++;
+}
+
+void eager_step(StepCall &sc)
+{
+    rtdm_ctx *c = sc.c;
+    const bool sc_now = sc.vary && c->opt.sc_iters > 0 && c->step_count < c->opt.sc_steps;
+    step_body(c, sc.dt, sc.vary || !c->U_valid || c->U_dt != sc.dt, sc_now ? 1 + c->opt.sc_iters : 1, sc.s);
+    after_step(sc);
+}
+
+// Steps that cannot be replayed from a captured step: the one that builds a
+// fixed H's propagator, and those with corrector passes after a kick.
+void eager_prefix(StepCall &sc)
+{
+    rtdm_ctx *c = sc.c;
+    while (sc.k < sc.n_steps && !sc.vary && (!c->U_valid || c->U_dt != sc.dt)) eager_step(sc);
+    while (sc.k < sc.n_steps && sc.vary && c->opt.sc_iters > 0 && c->step_count < c->opt.sc_steps)
+        eager_step(sc);
+}
+
+// Record `count` consecutive steps of every context into one graph: each
+// context's steps on a stream of its own forked from s (capture mode
+// thread-local), joined back into s at the end.
+void capture_steps(const std::vector<StepCall *> &calls, const std::vector<hipStream_t> &branch,
+                   const std::vector<hipEvent_t> &ev, int count, hipStream_t s, hipGraph_t &graph,
+                   hipGraphExec_t &exec)
+{
+    const size_t n = calls.size();
+    for (auto *sc : calls) sc->c->capturing = true;
+    RT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    try {
+        if (n == 1) {
+            for (int j = 0; j < count; ++j) step_body(calls[0]->c, calls[0]->dt, calls[0]->vary, 1, s);
+        } else {
+            RT_HIP(hipEventRecord(ev[0], s));
+            for (size_t i = 0; i < n; ++i) {
+                RT_HIP(hipStreamWaitEvent(branch[i], ev[0], 0));
+                for (int j = 0; j < count; ++j) step_body(calls[i]->c, calls[i]->dt, calls[i]->vary, 1, branch[i]);
+                RT_HIP(hipEventRecord(ev[1 + i], branch[i]));
+                RT_HIP(hipStreamWaitEvent(s, ev[1 + i], 0));
             }
-            RT_HIP(hipStreamEndCapture(s, &graph));
-            c->capturing = false;
-            RT_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-        };
+        }
+    } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(s, &g);
+        if (g) (void)hipGraphDestroy(g);
+        for (auto *sc : calls) sc->c->capturing = false;
+        throw;
+    }
+    RT_HIP(hipStreamEndCapture(s, &graph));
+    for (auto *sc : calls) sc->c->capturing = false;
+    RT_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+}
+
+}  // namespace
+
+int rtdm_step(rtdm_ctx *c, double dt, int64_t n_steps, void *stream)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    step_ready(c, dt, n_steps);
+    hipStream_t s = (hipStream_t)stream;
+    if (c->opt.use_graph && !s) {
+        if (!c->gstream) RT_HIP(hipStreamCreate(&c->gstream));
+        s = c->gstream;
+    }
+    StepCall sc = step_begin(c, dt, n_steps, s);
+    eager_prefix(sc);
+    if (sc.k < n_steps && c->opt.use_graph) {
+        if (c->gexec && (c->graph_dt != dt || c->graph_rebuilds_u != sc.vary)) drop_graph(c);
+        const std::vector<StepCall *> one{&sc};
         if (!c->gexec) {
-            capture(1, c->graph, c->gexec);
+            capture_steps(one, {}, {}, 1, s, c->graph, c->gexec);
             c->graph_dt = dt;
-            c->graph_rebuilds_u = vary;
+            c->graph_rebuilds_u = sc.vary;
         }
         // whole groups of graph_steps steps replay one multi-step graph (the
         // step state lives on the device, so the steps of one graph follow
@@ -1889,22 +1947,176 @@ int rtdm_step(rtdm_ctx *c, double dt, int64_t n_steps, void *stream)
         // between steps, so it keeps single-step replays
         const int G = c->opt.graph_steps;
         if (G > 1 && c->opt.unit_check_every == 0) {
-            while (n_steps - k >= G) {
-                if (!c->gexec_multi) capture(G, c->graph_multi, c->gexec_multi);
+            while (n_steps - sc.k >= G) {
+                if (!c->gexec_multi) capture_steps(one, {}, {}, G, s, c->graph_multi, c->gexec_multi);
                 RT_HIP(hipGraphLaunch(c->gexec_multi, s));
-                for (int j = 0; j < G; ++j) after_step(k++);
+                for (int j = 0; j < G; ++j) after_step(sc);
             }
         }
-        for (; k < n_steps; ++k) {
+        while (sc.k < n_steps) {
             RT_HIP(hipGraphLaunch(c->gexec, s));
-            after_step(k);
+            after_step(sc);
         }
     }
-    for (; k < n_steps; ++k) {
-        step_body(c, dt, vary || !c->U_valid || c->U_dt != dt, 1, s);
-        after_step(k);
-    }
+    while (sc.k < n_steps) eager_step(sc);
     API_END(c)
+}
+
+// ------------------------------------------------------------------ batches
+
+struct rtdm_batch {
+    std::vector<rtdm_ctx *> ctx;
+    int device = 0;
+    int graph_steps = 16;
+    std::vector<hipStream_t> branch;   // one capture branch per context
+    std::vector<hipEvent_t> ev;        // fork, then one join per context
+    hipStream_t own = nullptr;         // the call's stream when the caller passes none (blocking)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<uint64_t> epochs;      // graph_epoch of every context at capture
+    std::vector<char> varies;          // every context's H varied (U rebuilt each step) at capture
+    double dt = 0.0;
+    std::string err;
+};
+
+namespace {
+
+static void batch_drop(rtdm_batch *bt)
+{
+    if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+    if (bt->graph) (void)hipGraphDestroy(bt->graph);
+    bt->exec = nullptr;
+    bt->graph = nullptr;
+}
+
+}  // namespace
+
+#define BATCH_BEGIN try {
+#define BATCH_END(bt)                                             \
+    }                                                             \
+    catch (const rtdm::Error &e) {                                \
+        (bt)->err = e.what();                                     \
+        return e.code;                                            \
+    }                                                             \
+    catch (const std::bad_alloc &) {                              \
+        (bt)->err = "host allocation failed";                     \
+        return RTDM_E_OOM;                                        \
+    }                                                             \
+    catch (const std::exception &e) {                             \
+        (bt)->err = e.what();                                     \
+        return RTDM_E_ARG;                                        \
+    }                                                             \
+    (bt)->err.clear();                                            \
+    return RTDM_OK;
+
+int rtdm_batch_create(rtdm_batch **out, rtdm_ctx *const *ctxs, int n_ctx, int graph_steps)
+{
+    if (!out || !ctxs || n_ctx < 1 || n_ctx > 64 || graph_steps < 1 || graph_steps > 1024) return RTDM_E_ARG;
+    *out = nullptr;
+    for (int i = 0; i < n_ctx; ++i) {
+        if (!ctxs[i] || ctxs[i]->device != ctxs[0]->device) return RTDM_E_ARG;
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return RTDM_E_ARG;
+    }
+    auto *bt = new (std::nothrow) rtdm_batch;
+    if (!bt) return RTDM_E_OOM;
+    bt->ctx.assign(ctxs, ctxs + n_ctx);
+    bt->device = ctxs[0]->device;
+    bt->graph_steps = graph_steps;
+    if (hipSetDevice(bt->device) != hipSuccess) {
+        delete bt;
+        return RTDM_E_HIP;
+    }
+    bool ok = true;
+    bt->branch.assign(n_ctx, nullptr);
+    bt->ev.assign(n_ctx + 1, nullptr);
+    for (auto &st : bt->branch) ok = ok && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+    for (auto &e : bt->ev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        rtdm_batch_destroy(bt);
+        return RTDM_E_HIP;
+    }
+    *out = bt;
+    return RTDM_OK;
+}
+
+int rtdm_batch_step(rtdm_batch *bt, double dt, int64_t n_steps, void *stream)
+{
+    if (!bt) return RTDM_E_ARG;
+    BATCH_BEGIN
+    RT_HIP(hipSetDevice(bt->device));
+    hipStream_t s = (hipStream_t)stream;
+    if (!s) {
+        // blocking (ordered with the null stream), so that later null-stream calls see the steps
+        if (!bt->own) RT_HIP(hipStreamCreate(&bt->own));
+        s = bt->own;
+    }
+    for (auto *c : bt->ctx) {
+        step_ready(c, dt, n_steps);
+        RT_CHECK(c->opt.unit_check_every == 0, RTDM_E_UNSUPPORTED,
+                 "batched steps need unit_check_every = 0 (the check runs between steps on the host)");
+    }
+    std::vector<StepCall> calls;
+    calls.reserve(bt->ctx.size());
+    for (auto *c : bt->ctx) {
+        DevMemScope scope(&c->mem);
+        calls.push_back(step_begin(c, dt, n_steps, s));
+        eager_prefix(calls.back());
+    }
+    // the captured part starts where every context has done its eager steps
+    int64_t k0 = 0;
+    for (auto &sc : calls) k0 = std::max(k0, sc.k);
+    for (auto &sc : calls) {
+        DevMemScope scope(&sc.c->mem);
+        while (sc.k < k0) eager_step(sc);
+    }
+    const int G = bt->graph_steps;
+    if (n_steps - k0 >= G) {
+        bool stale = !bt->exec || bt->dt != dt;
+        for (size_t i = 0; i < calls.size() && !stale; ++i)
+            stale = bt->epochs[i] != calls[i].c->graph_epoch || bt->varies[i] != (char)calls[i].vary;
+        if (stale) {
+            batch_drop(bt);
+            std::vector<StepCall *> ptrs;
+            for (auto &sc : calls) ptrs.push_back(&sc);
+            capture_steps(ptrs, bt->branch, bt->ev, G, s, bt->graph, bt->exec);
+            bt->dt = dt;
+            bt->epochs.clear();
+            bt->varies.clear();
+            for (auto &sc : calls) {
+                bt->epochs.push_back(sc.c->graph_epoch);
+                bt->varies.push_back((char)sc.vary);
+            }
+        }
+        while (n_steps - calls[0].k >= G) {
+            RT_HIP(hipGraphLaunch(bt->exec, s));
+            for (auto &sc : calls)
+                for (int j = 0; j < G; ++j) after_step(sc);
+        }
+    }
+    // the rest as eager steps (a captured graph of fewer steps would be used once)
+    for (auto &sc : calls) {
+        DevMemScope scope(&sc.c->mem);
+        while (sc.k < n_steps) eager_step(sc);
+    }
+    BATCH_END(bt)
+}
+
+const char *rtdm_batch_last_error(const rtdm_batch *bt) { return bt ? bt->err.c_str() : "null batch"; }
+
+int rtdm_batch_destroy(rtdm_batch *bt)
+{
+    if (!bt) return RTDM_OK;
+    (void)hipSetDevice(bt->device);
+    batch_drop(bt);
+    for (auto st : bt->branch)
+        if (st) (void)hipStreamDestroy(st);
+    for (auto e : bt->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (bt->own) (void)hipStreamDestroy(bt->own);
+    delete bt;
+    return RTDM_OK;
 }
 
 int rtdm_ground_state(rtdm_ctx *c, double n_occ, double tol, int max_iter, void *stream, int *iters_out,

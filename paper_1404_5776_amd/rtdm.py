@@ -37,7 +37,8 @@ EXPORTED = ["rtdm_default_options", "rtdm_create", "rtdm_destroy", "rtdm_set_geo
             "rtdm_timing", "rtdm_timing_stats", "rtdm_inverse_info", "rtdm_mlp_params", "rtdm_mlp_init",
             "rtdm_mlp_set_weights", "rtdm_mlp_get_weights", "rtdm_mlp_collect", "rtdm_mlp_clear",
             "rtdm_mlp_train", "rtdm_mlp_loss_grad", "rtdm_mlp_step", "rtdm_mlp_predict", "rtdm_set_groups",
-            "rtdm_apply_kick_groups", "rtdm_group_trace", "rtdm_apply_kicks", "rtdm_select_kick", "rtdm_autotune", "rtdm_set_field",
+            "rtdm_apply_kick_groups", "rtdm_group_trace", "rtdm_apply_kicks", "rtdm_select_kick",
+            "rtdm_batch_create", "rtdm_batch_step", "rtdm_batch_last_error", "rtdm_batch_destroy", "rtdm_autotune", "rtdm_set_field",
             "rtdm_spectrum", "rtdm_workspace_size", "rtdm_bind_workspace", "rtdm_ground_state",
             "rtdm_get_state", "rtdm_set_state", "rtdm_last_error"]
 
@@ -106,6 +107,10 @@ def load():
         "rtdm_apply_kick_groups": [P, P, P],
         "rtdm_group_trace": [P, P, I64, P],
         "rtdm_apply_kicks": [P, P, P],
+        "rtdm_batch_create": [P, P, I, I],
+        "rtdm_batch_step": [P, D, I64, P],
+        "rtdm_batch_last_error": [P],
+        "rtdm_batch_destroy": [P],
         "rtdm_select_kick": [P, I],
         "rtdm_autotune": [P, P, P, P],
         "rtdm_set_field": [P, P, D, D],
@@ -120,7 +125,7 @@ def load():
     for name, args in sig.items():
         f = getattr(L, name)
         f.argtypes = args
-        f.restype = ctypes.c_char_p if name == "rtdm_last_error" else ctypes.c_int
+        f.restype = ctypes.c_char_p if name in ("rtdm_last_error", "rtdm_batch_last_error") else ctypes.c_int
     _lib = L
     return L
 
@@ -389,6 +394,26 @@ def rtdm_apply_kick_groups(ctx, kappa, stream=None) -> None:
 def rtdm_apply_kicks(ctx, kappas, stream=None) -> None:
     k = np.ascontiguousarray(kappas, dtype=np.float64).reshape(-1)
     _check(ctx, load().rtdm_apply_kicks(ctx, _p(k), _stream(stream)))
+
+
+def rtdm_batch_create(ctxs, graph_steps: int = 16):
+    arr = (ctypes.c_void_p * len(ctxs))(*[c.value if isinstance(c, ctypes.c_void_p) else c for c in ctxs])
+    h = ctypes.c_void_p()
+    rc = load().rtdm_batch_create(ctypes.byref(h), arr, len(ctxs), int(graph_steps))
+    if rc != 0:
+        raise RtdmError(rc, "rtdm_batch_create failed")
+    return h
+
+
+def rtdm_batch_step(batch, dt: float, n_steps: int, stream=None) -> None:
+    rc = load().rtdm_batch_step(batch, float(dt), int(n_steps), _stream(stream))
+    if rc != 0:
+        m = load().rtdm_batch_last_error(batch)
+        raise RtdmError(rc, m.decode() if m else "")
+
+
+def rtdm_batch_destroy(batch) -> None:
+    load().rtdm_batch_destroy(batch)
 
 
 def rtdm_select_kick(ctx, k: int) -> None:

@@ -443,6 +443,32 @@ def config4_cluster(k: int, seed: int = 4) -> System:
     return random_cluster(n, b, 8.0, 12.0, seed * 1000 + k, n_steps=100, h_model="fixed")
 
 
+def _one_blas_thread():
+    """Worker set-up: one BLAS thread per process (the pool supplies the parallelism)."""
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1)
+
+
+def config4_all(seed: int = 4, n_clusters: int = 64, workers: int = 0) -> List[System]:
+    """The first n_clusters clusters of the 64-cluster list, generated in
+    worker processes (spawned, so a parent that already uses the GPU is not
+    forked); workers 0 means one per CPU, at most 16."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    import os
+    if workers <= 0:
+        workers = min(16, os.cpu_count() or 1)
+    if workers == 1 or n_clusters <= 1:
+        return [config4_cluster(k, seed) for k in range(n_clusters)]
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn"),
+                                initializer=_one_blas_thread) as ex:
+        # largest first, so the long ones do not finish last
+        sizes = config4_sizes(seed)[:n_clusters]
+        order = sorted(range(n_clusters), key=lambda k: -sizes[k][0] * sizes[k][1])
+        futs = {k: ex.submit(config4_cluster, k, seed) for k in order}
+        return [futs[k].result() for k in range(n_clusters)]
+
+
 def config5(seed: int = 5, cells=(16, 16, 32), n_steps: int = 100) -> System:
     """65,536-atom lattice, b=4, R_HS 10, R_K 12, Mulliken H."""
     return diamond_lattice(cells, 4, 10.0, 12.0, seed, n_steps=n_steps, h_model="mulliken")

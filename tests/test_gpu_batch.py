@@ -142,3 +142,77 @@ def test_sixteen_step_graphs_equal_eager_steps_over_a_long_run():
     K_g, tr_g = _run(s, (100,), True)
     assert np.array_equal(K_e, K_g)
     assert np.array_equal(tr_e[:, :6], tr_g[:, :6])
+
+
+def _members():
+    """Contexts of differing kinds: b = 4 and b = 13 kick sets (fixed H: the
+    first step builds U eagerly), a Mulliken-H b = 13 lattice with two
+    corrector steps after the kick (eager too), and an ETRS b = 4 lattice."""
+    kicks = [(0.01, 0, 0), (0, 0.01, 0), (0, 0, 0.01)]
+    out = []
+    for b in (4, 13):
+        ctx = rtdm.Context(0, h_model="fixed", n_kicks=3)
+        ctx.load_kick_sets(small_clusters(b), kicks)
+        rtdm.rtdm_build_inverse(ctx.h)
+        rtdm.rtdm_apply_kicks(ctx.h, ctx.kick_vectors)
+        out.append(ctx)
+    s13 = synth.diamond_lattice((2, 2, 2), 13, 10.0, 16.0, seed=25, k0="local", h_model="mulliken")
+    s4 = synth.diamond_lattice((3, 3, 3), 4, 10.0, 12.0, seed=26, h_model="mulliken")
+    for s, opts in ((s13, dict(h_model="mulliken", sc_steps=2, sc_iters=1)),
+                    (s4, dict(h_model="mulliken", propagator="etrs"))):
+        ctx = gpu_context(s, **opts)
+        rtdm.rtdm_build_inverse(ctx.h)
+        rtdm.rtdm_apply_kick(ctx.h, s.kappa)
+        out.append(ctx)
+    return out
+
+
+def _state(ctx):
+    out = []
+    for k in range(ctx.options.n_kicks):
+        rtdm.rtdm_select_kick(ctx.h, k)
+        out.append((rtdm.rtdm_download(ctx.h, "K", ctx.b), rtdm.rtdm_dipole_trace(ctx.h)[:, :6]))
+    return out
+
+
+def test_batch_step_equals_separate_steps():
+    """One batch stepping four unlike contexts (4-step graphs, calls of 6 and
+    11 steps: eager first steps, two and then one graph replay, an eager
+    rest) leaves each context bit for bit where rtdm_step leaves it."""
+    print("[gpu] batch of contexts vs separate rtdm_step calls", flush=True)
+    dt, chunks = 0.05, (6, 11)
+    ref = []
+    for ctx in _members():
+        for n in chunks:
+            rtdm.rtdm_step(ctx.h, dt, n)
+        ref.append(_state(ctx))
+        ctx.close()
+    ctxs = _members()
+    bt = rtdm.rtdm_batch_create([c.h for c in ctxs], graph_steps=4)
+    try:
+        for n in chunks:
+            rtdm.rtdm_batch_step(bt, dt, n)
+            rtdm.rtdm_observables(ctxs[0].h)   # eager work and a synchronisation between calls
+        got = [_state(c) for c in ctxs]
+    finally:
+        rtdm.rtdm_batch_destroy(bt)
+    for i, (r, g) in enumerate(zip(ref, got)):
+        for k, ((Kr, tr), (Kg, tg)) in enumerate(zip(r, g)):
+            assert tr.shape == tg.shape == (sum(chunks), 6), (i, k)
+            assert np.array_equal(Kr, Kg), (i, k)
+            assert np.array_equal(tr, tg), (i, k)
+    for c in ctxs:
+        c.close()
+
+
+def test_batch_step_refuses_unitarity_checks():
+    s = synth.config1()
+    ctx = gpu_context(s, unit_check_every=1)
+    rtdm.rtdm_build_inverse(ctx.h)
+    bt = rtdm.rtdm_batch_create([ctx.h])
+    try:
+        with pytest.raises(rtdm.RtdmError, match="unit_check_every"):
+            rtdm.rtdm_batch_step(bt, s.dt, 2)
+    finally:
+        rtdm.rtdm_batch_destroy(bt)
+        ctx.close()
