@@ -280,8 +280,9 @@ def b4_leg(args):
     sub = argparse.Namespace(**vars(args))
     sub.steps, sub.warmup = args.b4_steps, 2
     out = {}
-    for key, make in (("lattice65536_rk12", lambda: synth.config5(n_steps=sub.steps)),
-                      ("lattice32768_rk12", lambda: synth.config3(12.0, n_steps=sub.steps))):
+    makers = {"65536": ("lattice65536_rk12", lambda: synth.config5(n_steps=sub.steps)),
+              "32768": ("lattice32768_rk12", lambda: synth.config3(12.0, n_steps=sub.steps))}
+    for key, make in (makers[k] for k in args.b4_lattices.split(",") if k):
         t = time.time()
         s = make()
         log(f"b4 {key}: generated in {time.time() - t:.1f} s")
@@ -408,6 +409,9 @@ def main():
     ap.add_argument("--small-graph-steps", type=int, default=16,
                     help="steps per captured graph, 64-atom cluster leg (0: skip the leg)")
     ap.add_argument("--b4-steps", type=int, default=10, help="timed steps of the b = 4 lattices (0: skip)")
+    ap.add_argument("--b4-lattices", default="65536,32768", help="b = 4 lattices to run (atom counts)")
+    ap.add_argument("--leg", choices=["batch", "small", "b4"], default=None,
+                    help="run only this leg of the benchmark and print its JSON object (for profiling)")
     ap.add_argument("--low-from", type=int, default=3, help="first Taylor order in reduced precision in the *_taylor forms")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (read + write) before the workload, "
@@ -444,6 +448,12 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: 3 elementwise copies of {args.calibrate_copy} MiB")
         del x, y
+
+    if args.leg:
+        import torch
+        torch.cuda.init()
+        print(json.dumps({"leg": args.leg, **{"batch": batch_leg, "small": small_leg, "b4": b4_leg}[args.leg](args)}))
+        return
 
     t = time.time()
     s = make_workload(args)

@@ -170,16 +170,18 @@ __global__ __launch_bounds__(kT) void k_mulliken(int64_t n_atoms, int b,
     const int64_t i = (int64_t)blockIdx.x * (kT / 64) + (threadIdx.x >> 6);
     if (i >= n_atoms) return;
     const int bb = b * b;
+    // the row's (block, element) pairs flattened, 64 per pass, so every lane
+    // works and a pass has 64 independent loads (b = 4: four blocks at once)
+    const int64_t p0 = s_ptr[i];
+    const int64_t nel = (s_ptr[i + 1] - p0) * bb;
     double acc = 0.0;
-    for (int64_t p = s_ptr[i]; p < s_ptr[i + 1]; ++p) {
+    for (int64_t x = lane; x < nel; x += 64) {
+        const int64_t p = p0 + x / bb;
+        const int w = (int)(x % bb);
         const int kb = s_to_k[p];
         if (kb < 0) continue;
-        const int64_t st = (int64_t)s_trans[p] * bb;
-        const int64_t kk = (int64_t)kb * bb;
-        for (int w = lane; w < bb; w += 64) {
-            const int a = w / b, c = w - a * b;
-            acc += kr[kk + w] * sv[st + c * b + a];
-        }
+        const int a = w / b, c = w - a * b;
+        acc += kr[(int64_t)kb * bb + w] * sv[(int64_t)s_trans[p] * bb + c * b + a];
     }
     acc = wave_sum(acc);
     if (lane == 0) q[i] = acc;

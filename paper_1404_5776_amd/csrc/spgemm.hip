@@ -1196,10 +1196,101 @@ __global__ __launch_bounds__(256) void k_spgemm_b4j(
     }
 }
 
+// The same product for products with few runs (small systems): one
+// workgroup per run, its four waves taking every fourth entry (wave w the
+// entries w, w + 4, ...), so that a run's chain of dependent loads is a
+// quarter as long and four times as many waves share the chip.  The waves'
+// partial sums are added in LDS in the fixed order w = 0, 1, 2, 3.
+template <bool AC, bool BC, int OPB>
+__global__ __launch_bounds__(256) void k_spgemm_b4js(
+    int64_t nch, const int64_t *__restrict__ off, const int32_t *__restrict__ ea,
+    const int32_t *__restrict__ eb, const int32_t *__restrict__ cout, const double *__restrict__ ar,
+    const double *__restrict__ ai, const double *__restrict__ br, const double *__restrict__ bi,
+    double *__restrict__ cr, double *__restrict__ ci, double alr, double ali)
+{
+    constexpr int NACC = 1 + (AC && BC) + BC + AC;   // accumulators per output: rr, ii, ri, ir
+    __shared__ double part[3][NACC * 4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int g = (lane >> 2) & 3, r = lane & 3, q = lane >> 4;
+    const int64_t c = blockIdx.x;              // grid = nch: uniform across the workgroup
+    const int ia = r * 4 + q;
+    const int ib = OPB ? (r * 4 + q) : (q * 4 + r);
+    const double cb = OPB ? -1.0 : 1.0;
+    const int64_t e0 = off[c], e1 = off[c + 1];
+    double rr[4] = {0, 0, 0, 0}, ii[4] = {0, 0, 0, 0}, ri[4] = {0, 0, 0, 0}, ir[4] = {0, 0, 0, 0};
+    for (int64_t e = e0 + wv; e < e1; e += 4) {
+        const int64_t pa = (int64_t)ea[e] * 16 + ia;
+        const double xar = ar[pa];
+        const double xai = AC ? ai[pa] : 0.0;
+        const int4 kb4 = *reinterpret_cast<const int4 *>(eb + e * 16 + g * 4);
+        const int kb[4] = {kb4.x, kb4.y, kb4.z, kb4.w};
+        double xbr[4], xbi[4];
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            xbr[jj] = xbi[jj] = 0.0;
+            if (kb[jj] >= 0) {
+                const int64_t pb = (int64_t)kb[jj] * 16 + ib;
+                xbr[jj] = br[pb];
+                if (BC) xbi[jj] = cb * bi[pb];
+            }
+        }
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            rr[jj] = __builtin_amdgcn_mfma_f64_4x4x4f64(xar, xbr[jj], rr[jj], 0, 0, 0);
+            if (AC && BC) ii[jj] = __builtin_amdgcn_mfma_f64_4x4x4f64(xai, xbi[jj], ii[jj], 0, 0, 0);
+            if (BC) ri[jj] = __builtin_amdgcn_mfma_f64_4x4x4f64(xar, xbi[jj], ri[jj], 0, 0, 0);
+            if (AC) ir[jj] = __builtin_amdgcn_mfma_f64_4x4x4f64(xai, xbr[jj], ir[jj], 0, 0, 0);
+        }
+    }
+    auto pack = [&](double (*dst)[64]) {
+        int k = 0;
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            dst[k++][lane] = rr[jj];
+            if (AC && BC) dst[k++][lane] = ii[jj];
+            if (BC) dst[k++][lane] = ri[jj];
+            if (AC) dst[k++][lane] = ir[jj];
+        }
+    };
+    if (wv > 0) pack(part[wv - 1]);
+    __syncthreads();
+    if (wv != 0) return;
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+        int k = 0;
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            rr[jj] += part[w][k++][lane];
+            if (AC && BC) ii[jj] += part[w][k++][lane];
+            if (BC) ri[jj] += part[w][k++][lane];
+            if (AC) ir[jj] += part[w][k++][lane];
+        }
+    }
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+        const int p = cout[c * 16 + 4 * jj + g];
+        if (p >= 0) {
+            const double re = rr[jj] - ii[jj], im = ri[jj] + ir[jj];
+            const int64_t o = (int64_t)p * 16 + q * 4 + r;
+            cr[o] = alr * re - ali * im;
+            if (ci) ci[o] = alr * im + ali * re;
+        }
+    }
+}
+
+// Below this many runs a product takes the split form (one run per
+// workgroup): a wave per run would leave most of the 1,024 SIMDs idle.
+constexpr int64_t kB4SplitRuns = 4096;
+
 template <bool AC, bool BC, int OB>
 static void launch_b4j(hipStream_t s, const SpgemmArgs &a)
 {
     RT_CHECK(a.nj == 16, RTDM_E_ARG, "b = 4 row runs hold 16 outputs");
+    if (a.nch < kB4SplitRuns) {
+        hipLaunchKernelGGL((k_spgemm_b4js<AC, BC, OB>), dim3((unsigned)a.nch), dim3(256), 0, s, a.nch, a.ch_off,
+                           a.ch_a, a.ch_b, a.ch_out, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re, a.alpha_im);
+        return;
+    }
     const int remap = b4_chunk();
     hipLaunchKernelGGL((k_spgemm_b4j<AC, BC, OB>), dim3(xcd_grid((a.nch + 3) / 4, remap)), dim3(256), 0, s,
                        a.nch, a.ch_off, a.ch_a, a.ch_b, a.ch_out, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re,
