@@ -515,6 +515,20 @@ def main():
     tot_ms = sum(v[1] for v in stats.values())
     flops_per_step = tot_fl / args.steps
 
+    traffic = measured_traffic(dom)
+    roofline = {"bound": "mfma", "kernel": f"k_spgemm_q4j<13, NJ=2> ({dom} product)", "achieved": achieved,
+                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                "traffic": traffic, "traffic_unit": "bytes per launch",
+                "avg_launch_ms": avg_s * 1e3, "flops_per_launch": fl / n_l}
+    if traffic is not None:
+        # the roof that binds in practice: bytes beyond L2 (hardware counters of this
+        # kernel build) per launch over this run's launch time, against the copy rate
+        rate = traffic / avg_s / 1e9
+        roofline["beyond_l2_gb_per_s"] = rate
+        roofline["beyond_l2_frac_of_hbm_peak"] = rate / 8000.0
+        if peaks:
+            roofline["beyond_l2_frac_of_measured_copy"] = rate / peaks["copy_gb_per_s"]
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import oracle as O
@@ -564,11 +578,7 @@ def main():
         "spgemm_tflop_per_step": flops_per_step / 1e12,
         "accuracy": "FP64 path; equals the FP64 oracle within 1e-10 relative in the parity tests, "
                     "so its dipole error vs FP64 is at that level",
-        "roofline": {"bound": "mfma", "kernel": f"k_spgemm_q4j<13, NJ=2> ({dom} product)", "achieved": achieved,
-                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": measured_traffic(dom), "traffic_unit": "bytes per launch",
-                     "avg_launch_ms": avg_s * 1e3,
-                     "flops_per_launch": fl / n_l},
+        "roofline": roofline,
         "per_product_ms": {k: v[1] / max(v[0], 1) for k, v in stats.items()},
         "trace_last": trace[-1, :6].tolist() if len(trace) else None,
         "cpu_baseline": cpu,

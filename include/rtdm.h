@@ -190,16 +190,30 @@ int rtdm_create(rtdm_ctx **out, int hip_device, const rtdm_options *opt);
 /* Release every host and device resource of ctx (NULL is accepted). */
 int rtdm_destroy(rtdm_ctx *ctx);
 
-/* Set the atoms: xyz[n][3] (bohr, host, copied) and nbf[n] functions per atom.
- * This build requires every nbf[i] to be equal and in 1..16
- * (RTDM_E_UNSUPPORTED otherwise).  Invalidates ranges, matrices and schedules. */
+/* Set the atoms: xyz[n][3] (bohr, host, copied) and nbf[n] functions per atom
+ * (each in 1..16; the basis may differ per element, Sec. III).  With unequal
+ * sizes the largest must be 4 or 13: every block is stored padded to that
+ * size b, S and X carry the identity on an atom's padded functions and every
+ * other matrix zeros, so the padded functions never mix with the atom's own
+ * (all products act on them as on a separate identity block) and the
+ * results on the real functions are those of the unpadded method.  Mixed
+ * sizes need the FP64 exponential-midpoint step without corrector passes and
+ * the block-Jacobi or previous inverse start (RTDM_E_UNSUPPORTED otherwise,
+ * and for the external field, the ground state and training samples).  The
+ * caller's blocks are then nbf_i x nbf_j (row-major) in every upload and
+ * download.  Invalidates ranges, matrices and schedules. */
 int rtdm_set_geometry(rtdm_ctx *ctx, int64_t n_atoms, const double *xyz, const int32_t *nbf);
 
 /* Set the cut-off radii (Sec. II.A, Sec. V.A): R_HS for S and H, R_P for
  * S^-1, S^-1 H and U, R_K for K (R_P <= 0 selects max(R_HS, R_K)).  Builds the
- * neighbour lists of each range and the symbolic schedules of every product
- * of RTDM_PROD_* (on the device; the triple counts are then fixed).  Zeroes
- * every matrix.  Synchronises the device. */
+ * neighbour lists of each range and the symbolic schedules (on the device;
+ * the triple counts are then fixed) of the step's and the inverse's products
+ * (XH, AT, UK, WU, SX), and of UV when the options check unitarity during
+ * steps, so that rtdm_step allocates nothing.  UV otherwise (first
+ * rtdm_unitarity or rtdm_observables after a step) and ZX (first
+ * rtdm_ground_state) are scheduled on first use, in a bound workspace from
+ * its reserve (RTDM_E_OOM when that is too small).  Zeroes every matrix.
+ * Synchronises the device. */
 int rtdm_set_ranges(rtdm_ctx *ctx, double R_HS, double R_P, double R_K);
 
 /* Pattern of a slot's range: CSR over atoms, *row_ptr has n+1 entries and
@@ -208,7 +222,8 @@ int rtdm_set_ranges(rtdm_ctx *ctx, double R_HS, double R_P, double R_K);
 int rtdm_pattern(rtdm_ctx *ctx, rtdm_mat mat, int64_t *n_rows, int64_t *nnzb,
                  const int64_t **row_ptr, const int32_t **col_idx);
 
-/* Upload a slot from blocks in rtdm_pattern order (nnzb blocks of b*b).
+/* Upload a slot from blocks in rtdm_pattern order (nnzb blocks of b*b, or of
+ * nbf_i*nbf_j with mixed sizes, host data only).
  * is_complex: 1 = complex128 interleaved, 0 = double.  is_device: data is a
  * device pointer (1) or host pointer (0).  Real slots (S, H0, H, X, A) refuse
  * complex data whose imaginary part is not zero (RTDM_E_UNSUPPORTED).
@@ -217,14 +232,15 @@ int rtdm_upload(rtdm_ctx *ctx, rtdm_mat mat, const void *data, int is_complex,
                 int is_device, void *hip_stream);
 
 /* Upload a slot from host blocks in any order: rows[t], cols[t] name the
- * atom pair of block t (nnzb blocks of b*b, complex128 if is_complex else
- * double).  Blocks absent from the list are zero; a pair outside the slot's
+ * atom pair of block t (nnzb blocks of b*b, or nbf_i*nbf_j with mixed sizes,
+ * concatenated; complex128 if is_complex else double).  Blocks absent from the list are zero; a pair outside the slot's
  * range is RTDM_E_ARG.  Synchronises the stream. */
 int rtdm_upload_coo(rtdm_ctx *ctx, rtdm_mat mat, int64_t nnzb, const int32_t *rows,
                     const int32_t *cols, const void *data, int is_complex, void *hip_stream);
 
 /* Download a slot as complex128 interleaved blocks in rtdm_pattern order
- * (real slots get zero imaginary parts) into dst (host or device).
+ * (real slots get zero imaginary parts) into dst (host or device; with mixed
+ * sizes host only, blocks of nbf_i*nbf_j concatenated).
  * Synchronises the stream. */
 int rtdm_download(rtdm_ctx *ctx, rtdm_mat mat, void *dst, int is_device, void *hip_stream);
 
@@ -336,6 +352,29 @@ int rtdm_workspace_size(rtdm_ctx *ctx, size_t *bytes);
  * ranges are fixed (RTDM_E_STATE); a captured step graph is rebuilt.  Binding
  * twice is RTDM_E_STATE.  Synchronises the device. */
 int rtdm_bind_workspace(rtdm_ctx *ctx, void *ptr, size_t bytes);
+/* Device memory from the caller's allocator (e.g. PyTorch's caching
+ * allocator): from now on every buffer of the context is alloc_fn(bytes,
+ * user) (NULL means out of memory: RTDM_E_OOM; 256-byte alignment required)
+ * and is given back with free_fn(ptr, user) when the context releases it
+ * (set-up calls, destroy; never inside rtdm_step).  The buffers allocated so
+ * far move into such allocations.  Once per context (RTDM_E_STATE after that
+ * or while a workspace is bound); free_fn must stay callable until
+ * rtdm_destroy returns.  Called from the thread of the API call that
+ * allocates.  Synchronises the device. */
+int rtdm_set_allocator(rtdm_ctx *ctx, void *(*alloc_fn)(size_t bytes, void *user),
+                       void (*free_fn)(void *ptr, void *user), void *user);
+/* Move every device buffer of the context out of the bound region into
+ * allocations of the library's own (the region may be freed afterwards), so
+ * that the geometry and ranges can be set again, e.g. to load another system
+ * and bind a region of its size (the caller's allocator's, if one is set).  A captured step graph is rebuilt.
+ * RTDM_E_STATE without a bound workspace; RTDM_E_OOM (the context stays bound
+ * as it was) when the allocations fail.  Synchronises the device. */
+int rtdm_unbind_workspace(rtdm_ctx *ctx);
+/* Room in the observable trace for `rows` rows in all (every kick set and
+ * group), so that steps up to that count allocate nothing; rtdm_step grows
+ * the trace itself (from the bound workspace, if any) when a call needs more.
+ * The default after set-up is 1,024 rows. */
+int rtdm_reserve_trace(rtdm_ctx *ctx, int64_t rows);
 
 /* External field of Gaussian time profile (Sec. II.B, linear response):
  * E(t) = E0 exp(-(t - t0)^2 / (2 sigma^2)) enters H(t) as the electrons'

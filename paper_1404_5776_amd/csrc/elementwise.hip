@@ -203,26 +203,27 @@ void launch_mulliken(hipStream_t s, int64_t n_atoms, int b, const int64_t *s_ptr
 // extrapolation (q_x, q_y) = (q(t), q(t - dt)) or interpolation
 // (q(t + dt), q(t)), q_a = q(t).
 __global__ void k_onsite_shift(int64_t n_atoms, int b, const int32_t *__restrict__ diag,
-                               double gain, const double *__restrict__ q_a, double theta,
-                               const double *__restrict__ q_x, const double *__restrict__ q_y,
+                               const int32_t *__restrict__ nbf, double gain, const double *__restrict__ q_a,
+                               double theta, const double *__restrict__ q_x, const double *__restrict__ q_y,
                                const double *__restrict__ q_ref, double *__restrict__ h)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n_atoms * b) return;
     const int64_t i = e / b;
     const int a = (int)(e % b);
+    if (nbf && a >= nbf[i]) return;            // a padded function of a smaller atom
     const double q = q_a[i] + theta * (q_x[i] - q_y[i]);
     h[(int64_t)diag[i] * b * b + a * b + a] += gain * (q - q_ref[i]);
 }
 
-void launch_onsite_shift(hipStream_t s, int64_t n_atoms, int b, const int32_t *diag, double gain,
+void launch_onsite_shift(hipStream_t s, int64_t n_atoms, int b, const int32_t *diag, const int32_t *nbf, double gain,
                          const double *q_a, double theta, const double *q_x, const double *q_y,
                          const double *q_ref, double *h)
 {
     const int64_t n = n_atoms * b;
     if (n == 0) return;
     hipLaunchKernelGGL(k_onsite_shift, dim3((unsigned)((n + kT - 1) / kT)), dim3(kT), 0, s, n_atoms,
-                       b, diag, gain, q_a, theta, q_x, q_y, q_ref, h);
+                       b, diag, nbf, gain, q_a, theta, q_x, q_y, q_ref, h);
     RT_HIP(hipGetLastError());
 }
 
@@ -897,4 +898,17 @@ void launch_interleave(hipStream_t s, int64_t n, const double *re, const double 
     RT_HIP(hipGetLastError());
 }
 
+// x[0] += v (one thread): a device scalar corrected in stream order.
+__global__ void k_add_scalar(double *x, double v)
+{
+    if (threadIdx.x == 0) x[0] += v;
+}
+
+void launch_add_scalar(hipStream_t s, double *x, double v)
+{
+    hipLaunchKernelGGL(k_add_scalar, dim3(1), dim3(64), 0, s, x, v);
+    RT_HIP(hipGetLastError());
+}
+
 }  // namespace rtdm
+

@@ -32,15 +32,19 @@ struct Error : std::runtime_error {
     } while (0)
 
 // Device memory of one context.  Every buffer the context allocates is
-// registered here.  Without a bound workspace a buffer owns a hipMalloc
-// allocation; once the caller binds a workspace (rtdm_bind_workspace) every
-// registered buffer is moved into it and later allocations are 256-byte
-// aligned slices of it, taken in order (a released slice is not reused).
+// registered here.  A buffer owns an allocation of the caller's allocator
+// (rtdm_set_allocator) or, without one, a hipMalloc allocation; once the
+// caller binds a workspace (rtdm_bind_workspace) every registered buffer is
+// moved into it and later allocations are 256-byte aligned slices of it,
+// taken in order (a released slice is reused only when it is the last one).
 struct DBufBase;
 struct DevMem {
     std::unordered_set<DBufBase *> bufs;
     char *base = nullptr;
     size_t cap = 0, used = 0;
+    void *(*ext_alloc)(size_t bytes, void *user) = nullptr;   // the caller's allocator, if set
+    void (*ext_free)(void *ptr, void *user) = nullptr;
+    void *ext_user = nullptr;
 };
 // The context of the API call in progress on this thread (null outside calls).
 extern thread_local DevMem *g_devmem;
@@ -48,6 +52,7 @@ extern thread_local DevMem *g_devmem;
 struct DBufBase {
     DevMem *mem = nullptr;   // registry the buffer belongs to (null: unregistered)
     bool in_ws = false;      // the memory is a slice of a bound workspace
+    bool ext = false;        // the memory came from the caller's allocator
     size_t nbytes = 0;
     virtual void *raw() const = 0;
     virtual void set_raw(void *p) = 0;
@@ -94,6 +99,7 @@ private:
         n = o.n;
         mem = o.mem;
         in_ws = o.in_ws;
+        ext = o.ext;
         nbytes = o.nbytes;
         devmem_moved(&o, this);
         o.p = nullptr;
@@ -194,7 +200,8 @@ void launch_mulliken(hipStream_t s, int64_t n_atoms, int b, const int64_t *s_ptr
                      const int32_t *s_trans, const int32_t *s_to_k, const double *sv,
                      const double *kr, double *q);
 // H[diag] += gain*(q_a + theta (q_x - q_y) - q_ref) on the diagonal elements.
-void launch_onsite_shift(hipStream_t s, int64_t n_atoms, int b, const int32_t *diag, double gain,
+void launch_add_scalar(hipStream_t s, double *x, double v);
+void launch_onsite_shift(hipStream_t s, int64_t n_atoms, int b, const int32_t *diag, const int32_t *nbf, double gain,
                          const double *q_a, double theta, const double *q_x, const double *q_y,
                          const double *q_ref, double *h);
 void launch_field(hipStream_t s, int64_t nnzb, int b, const int32_t *rowof, const int32_t *col,

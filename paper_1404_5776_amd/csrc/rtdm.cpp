@@ -43,6 +43,13 @@ void *devmem_alloc(DBufBase *b, size_t bytes)
         p = m->base + off;
         m->used = off + bytes;
         b->in_ws = true;
+    } else if (m && m->ext_alloc) {
+        p = m->ext_alloc(bytes, m->ext_user);
+        RT_CHECK(p, RTDM_E_OOM, "the caller's allocator refused " + std::to_string(bytes) + " bytes");
+        RT_CHECK((reinterpret_cast<uintptr_t>(p) & 255) == 0, RTDM_E_ARG,
+                 "the caller's allocator returned memory that is not 256-byte aligned");
+        b->in_ws = false;
+        b->ext = true;
     } else {
         hipError_t e = hipMalloc(&p, bytes);
         if (e != hipSuccess) {
@@ -50,6 +57,7 @@ void *devmem_alloc(DBufBase *b, size_t bytes)
             throw Error(RTDM_E_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
         }
         b->in_ws = false;
+        b->ext = false;
     }
     b->mem = m;
     b->nbytes = bytes;
@@ -64,6 +72,8 @@ void devmem_free(DBufBase *b, void *p)
         // the most recent slice (a temporary of the current call) is given back
         if (m && static_cast<char *>(p) + b->nbytes == m->base + m->used)
             m->used = (size_t)(static_cast<char *>(p) - m->base);
+    } else if (b->ext) {
+        m->ext_free(p, m->ext_user);
     } else {
         (void)hipFree(p);
     }
@@ -71,6 +81,7 @@ void devmem_free(DBufBase *b, void *p)
     b->mem = nullptr;
     b->nbytes = 0;
     b->in_ws = false;
+    b->ext = false;
 }
 
 void devmem_moved(DBufBase *from, DBufBase *to)
@@ -272,6 +283,12 @@ struct rtdm_ctx {
     int b = 0;
     std::vector<double> xyz;
     DBuf<double> d_xyz;
+    // per-atom block sizes: atoms with fewer than b functions are padded to b
+    // (identity in S and X, zero elsewhere on the padded functions)
+    bool mixed = false;
+    std::vector<int32_t> nbf;
+    DBuf<int32_t> d_nbf;
+    int64_t n_pad = 0;          // padded functions in all
 
     double radius[3] = {0, 0, 0};
     bool ranges_set = false;
@@ -796,6 +813,7 @@ void ensure_s_norm(rtdm_ctx *c, hipStream_t s)
     if (c->s_norm_valid) return;
     launch_red_sumsq(s, elems(c, c->mats[RTDM_MAT_S]), c->mats[RTDM_MAT_S].re.p, c->partials.p);
     reduce_finish(c, s, c->s_norm2.p);
+    if (c->mixed) launch_add_scalar(s, c->s_norm2.p, -(double)c->n_pad);   // the padded identity's ones
     c->s_norm_valid = true;
 }
 
@@ -1206,10 +1224,23 @@ int rtdm_set_geometry(rtdm_ctx *c, int64_t n_atoms, const double *xyz, const int
     set_device(c);
     RT_CHECK(n_atoms >= 1 && n_atoms < (int64_t)INT32_MAX && xyz && nbf, RTDM_E_ARG, "bad geometry arguments");
     RT_CHECK(!c->mem.base, RTDM_E_STATE, "the geometry is fixed once a workspace is bound");
-    const int b = nbf[0];
-    for (int64_t i = 0; i < n_atoms; ++i)
-        RT_CHECK(nbf[i] == b, RTDM_E_UNSUPPORTED, "atoms with different numbers of functions");
-    RT_CHECK(b >= 1 && b <= 16, RTDM_E_UNSUPPORTED, "functions per atom must be 1..16");
+    int b = 0;
+    bool mixed = false;
+    for (int64_t i = 0; i < n_atoms; ++i) {
+        RT_CHECK(nbf[i] >= 1 && nbf[i] <= 16, RTDM_E_UNSUPPORTED, "functions per atom must be 1..16");
+        b = std::max(b, (int)nbf[i]);
+        mixed |= nbf[i] != nbf[0];
+    }
+    if (mixed) {
+        RT_CHECK(b == 4 || b == 13, RTDM_E_UNSUPPORTED,
+                 "mixed block sizes need a largest size of 4 or 13 (the padded size)");
+        RT_CHECK(c->opt.precision == RTDM_PREC_FP64 && c->opt.inv_start != RTDM_INV_COLD &&
+                     c->opt.inv_start != RTDM_INV_LEARNED && c->opt.propagator == RTDM_PROP_EM &&
+                     c->opt.sc_steps == 0,
+                 RTDM_E_UNSUPPORTED,
+                 "mixed block sizes run the FP64 exponential-midpoint step (no corrector) with the block-Jacobi "
+                 "or previous start");
+    }
     for (int64_t e = 0; e < 3 * n_atoms; ++e) RT_CHECK(std::isfinite(xyz[e]), RTDM_E_ARG, "non-finite position");
     RT_HIP(hipDeviceSynchronize());
     c->scheds.clear();
@@ -1218,6 +1249,16 @@ int rtdm_set_geometry(rtdm_ctx *c, int64_t n_atoms, const double *xyz, const int
     c->ranges_set = false;
     c->n = n_atoms;
     c->b = b;
+    c->mixed = mixed;
+    c->nbf.assign(nbf, nbf + n_atoms);
+    c->n_pad = 0;
+    for (int64_t i = 0; i < n_atoms; ++i) c->n_pad += b - nbf[i];
+    if (mixed) {
+        c->d_nbf.alloc(n_atoms);
+        RT_HIP(hipMemcpy(c->d_nbf.p, nbf, c->d_nbf.bytes(), hipMemcpyHostToDevice));
+    } else {
+        c->d_nbf.release();
+    }
     c->xyz.assign(xyz, xyz + 3 * n_atoms);
     c->d_xyz.alloc(3 * n_atoms);
     RT_HIP(hipMemcpy(c->d_xyz.p, xyz, c->d_xyz.bytes(), hipMemcpyHostToDevice));
@@ -1350,6 +1391,8 @@ int rtdm_set_ranges(rtdm_ctx *c, double R_hs, double R_p, double R_k)
     c->herm_valid = false;
     c->ranges_set = true;
     for (int prod : {RTDM_PROD_XH, RTDM_PROD_AT, RTDM_PROD_UK, RTDM_PROD_WU, RTDM_PROD_SX}) schedule(c, prod);
+    // the unitarity product too when steps check it, so that rtdm_step allocates nothing
+    if (c->opt.unit_check_every > 0) schedule(c, RTDM_PROD_UV);
     RT_HIP(hipDeviceSynchronize());
     API_END(c)
 }
@@ -1369,6 +1412,53 @@ int rtdm_pattern(rtdm_ctx *c, rtdm_mat mat, int64_t *n_rows, int64_t *nnzb, cons
     API_END(c)
 }
 
+namespace {
+
+// Elements of block (i, j) in the caller's layout: b x b, or nbf_i x nbf_j
+// (row-major) with mixed block sizes.
+inline int64_t api_block_elems(const rtdm_ctx *c, int32_t i, int32_t j)
+{
+    return c->mixed ? (int64_t)c->nbf[i] * c->nbf[j] : (int64_t)c->b * c->b;
+}
+
+// Block t of the caller's data (starting at element offset `at`) into the
+// padded b x b block at slot position p.
+void put_block(const rtdm_ctx *c, int32_t i, int32_t j, const double *d, int64_t at, bool is_complex, int64_t p,
+               std::vector<double> &re, std::vector<double> *im)
+{
+    const int b = c->b;
+    const int ni = c->mixed ? c->nbf[i] : b, nj = c->mixed ? c->nbf[j] : b;
+    for (int r = 0; r < ni; ++r)
+        for (int q = 0; q < nj; ++q) {
+            const int64_t src = at + (int64_t)r * nj + q, dst = p * b * b + (int64_t)r * b + q;
+            if (is_complex) {
+                re[dst] = d[2 * src];
+                const double v = d[2 * src + 1];
+                if (im) (*im)[dst] = v;
+                else RT_CHECK(v == 0.0, RTDM_E_UNSUPPORTED, "complex data for a real matrix slot");
+            } else {
+                re[dst] = d[src];
+            }
+        }
+}
+
+// S and its inverse carry the identity on padded functions, so that these
+// stay decoupled from the atom's own functions through every product.
+void pad_identity(const rtdm_ctx *c, int mat, const Pattern &P, std::vector<double> &re)
+{
+    if (!c->mixed || (mat != RTDM_MAT_S && mat != RTDM_MAT_X)) return;
+    const int b = c->b;
+    for (int64_t i = 0; i < c->n; ++i) {
+        auto b0 = P.col.begin() + P.rowptr[i], b1 = P.col.begin() + P.rowptr[i + 1];
+        auto it = std::lower_bound(b0, b1, (int32_t)i);
+        RT_CHECK(it != b1 && *it == i, RTDM_E_STATE, "pattern without its diagonal block");
+        const int64_t p = it - P.col.begin();
+        for (int a = c->nbf[i]; a < b; ++a) re[p * b * b + (int64_t)a * b + a] = 1.0;
+    }
+}
+
+}  // namespace
+
 int rtdm_upload(rtdm_ctx *c, rtdm_mat mat, const void *data, int is_complex, int is_device, void *stream)
 {
     if (!c) return RTDM_E_ARG;
@@ -1379,7 +1469,21 @@ int rtdm_upload(rtdm_ctx *c, rtdm_mat mat, const void *data, int is_complex, int
     hipStream_t s = (hipStream_t)stream;
     Mat &M = c->mats[mat];
     const int64_t ne = elems(c, M);
-    if (!is_device) {
+    RT_CHECK(!(c->mixed && is_device), RTDM_E_UNSUPPORTED, "device uploads need equal block sizes");
+    if (!is_device && c->mixed) {
+        // blocks of their own sizes, in pattern order
+        const Pattern &P = *c->pats[M.pat];
+        std::vector<double> re(ne, 0.0), im;
+        if (M.cplx) im.assign(ne, 0.0);
+        int64_t at = 0;
+        for (int64_t i = 0; i < c->n; ++i)
+            for (int64_t p = P.rowptr[i]; p < P.rowptr[i + 1]; ++p) {
+                put_block(c, (int32_t)i, P.col[p], (const double *)data, at, is_complex, p, re, M.cplx ? &im : nullptr);
+                at += api_block_elems(c, (int32_t)i, P.col[p]);
+            }
+        pad_identity(c, mat, P, re);
+        upload_planes(c, mat, re.data(), M.cplx ? im.data() : nullptr, s);
+    } else if (!is_device) {
         const double *d = (const double *)data;
         if (!is_complex) {
             upload_planes(c, mat, d, nullptr, s);
@@ -1431,7 +1535,9 @@ int rtdm_upload_coo(rtdm_ctx *c, rtdm_mat mat, int64_t nnzb, const int32_t *rows
     const int64_t ne = P.nnzb * bb;
     std::vector<double> re(ne, 0.0), im;
     if (M.cplx) im.assign(ne, 0.0);
+    (void)bb;
     const double *d = (const double *)data;
+    int64_t at = 0;
     for (int64_t t = 0; t < nnzb; ++t) {
         const int32_t i = rows[t], j = cols[t];
         RT_CHECK(i >= 0 && i < c->n && j >= 0 && j < c->n, RTDM_E_ARG, "block index out of range");
@@ -1439,18 +1545,10 @@ int rtdm_upload_coo(rtdm_ctx *c, rtdm_mat mat, int64_t nnzb, const int32_t *rows
         auto it = std::lower_bound(b0, b1, j);
         RT_CHECK(it != b1 && *it == j, RTDM_E_ARG,
                  "block (" + std::to_string(i) + "," + std::to_string(j) + ") is outside the range");
-        const int64_t p = it - P.col.begin();
-        for (int64_t e = 0; e < bb; ++e) {
-            if (is_complex) {
-                re[p * bb + e] = d[2 * (t * bb + e)];
-                const double v = d[2 * (t * bb + e) + 1];
-                if (M.cplx) im[p * bb + e] = v;
-                else RT_CHECK(v == 0.0, RTDM_E_UNSUPPORTED, "complex data for a real matrix slot");
-            } else {
-                re[p * bb + e] = d[t * bb + e];
-            }
-        }
+        put_block(c, i, j, d, at, is_complex, it - P.col.begin(), re, M.cplx ? &im : nullptr);
+        at += api_block_elems(c, i, j);
     }
+    pad_identity(c, mat, P, re);
     upload_planes(c, mat, re.data(), M.cplx ? im.data() : nullptr, (hipStream_t)stream);
     after_upload(c, mat);
     API_END(c)
@@ -1470,6 +1568,7 @@ int rtdm_download(rtdm_ctx *c, rtdm_mat mat, void *dst, int is_device, void *str
         transpose_into(c, c->Wc, M, s);
         c->W_in_cm = false;
     }
+    RT_CHECK(!(c->mixed && is_device), RTDM_E_UNSUPPORTED, "device downloads need equal block sizes");
     if (is_device) {
         launch_interleave(s, ne, M.re.p, M.cplx ? M.im.p : nullptr, (double *)dst);
         RT_HIP(hipStreamSynchronize(s));
@@ -1479,9 +1578,26 @@ int rtdm_download(rtdm_ctx *c, rtdm_mat mat, void *dst, int is_device, void *str
         if (M.cplx) RT_HIP(hipMemcpyAsync(im.data(), M.im.p, ne * sizeof(double), hipMemcpyDeviceToHost, s));
         RT_HIP(hipStreamSynchronize(s));
         double *o = (double *)dst;
-        for (int64_t e = 0; e < ne; ++e) {
-            o[2 * e] = re[e];
-            o[2 * e + 1] = M.cplx ? im[e] : 0.0;
+        if (c->mixed) {
+            // each block cut to its own nbf_i x nbf_j size, in pattern order
+            const Pattern &P = *c->pats[M.pat];
+            const int b = c->b;
+            int64_t at = 0;
+            for (int64_t i = 0; i < c->n; ++i)
+                for (int64_t p = P.rowptr[i]; p < P.rowptr[i + 1]; ++p) {
+                    const int ni = c->nbf[i], nj = c->nbf[P.col[p]];
+                    for (int r = 0; r < ni; ++r)
+                        for (int q = 0; q < nj; ++q, ++at) {
+                            const int64_t e = p * b * b + (int64_t)r * b + q;
+                            o[2 * at] = re[e];
+                            o[2 * at + 1] = M.cplx ? im[e] : 0.0;
+                        }
+                }
+        } else {
+            for (int64_t e = 0; e < ne; ++e) {
+                o[2 * e] = re[e];
+                o[2 * e + 1] = M.cplx ? im[e] : 0.0;
+            }
         }
     }
     API_END(c)
@@ -1566,7 +1682,8 @@ int rtdm_build_inverse(rtdm_ctx *c, void *stream, int *iters, double *residual)
             reduce_finish(c, s, c->hot_sums.p);
             double h[4];
             read_scalars(h, c->hot_sums.p, 4, s);
-            const double r = std::sqrt(h[0] / h[1]);
+            // ||X'||^2 without the padded identity's ones (exactly n_pad of them)
+            const double r = std::sqrt(h[0] / (h[1] - (double)c->n_pad));
             res.push_back(r);
             k_out = k + 1;
             r_out = r;
@@ -1580,15 +1697,19 @@ int rtdm_build_inverse(rtdm_ctx *c, void *stream, int *iters, double *residual)
         MlpState &M = c->mlp;
         RT_CHECK(M.ready && M.b == c->b, RTDM_E_STATE, "no trained network for the learned start");
         const int64_t n = ps.nnzb;
-        DBuf<float> desc, y;
-        desc.alloc((size_t)n * M.in);
-        y.alloc((size_t)n * M.out);
+        // descriptors and predictions live in the A and U planes, which the
+        // next step recomputes (U is marked stale below): no temporaries
+        Mat &Am = c->mats[RTDM_MAT_A], &Um = c->mats[RTDM_MAT_U];
+        RT_CHECK(Am.re.n * 2 >= (size_t)n * M.in && Um.re.n * 2 >= (size_t)n * M.out, RTDM_E_STATE,
+                 "learned start: work planes too small");
+        float *desc_p = reinterpret_cast<float *>(Am.re.p), *y_p = reinterpret_cast<float *>(Um.re.p);
+        c->U_valid = false;
         const double inv_r = c->radius[R_HS] > 0 ? 1.0 / c->radius[R_HS] : 1.0;
-        launch_mlp_desc(s, n, c->b, c->hs_iota.p, ps.d_rowof.p, ps.d_col.p, c->d_xyz.p, S.re.p, inv_r, desc.p);
-        launch_mlp_forward(s, n, M.in, M.out, nullptr, desc.p, M.w1h.p, mlp_b1(M), M.w2h.p, mlp_b2(M),
-                           nullptr, y.p);
+        launch_mlp_desc(s, n, c->b, c->hs_iota.p, ps.d_rowof.p, ps.d_col.p, c->d_xyz.p, S.re.p, inv_r, desc_p);
+        launch_mlp_forward(s, n, M.in, M.out, nullptr, desc_p, M.w1h.p, mlp_b1(M), M.w2h.p, mlp_b2(M),
+                           nullptr, y_p);
         RT_HIP(hipMemsetAsync(X.re.p, 0, X.re.bytes(), s));
-        launch_mlp_apply(s, n, c->b, c->hs_iota.p, c->hs_to_p.p, ps.d_rowof.p, ps.d_col.p, S.re.p, y.p, X.re.p);
+        launch_mlp_apply(s, n, c->b, c->hs_iota.p, c->hs_to_p.p, ps.d_rowof.p, ps.d_col.p, S.re.p, y_p, X.re.p);
         RT_HIP(hipStreamSynchronize(s));
     };
     int k = 0;
@@ -1651,10 +1772,10 @@ void build_h(rtdm_ctx *c, double theta, bool corr, hipStream_t s)
     launch_axpby(s, elems(c, H), 1.0, H0.re.p, 0.0, nullptr, H.re.p);
     if (c->opt.h_model == RTDM_HMODEL_MULLIKEN) {
         if (corr)
-            launch_onsite_shift(s, c->n, c->b, ps.d_diag.p, c->opt.h_gain, c->q_cur, theta, c->q_c.p, c->q_cur,
+            launch_onsite_shift(s, c->n, c->b, ps.d_diag.p, c->mixed ? c->d_nbf.p : nullptr, c->opt.h_gain, c->q_cur, theta, c->q_c.p, c->q_cur,
                                 c->q_ref.p, H.re.p);
         else
-            launch_onsite_shift(s, c->n, c->b, ps.d_diag.p, c->opt.h_gain, c->q_cur, theta, c->q_cur, c->q_prev,
+            launch_onsite_shift(s, c->n, c->b, ps.d_diag.p, c->mixed ? c->d_nbf.p : nullptr, c->opt.h_gain, c->q_cur, theta, c->q_cur, c->q_prev,
                                 c->q_ref.p, H.re.p);
     }
     if (c->field_on)
@@ -1818,6 +1939,7 @@ void step_ready(rtdm_ctx *c, double dt, int64_t n_steps)
                 c->uploaded[RTDM_MAT_S],
             "upload S, H0, K and build (or upload) the inverse first");
     RT_CHECK(std::isfinite(dt) && n_steps >= 0, RTDM_E_ARG, "bad step arguments");
+    RT_CHECK(!(c->mixed && c->field_on), RTDM_E_UNSUPPORTED, "the external field needs equal block sizes");
 }
 
 // Trace room, charges and the device step state for n_steps more steps.
@@ -2127,6 +2249,7 @@ int rtdm_ground_state(rtdm_ctx *c, double n_occ, double tol, int max_iter, void 
     set_device(c);
     require(c->ranges_set && c->X_valid && c->uploaded[RTDM_MAT_H0] && c->uploaded[RTDM_MAT_S],
             "upload S, H0 and build (or upload) the inverse first");
+    RT_CHECK(!c->mixed, RTDM_E_UNSUPPORTED, "the ground state needs equal block sizes");
     RT_CHECK(n_occ > 0 && std::isfinite(n_occ) && tol > 0 && max_iter >= 1 && max_iter <= 64, RTDM_E_ARG,
              "bad ground-state arguments (max_iter 1..64)");
     hipStream_t s = (hipStream_t)stream;
@@ -2191,6 +2314,16 @@ int rtdm_ground_state(rtdm_ctx *c, double n_occ, double tol, int max_iter, void 
     API_END(c)
 }
 
+int rtdm_reserve_trace(rtdm_ctx *c, int64_t rows)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    RT_CHECK(rows >= 0 && rows <= (int64_t(1) << 32), RTDM_E_ARG, "rows outside 0..2^32");
+    ensure_obs(c, rows);
+    API_END(c)
+}
+
 int rtdm_workspace_size(rtdm_ctx *c, size_t *bytes)
 {
     if (!c || !bytes) return RTDM_E_ARG;
@@ -2226,14 +2359,107 @@ int rtdm_bind_workspace(rtdm_ctx *c, void *ptr, size_t bytes)
     for (auto *b : list) {
         void *np = base + off;
         RT_HIP(hipMemcpy(np, b->raw(), b->nbytes, hipMemcpyDeviceToDevice));
-        RT_HIP(hipFree(b->raw()));
+        if (b->ext) c->mem.ext_free(b->raw(), c->mem.ext_user);
+        else RT_HIP(hipFree(b->raw()));
         b->set_raw(np);
         b->in_ws = true;
+        b->ext = false;
         off += devmem_align(b->nbytes);
     }
     c->mem.base = base;
     c->mem.cap = bytes;
     c->mem.used = off;
+    if (c->q_a.p) {
+        c->q_cur = cur_a ? c->q_a.p : c->q_b.p;
+        c->q_prev = cur_a ? c->q_b.p : c->q_a.p;
+    }
+    API_END(c)
+}
+
+int rtdm_set_allocator(rtdm_ctx *c, void *(*alloc_fn)(size_t, void *), void (*free_fn)(void *, void *),
+                       void *user)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    RT_CHECK(alloc_fn && free_fn, RTDM_E_ARG, "null allocator functions");
+    RT_CHECK(!c->mem.ext_alloc, RTDM_E_STATE, "the context already has an allocator");
+    RT_CHECK(!c->mem.base, RTDM_E_STATE, "a workspace is bound");
+    RT_HIP(hipDeviceSynchronize());
+    drop_graph(c);
+    const bool cur_a = c->q_cur == c->q_a.p;
+    // move the buffers allocated so far into the caller's allocations
+    std::vector<DBufBase *> list(c->mem.bufs.begin(), c->mem.bufs.end());
+    std::vector<void *> homes(list.size(), nullptr);
+    for (size_t k = 0; k < list.size(); ++k) {
+        homes[k] = alloc_fn(list[k]->nbytes, user);
+        if (!homes[k] || (reinterpret_cast<uintptr_t>(homes[k]) & 255) != 0) {
+            for (void *h : homes)
+                if (h) free_fn(h, user);
+            throw Error(homes[k] ? RTDM_E_ARG : RTDM_E_OOM,
+                        homes[k] ? "the allocator returned memory that is not 256-byte aligned"
+                                 : "the allocator refused the context's buffers");
+        }
+    }
+    for (size_t k = 0; k < list.size(); ++k) {
+        RT_HIP(hipMemcpy(homes[k], list[k]->raw(), list[k]->nbytes, hipMemcpyDeviceToDevice));
+        RT_HIP(hipFree(list[k]->raw()));
+        list[k]->set_raw(homes[k]);
+        list[k]->ext = true;
+    }
+    c->mem.ext_alloc = alloc_fn;
+    c->mem.ext_free = free_fn;
+    c->mem.ext_user = user;
+    if (c->q_a.p) {
+        c->q_cur = cur_a ? c->q_a.p : c->q_b.p;
+        c->q_prev = cur_a ? c->q_b.p : c->q_a.p;
+    }
+    API_END(c)
+}
+
+int rtdm_unbind_workspace(rtdm_ctx *c)
+{
+    if (!c) return RTDM_E_ARG;
+    API_BEGIN
+    set_device(c);
+    RT_CHECK(c->mem.base, RTDM_E_STATE, "no workspace is bound");
+    RT_HIP(hipDeviceSynchronize());
+    drop_graph(c);
+    const bool cur_a = c->q_cur == c->q_a.p;
+    std::vector<DBufBase *> list(c->mem.bufs.begin(), c->mem.bufs.end());
+    // allocate every new home first, so that a failure leaves the context bound as it was
+    std::vector<void *> homes(list.size(), nullptr);
+    const bool ext = c->mem.ext_alloc != nullptr;
+    auto give_back = [&]() {
+        for (void *h : homes)
+            if (h) {
+                if (ext) c->mem.ext_free(h, c->mem.ext_user);
+                else (void)hipFree(h);
+            }
+    };
+    for (size_t k = 0; k < list.size(); ++k) {
+        if (!list[k]->in_ws) continue;
+        if (ext) {
+            homes[k] = c->mem.ext_alloc(list[k]->nbytes, c->mem.ext_user);
+        } else if (hipMalloc(&homes[k], list[k]->nbytes) != hipSuccess) {
+            (void)hipGetLastError();
+            homes[k] = nullptr;
+        }
+        if (!homes[k]) {
+            give_back();
+            throw Error(RTDM_E_OOM, "allocation failed while moving out of the workspace");
+        }
+    }
+    for (size_t k = 0; k < list.size(); ++k) {
+        if (!homes[k]) continue;
+        RT_HIP(hipMemcpy(homes[k], list[k]->raw(), list[k]->nbytes, hipMemcpyDeviceToDevice));
+        list[k]->set_raw(homes[k]);
+        list[k]->in_ws = false;
+        list[k]->ext = ext;
+    }
+    c->mem.base = nullptr;
+    c->mem.cap = 0;
+    c->mem.used = 0;
     if (c->q_a.p) {
         c->q_cur = cur_a ? c->q_a.p : c->q_b.p;
         c->q_prev = cur_a ? c->q_b.p : c->q_a.p;
@@ -2875,6 +3101,7 @@ int rtdm_mlp_collect(rtdm_ctx *c, int64_t max_samples, uint64_t seed, int64_t *t
 {
     if (!c) return RTDM_E_ARG;
     API_BEGIN
+    RT_CHECK(!c->mixed, RTDM_E_UNSUPPORTED, "training samples need equal block sizes");
     set_device(c);
     require(c->ranges_set && c->uploaded[RTDM_MAT_S] && c->X_valid, "build the inverse first");
     RT_CHECK(max_samples >= 0, RTDM_E_ARG, "max_samples < 0");

@@ -8,9 +8,11 @@ been built: there is no fallback path.
 
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 import sys
+import weakref
 from typing import Optional, Sequence, Tuple
 
 import numpy as np
@@ -37,7 +39,7 @@ EXPORTED = ["rtdm_default_options", "rtdm_create", "rtdm_destroy", "rtdm_set_geo
             "rtdm_timing", "rtdm_timing_stats", "rtdm_inverse_info", "rtdm_mlp_params", "rtdm_mlp_init",
             "rtdm_mlp_set_weights", "rtdm_mlp_get_weights", "rtdm_mlp_collect", "rtdm_mlp_clear",
             "rtdm_mlp_train", "rtdm_mlp_loss_grad", "rtdm_mlp_step", "rtdm_mlp_predict", "rtdm_set_groups",
-            "rtdm_apply_kick_groups", "rtdm_group_trace", "rtdm_apply_kicks", "rtdm_select_kick",
+            "rtdm_apply_kick_groups", "rtdm_group_trace", "rtdm_apply_kicks", "rtdm_select_kick", "rtdm_unbind_workspace", "rtdm_reserve_trace", "rtdm_set_allocator",
             "rtdm_batch_create", "rtdm_batch_step", "rtdm_batch_last_error", "rtdm_batch_destroy", "rtdm_autotune", "rtdm_set_field",
             "rtdm_spectrum", "rtdm_workspace_size", "rtdm_bind_workspace", "rtdm_ground_state",
             "rtdm_get_state", "rtdm_set_state", "rtdm_last_error"]
@@ -68,6 +70,13 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build()")
+    # PyTorch first: it ships its own HIP runtime under the same soname, and the
+    # process must hold one runtime (the first loaded serves both), so that
+    # torch's device memory and streams are the library's too
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     P, I, I64, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
     sig = {
@@ -107,6 +116,9 @@ def load():
         "rtdm_apply_kick_groups": [P, P, P],
         "rtdm_group_trace": [P, P, I64, P],
         "rtdm_apply_kicks": [P, P, P],
+        "rtdm_unbind_workspace": [P],
+        "rtdm_set_allocator": [P, P, P, P],
+        "rtdm_reserve_trace": [P, I64],
         "rtdm_batch_create": [P, P, I, I],
         "rtdm_batch_step": [P, D, I64, P],
         "rtdm_batch_last_error": [P],
@@ -234,6 +246,19 @@ def rtdm_download(ctx, mat, b: int, out=None, stream=None):
     arr = np.empty((col.size, b, b), dtype=np.complex128)
     _check(ctx, load().rtdm_download(ctx, _mat(mat), _p(arr), 0, _stream(stream)))
     return arr
+
+
+def rtdm_download_mixed(ctx, mat, nbf, stream=None):
+    """Blocks of a slot with per-atom sizes nbf: (flat complex128 data, block
+    offsets); block p (rtdm_pattern order) is data[off[p]:off[p+1]], row-major
+    nbf_i x nbf_j."""
+    rp, col = rtdm_pattern(ctx, mat)
+    nbf = np.asarray(nbf, dtype=np.int64)
+    rows = np.repeat(np.arange(rp.size - 1), np.diff(rp))
+    sizes = nbf[rows] * nbf[col]
+    arr = np.empty(int(sizes.sum()), dtype=np.complex128)
+    _check(ctx, load().rtdm_download(ctx, _mat(mat), _p(arr), 0, _stream(stream)))
+    return arr, np.concatenate([[0], np.cumsum(sizes)])
 
 
 def rtdm_apply_kick(ctx, kappa: Sequence[float], stream=None) -> None:
@@ -416,6 +441,14 @@ def rtdm_batch_destroy(batch) -> None:
     load().rtdm_batch_destroy(batch)
 
 
+def rtdm_unbind_workspace(ctx) -> None:
+    _check(ctx, load().rtdm_unbind_workspace(ctx))
+
+
+def rtdm_reserve_trace(ctx, rows: int) -> None:
+    _check(ctx, load().rtdm_reserve_trace(ctx, int(rows)))
+
+
 def rtdm_select_kick(ctx, k: int) -> None:
     _check(ctx, load().rtdm_select_kick(ctx, int(k)))
 
@@ -491,10 +524,65 @@ def rtdm_last_error(ctx) -> str:
 
 # ------------------------------------------------------------------ convenience
 
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class TorchAllocator:
+    """rtdm_set_allocator functions that take a context's device memory from
+    PyTorch's caching allocator on one device (kept alive by the Context)."""
+
+    def __init__(self, device: int):
+        import torch
+        torch.cuda.init()          # the caching allocator needs torch's runtime up
+        self._torch = torch
+        self.device = device
+        self.last_error = None
+        self.alloc_fn = _ALLOC_FN(self._alloc)
+        self.free_fn = _FREE_FN(self._free)
+
+    def _alloc(self, nbytes, user):
+        try:
+            return self._torch.cuda.caching_allocator_alloc(int(nbytes), self.device)
+        except Exception as e:     # out of memory: the library reports RTDM_E_OOM
+            self.last_error = repr(e)
+            return None
+
+    def _free(self, ptr, user):
+        try:
+            self._torch.cuda.caching_allocator_delete(ptr)
+        except Exception:
+            pass
+
+
+def rtdm_set_allocator(ctx, allocator: TorchAllocator) -> None:
+    rc = load().rtdm_set_allocator(ctx, allocator.alloc_fn, allocator.free_fn, None)
+    if rc != 0 and allocator.last_error:
+        raise RtdmError(rc, f"{rtdm_last_error(ctx)} ({allocator.last_error})")
+    _check(ctx, rc)
+
+
+_live_contexts = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_contexts():
+    # give device memory back while PyTorch is still whole
+    for c in list(_live_contexts):
+        try:
+            c.close()
+        except Exception:
+            pass
+
+
 class Context:
     """Owns one rtdm context; `load_system` runs the set-up calls for a generated system."""
 
-    def __init__(self, device: int = 0, **opts):
+    def __init__(self, device: int = 0, memory: str = "torch", **opts):
+        """memory: "torch" (default) takes every device buffer of the context
+        from PyTorch's caching allocator (rtdm_set_allocator); "library" leaves
+        it to the library's own hipMalloc.  Either way bind_workspace can move
+        the buffers into one region; a later load moves them out first."""
         o = rtdm_default_options()
         for k, v in opts.items():
             if k == "h_model" and isinstance(v, str):
@@ -506,14 +594,30 @@ class Context:
             if k == "propagator" and isinstance(v, str):
                 v = PROPAGATOR[v]
             setattr(o, k, v)
+        if memory not in ("torch", "library"):
+            raise ValueError(memory)
         self.options = o
+        self.device = device
+        self.workspace = None
+        self.allocator = None
         self.h = rtdm_create(device, o)
         self.b = 0
+        _live_contexts.add(self)
+        if memory == "torch":
+            self.allocator = TorchAllocator(device)
+            rtdm_set_allocator(self.h, self.allocator)
+
+    def _unbind(self):
+        if self.workspace is not None:
+            rtdm_unbind_workspace(self.h)
+            self.workspace = None
 
     def close(self):
         if self.h is not None:
             rtdm_destroy(self.h)
             self.h = None
+        self.workspace = None
+        self.allocator = None
 
     def __del__(self):
         try:
@@ -521,11 +625,14 @@ class Context:
         except Exception:
             pass
 
-    def bind_workspace(self, device: int = 0):
+    def bind_workspace(self, device: int = 0, extra: int = 0):
         """Move the context's device buffers into one torch allocation (kept
-        alive by this object)."""
+        alive by this object), `extra` bytes beyond rtdm_workspace_size's
+        figure for calls with large temporaries."""
         import torch
-        n = rtdm_workspace_size(self.h)
+        if self.workspace is not None:
+            return self.workspace.numel()
+        n = rtdm_workspace_size(self.h) + int(extra)
         self.workspace = torch.empty(n, dtype=torch.uint8, device=f"cuda:{device}")
         rtdm_bind_workspace(self.h, self.workspace.data_ptr(), n)
         return n
@@ -560,6 +667,7 @@ class Context:
                 kap.append(k)
         self.b = s0.b
         xyz = np.concatenate(xyz)
+        self._unbind()
         rtdm_set_geometry(self.h, xyz, np.full(n, s0.b, dtype=np.int32))
         rtdm_set_ranges(self.h, s0.R_HS, s0.R_P, s0.R_K)
         rtdm_set_groups(self.h, gptr)
@@ -582,8 +690,19 @@ class Context:
         self.kick_vectors = np.asarray(kicks, dtype=np.float64)
         return gptr
 
+    def load_mixed(self, sys_, stream=None):
+        """A system with per-atom block sizes (synth.MixedSystem)."""
+        self.b = int(sys_.nbf.max())
+        self._unbind()
+        rtdm_set_geometry(self.h, sys_.xyz, sys_.nbf)
+        rtdm_set_ranges(self.h, sys_.R_HS, sys_.R_P, sys_.R_K)
+        for name, m in (("S", sys_.S), ("H0", sys_.H0), ("K", sys_.K0)):
+            rtdm_upload_coo(self.h, name, m.rows, m.cols, m.data, stream)
+        return self
+
     def load_system(self, sys_, stream=None):
         self.b = sys_.b
+        self._unbind()
         rtdm_set_geometry(self.h, sys_.xyz, sys_.nbf)
         rtdm_set_ranges(self.h, sys_.R_HS, sys_.R_P, sys_.R_K)
         for name, m in (("S", sys_.S), ("H0", sys_.H0), ("K", sys_.K0)):

@@ -475,6 +475,113 @@ def config5(seed: int = 5, cells=(16, 16, 32), n_steps: int = 100) -> System:
 
 
 # ----------------------------------------------------------------------------
+# per-atom block sizes (e.g. 4 functions on some elements, 13 on others)
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class MixedCOO:
+    """Atom-pair blocks of per-atom sizes: block t is nbf[rows[t]] x
+    nbf[cols[t]], row-major; the blocks are concatenated in data."""
+
+    rows: np.ndarray   # (nnzb,) int32
+    cols: np.ndarray   # (nnzb,) int32
+    data: np.ndarray   # (sum of block sizes,) float64
+
+    @property
+    def nnzb(self) -> int:
+        return int(self.rows.shape[0])
+
+
+@dataclasses.dataclass
+class MixedSystem:
+    """A system whose atoms carry different numbers of functions."""
+
+    name: str
+    xyz: np.ndarray
+    nbf: np.ndarray          # (N,) int32
+    R_HS: float
+    R_K: float
+    R_P: float
+    S: MixedCOO
+    H0: MixedCOO
+    K0: MixedCOO
+    dt: float = 0.05
+    n_steps: int = 20
+    h_model: str = "fixed"
+    h_gain: float = 0.5
+    kappa: Tuple[float, float, float] = (0.01, 0.0, 0.0)
+    seed: int = 0
+
+    @property
+    def n_atoms(self) -> int:
+        return int(self.xyz.shape[0])
+
+    @property
+    def offsets(self) -> np.ndarray:
+        return np.concatenate([[0], np.cumsum(self.nbf)]).astype(np.int64)
+
+
+def dense_to_mixed(dense: np.ndarray, xyz: np.ndarray, nbf: np.ndarray, R: float) -> MixedCOO:
+    """Blocks of a dense matrix (functions ordered atom by atom) for the pairs
+    closer than R, plus the diagonal, in row-major pair order."""
+    n = xyz.shape[0]
+    off = np.concatenate([[0], np.cumsum(nbf)])
+    lo, hi, _ = pairs_within(xyz, R)
+    rows = np.concatenate([np.arange(n), lo, hi]).astype(np.int32)
+    cols = np.concatenate([np.arange(n), hi, lo]).astype(np.int32)
+    o = np.lexsort((cols, rows))
+    rows, cols = rows[o], cols[o]
+    data = np.concatenate([dense[off[i]:off[i + 1], off[j]:off[j + 1]].ravel() for i, j in zip(rows, cols)])
+    return MixedCOO(rows, cols, data)
+
+
+def mixed_cluster(n_atoms: int, seed: int, R_HS: float = 8.0, R_K: float = 12.0, sizes=(4, 13),
+                  h_model: str = "fixed", n_steps: int = 20) -> MixedSystem:
+    """Random cluster (config-1 density and spacing) whose atoms carry
+    sizes[0] or sizes[1] functions (equal odds); S, H0 with the same
+    Gaussian-decaying random blocks as the equal-size systems, K0 the
+    occupied projector of the generalised eigenproblem (sum of floor(nbf/2)
+    states), cut to R_K."""
+    from scipy.linalg import eigh
+    r_pos, r_b, r_s, r_h = _children(seed, 4)
+    xyz = cluster_positions(n_atoms, r_pos)
+    xyz = np.ascontiguousarray(xyz[morton_order(xyz)])
+    check_no_ties(xyz, sorted({R_HS, R_K}))
+    nbf = np.where(r_b.uniform(size=n_atoms) < 0.5, sizes[0], sizes[1]).astype(np.int32)
+    off = np.concatenate([[0], np.cumsum(nbf)])
+    nf = int(off[-1])
+    lo, hi, d2 = pairs_within(xyz, R_HS)
+    decay = np.exp(-(np.sqrt(d2) / DECAY_LEN) ** 2)
+    # overlap: unit diagonal blocks, off-diagonal blocks scaled to row sums S_ROWSUM at most
+    S = np.eye(nf)
+    for t, (i, j) in enumerate(zip(lo, hi)):
+        S[off[i]:off[i + 1], off[j]:off[j + 1]] = decay[t] * r_s.uniform(-1.0, 1.0, size=(nbf[i], nbf[j]))
+    up = np.triu(S, 1)
+    S = np.eye(nf) + up + up.T
+    rs = np.abs(S - np.eye(nf)).sum(axis=1).max()
+    if rs > 0:
+        S = np.eye(nf) + (S - np.eye(nf)) * (S_ROWSUM / rs)
+    # Hamiltonian: split on-site levels plus symmetric noise, hopping -T0 decay U(-1, 1)
+    H = np.zeros((nf, nf))
+    for i in range(n_atoms):
+        b = nbf[i]
+        lev = np.where(np.arange(b) < b // 2, -0.5 * GAP, 0.5 * GAP)
+        nz = r_h.uniform(-1.0, 1.0, size=(b, b))
+        H[off[i]:off[i + 1], off[i]:off[i + 1]] = np.diag(lev) + ETA * 0.5 * (nz + nz.T)
+    for t, (i, j) in enumerate(zip(lo, hi)):
+        blk = -T0 * decay[t] * r_h.uniform(-1.0, 1.0, size=(nbf[i], nbf[j]))
+        H[off[i]:off[i + 1], off[j]:off[j + 1]] = blk
+        H[off[j]:off[j + 1], off[i]:off[i + 1]] = blk.T
+    nocc = int(sum(b // 2 for b in nbf))
+    _, V = eigh(H, S, subset_by_index=[0, nocc - 1])
+    K = V @ V.T
+    K = 0.5 * (K + K.T)
+    return MixedSystem(name=f"mixed{n_atoms}", xyz=xyz, nbf=nbf, R_HS=R_HS, R_K=R_K, R_P=max(R_HS, R_K),
+                       S=dense_to_mixed(S, xyz, nbf, R_HS), H0=dense_to_mixed(H, xyz, nbf, R_HS),
+                       K0=dense_to_mixed(K, xyz, nbf, R_K), h_model=h_model, n_steps=n_steps, seed=seed)
+
+
+# ----------------------------------------------------------------------------
 # free-standing random operands for product-level tests
 # ----------------------------------------------------------------------------
 

@@ -1,0 +1,79 @@
+"""Atoms with different numbers of functions (4 and 13) in one system.
+
+The library pads every block to 13 functions (identity in S and X on the
+padded functions, zeros elsewhere); the caller's blocks keep their own
+sizes.  K, X, the per-atom charges and the traces must equal the mixed-size
+oracle (dense over functions, no padding) at the FP64 bar, for a fixed and
+a Mulliken H.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import mixed as M
+from paper_1404_5776_amd import rtdm, synth
+from tests._common import TOL, dipole_floor, gpu_charges, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _blocks(ctx, slot, mt):
+    rp, col = rtdm.rtdm_pattern(ctx.h, slot)
+    rows = np.repeat(np.arange(rp.size - 1), np.diff(rp))
+    return rows, col
+
+
+@pytest.mark.parametrize("h_model", ["fixed", "mulliken"])
+def test_mixed_sizes_match_oracle(h_model):
+    ms = synth.mixed_cluster(48, 11, h_model=h_model)
+    print(f"[gpu] mixed cluster {ms.n_atoms} atoms, nbf counts {np.bincount(ms.nbf).nonzero()}, {h_model}",
+          flush=True)
+    n_steps, dt = 8, 0.05
+    ctx = rtdm.Context(0, h_model=h_model).load_mixed(ms)
+    it, res = rtdm.rtdm_build_inverse(ctx.h)
+    rtdm.rtdm_apply_kick(ctx.h, ms.kappa)
+    rtdm.rtdm_step(ctx.h, dt, n_steps)
+    K, _ = rtdm.rtdm_download_mixed(ctx.h, "K", ms.nbf)
+    X, _ = rtdm.rtdm_download_mixed(ctx.h, "X", ms.nbf)
+    tr = rtdm.rtdm_dipole_trace(ctx.h)
+    u_gpu = rtdm.rtdm_unitarity(ctx.h)[0]
+    q = gpu_charges(ctx, ms.n_atoms)
+    rk, ck = _blocks(ctx, "K", None)
+    rx, cx = _blocks(ctx, "X", None)
+    ctx.close()
+
+    mt = M.setup(ms)
+    ref = M.propagate(mt, n_steps, dt, ms.kappa, h_model=h_model)
+    assert it == ref.inverse_iters
+    assert rel(X, M.to_blocks(ref.X, mt.off, rx, cx)) <= TOL
+    assert rel(K, M.to_blocks(ref.K, mt.off, rk, ck)) <= TOL
+    dq = float(np.abs(q - ref.q).max())
+    assert dq <= TOL * np.abs(ref.q).max()
+    q0 = M.mulliken(mt, M.kick(mt, mt.K0, ms.kappa))
+    from oracle import oracle as O
+    P0 = O.dipole(q0, ms.xyz)
+    induced = np.abs(ref.rows[:, 1:4] - P0).max()
+    assert np.abs(tr[:, 1:4] - ref.rows[:, 1:4]).max() <= TOL * induced + dipole_floor(q0, ms.xyz, dq)
+    assert np.abs(tr[:, 4] - ref.rows[:, 4]).max() <= TOL * abs(ref.rows[0, 4])
+    # unitarity of the last propagator, ||P_P(U^dagger P_P(S U)) - S||_F / ||S||_F over the real functions
+    V = M.product(mt.S, ref.U, mt.mask_p)
+    Z = M.product(ref.U.conj().T, V, mt.mask_p)
+    u_ref = M.frob(Z - mt.S) / M.frob(mt.S)
+    assert abs(u_gpu - u_ref) <= 1e-6 * u_ref + 1e-14
+
+
+def test_mixed_sizes_refuse_what_they_do_not_support():
+    ms = synth.mixed_cluster(20, 12)
+    with pytest.raises(rtdm.RtdmError):
+        rtdm.Context(0, precision="fp32").load_mixed(ms)
+    with pytest.raises(rtdm.RtdmError):
+        rtdm.Context(0, inv_start="cold").load_mixed(ms)
+    ctx = rtdm.Context(0).load_mixed(ms)
+    rtdm.rtdm_build_inverse(ctx.h)
+    with pytest.raises(rtdm.RtdmError):
+        rtdm.rtdm_ground_state(ctx.h, 10.0)
+    import torch
+    dev = torch.empty(1 << 20, dtype=torch.complex128, device="cuda:0")
+    with pytest.raises(rtdm.RtdmError):
+        rtdm.rtdm_download(ctx.h, "K", 13, out=dev)
+    ctx.close()

@@ -265,8 +265,8 @@ def test_error_paths():
         rtdm.rtdm_set_ranges(ctx.h, 6.0, 0.0, 8.0)
     assert e.value.code == -2                                   # geometry first
     with pytest.raises(rtdm.RtdmError) as e:
-        rtdm.rtdm_set_geometry(ctx.h, s.xyz, np.r_[s.nbf[:-1], 13])
-    assert e.value.code == -7                                   # mixed block sizes
+        rtdm.rtdm_set_geometry(ctx.h, s.xyz, np.r_[s.nbf[:-1], 6])
+    assert e.value.code == -7                                   # mixed sizes padded to neither 4 nor 13
     ctx.load_system(s)
     with pytest.raises(rtdm.RtdmError) as e:
         rtdm.rtdm_step(ctx.h, 0.05, 1)

@@ -1,6 +1,8 @@
 """Caller-owned device memory: after rtdm_bind_workspace every buffer of the
 context lives in one torch allocation, and the results are bit-identical to
-the same run on the library's own allocations."""
+the same run on the library's own allocations; loading again moves the
+buffers out first.  Contexts take their memory from PyTorch's caching
+allocator by default (rtdm_set_allocator), with the same results."""
 
 import numpy as np
 import pytest
@@ -12,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _run(s, bind, use_graph=0, **opts):
-    ctx = gpu_context(s, h_model=s.h_model, use_graph=use_graph, **opts)
+    ctx = gpu_context(s, h_model=s.h_model, use_graph=use_graph, memory="library", **opts)
     n = ctx.bind_workspace() if bind else 0
     rtdm.rtdm_build_inverse(ctx.h)
     rtdm.rtdm_apply_kick(ctx.h, s.kappa)
@@ -45,7 +47,7 @@ def test_bound_workspace_gives_identical_results(which, use_graph):
 def test_too_small_or_foreign_workspace_is_refused():
     import torch
     s = synth.config1()
-    ctx = gpu_context(s)
+    ctx = gpu_context(s, memory="library")
     n = rtdm.rtdm_workspace_size(ctx.h)
     live = n - (64 << 20)               # the size includes a 64 MiB reserve
     small = torch.empty(live // 2, dtype=torch.uint8, device="cuda:0")
@@ -68,7 +70,7 @@ def test_workspace_without_reserve_suffices_for_inverse_and_steps():
     import torch
     s = synth.diamond_lattice((2, 2, 2), 13, 10.0, 16.0, seed=25, k0="local", h_model="mulliken")
     ref, _ = _run(s, False)
-    ctx = gpu_context(s, h_model="mulliken")
+    ctx = gpu_context(s, h_model="mulliken", memory="library")
     live = rtdm.rtdm_workspace_size(ctx.h) - (64 << 20)
     ws = torch.empty(live, dtype=torch.uint8, device="cuda:0")
     rtdm.rtdm_bind_workspace(ctx.h, ws.data_ptr(), live)
@@ -79,3 +81,61 @@ def test_workspace_without_reserve_suffices_for_inverse_and_steps():
     K = rtdm.rtdm_download(ctx.h, "K", s.b)
     ctx.close()
     assert np.array_equal(K, ref[0])
+
+
+def test_reload_in_a_bound_context_and_reserved_trace():
+    """A bound context loads another system (its buffers move out of the
+    workspace, the new system's set-up runs, a new workspace is bound) and
+    then steps exactly as a fresh context does; with the trace reserved, the
+    steps add no buffer (the context's memory total stays the same)."""
+    a = synth.config1()
+    b = synth.diamond_lattice((2, 2, 2), 13, 10.0, 16.0, seed=27, k0="local", h_model="mulliken")
+    ref, _ = _run(b, False)
+    ctx = gpu_context(a, h_model="mulliken")
+    ctx.bind_workspace()
+    rtdm.rtdm_build_inverse(ctx.h)
+    rtdm.rtdm_step(ctx.h, a.dt, 2)
+    ctx.load_system(b)                          # moves the buffers out of the region first
+    assert ctx.workspace is None
+    ctx.bind_workspace()
+    rtdm.rtdm_reserve_trace(ctx.h, 4096)
+    size0 = rtdm.rtdm_workspace_size(ctx.h)
+    rtdm.rtdm_build_inverse(ctx.h)
+    rtdm.rtdm_apply_kick(ctx.h, b.kappa)
+    rtdm.rtdm_step(ctx.h, b.dt, 3)
+    rtdm.rtdm_step(ctx.h, b.dt, 4)
+    assert rtdm.rtdm_workspace_size(ctx.h) == size0
+    K = rtdm.rtdm_download(ctx.h, "K", b.b)
+    tr = rtdm.rtdm_dipole_trace(ctx.h)
+    rtdm.rtdm_unbind_workspace(ctx.h)
+    ctx.workspace = None
+    with pytest.raises(rtdm.RtdmError):
+        rtdm.rtdm_unbind_workspace(ctx.h)
+    rtdm.rtdm_step(ctx.h, b.dt, 1)             # still steps on the library's own memory
+    ctx.close()
+    assert np.array_equal(K, ref[0])
+    assert np.array_equal(tr[:, :6], ref[1][:, :6])
+
+
+def test_torch_allocator_holds_the_context_and_gives_identical_results():
+    """With the default memory="torch" every buffer is a PyTorch caching
+    allocation: torch's allocated bytes grow by the context's total on load
+    and fall back on close, and the run equals the one on hipMalloc memory."""
+    import torch
+    s = synth.diamond_lattice((2, 2, 2), 13, 10.0, 16.0, seed=28, k0="local", h_model="mulliken")
+    ref, _ = _run(s, False)
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated(0)
+    ctx = gpu_context(s, h_model="mulliken")
+    total = rtdm.rtdm_workspace_size(ctx.h) - (64 << 20)
+    assert torch.cuda.memory_allocated(0) - before >= total
+    rtdm.rtdm_build_inverse(ctx.h)
+    rtdm.rtdm_apply_kick(ctx.h, s.kappa)
+    rtdm.rtdm_step(ctx.h, s.dt, 3)
+    rtdm.rtdm_step(ctx.h, s.dt, 4)
+    K = rtdm.rtdm_download(ctx.h, "K", s.b)
+    tr = rtdm.rtdm_dipole_trace(ctx.h)
+    ctx.close()
+    assert torch.cuda.memory_allocated(0) == before
+    assert np.array_equal(K, ref[0])
+    assert np.array_equal(tr[:, :6], ref[1][:, :6])
