@@ -1136,6 +1136,70 @@ __global__ __launch_bounds__(256) void k_spgemm_b4w(
     }
 }
 
+// The entries [e0, e1) (every `stride`-th) of one b = 4 row run, software
+// pipelined: the indices of entry e + 2 and the operands of entry e + 1 are
+// requested before the products of entry e, so that a wave has the next
+// entry's loads in flight while its products run (the loads return in order,
+// so waiting for an entry's operands never waits for later requests).  The
+// products are issued in the same order as a plain loop over the entries.
+template <bool AC, bool BC>
+__device__ inline void b4_run_entries(int64_t e0, int64_t e1, int stride, const int32_t *__restrict__ ea,
+                                      const int32_t *__restrict__ eb, const double *__restrict__ ar,
+                                      const double *__restrict__ ai, const double *__restrict__ br,
+                                      const double *__restrict__ bi, int ia, int ib, int g, double cb,
+                                      double rr[4], double ii[4], double ri[4], double ir[4])
+{
+    struct Ops {
+        double xar, xai, xbr[4], xbi[4];
+    };
+    auto load_idx = [&](int64_t e, int &a, int4 &kb) {
+        a = ea[e];
+        kb = *reinterpret_cast<const int4 *>(eb + e * 16 + g * 4);
+    };
+    auto load_ops = [&](int a, int4 kb4, Ops &o) {
+        const int64_t pa = (int64_t)a * 16 + ia;
+        o.xar = ar[pa];
+        o.xai = AC ? ai[pa] : 0.0;
+        const int kb[4] = {kb4.x, kb4.y, kb4.z, kb4.w};
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            o.xbr[jj] = o.xbi[jj] = 0.0;
+            if (kb[jj] >= 0) {
+                const int64_t pb = (int64_t)kb[jj] * 16 + ib;
+                o.xbr[jj] = br[pb];
+                if (BC) o.xbi[jj] = cb * bi[pb];
+            }
+        }
+    };
+    if (e0 >= e1) return;
+    Ops cur, nxt;
+    int a_n = 0;
+    int4 kb_n = make_int4(-1, -1, -1, -1);
+    {
+        int a0;
+        int4 k0;
+        load_idx(e0, a0, k0);
+        if (e0 + stride < e1) load_idx(e0 + stride, a_n, kb_n);
+        load_ops(a0, k0, cur);
+    }
+    for (int64_t e = e0; e < e1; e += stride) {
+        int a_nn = 0;
+        int4 kb_nn = make_int4(-1, -1, -1, -1);
+        if (e + 2 * stride < e1) load_idx(e + 2 * stride, a_nn, kb_nn);
+        if (e + stride < e1) load_ops(a_n, kb_n, nxt);
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            rr[jj] = __builtin_amdgcn_mfma_f64_4x4x4f64(cur.xar, cur.xbr[jj], rr[jj], 0, 0, 0);
+            if (AC && BC) ii[jj] = __builtin_amdgcn_mfma_f64_4x4x4f64(cur.xai, cur.xbi[jj], ii[jj], 0, 0, 0);
+            if (BC) ri[jj] = __builtin_amdgcn_mfma_f64_4x4x4f64(cur.xar, cur.xbi[jj], ri[jj], 0, 0, 0);
+            if (AC) ir[jj] = __builtin_amdgcn_mfma_f64_4x4x4f64(cur.xai, cur.xbr[jj], ir[jj], 0, 0, 0);
+        }
+        cur = nxt;
+        a_n = a_nn;
+        kb_n = kb_nn;
+    }
+}
+
 // FP64 b = 4 product over row runs of 16 outputs (SpgemmArgs::ch_*, slots in
 // the lane order below): one wave per run.  Each entry k of the run is one
 // triple step: every lane loads the same op(A)_ik element position (one
@@ -1158,32 +1222,8 @@ __global__ __launch_bounds__(256) void k_spgemm_b4j(
     const int ia = r * 4 + q;                          // A[r][q]
     const int ib = OPB ? (r * 4 + q) : (q * 4 + r);    // op(B)[q][r]
     const double cb = OPB ? -1.0 : 1.0;
-    const int64_t e0 = off[c], e1 = off[c + 1];
     double rr[4] = {0, 0, 0, 0}, ii[4] = {0, 0, 0, 0}, ri[4] = {0, 0, 0, 0}, ir[4] = {0, 0, 0, 0};
-    for (int64_t e = e0; e < e1; ++e) {
-        const int64_t pa = (int64_t)ea[e] * 16 + ia;
-        const double xar = ar[pa];
-        const double xai = AC ? ai[pa] : 0.0;
-        const int4 kb4 = *reinterpret_cast<const int4 *>(eb + e * 16 + g * 4);
-        const int kb[4] = {kb4.x, kb4.y, kb4.z, kb4.w};
-        double xbr[4], xbi[4];
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-            xbr[jj] = xbi[jj] = 0.0;
-            if (kb[jj] >= 0) {
-                const int64_t pb = (int64_t)kb[jj] * 16 + ib;
-                xbr[jj] = br[pb];
-                if (BC) xbi[jj] = cb * bi[pb];
-            }
-        }
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-            rr[jj] = __builtin_amdgcn_mfma_f64_4x4x4f64(xar, xbr[jj], rr[jj], 0, 0, 0);
-            if (AC && BC) ii[jj] = __builtin_amdgcn_mfma_f64_4x4x4f64(xai, xbi[jj], ii[jj], 0, 0, 0);
-            if (BC) ri[jj] = __builtin_amdgcn_mfma_f64_4x4x4f64(xar, xbi[jj], ri[jj], 0, 0, 0);
-            if (AC) ir[jj] = __builtin_amdgcn_mfma_f64_4x4x4f64(xai, xbr[jj], ir[jj], 0, 0, 0);
-        }
-    }
+    b4_run_entries<AC, BC>(off[c], off[c + 1], 1, ea, eb, ar, ai, br, bi, ia, ib, g, cb, rr, ii, ri, ir);
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj) {
         const int p = cout[c * 16 + 4 * jj + g];
@@ -1216,32 +1256,8 @@ __global__ __launch_bounds__(256) void k_spgemm_b4js(
     const int ia = r * 4 + q;
     const int ib = OPB ? (r * 4 + q) : (q * 4 + r);
     const double cb = OPB ? -1.0 : 1.0;
-    const int64_t e0 = off[c], e1 = off[c + 1];
     double rr[4] = {0, 0, 0, 0}, ii[4] = {0, 0, 0, 0}, ri[4] = {0, 0, 0, 0}, ir[4] = {0, 0, 0, 0};
-    for (int64_t e = e0 + wv; e < e1; e += 4) {
-        const int64_t pa = (int64_t)ea[e] * 16 + ia;
-        const double xar = ar[pa];
-        const double xai = AC ? ai[pa] : 0.0;
-        const int4 kb4 = *reinterpret_cast<const int4 *>(eb + e * 16 + g * 4);
-        const int kb[4] = {kb4.x, kb4.y, kb4.z, kb4.w};
-        double xbr[4], xbi[4];
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-            xbr[jj] = xbi[jj] = 0.0;
-            if (kb[jj] >= 0) {
-                const int64_t pb = (int64_t)kb[jj] * 16 + ib;
-                xbr[jj] = br[pb];
-                if (BC) xbi[jj] = cb * bi[pb];
-            }
-        }
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-            rr[jj] = __builtin_amdgcn_mfma_f64_4x4x4f64(xar, xbr[jj], rr[jj], 0, 0, 0);
-            if (AC && BC) ii[jj] = __builtin_amdgcn_mfma_f64_4x4x4f64(xai, xbi[jj], ii[jj], 0, 0, 0);
-            if (BC) ri[jj] = __builtin_amdgcn_mfma_f64_4x4x4f64(xar, xbi[jj], ri[jj], 0, 0, 0);
-            if (AC) ir[jj] = __builtin_amdgcn_mfma_f64_4x4x4f64(xai, xbr[jj], ir[jj], 0, 0, 0);
-        }
-    }
+    b4_run_entries<AC, BC>(off[c] + wv, off[c + 1], 4, ea, eb, ar, ai, br, bi, ia, ib, g, cb, rr, ii, ri, ir);
     auto pack = [&](double (*dst)[64]) {
         int k = 0;
 #pragma unroll
