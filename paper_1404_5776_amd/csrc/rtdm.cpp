@@ -372,11 +372,13 @@ namespace {
 
 void set_device(rtdm_ctx *c) { RT_HIP(hipSetDevice(c->device)); }
 
-// Centroid of atoms i0 .. i1-1: each coordinate sum accumulated without
-// rounding error (Knuth's two-sum, the error terms carried in a second
-// double), rounded once, then divided by the count.  Every implementation
-// that rounds the exact sum once gets the same centroid, so the dipole
-// about it does not depend on the summation order of the positions.
+// Centroid of atoms i0 .. i1-1: each coordinate summed with compensation
+// (Knuth's two-sum on every addition, the error terms accumulated in a second
+// double), rounded once, then divided by the count.  For atom coordinates the
+// error terms are far below the sum's last digit, so this is the correctly
+// rounded sum, which every implementation that rounds the exact sum once
+// also gets: the dipole about the centroid then does not depend on the
+// summation order of the positions.
 void exact_centre(const std::vector<double> &xyz, int64_t i0, int64_t i1, double out[3])
 {
     for (int k = 0; k < 3; ++k) {

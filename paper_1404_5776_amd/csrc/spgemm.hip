@@ -1621,11 +1621,9 @@ __global__ __launch_bounds__(256) void k_spgemm_b4r32(
     }
     const int slot = (blk & 3) * 4 + (blk >> 2);
     f32x4 h = {0, 0, 0, 0};
-    for (int t = 0; t < ntmax; ++t) {
-        int2 ab = make_int2(0, -1);
-        if (RUNS) ab = make_int2(ea[t0 + t], eb[(t0 + t) * 16 + slot]);
-        else if (t < nt) ab = trip[t0 + t];
-        float xa[4] = {0, 0, 0, 0}, xb[4] = {0, 0, 0, 0};
+    auto load_ops = [&](int2 ab, float (&xa)[4], float (&xb)[4]) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) xa[k] = xb[k] = 0.0f;
         if (ab.y >= 0) {
             const f32x4 ar4 = *reinterpret_cast<const f32x4 *>(a + (int64_t)ab.x * 16 + r * 4);   // A[r][0..3]
             const int64_t pb = (int64_t)ab.y * 16 + r;
@@ -1635,8 +1633,40 @@ __global__ __launch_bounds__(256) void k_spgemm_b4r32(
                 xb[k] = b[pb + k * 4];                                                         // B[k][r]
             }
         }
+    };
+    if constexpr (RUNS) {
+        // software pipeline as in b4_run_entries: indices two entries ahead,
+        // operands one entry ahead, products in entry order
+        auto load_idx = [&](int t) { return make_int2(ea[t0 + t], eb[(t0 + t) * 16 + slot]); };
+        if (nt > 0) {
+            float xa[4], xb[4];
+            int2 ab_n = make_int2(0, -1);
+            const int2 ab0 = load_idx(0);
+            if (1 < nt) ab_n = load_idx(1);
+            load_ops(ab0, xa, xb);
+            for (int t = 0; t < nt; ++t) {
+                int2 ab_nn = make_int2(0, -1);
+                if (t + 2 < nt) ab_nn = load_idx(t + 2);
+                float na[4] = {0, 0, 0, 0}, nb[4] = {0, 0, 0, 0};
+                if (t + 1 < nt) load_ops(ab_n, na, nb);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) h = __builtin_amdgcn_mfma_f32_4x4x1f32(xa[k], xb[k], h, 0, 0, 0);
+                for (int k = 0; k < 4; ++k) h = __builtin_amdgcn_mfma_f32_4x4x1f32(xa[k], xb[k], h, 0, 0, 0);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    xa[k] = na[k];
+                    xb[k] = nb[k];
+                }
+                ab_n = ab_nn;
+            }
+        }
+    } else {
+        for (int t = 0; t < ntmax; ++t) {
+            const int2 ab = t < nt ? trip[t0 + t] : make_int2(0, -1);
+            float xa[4], xb[4];
+            load_ops(ab, xa, xb);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) h = __builtin_amdgcn_mfma_f32_4x4x1f32(xa[k], xb[k], h, 0, 0, 0);
+        }
     }
     if (!live) return;
 #pragma unroll
