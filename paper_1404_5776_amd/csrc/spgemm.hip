@@ -1137,12 +1137,14 @@ __global__ __launch_bounds__(256) void k_spgemm_b4w(
 }
 
 // The entries [e0, e1) (every `stride`-th) of one b = 4 row run, software
-// pipelined: the indices of entry e + 2 and the operands of entry e + 1 are
-// requested before the products of entry e, so that a wave has the next
-// entry's loads in flight while its products run (the loads return in order,
-// so waiting for an entry's operands never waits for later requests).  The
-// products are issued in the same order as a plain loop over the entries.
-template <bool AC, bool BC>
+// pipelined (complex x complex only in the split form for few runs, where
+// latency and not occupancy decides): the indices of entry e + 2 and the operands of
+// entry e + 1 are requested before the products of entry e, so that a wave
+// has the next entry's loads in flight while its products run (the loads
+// return in order, so waiting for an entry's operands never waits for later
+// requests).  The products are issued in the same order as a plain loop over
+// the entries.
+template <bool AC, bool BC, bool PIPE_CPLX>
 __device__ inline void b4_run_entries(int64_t e0, int64_t e1, int stride, const int32_t *__restrict__ ea,
                                       const int32_t *__restrict__ eb, const double *__restrict__ ar,
                                       const double *__restrict__ ai, const double *__restrict__ br,
@@ -1172,6 +1174,26 @@ __device__ inline void b4_run_entries(int64_t e0, int64_t e1, int stride, const 
         }
     };
     if (e0 >= e1) return;
+    if constexpr (AC && BC && !PIPE_CPLX) {
+        // complex x complex over many runs: twice the operand registers; the
+        // pipeline's extra set cost waves per SIMD and made these products
+        // slower, so they take the entries one at a time
+        for (int64_t e = e0; e < e1; e += stride) {
+            int a;
+            int4 kb;
+            Ops o;
+            load_idx(e, a, kb);
+            load_ops(a, kb, o);
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                rr[jj] = __builtin_amdgcn_mfma_f64_4x4x4f64(o.xar, o.xbr[jj], rr[jj], 0, 0, 0);
+                ii[jj] = __builtin_amdgcn_mfma_f64_4x4x4f64(o.xai, o.xbi[jj], ii[jj], 0, 0, 0);
+                ri[jj] = __builtin_amdgcn_mfma_f64_4x4x4f64(o.xar, o.xbi[jj], ri[jj], 0, 0, 0);
+                ir[jj] = __builtin_amdgcn_mfma_f64_4x4x4f64(o.xai, o.xbr[jj], ir[jj], 0, 0, 0);
+            }
+        }
+        return;
+    }
     Ops cur, nxt;
     int a_n = 0;
     int4 kb_n = make_int4(-1, -1, -1, -1);
@@ -1223,7 +1245,7 @@ __global__ __launch_bounds__(256) void k_spgemm_b4j(
     const int ib = OPB ? (r * 4 + q) : (q * 4 + r);    // op(B)[q][r]
     const double cb = OPB ? -1.0 : 1.0;
     double rr[4] = {0, 0, 0, 0}, ii[4] = {0, 0, 0, 0}, ri[4] = {0, 0, 0, 0}, ir[4] = {0, 0, 0, 0};
-    b4_run_entries<AC, BC>(off[c], off[c + 1], 1, ea, eb, ar, ai, br, bi, ia, ib, g, cb, rr, ii, ri, ir);
+    b4_run_entries<AC, BC, false>(off[c], off[c + 1], 1, ea, eb, ar, ai, br, bi, ia, ib, g, cb, rr, ii, ri, ir);
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj) {
         const int p = cout[c * 16 + 4 * jj + g];
@@ -1257,7 +1279,7 @@ __global__ __launch_bounds__(256) void k_spgemm_b4js(
     const int ib = OPB ? (r * 4 + q) : (q * 4 + r);
     const double cb = OPB ? -1.0 : 1.0;
     double rr[4] = {0, 0, 0, 0}, ii[4] = {0, 0, 0, 0}, ri[4] = {0, 0, 0, 0}, ir[4] = {0, 0, 0, 0};
-    b4_run_entries<AC, BC>(off[c] + wv, off[c + 1], 4, ea, eb, ar, ai, br, bi, ia, ib, g, cb, rr, ii, ri, ir);
+    b4_run_entries<AC, BC, true>(off[c] + wv, off[c + 1], 4, ea, eb, ar, ai, br, bi, ia, ib, g, cb, rr, ii, ri, ir);
     auto pack = [&](double (*dst)[64]) {
         int k = 0;
 #pragma unroll
