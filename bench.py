@@ -36,13 +36,19 @@ FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 (matrix and vector)
 KERNEL_TAG = "q4j-b13-nj2seg-xcdchunk128-tile256-v1"
 
 
-def measured_traffic(dom):
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+# The same for the real b = 4 run kernel on the 32,768-atom lattice at R_K 12.
+KERNEL_TAG_B4 = "b4j-runs16-pipelined-real-v1"
+
+
+def measured_traffic(dom, name="traffic.json", tag=KERNEL_TAG, workload=None):
+    path = os.path.join(ROOT, "profiles", name)
     try:
         t = json.load(open(path))
     except (OSError, ValueError):
         return None
-    if t.get("kernel_tag") != KERNEL_TAG or t.get("product") != dom:
+    if t.get("kernel_tag") != tag or t.get("product") != dom:
+        return None
+    if workload is not None and t.get("workload") != workload:
         return None
     return t["bytes_per_launch"]
 METRIC = "propagation steps/s + block-SpGEMM GFLOP/s (% roofline) at stated dipole error vs FP64"
@@ -291,12 +297,18 @@ def b4_leg(args):
         dom = max(stats, key=lambda k: stats[k][1])
         n_l, ms, fl = stats[dom]
         ach = fl / n_l / (ms / 1e3 / n_l) / 1e12
+        roof = {"bound": "mfma", "kernel": f"k_spgemm_b4j ({dom} product)", "achieved": ach,
+                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS,
+                "avg_launch_ms": ms / n_l, "flops_per_launch": fl / n_l,
+                "traffic": measured_traffic(dom, "traffic_b4.json", KERNEL_TAG_B4, key),
+                "traffic_unit": "bytes per launch"}
+        if roof["traffic"] is not None:
+            roof["beyond_l2_gb_per_s"] = roof["traffic"] / (ms / 1e3 / n_l) / 1e9
+            roof["beyond_l2_frac_of_hbm_peak"] = roof["beyond_l2_gb_per_s"] / 8000.0
         out[key] = {"atoms": s.n_atoms, "b": s.b, "R_HS": s.R_HS, "R_K": s.R_K, "steps": sub.steps,
                     "steps_per_s": sub.steps / r["elapsed"],
                     "per_product_ms": {k: v[1] / max(v[0], 1) for k, v in stats.items()},
-                    "roofline": {"bound": "mfma", "kernel": f"k_spgemm_b4j ({dom} product)", "achieved": ach,
-                                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS,
-                                 "avg_launch_ms": ms / n_l, "flops_per_launch": fl / n_l}}
+                    "roofline": roof}
         log(f"b4 {key}: {out[key]['steps_per_s']:.2f} steps/s, {dom} {out[key]['roofline']['frac']:.3f} of peak")
     return out
 
