@@ -256,21 +256,34 @@ def small_leg(args):
     out = {"workload": f"cluster {s.n_atoms} atoms x {s.b} functions, R_HS {s.R_HS} R_K {s.R_K} bohr, "
                        f"fixed H, EM + Taylor p=5, dt {s.dt}, {s.n_steps} steps",
            "graph_steps": args.small_graph_steps}
+    import gc
     traces = {}
+    reps = 5
+    out["timing"] = (f"median over {reps} consecutive calls of {s.n_steps} steps each (a call of 100 steps "
+                     f"lasts about 5 ms, so one host hiccup would otherwise decide it); Python's collector "
+                     f"paused while timing")
     for use_graph in (0, 1):
         ctx = rtdm.Context(0, use_graph=use_graph, graph_steps=args.small_graph_steps)
         ctx.load_system(s, stream)
+        rtdm.rtdm_reserve_trace(ctx.h, 1 + args.small_graph_steps + reps * s.n_steps)
         rtdm.rtdm_build_inverse(ctx.h, stream)
         rtdm.rtdm_apply_kick(ctx.h, s.kappa, stream)
         rtdm.rtdm_step(ctx.h, s.dt, 1 + args.small_graph_steps, stream)      # U, capture, one replay
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rtdm.rtdm_step(ctx.h, s.dt, s.n_steps, stream)
-        torch.cuda.synchronize()
-        dt_s = time.perf_counter() - t0
+        gc.collect()
+        gc.disable()
+        try:
+            times = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                rtdm.rtdm_step(ctx.h, s.dt, s.n_steps, stream)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+        finally:
+            gc.enable()
         traces[use_graph] = rtdm.rtdm_dipole_trace(ctx.h)
         ctx.close()
-        out["graph_steps_per_s" if use_graph else "eager_steps_per_s"] = s.n_steps / dt_s
+        out["graph_steps_per_s" if use_graph else "eager_steps_per_s"] = s.n_steps / float(np.median(times))
     out["speedup_graph_vs_eager"] = out["graph_steps_per_s"] / out["eager_steps_per_s"]
     out["bit_identical_trace"] = bool(np.array_equal(traces[0][:, :6], traces[1][:, :6]))
     log(f"small system: {out}")
