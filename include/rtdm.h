@@ -356,7 +356,9 @@ int rtdm_bind_workspace(rtdm_ctx *ctx, void *ptr, size_t bytes);
  * allocator): from now on every buffer of the context is alloc_fn(bytes,
  * user) (NULL means out of memory: RTDM_E_OOM; 256-byte alignment required)
  * and is given back with free_fn(ptr, user) when the context releases it
- * (set-up calls, destroy; never inside rtdm_step).  The buffers allocated so
+ * (set-up calls, growth of the observable trace, temporaries of calls such as
+ * rtdm_multiply, destroy), after a device synchronisation, so that the
+ * allocator may reuse it at once on any stream.  The buffers allocated so
  * far move into such allocations.  Once per context (RTDM_E_STATE after that
  * or while a workspace is bound); free_fn must stay callable until
  * rtdm_destroy returns.  Called from the thread of the API call that

@@ -73,6 +73,10 @@ void devmem_free(DBufBase *b, void *p)
         if (m && static_cast<char *>(p) + b->nbytes == m->base + m->used)
             m->used = (size_t)(static_cast<char *>(p) - m->base);
     } else if (b->ext) {
+        // the caller's allocator may hand the memory out again at once (a
+        // caching allocator does, to work ordered on another stream): let every
+        // kernel that may still use it finish first
+        (void)hipDeviceSynchronize();
         m->ext_free(p, m->ext_user);
     } else {
         (void)hipFree(p);
@@ -960,6 +964,8 @@ void ensure_obs(rtdm_ctx *c, int64_t rows)
         return;
     int64_t cap = std::max<int64_t>(2 * c->obs_cap, 1024);
     while (cap < rows) cap *= 2;
+    // earlier steps may still write rows on the caller's stream: let them land
+    RT_HIP(hipDeviceSynchronize());
     // one trace of cap rows per kick, each kick's rows contiguous
     DBuf<double> nb;
     nb.alloc(cap * 8 * NK);

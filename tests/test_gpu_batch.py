@@ -216,3 +216,23 @@ def test_batch_step_refuses_unitarity_checks():
     finally:
         rtdm.rtdm_batch_destroy(bt)
         ctx.close()
+
+
+def test_batch_of_one_context_equals_rtdm_step():
+    s = synth.diamond_lattice((2, 2, 2), 13, 10.0, 16.0, seed=29, k0="local", h_model="mulliken")
+    K_e, tr_e = _run(s, (7, 9), False, h_model="mulliken")
+    ctx = gpu_context(s, h_model="mulliken")
+    rtdm.rtdm_build_inverse(ctx.h)
+    rtdm.rtdm_apply_kick(ctx.h, s.kappa)
+    bt = rtdm.rtdm_batch_create([ctx.h], graph_steps=3)
+    try:
+        for n in (7, 9):
+            rtdm.rtdm_batch_step(bt, s.dt, n)
+            rtdm.rtdm_observables(ctx.h)
+        K = rtdm.rtdm_download(ctx.h, "K", s.b)
+        tr = rtdm.rtdm_dipole_trace(ctx.h)
+    finally:
+        rtdm.rtdm_batch_destroy(bt)
+        ctx.close()
+    assert np.array_equal(K, K_e)
+    assert np.array_equal(tr[:, :6], tr_e[:, :6])

@@ -107,3 +107,33 @@ def test_kick_sets_refuse_a_k_dependent_propagator():
     with pytest.raises(rtdm.RtdmError):
         rtdm.rtdm_set_state(ctx.h, np.zeros(2 + 3 * ctx.batch_xyz.shape[0]))
     ctx.close()
+
+
+def test_kick_sets_with_unitarity_checks_record_every_set():
+    """With unit_check_every = 2 the unitarity error of the shared propagator
+    lands in the trace of every kick set (the same value), and each set's
+    dipole rows still equal a one-kick run's."""
+    systems = small_clusters(4)[:2]
+    ctx = rtdm.Context(0, h_model="fixed", n_kicks=len(KICKS), unit_check_every=2)
+    ctx.load_kick_sets(systems, KICKS)
+    rtdm.rtdm_build_inverse(ctx.h)
+    rtdm.rtdm_apply_kicks(ctx.h, ctx.kick_vectors)
+    rtdm.rtdm_step(ctx.h, DT, 6)
+    traces = []
+    for k in range(len(KICKS)):
+        rtdm.rtdm_select_kick(ctx.h, k)
+        traces.append(rtdm.rtdm_dipole_trace(ctx.h))
+    ctx.close()
+    u = traces[0][:, 6]
+    assert np.all(np.isfinite(u[1::2])) and np.all(np.isnan(u[0::2]))
+    for k, kap in enumerate(KICKS):
+        assert np.array_equal(traces[k][:, 6], u, equal_nan=True)
+        one = rtdm.Context(0, h_model="fixed", unit_check_every=2)
+        one.load_batch(systems, [[(0.0, 0.0, 0.0)]] * len(systems))
+        rtdm.rtdm_build_inverse(one.h)
+        rtdm.rtdm_apply_kick(one.h, kap)
+        rtdm.rtdm_step(one.h, DT, 6)
+        tr1 = rtdm.rtdm_dipole_trace(one.h)
+        one.close()
+        assert np.array_equal(traces[k][:, :6], tr1[:, :6]), k
+        assert np.array_equal(traces[k][:, 6], tr1[:, 6], equal_nan=True), k

@@ -77,3 +77,33 @@ def test_mixed_sizes_refuse_what_they_do_not_support():
     with pytest.raises(rtdm.RtdmError):
         rtdm.rtdm_download(ctx.h, "K", 13, out=dev)
     ctx.close()
+
+
+def test_mixed_sizes_with_kick_sets_equal_one_kick_runs():
+    """Kick sets on a mixed-size system: each set equals a one-kick context
+    bit for bit, and the x set matches the mixed-size oracle."""
+    ms = synth.mixed_cluster(40, 13)
+    kicks = [(0.01, 0.0, 0.0), (0.0, 0.01, 0.0), (0.0, 0.0, 0.01)]
+    ctx = rtdm.Context(0, n_kicks=3).load_mixed(ms)
+    rtdm.rtdm_build_inverse(ctx.h)
+    rtdm.rtdm_apply_kicks(ctx.h, kicks)
+    rtdm.rtdm_step(ctx.h, 0.05, 5)
+    sets = []
+    for k in range(3):
+        rtdm.rtdm_select_kick(ctx.h, k)
+        sets.append((rtdm.rtdm_download_mixed(ctx.h, "K", ms.nbf)[0], rtdm.rtdm_dipole_trace(ctx.h)[:, :6]))
+    rk, ck = _blocks(ctx, "K", None)
+    ctx.close()
+    for k, kap in enumerate(kicks):
+        one = rtdm.Context(0).load_mixed(ms)
+        rtdm.rtdm_build_inverse(one.h)
+        rtdm.rtdm_apply_kick(one.h, kap)
+        rtdm.rtdm_step(one.h, 0.05, 5)
+        K1 = rtdm.rtdm_download_mixed(one.h, "K", ms.nbf)[0]
+        tr1 = rtdm.rtdm_dipole_trace(one.h)[:, :6]
+        one.close()
+        assert np.array_equal(sets[k][0], K1), k
+        assert np.array_equal(sets[k][1], tr1), k
+    mt = M.setup(ms)
+    ref = M.propagate(mt, 5, 0.05, kicks[0])
+    assert rel(sets[0][0], M.to_blocks(ref.K, mt.off, rk, ck)) <= TOL

@@ -139,3 +139,28 @@ def test_torch_allocator_holds_the_context_and_gives_identical_results():
     assert torch.cuda.memory_allocated(0) == before
     assert np.array_equal(K, ref[0])
     assert np.array_equal(tr[:, :6], ref[1][:, :6])
+
+
+def test_torch_allocator_on_a_side_stream_with_graphs():
+    """Steps issued on a torch side stream (captured graphs on it) with the
+    context's memory from torch's caching allocator give the trace of steps
+    on the default stream, and torch tensors allocated on that stream in
+    between do not disturb them."""
+    import torch
+    s = synth.config1()
+    ref, _ = _run(s, False)
+    side = torch.cuda.Stream()
+    ctx = gpu_context(s, h_model=s.h_model, use_graph=1, graph_steps=2)
+    with torch.cuda.stream(side):
+        rtdm.rtdm_build_inverse(ctx.h, side)
+        rtdm.rtdm_apply_kick(ctx.h, s.kappa, side)
+        rtdm.rtdm_step(ctx.h, s.dt, 3, side)
+        junk = torch.randn(1 << 20, device="cuda:0")      # caching-allocator traffic on the same stream
+        rtdm.rtdm_step(ctx.h, s.dt, 4, side)
+        del junk
+    side.synchronize()
+    K = rtdm.rtdm_download(ctx.h, "K", s.b)
+    tr = rtdm.rtdm_dipole_trace(ctx.h)
+    ctx.close()
+    assert np.array_equal(K, ref[0])
+    assert np.array_equal(tr[:, :6], ref[1][:, :6])
