@@ -1259,19 +1259,19 @@ __global__ __launch_bounds__(256) void k_spgemm_b4j(
 }
 
 // The same product for products with few runs (small systems): one
-// workgroup per run, its four waves taking every fourth entry (wave w the
-// entries w, w + 4, ...), so that a run's chain of dependent loads is a
-// quarter as long and four times as many waves share the chip.  The waves'
-// partial sums are added in LDS in the fixed order w = 0, 1, 2, 3.
-template <bool AC, bool BC, int OPB>
-__global__ __launch_bounds__(256) void k_spgemm_b4js(
+// workgroup of W waves per run, wave w taking the entries w, w + W, ..., so
+// that a run's chain of dependent loads is 1/W as long and W times as many
+// waves share the chip.  The waves' partial sums are added in LDS in the
+// fixed order w = 0, 1, ..., W - 1.
+template <bool AC, bool BC, int OPB, int W>
+__global__ __launch_bounds__(64 * W) void k_spgemm_b4js(
     int64_t nch, const int64_t *__restrict__ off, const int32_t *__restrict__ ea,
     const int32_t *__restrict__ eb, const int32_t *__restrict__ cout, const double *__restrict__ ar,
     const double *__restrict__ ai, const double *__restrict__ br, const double *__restrict__ bi,
     double *__restrict__ cr, double *__restrict__ ci, double alr, double ali)
 {
     constexpr int NACC = 1 + (AC && BC) + BC + AC;   // accumulators per output: rr, ii, ri, ir
-    __shared__ double part[3][NACC * 4][64];
+    __shared__ double part[W - 1][NACC * 4][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int g = (lane >> 2) & 3, r = lane & 3, q = lane >> 4;
     const int64_t c = blockIdx.x;              // grid = nch: uniform across the workgroup
@@ -1279,7 +1279,7 @@ __global__ __launch_bounds__(256) void k_spgemm_b4js(
     const int ib = OPB ? (r * 4 + q) : (q * 4 + r);
     const double cb = OPB ? -1.0 : 1.0;
     double rr[4] = {0, 0, 0, 0}, ii[4] = {0, 0, 0, 0}, ri[4] = {0, 0, 0, 0}, ir[4] = {0, 0, 0, 0};
-    b4_run_entries<AC, BC, true>(off[c] + wv, off[c + 1], 4, ea, eb, ar, ai, br, bi, ia, ib, g, cb, rr, ii, ri, ir);
+    b4_run_entries<AC, BC, true>(off[c] + wv, off[c + 1], W, ea, eb, ar, ai, br, bi, ia, ib, g, cb, rr, ii, ri, ir);
     auto pack = [&](double (*dst)[64]) {
         int k = 0;
 #pragma unroll
@@ -1294,7 +1294,7 @@ __global__ __launch_bounds__(256) void k_spgemm_b4js(
     __syncthreads();
     if (wv != 0) return;
 #pragma unroll
-    for (int w = 0; w < 3; ++w) {
+    for (int w = 0; w < W - 1; ++w) {
         int k = 0;
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
@@ -1317,16 +1317,24 @@ __global__ __launch_bounds__(256) void k_spgemm_b4js(
 }
 
 // Below this many runs a product takes the split form (one run per
-// workgroup): a wave per run would leave most of the 1,024 SIMDs idle.
-constexpr int64_t kB4SplitRuns = 4096;
+// workgroup): a wave per run would leave most of the 1,024 SIMDs idle.  Below
+// kB4Split8Runs the runs are split over 8 waves instead of 4.
+constexpr int64_t kB4SplitRuns = 4096, kB4Split8Runs = 1024;
 
 template <bool AC, bool BC, int OB>
 static void launch_b4j(hipStream_t s, const SpgemmArgs &a)
 {
     RT_CHECK(a.nj == 16, RTDM_E_ARG, "b = 4 row runs hold 16 outputs");
+    if (a.nch < kB4Split8Runs) {
+        hipLaunchKernelGGL((k_spgemm_b4js<AC, BC, OB, 8>), dim3((unsigned)a.nch), dim3(512), 0, s, a.nch,
+                           a.ch_off, a.ch_a, a.ch_b, a.ch_out, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re,
+                           a.alpha_im);
+        return;
+    }
     if (a.nch < kB4SplitRuns) {
-        hipLaunchKernelGGL((k_spgemm_b4js<AC, BC, OB>), dim3((unsigned)a.nch), dim3(256), 0, s, a.nch, a.ch_off,
-                           a.ch_a, a.ch_b, a.ch_out, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re, a.alpha_im);
+        hipLaunchKernelGGL((k_spgemm_b4js<AC, BC, OB, 4>), dim3((unsigned)a.nch), dim3(256), 0, s, a.nch,
+                           a.ch_off, a.ch_a, a.ch_b, a.ch_out, a.ar, a.ai, a.br, a.bi, a.cr, a.ci, a.alpha_re,
+                           a.alpha_im);
         return;
     }
     const int remap = b4_chunk();
