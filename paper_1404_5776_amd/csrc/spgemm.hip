@@ -1293,8 +1293,8 @@ __global__ __launch_bounds__(64 * W) void k_spgemm_b4js(
     if (wv > 0) pack(part[wv - 1]);
     __syncthreads();
     if (wv != 0) return;
-#pragma unroll
-    for (int w = 0; w < W - 1; ++w) {
+#pragma unroll 1
+    for (int w = 0; w < W - 1; ++w) {          // one wave's partials at a time (registers)
         int k = 0;
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
@@ -1318,7 +1318,8 @@ __global__ __launch_bounds__(64 * W) void k_spgemm_b4js(
 
 // Below this many runs a product takes the split form (one run per
 // workgroup): a wave per run would leave most of the 1,024 SIMDs idle.  Below
-// kB4Split8Runs the runs are split over 8 waves instead of 4.
+// kB4Split8Runs the runs are split over 8 waves instead of 4 (16 measured no
+// faster on the 64-atom cluster).
 constexpr int64_t kB4SplitRuns = 4096, kB4Split8Runs = 1024;
 
 template <bool AC, bool BC, int OB>
