@@ -318,8 +318,11 @@ def b4_leg(args):
         if roof["traffic"] is not None:
             roof["beyond_l2_gb_per_s"] = roof["traffic"] / (ms / 1e3 / n_l) / 1e9
             roof["beyond_l2_frac_of_hbm_peak"] = roof["beyond_l2_gb_per_s"] / 8000.0
+        step_s = r["elapsed"] / sub.steps
         out[key] = {"atoms": s.n_atoms, "b": s.b, "R_HS": s.R_HS, "R_K": s.R_K, "steps": sub.steps,
                     "steps_per_s": sub.steps / r["elapsed"],
+                    "inverse": {"iterations": r["inv_iters"], "seconds": r["inv_s"]},
+                    "steps_per_s_with_inverse_build": {f"n{n}": n / (r["inv_s"] + n * step_s) for n in (10, 100)},
                     "per_product_ms": {k: v[1] / max(v[0], 1) for k, v in stats.items()},
                     "roofline": roof}
         log(f"b4 {key}: {out[key]['steps_per_s']:.2f} steps/s, {dom} {out[key]['roofline']['frac']:.3f} of peak")
