@@ -4,6 +4,8 @@ the same run on the library's own allocations; loading again moves the
 buffers out first.  Contexts take their memory from PyTorch's caching
 allocator by default (rtdm_set_allocator), with the same results."""
 
+import gc
+
 import numpy as np
 import pytest
 
@@ -124,6 +126,7 @@ def test_torch_allocator_holds_the_context_and_gives_identical_results():
     import torch
     s = synth.diamond_lattice((2, 2, 2), 13, 10.0, 16.0, seed=28, k0="local", h_model="mulliken")
     ref, _ = _run(s, False)
+    gc.collect()                    # contexts other tests left to the collector give their memory back now
     torch.cuda.synchronize()
     before = torch.cuda.memory_allocated(0)
     ctx = gpu_context(s, h_model="mulliken")
