@@ -293,7 +293,10 @@ def small_leg(args):
 def b4_leg(args):
     """FP64 steps/s of the b = 4 lattices, with the roofline fraction of their
     dominant product kernel: the 65,536-atom lattice (R_K 12) and the
-    32,768-atom lattice at R_K 12, both with the Mulliken on-site H."""
+    32,768-atom lattice at R_K 12, both with the Mulliken on-site H.  On the
+    65,536-atom lattice also the mixed-precision + learned form (late Taylor
+    terms in FP32, network-started inverse) against the FP64 run: steps/s
+    with and without the inverse build, and its dipole error."""
     from paper_1404_5776_amd import synth
 
     sub = argparse.Namespace(**vars(args))
@@ -326,6 +329,23 @@ def b4_leg(args):
                     "per_product_ms": {k: v[1] / max(v[0], 1) for k, v in stats.items()},
                     "roofline": roof}
         log(f"b4 {key}: {out[key]['steps_per_s']:.2f} steps/s, {dom} {out[key]['roofline']['frac']:.3f} of peak")
+        if key == "lattice65536_rk12" and not args.no_learned:
+            w, loss = train_learned_start(4)
+            m = gpu_run(s, sub, precision="fp32_taylor", taylor_low_from=args.low_from, inv_start="learned",
+                        mlp_weights=w)
+            n = min(len(r["trace"]), len(m["trace"]))
+            induced = np.abs(r["trace"][:n, 1:4] - r["p0"]).max()
+            m_step = m["elapsed"] / sub.steps
+            out[key]["fp32_taylor_learned"] = {
+                "steps_per_s": sub.steps / m["elapsed"], "speedup_vs_fp64": r["elapsed"] / m["elapsed"],
+                "dipole_error_vs_fp64": float(np.abs(m["trace"][:n, 1:4] - r["trace"][:n, 1:4]).max() / induced),
+                "compared_steps": int(n),
+                "inverse": {"iterations": m["inv_iters"], "seconds": m["inv_s"]},
+                "steps_per_s_with_inverse_build": {f"n{k}": k / (m["inv_s"] + k * m_step) for k in (10, 100)},
+                "speedup_with_inverse_build": {f"n{k}": (r["inv_s"] + k * step_s) / (m["inv_s"] + k * m_step)
+                                               for k in (10, 100)},
+                "training_loss": loss}
+            log(f"b4 {key} fp32_taylor + learned: {out[key]['fp32_taylor_learned']}")
     return out
 
 
