@@ -535,6 +535,7 @@ class TorchAllocator:
     def __init__(self, device: int):
         import torch
         torch.cuda.init()          # the caching allocator needs torch's runtime up
+        _close_at_exit()
         self._torch = torch
         self.device = device
         self.last_error = None
@@ -563,9 +564,9 @@ def rtdm_set_allocator(ctx, allocator: TorchAllocator) -> None:
 
 
 _live_contexts = weakref.WeakSet()
+_exit_hook = False
 
 
-@atexit.register
 def _close_live_contexts():
     # give device memory back while PyTorch is still whole
     for c in list(_live_contexts):
@@ -573,6 +574,16 @@ def _close_live_contexts():
             c.close()
         except Exception:
             pass
+
+
+def _close_at_exit():
+    """Register the closing of live contexts once, after torch is imported:
+    exit handlers run last-registered first, so this one runs before
+    PyTorch's own."""
+    global _exit_hook
+    if not _exit_hook:
+        atexit.register(_close_live_contexts)
+        _exit_hook = True
 
 
 class Context:
