@@ -3,7 +3,10 @@
 Workload (default): the 4,096-atom diamond-like lattice with 13 functions per
 atom (53,248 x 53,248 complex K), cut-offs R_HS 10, R_K 16 and R_P 16 bohr,
 H = H0 + 0.5 diag(Mulliken charges) rebuilt every step, dt 0.05 a.u.  Every
-step rebuilds A = P(X H), the 6-term Taylor propagator and K <- U K U^dagger.
+step rebuilds A = P(X H) (as P(X H0), kept from the set-up, plus X's block
+columns scaled by the on-site term: the model's H differs from H0 only on the
+diagonal), the 6-term Taylor propagator and K <- U K U^dagger.  The same run
+with the full X H product at every step is reported beside it.
 Inputs are synthetic and seeded; all of them are resident in HBM before the
 timed region starts.
 
@@ -54,6 +57,23 @@ def measured_traffic(dom, name="traffic.json", tag=KERNEL_TAG, workload=None):
 METRIC = "propagation steps/s + block-SpGEMM GFLOP/s (% roofline) at stated dipole error vs FP64"
 
 
+def per_product_ms(stats):
+    """Mean milliseconds per launch of each product kind that ran."""
+    return {k: v[1] / v[0] for k, v in stats.items() if v[0]}
+
+
+def full_xh(s, args, base):
+    """The same FP64 run with A = P_P(X H) formed by the full product at every
+    step (what a Hamiltonian that changes everywhere costs), against the
+    default A0 + X D form."""
+    f = gpu_run(s, args, xh_every_step=1)
+    n = min(len(base["trace"]), len(f["trace"]))
+    induced = np.abs(base["trace"][:n, 1:4] - base["p0"]).max()
+    return {"steps_per_s": args.steps / f["elapsed"], "a0_form_speedup": f["elapsed"] / base["elapsed"],
+            "dipole_difference_rel": float(np.abs(f["trace"][:n, 1:4] - base["trace"][:n, 1:4]).max() / induced),
+            "per_product_ms": per_product_ms(f["stats"])}
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -66,14 +86,15 @@ def make_workload(args):
 
 
 def gpu_run(s, args, precision="fp64", taylor_low_from=3, use_graph=0, inv_start="block_jacobi",
-            mlp_weights=None):
+            mlp_weights=None, xh_every_step=0):
     import torch  # device memory and streams come from torch's runtime
     from paper_1404_5776_amd import rtdm
 
     torch.cuda.init()
     stream = torch.cuda.current_stream()
     ctx = rtdm.Context(0, h_model=s.h_model, h_gain=s.h_gain, precision=precision,
-                       taylor_low_from=taylor_low_from, use_graph=use_graph, inv_start=inv_start)
+                       taylor_low_from=taylor_low_from, use_graph=use_graph, inv_start=inv_start,
+                       xh_every_step=xh_every_step)
     t = time.time()
     ctx.load_system(s, stream)
     log(f"[{precision}] set-up (neighbour lists, schedules, upload) {time.time() - t:.1f} s")
@@ -326,9 +347,12 @@ def b4_leg(args):
                     "steps_per_s": sub.steps / r["elapsed"],
                     "inverse": {"iterations": r["inv_iters"], "seconds": r["inv_s"]},
                     "steps_per_s_with_inverse_build": {f"n{n}": n / (r["inv_s"] + n * step_s) for n in (10, 100)},
-                    "per_product_ms": {k: v[1] / max(v[0], 1) for k, v in stats.items()},
+                    "per_product_ms": per_product_ms(stats),
                     "roofline": roof}
         log(f"b4 {key}: {out[key]['steps_per_s']:.2f} steps/s, {dom} {out[key]['roofline']['frac']:.3f} of peak")
+        if key == "lattice32768_rk12":
+            out[key]["full_xh_product"] = full_xh(s, sub, r)
+            log(f"b4 {key} full X H product: {out[key]['full_xh_product']}")
         if key == "lattice65536_rk12" and not args.no_learned:
             w, loss = train_learned_start(4)
             m = gpu_run(s, sub, precision="fp32_taylor", taylor_low_from=args.low_from, inv_start="learned",
@@ -530,7 +554,7 @@ def main():
                           "steps_per_s": args.steps / r["elapsed"], "speedup_vs_fp64": elapsed / r["elapsed"],
                           "dipole_error_vs_fp64": e_rel, "dipole_error_abs": e_abs, "compared_steps": int(n),
                           "inverse_iterations": r["inv_iters"], "inverse_s": r["inv_s"],
-                          "per_product_ms": {k: v[1] / max(v[0], 1) for k, v in r["stats"].items()}})
+                          "per_product_ms": per_product_ms(r["stats"])})
             log(f"form {form}: {forms[-1]['steps_per_s']:.3f} steps/s, dipole error {e_rel:.2e}")
     graph = None
     if not args.no_graph:
@@ -538,6 +562,8 @@ def main():
         graph = {"steps_per_s": args.steps / g["elapsed"], "speedup_vs_eager": elapsed / g["elapsed"],
                  "bit_identical_trace": bool(np.array_equal(g["trace"][:, :6], trace[:, :6]))}
         log(f"graph: {graph}")
+    fullxh = full_xh(s, args, base)
+    log(f"full X H product: {fullxh}")
     learned = None
     if weights is not None:
         learned = {"inverse_iterations_block_jacobi": base["inv_iters"],
@@ -627,11 +653,12 @@ def main():
         "accuracy": "FP64 path; equals the FP64 oracle within 1e-10 relative in the parity tests, "
                     "so its dipole error vs FP64 is at that level",
         "roofline": roofline,
-        "per_product_ms": {k: v[1] / max(v[0], 1) for k, v in stats.items()},
+        "per_product_ms": per_product_ms(stats),
         "trace_last": trace[-1, :6].tolist() if len(trace) else None,
         "cpu_baseline": cpu,
         "precision_forms": forms,
         "graph": graph,
+        "full_xh_product": fullxh,
         "learned_start": learned,
         "batch": batch,
         "small_system": small,

@@ -171,6 +171,12 @@ typedef struct {
     int n_kicks;           /* kick sets (1..8, default 1): K matrices propagated side by side with one
                               shared propagator per step (rtdm_apply_kicks, rtdm_select_kick); more than
                               one needs h_model FIXED and sc_steps 0, since U must not depend on K */
+    int xh_every_step;     /* MULLIKEN: 1 forms A(theta) = P_P(X H(t + theta dt)) by the full block product at
+                              every time point (the cost of a Hamiltonian that changes everywhere); 0
+                              (default) forms it as A0 + X D with A0 = P_P(X H0), built once while X and H0
+                              stay unchanged, and D the diagonal on-site term, which scales block columns of
+                              X: equal in exact arithmetic, rounded differently (FP64 products without a
+                              field; otherwise always the full product) */
 } rtdm_options;
 
 /* Fill *opt with the defaults above.  Never fails for a non-NULL opt. */

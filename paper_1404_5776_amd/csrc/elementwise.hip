@@ -216,6 +216,50 @@ __global__ void k_onsite_shift(int64_t n_atoms, int b, const int32_t *__restrict
     h[(int64_t)diag[i] * b * b + a * b + a] += gain * (q - q_ref[i]);
 }
 
+// A = A0 + X D on the range of X and A, with A0 = P(X H0) and D the on-site
+// term of the Mulliken model: D_jj = g (q_a + theta (q_x - q_y) - q_ref)_j on
+// each of atom j's own functions.  Since D only scales block columns of X,
+// P(X (H0 + D)) = P(X H0) + X D exactly in arithmetic; the sums are rounded
+// differently from the product of X with H0 + D.
+template <typename I>
+__global__ void k_a_onsite(I n, int b, const int32_t *__restrict__ col, const int32_t *__restrict__ nbf,
+                           double gain, const double *__restrict__ q_a, double theta,
+                           const double *__restrict__ q_x, const double *__restrict__ q_y,
+                           const double *__restrict__ q_ref, const double *__restrict__ a0,
+                           const double *__restrict__ x, double *__restrict__ a)
+{
+    const I bb = (I)b * b;
+    for (I e = (I)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (I)gridDim.x * blockDim.x) {
+        const I p = e / bb;
+        const int cc = (int)((e - p * bb) % (I)b);
+        const int j = col[p];
+        double v = a0[e];
+        if (!nbf || cc < nbf[j]) {
+            const double q = q_a[j] + theta * (q_x[j] - q_y[j]);
+            v += x[e] * (gain * (q - q_ref[j]));
+        }
+        a[e] = v;
+    }
+}
+
+void launch_a_onsite(hipStream_t s, int64_t nnzb, int b, const int32_t *col, const int32_t *nbf, double gain,
+                     const double *q_a, double theta, const double *q_x, const double *q_y, const double *q_ref,
+                     const double *a0, const double *x, double *a)
+{
+    const int64_t n = nnzb * b * b;
+    if (n == 0) return;
+    int64_t g = (n + kT - 1) / kT;
+    if (g > 65536) g = 65536;
+    // 32-bit index arithmetic (the divisions by b^2 and b) whenever it fits
+    if (n + (int64_t)g * kT < ((int64_t)1 << 32))
+        hipLaunchKernelGGL(k_a_onsite<uint32_t>, dim3((unsigned)g), dim3(kT), 0, s, (uint32_t)n, b, col, nbf, gain,
+                           q_a, theta, q_x, q_y, q_ref, a0, x, a);
+    else
+        hipLaunchKernelGGL(k_a_onsite<int64_t>, dim3((unsigned)g), dim3(kT), 0, s, n, b, col, nbf, gain, q_a, theta,
+                           q_x, q_y, q_ref, a0, x, a);
+    RT_HIP(hipGetLastError());
+}
+
 void launch_onsite_shift(hipStream_t s, int64_t n_atoms, int b, const int32_t *diag, const int32_t *nbf, double gain,
                          const double *q_a, double theta, const double *q_x, const double *q_y,
                          const double *q_ref, double *h)

@@ -201,6 +201,9 @@ void launch_mulliken(hipStream_t s, int64_t n_atoms, int b, const int64_t *s_ptr
                      const double *kr, double *q);
 // H[diag] += gain*(q_a + theta (q_x - q_y) - q_ref) on the diagonal elements.
 void launch_add_scalar(hipStream_t s, double *x, double v);
+void launch_a_onsite(hipStream_t s, int64_t nnzb, int b, const int32_t *col, const int32_t *nbf, double gain,
+                     const double *q_a, double theta, const double *q_x, const double *q_y, const double *q_ref,
+                     const double *a0, const double *x, double *a);
 void launch_onsite_shift(hipStream_t s, int64_t n_atoms, int b, const int32_t *diag, const int32_t *nbf, double gain,
                          const double *q_a, double theta, const double *q_x, const double *q_y,
                          const double *q_ref, double *h);

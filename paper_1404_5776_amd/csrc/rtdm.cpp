@@ -301,6 +301,9 @@ struct rtdm_ctx {
 
     Mat mats[RTDM_MAT_COUNT];
     Mat tau[2], Kn, Xn, Wh, V, Z;
+    // Mulliken model: A0 = P(X H0), so that a step's A is A0 + X D (D diagonal)
+    Mat A0;
+    bool A0_valid = false;
     // column-major block copies of the step's left operands (b = 13, FP64) and
     // of S for the inverse iteration
     Mat Xc, Ac, Uc, Wc, Sc;
@@ -1008,12 +1011,13 @@ void after_upload(rtdm_ctx *c, int m)
     case RTDM_MAT_S:
         c->X_valid = false;
         c->U_valid = false;
+        c->A0_valid = false;
         c->s_norm_valid = false;
         c->charges_valid = false;
         c->q_ref_valid = false;
         break;
-    case RTDM_MAT_H0: c->U_valid = false; break;
-    case RTDM_MAT_X: c->X_valid = true; c->U_valid = false; c->Xc_valid = false; break;
+    case RTDM_MAT_H0: c->U_valid = false; c->A0_valid = false; break;
+    case RTDM_MAT_X: c->X_valid = true; c->U_valid = false; c->Xc_valid = false; c->A0_valid = false; break;
     case RTDM_MAT_K:
         for (int k = 1; k < n_kicks(c); ++k) {   // every kick starts from the uploaded K
             const int64_t ne = elems(c, c->mats[RTDM_MAT_K]);
@@ -1140,6 +1144,7 @@ int rtdm_default_options(rtdm_options *opt)
     opt->unit_tol = 0.0;
     opt->graph_steps = 16;
     opt->n_kicks = 1;
+    opt->xh_every_step = 0;
     return RTDM_OK;
 }
 
@@ -1177,6 +1182,7 @@ int rtdm_create(rtdm_ctx **out, int hip_device, const rtdm_options *opt)
     RT_CHECK(c->opt.unit_tol >= 0.0, RTDM_E_ARG, "unit_tol < 0");
     RT_CHECK(c->opt.graph_steps >= 1 && c->opt.graph_steps <= 1024, RTDM_E_ARG, "graph_steps outside 1..1024");
     RT_CHECK(c->opt.n_kicks >= 1 && c->opt.n_kicks <= 8, RTDM_E_ARG, "n_kicks outside 1..8");
+    RT_CHECK(c->opt.xh_every_step == 0 || c->opt.xh_every_step == 1, RTDM_E_ARG, "xh_every_step must be 0 or 1");
     RT_CHECK(c->opt.n_kicks == 1 || (c->opt.h_model == RTDM_HMODEL_FIXED && c->opt.sc_steps == 0),
              RTDM_E_UNSUPPORTED, "several kicks share one propagator: they need a fixed H and no corrector");
     set_device(c);
@@ -1304,6 +1310,9 @@ int rtdm_set_ranges(rtdm_ctx *c, double R_hs, double R_p, double R_k)
     for (int m = 0; m < RTDM_MAT_COUNT; ++m) alloc_mat(c, c->mats[m], slot_range(m), slot_complex(m));
     alloc_mat(c, c->tau[0], R_P, false);
     alloc_mat(c, c->tau[1], R_P, false);
+    if (c->opt.h_model == RTDM_HMODEL_MULLIKEN && !c->opt.xh_every_step) alloc_mat(c, c->A0, R_P, false);
+    else c->A0.re.release();
+    c->A0_valid = false;
     alloc_mat(c, c->Kn, R_K, true);
     alloc_mat(c, c->Xn, R_P, false);
     alloc_mat(c, c->Wh, R_P, false);
@@ -1749,6 +1758,7 @@ int rtdm_build_inverse(rtdm_ctx *c, void *stream, int *iters, double *residual)
         c->Xc_valid = true;
     }
     c->U_valid = false;
+    c->A0_valid = false;
     RT_CHECK(st == 1, RTDM_E_NOCONV,
              "Hotelling iteration " + std::string(st == 0 ? "diverged" : "hit the iteration cap") +
                  " (residual " + std::to_string(r) + ")");
@@ -1792,10 +1802,57 @@ void build_h(rtdm_ctx *c, double theta, bool corr, hipStream_t s)
                      c->step_st.p, c->step_tt.p, theta, H.re.p);
 }
 
+// The Mulliken model without a field and with FP64 products forms A from
+// A0 = P(X H0) and a column scaling of X (k_a_onsite): one product less per
+// time point of a step.
+bool a_from_a0(const rtdm_ctx *c)
+{
+    return c->opt.h_model == RTDM_HMODEL_MULLIKEN && !c->opt.xh_every_step && !c->field_on && c->A0.re.p != nullptr &&
+           all_products_prec(const_cast<rtdm_ctx *>(c)) == RTDM_PREC_FP64;
+}
+
+// The column-major copy of X on the b = 13 path, refreshed when X changed.
+// rtdm_step calls it before its steps, outside any capture: a captured step
+// holds no transpose of X, so a graph replayed after X was replaced reads
+// the copy made here.
+void ensure_xc(rtdm_ctx *c, hipStream_t s)
+{
+    if (c->b != 13 || c->Xc_valid || !c->Xc.re.p) return;
+    transpose_into(c, c->mats[RTDM_MAT_X], c->Xc, s);
+    c->Xc_valid = true;
+}
+
+// A0 = P(X H0) for a_from_a0, built when X or H0 changed (outside any capture:
+// rtdm_step calls it before its steps).
+void ensure_a0(rtdm_ctx *c, hipStream_t s)
+{
+    if (!a_from_a0(c) || c->A0_valid) return;
+    Mat &X = c->mats[RTDM_MAT_X], &H0 = c->mats[RTDM_MAT_H0];
+    const int saved = c->prec;
+    c->prec = RTDM_PREC_FP64;
+    if (use_cm(c)) {
+        ensure_xc(c, s);
+        product_cm(c, RTDM_PROD_XH, c->Xc, H0, c->A0, 0, 0, 1.0, s);
+    } else {
+        product(c, RTDM_PROD_XH, X, H0, c->A0, 1.0, 0.0, s);
+    }
+    c->prec = saved;
+    c->A0_valid = true;
+}
+
 // A = P_P(X H(t + theta dt)) (and its column-major copy on the b = 13 path).
 void make_a(rtdm_ctx *c, double theta, bool corr, hipStream_t s)
 {
     Mat &H = c->mats[RTDM_MAT_H], &X = c->mats[RTDM_MAT_X], &A = c->mats[RTDM_MAT_A];
+    if (a_from_a0(c)) {
+        RT_CHECK(c->A0_valid, RTDM_E_STATE, "A0 = P(X H0) not built before the step");
+        const Pattern &pp = pat_of(c, R_P);
+        launch_a_onsite(s, pp.nnzb, c->b, pp.d_col.p, c->mixed ? c->d_nbf.p : nullptr, c->opt.h_gain, c->q_cur,
+                        theta, corr ? c->q_c.p : c->q_cur, corr ? c->q_cur : c->q_prev, c->q_ref.p, c->A0.re.p,
+                        X.re.p, A.re.p);
+        if (use_cm(c)) transpose_into(c, A, c->Ac, s);
+        return;
+    }
     build_h(c, theta, corr, s);
     if (use_cm(c)) {
         if (!c->Xc_valid) {
@@ -1955,6 +2012,8 @@ StepCall step_begin(rtdm_ctx *c, double dt, int64_t n_steps, hipStream_t s)
 {
     ensure_obs(c, c->obs_rows + n_steps);
     ensure_charges(c, s);
+    ensure_xc(c, s);
+    ensure_a0(c, s);
     if (c->obs_reset_pending) {
         RT_HIP(hipMemsetAsync(c->step_st.p, 0, c->step_st.bytes(), s));
         c->obs_reset_pending = false;

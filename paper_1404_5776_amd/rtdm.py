@@ -57,7 +57,8 @@ class Options(ctypes.Structure):
                 ("inv_start", ctypes.c_int), ("inv_tol", ctypes.c_double),
                 ("inv_max_iter", ctypes.c_int), ("taylor_low_from", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("propagator", ctypes.c_int), ("sc_steps", ctypes.c_int), ("sc_iters", ctypes.c_int),
-                ("unit_tol", ctypes.c_double), ("graph_steps", ctypes.c_int), ("n_kicks", ctypes.c_int)]
+                ("unit_tol", ctypes.c_double), ("graph_steps", ctypes.c_int), ("n_kicks", ctypes.c_int),
+                ("xh_every_step", ctypes.c_int)]
 
 
 _lib = None

@@ -34,6 +34,28 @@ def test_binding_loads_and_defaults():
     assert rtdm.load().rtdm_last_error(None) == b"null context"
 
 
+def test_options_struct_matches_the_header(tmp_path):
+    """The binding's Options mirror has the C struct's size and field offsets
+    (a C program built from include/rtdm.h prints them)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    fields = [f[0] for f in rtdm.Options._fields_]
+    src = tmp_path / "opts.c"
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "rtdm.h"\nint main(void) {\n'
+                   '  printf("%zu\\n", sizeof(rtdm_options));\n'
+                   + "".join(f'  printf("%zu\\n", offsetof(rtdm_options, {f}));\n' for f in fields)
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "opts"
+    inc = os.path.join(ROOT, "include")
+    subprocess.run([cc, "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    want = [ctypes.sizeof(rtdm.Options)] + [getattr(rtdm.Options, f).offset for f in fields]
+    assert got == want
+
+
 def test_null_context_is_an_argument_error():
     L = rtdm.load()
     assert L.rtdm_set_ranges(None, 1.0, 1.0, 1.0) == -1

@@ -198,9 +198,11 @@ def test_config1_full_run_matches_oracle():
     _propagation_parity(synth.config1(), 100, unit_every=25)
 
 
-def test_mulliken_b13_lattice_matches_oracle():
+@pytest.mark.parametrize("xh_every_step", [0, 1])
+def test_mulliken_b13_lattice_matches_oracle(xh_every_step):
+    """Both ways of forming A: A0 + X D (default) and the full X H product."""
     s = synth.diamond_lattice((2, 2, 2), 13, 10.0, 16.0, seed=21, k0="local", h_model="mulliken")
-    _propagation_parity(s, 5, unit_every=5)
+    _propagation_parity(s, 5, unit_every=5, xh_every_step=xh_every_step)
 
 
 def test_mulliken_b13_lattice512_matches_oracle():
@@ -211,9 +213,10 @@ def test_mulliken_b13_lattice512_matches_oracle():
     _propagation_parity(s, 2, check_unitarity=False)
 
 
-def test_mulliken_b4_lattice_matches_oracle():
+@pytest.mark.parametrize("xh_every_step", [0, 1])
+def test_mulliken_b4_lattice_matches_oracle(xh_every_step):
     s = synth.diamond_lattice((4, 4, 4), 4, 10.0, 12.0, seed=22, h_model="mulliken")
-    _propagation_parity(s, 20, unit_every=10)
+    _propagation_parity(s, 20, unit_every=10, xh_every_step=xh_every_step)
 
 
 def test_taylor_order_option_matches_oracle():
