@@ -350,7 +350,7 @@ def b4_leg(args):
                     "per_product_ms": per_product_ms(stats),
                     "roofline": roof}
         log(f"b4 {key}: {out[key]['steps_per_s']:.2f} steps/s, {dom} {out[key]['roofline']['frac']:.3f} of peak")
-        if key == "lattice32768_rk12":
+        if key == "lattice32768_rk12" and not args.no_full_xh:
             out[key]["full_xh_product"] = full_xh(s, sub, r)
             log(f"b4 {key} full X H product: {out[key]['full_xh_product']}")
         if key == "lattice65536_rk12" and not args.no_learned:
@@ -473,6 +473,8 @@ def main():
                     help="reduced-precision forms run beside FP64 (comma list, empty for none)")
     ap.add_argument("--no-learned", action="store_true", help="forms use the block-Jacobi inverse start")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-full-xh", action="store_true",
+                    help="skip the runs with the full X H product at every step (A0 + X D form only)")
     ap.add_argument("--no-peaks", action="store_true", help="skip the GEMM / copy rate measurement")
     ap.add_argument("--batch-clusters", type=int, default=64,
                     help="clusters of the batch leg, the first of the 64-cluster list (0: skip)")
@@ -562,8 +564,10 @@ def main():
         graph = {"steps_per_s": args.steps / g["elapsed"], "speedup_vs_eager": elapsed / g["elapsed"],
                  "bit_identical_trace": bool(np.array_equal(g["trace"][:, :6], trace[:, :6]))}
         log(f"graph: {graph}")
-    fullxh = full_xh(s, args, base)
-    log(f"full X H product: {fullxh}")
+    fullxh = None
+    if not args.no_full_xh:
+        fullxh = full_xh(s, args, base)
+        log(f"full X H product: {fullxh}")
     learned = None
     if weights is not None:
         learned = {"inverse_iterations_block_jacobi": base["inv_iters"],
