@@ -551,6 +551,42 @@ void launch_transpose_blocks(hipStream_t s, int64_t nblocks, int b, const double
     RT_HIP(hipGetLastError());
 }
 
+// out_ji = in_ij^dagger for every block p = (i, j) of a pattern (trans[p] =
+// the block (j, i)): out[trans[p]][c][r] = conj(in[p][r][c]).  B is the block
+// size when fixed at compile time (4), else 0 and b is read at run time.
+template <int B>
+__global__ void k_conj_transpose(int64_t nnzb, int b, const int32_t *__restrict__ trans,
+                                 const double *__restrict__ in_re, const double *__restrict__ in_im,
+                                 double *__restrict__ out_re, double *__restrict__ out_im)
+{
+    const int bs = B ? B : b, bb = bs * bs;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnzb * bb;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = e / bb;
+        const int w = (int)(e - p * bb);
+        const int r = w / bs, c = w - r * bs;
+        const int64_t o = (int64_t)trans[p] * bb + c * bs + r;
+        out_re[o] = in_re[e];
+        out_im[o] = -in_im[e];
+    }
+}
+
+void launch_conj_transpose(hipStream_t s, int64_t nnzb, int b, const int32_t *trans, const double *in_re,
+                           const double *in_im, double *out_re, double *out_im)
+{
+    const int64_t n = nnzb * b * b;
+    if (n == 0) return;
+    int64_t g = (n + kT - 1) / kT;
+    if (g > 65536) g = 65536;
+    if (b == 4)
+        hipLaunchKernelGGL(k_conj_transpose<4>, dim3((unsigned)g), dim3(kT), 0, s, nnzb, b, trans, in_re, in_im,
+                           out_re, out_im);
+    else
+        hipLaunchKernelGGL(k_conj_transpose<0>, dim3((unsigned)g), dim3(kT), 0, s, nnzb, b, trans, in_re, in_im,
+                           out_re, out_im);
+    RT_HIP(hipGetLastError());
+}
+
 __global__ void k_to_f32(int64_t nblocks, int b, int transpose, const double *__restrict__ in,
                          float *__restrict__ out)
 {

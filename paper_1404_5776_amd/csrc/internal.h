@@ -182,6 +182,12 @@ void launch_to_f32(hipStream_t s, int64_t nblocks, int b, int transpose, const d
 void launch_axpy_f32(hipStream_t s, int64_t n, double a, const float *x, double *y);
 // out[p] = in[p]^T for every b x b block (nblocks blocks).
 void launch_transpose_blocks(hipStream_t s, int64_t nblocks, int b, const double *in, double *out);
+// out_ji = in_ij^dagger over a pattern (trans: the transpose map of the pattern)
+void launch_conj_transpose(hipStream_t s, int64_t nnzb, int b, const int32_t *trans, const double *in_re,
+                           const double *in_im, double *out_re, double *out_im);
+// True when a b = 4 product over nch runs of 16 outputs takes the split form
+// (one workgroup per run: small systems, whose runs are too few to fill the chip).
+bool b4_split_form(int64_t nch);
 
 // out = a*x + c*y elementwise (y may be null: out = a*x).
 void launch_axpby(hipStream_t s, int64_t n, double a, const double *x, double c, const double *y,

@@ -304,6 +304,12 @@ struct rtdm_ctx {
     // Mulliken model: A0 = P(X H0), so that a step's A is A0 + X D (D diagonal)
     Mat A0;
     bool A0_valid = false;
+    // b = 4, FP64 products over row runs: Uh = U^dagger stored as a matrix, so
+    // that W U^dagger reads its right operand by rows of Uh (blocks of one row k
+    // for the 16 outputs of a run) instead of by columns of U
+    Mat Uh;
+    bool Uh_on = false;
+    bool u_copies_valid = false;   // Uc (b = 13) and Uh follow U
     // column-major block copies of the step's left operands (b = 13, FP64) and
     // of S for the inverse iteration
     Mat Xc, Ac, Uc, Wc, Sc;
@@ -572,9 +578,20 @@ std::tuple<int, int, int, int, int> prod_key(rtdm_ctx *c, int prod)
     throw Error(RTDM_E_ARG, "unknown product kind");
 }
 
-Sched &schedule(rtdm_ctx *c, int prod)
+// W U^dagger with U^dagger stored (Uh): a plain product of patterns K, P -> K.
+std::tuple<int, int, int, int, int> wuh_key(rtdm_ctx *c)
 {
-    auto key = prod_key(c, prod);
+    return {c->range_pat[R_K], c->range_pat[R_P], c->range_pat[R_K], 0, 0};
+}
+
+Sched &schedule_key(rtdm_ctx *c, int prod, const std::tuple<int, int, int, int, int> &key);
+
+Sched &schedule(rtdm_ctx *c, int prod) { return schedule_key(c, prod, prod_key(c, prod)); }
+
+// The schedule (triple lists and row runs) of the product with operand and
+// output patterns `key`; prod names the kind (run lengths, timing).
+Sched &schedule_key(rtdm_ctx *c, int prod, const std::tuple<int, int, int, int, int> &key)
+{
     // Row runs: b = 13 products of the column-major path (X H, A tau and the
     // inverse's S X real, U K and W U^dagger complex), b = 4 products with op(A) = A.
     const bool cm_kind = prod == RTDM_PROD_XH || prod == RTDM_PROD_AT || prod == RTDM_PROD_UK ||
@@ -639,12 +656,21 @@ hipEvent_t event_at(rtdm_ctx *c, size_t k)
 }
 
 
+void product_key(rtdm_ctx *c, int prod, const std::tuple<int, int, int, int, int> &key, const Mat &A,
+                 const Mat &B, Mat &C, double alr, double ali, hipStream_t s);
+
 // C = P_C(alpha op(A) op(B)) with the schedule of `prod`.
 void product(rtdm_ctx *c, int prod, const Mat &A, const Mat &B, Mat &C, double alr, double ali,
              hipStream_t s)
 {
-    Sched &S = schedule(c, prod);
-    auto key = prod_key(c, prod);
+    product_key(c, prod, prod_key(c, prod), A, B, C, alr, ali, s);
+}
+
+// The same with the schedule of operand and output patterns `key` (timed as `prod`).
+void product_key(rtdm_ctx *c, int prod, const std::tuple<int, int, int, int, int> &key, const Mat &A,
+                 const Mat &B, Mat &C, double alr, double ali, hipStream_t s)
+{
+    Sched &S = schedule_key(c, prod, key);
     RT_CHECK(A.pat == std::get<0>(key) && B.pat == std::get<1>(key) && C.pat == std::get<2>(key),
              RTDM_E_ARG, std::string("operand patterns do not match product ") + kProdName[prod]);
     SpgemmArgs a;
@@ -1035,7 +1061,7 @@ void after_upload(rtdm_ctx *c, int m)
         c->trace_dt_mixed = false;
         c->herm_valid = false;
         break;
-    case RTDM_MAT_U: c->U_valid = true; break;
+    case RTDM_MAT_U: c->U_valid = true; c->u_copies_valid = false; break;
     case RTDM_MAT_W: c->W_in_cm = false; break;
     default: break;
     }
@@ -1408,6 +1434,22 @@ int rtdm_set_ranges(rtdm_ctx *c, double R_hs, double R_p, double R_k)
     c->herm_valid = false;
     c->ranges_set = true;
     for (int prod : {RTDM_PROD_XH, RTDM_PROD_AT, RTDM_PROD_UK, RTDM_PROD_WU, RTDM_PROD_SX}) schedule(c, prod);
+    {
+        // W U^dagger over rows of a stored U^dagger where the b = 4 FP64 products run
+        // over row runs of 16 (not the split form of small systems)
+        Sched &uk = schedule(c, RTDM_PROD_UK);
+        auto r = uk.runs.find(16);
+        c->Uh_on = c->b == 4 && c->run_b4 == 16 && all_products_prec(c) == RTDM_PREC_FP64 && r != uk.runs.end() &&
+                   r->second->nch > 0 && !b4_split_form(r->second->nch);
+        if (c->Uh_on) {
+            alloc_mat(c, c->Uh, R_P, true);
+            schedule_key(c, RTDM_PROD_WU, wuh_key(c));
+        } else {
+            c->Uh.re.release();
+            c->Uh.im.release();
+        }
+        c->u_copies_valid = false;
+    }
     // the unitarity product too when steps check it, so that rtdm_step allocates nothing
     if (c->opt.unit_check_every > 0) schedule(c, RTDM_PROD_UV);
     RT_HIP(hipDeviceSynchronize());
@@ -1922,6 +1964,29 @@ void build_u(rtdm_ctx *c, double dt, bool corr, hipStream_t s)
     }
     default: throw Error(RTDM_E_ARG, "unknown propagator");
     }
+    if (c->Uh_on) {
+        const Pattern &pp = pat_of(c, R_P);
+        launch_conj_transpose(s, pp.nnzb, c->b, pp.d_trans.p, U.re.p, U.im.p, c->Uh.re.p, c->Uh.im.p);
+    }
+    c->u_copies_valid = true;
+}
+
+// After an upload of U: its column-major copy (b = 13) and U^dagger (b = 4),
+// made before the steps, outside any capture, since a step that keeps U
+// (fixed H) does not rebuild them.
+void ensure_u_copies(rtdm_ctx *c, hipStream_t s)
+{
+    if (c->u_copies_valid || !c->U_valid) return;
+    Mat &U = c->mats[RTDM_MAT_U];
+    const int saved = c->prec;
+    c->prec = all_products_prec(c);
+    if (use_cm(c)) transpose_into(c, U, c->Uc, s);
+    c->prec = saved;
+    if (c->Uh_on) {
+        const Pattern &pp = pat_of(c, R_P);
+        launch_conj_transpose(s, pp.nnzb, c->b, pp.d_trans.p, U.re.p, U.im.p, c->Uh.re.p, c->Uh.im.p);
+    }
+    c->u_copies_valid = true;
 }
 
 // One step on stream s: `passes` propagations of the same K(t) (the first
@@ -1951,7 +2016,8 @@ void step_body(rtdm_ctx *c, double dt, bool rebuild_u, int passes, hipStream_t s
                 c->W_in_cm = true;
             } else {
                 product(c, RTDM_PROD_UK, U, K, W, 1.0, 0.0, s);
-                product(c, RTDM_PROD_WU, W, U, c->Kn, 1.0, 0.0, s);
+                if (c->Uh_on) product_key(c, RTDM_PROD_WU, wuh_key(c), W, c->Uh, c->Kn, 1.0, 0.0, s);
+                else product(c, RTDM_PROD_WU, W, U, c->Kn, 1.0, 0.0, s);
                 c->W_in_cm = false;
             }
             launch_hermitize(s, pk.nnzb, c->b, pk.d_trans.p, c->Kn.re.p, c->Kn.im.p, dst.re.p, dst.im.p,
@@ -2014,6 +2080,7 @@ StepCall step_begin(rtdm_ctx *c, double dt, int64_t n_steps, hipStream_t s)
     ensure_charges(c, s);
     ensure_xc(c, s);
     ensure_a0(c, s);
+    ensure_u_copies(c, s);
     if (c->obs_reset_pending) {
         RT_HIP(hipMemsetAsync(c->step_st.p, 0, c->step_st.bytes(), s));
         c->obs_reset_pending = false;

@@ -1322,6 +1322,8 @@ __global__ __launch_bounds__(64 * W) void k_spgemm_b4js(
 // faster on the 64-atom cluster).
 constexpr int64_t kB4SplitRuns = 4096, kB4Split8Runs = 1024;
 
+bool b4_split_form(int64_t nch) { return nch < kB4SplitRuns; }
+
 template <bool AC, bool BC, int OB>
 static void launch_b4j(hipStream_t s, const SpgemmArgs &a)
 {
