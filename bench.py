@@ -114,7 +114,15 @@ def gpu_run(s, args, precision="fp64", taylor_low_from=3, use_graph=0, inv_start
     rtdm.rtdm_timing(ctx.h, not use_graph)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    rtdm.rtdm_step(ctx.h, s.dt, args.steps, stream)
+    chunk = getattr(args, "progress_every", 0)
+    done = 0
+    while done < args.steps:
+        n = min(chunk, args.steps - done) if chunk > 0 else args.steps - done
+        rtdm.rtdm_step(ctx.h, s.dt, n, stream)
+        done += n
+        if chunk > 0:
+            torch.cuda.synchronize()          # long runs report each finished chunk of steps
+            log(f"[{precision}] {done}/{args.steps} steps, {time.perf_counter() - t0:.1f} s")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     stats = {k: rtdm.rtdm_timing_stats(ctx.h, k) for k in ("XH", "AT", "UK", "WU")}
@@ -494,6 +502,8 @@ def main():
                     help="instead of the benchmark line: the precision sweep on the 32,768-atom lattice, or "
                          "the learned inverse start on the 65,536-atom lattice (one JSON line each)")
     ap.add_argument("--cutoffs", default="8,12,16,20", help="K cut-offs of the precision study (bohr)")
+    ap.add_argument("--progress-every", type=int, default=0, metavar="STEPS",
+                    help="time the steps in calls of this many, logging after each (0: one call)")
     ap.add_argument("--sweep-forms", default="fp32,fp32_taylor,bf16x3,bf16x3_taylor,fp16x2,fp16x2_taylor",
                     help="forms of the precision study beside FP64 (comma list)")
     args = ap.parse_args()
