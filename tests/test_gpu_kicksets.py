@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 from oracle import oracle as O
-from paper_1404_5776_amd import rtdm
+from paper_1404_5776_amd import rtdm, synth
 from tests._common import TOL, assert_charges, dipole_floor, gpu_charges, rel, small_clusters
 
 pytestmark = pytest.mark.gpu
@@ -84,6 +84,23 @@ def test_kick_sets_match_oracle_and_one_kick_runs(b):
             induced = np.abs(ref.rows[:, 1:4] - P0).max()
             assert np.abs(gtr[:, g, :3] - ref.rows[:, 1:4]).max() <= TOL * induced + dipole_floor(q0, st.xyz, dq)
             assert np.abs(gtr[:, g, 3] - ref.rows[:, 4]).max() <= TOL * abs(ref.rows[0, 4])
+
+
+def test_kick_sets_on_row_runs_equal_one_kick_runs():
+    """Two 1,728-atom b = 4 lattices: their products run over row runs of 16
+    (not the split form of small systems) and W U^dagger reads the stored
+    U^dagger, shared by the three kick sets; each set repeats a one-kick run
+    bit for bit."""
+    systems = [synth.diamond_lattice((6, 6, 6), 4, 10.0, 12.0, seed=36 + k, h_model="fixed") for k in range(2)]
+    print("[gpu] kick sets: two 1728-atom b=4 lattices x 3 kicks", flush=True)
+    gptr, _, _, sets = _kick_sets(systems, use_graph=1)
+    for k, kap in enumerate(KICKS):
+        K, gtr, tr, q_all = sets[k]
+        K1, gtr1, tr1, q1 = _one_kick(systems, kap)
+        assert np.array_equal(K, K1), k
+        assert np.array_equal(gtr, gtr1), k
+        assert np.array_equal(tr[:, :6], tr1[:, :6]), k
+        assert np.array_equal(q_all, q1), k
 
 
 def test_kick_sets_graph_replays_equal_eager_steps():

@@ -219,6 +219,14 @@ def test_mulliken_b4_lattice_matches_oracle(xh_every_step):
     _propagation_parity(s, 20, unit_every=10, xh_every_step=xh_every_step)
 
 
+def test_b4_lattice_on_row_runs_matches_oracle():
+    """1,728 atoms at b = 4: enough outputs (about 10,000 runs of 16) for the
+    products to run over row runs on the whole chip rather than the split
+    form of small systems, with W U^dagger reading the stored U^dagger."""
+    s = synth.diamond_lattice((6, 6, 6), 4, 10.0, 12.0, seed=35, h_model="mulliken")
+    _propagation_parity(s, 4, unit_every=4)
+
+
 def test_taylor_order_option_matches_oracle():
     s = _cluster(30, 4, 6.0, 8.0, 106, h_model="fixed")
     st = O.setup(s)
