@@ -361,6 +361,18 @@ def b4_leg(args):
         if key == "lattice32768_rk12" and not args.no_full_xh:
             out[key]["full_xh_product"] = full_xh(s, sub, r)
             log(f"b4 {key} full X H product: {out[key]['full_xh_product']}")
+        if key == "lattice32768_rk12" and not args.no_b4_forms:
+            n = len(r["trace"])
+            induced = np.abs(r["trace"][:, 1:4] - r["p0"]).max()
+            forms = {}
+            for form in ("fp32_taylor", "bf16x3_taylor"):
+                f = gpu_run(s, sub, precision=form, taylor_low_from=args.low_from)
+                forms[form] = {"steps_per_s": sub.steps / f["elapsed"], "speedup_vs_fp64": r["elapsed"] / f["elapsed"],
+                               "dipole_error_vs_fp64": float(np.abs(f["trace"][:n, 1:4] - r["trace"][:n, 1:4]).max()
+                                                             / induced),
+                               "per_product_ms": per_product_ms(f["stats"])}
+            out[key]["late_taylor_forms"] = forms
+            log(f"b4 {key} late-Taylor forms: {forms}")
         if key == "lattice65536_rk12" and not args.no_learned:
             w, loss = train_learned_start(4)
             m = gpu_run(s, sub, precision="fp32_taylor", taylor_low_from=args.low_from, inv_start="learned",
@@ -484,6 +496,8 @@ def main():
     ap.add_argument("--no-full-xh", action="store_true",
                     help="skip the runs with the full X H product at every step (A0 + X D form only)")
     ap.add_argument("--no-peaks", action="store_true", help="skip the GEMM / copy rate measurement")
+    ap.add_argument("--no-b4-forms", action="store_true",
+                    help="skip the FP32 / BF16x3 late-Taylor runs on the 32,768-atom b = 4 lattice")
     ap.add_argument("--batch-clusters", type=int, default=64,
                     help="clusters of the batch leg, the first of the 64-cluster list (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=32, help="timed steps of the batch leg")

@@ -178,6 +178,13 @@ void launch_spgemm_r32(hipStream_t s, const SpgemmArgs &a, const float *a32, con
                        const float *zero32);
 // out = (float)in, optionally transposing every b x b block.
 void launch_to_f32(hipStream_t s, int64_t nblocks, int b, int transpose, const double *in, float *out);
+// b = 4 blocks as BF16 hi / lo parts, 32 values per block (its 16 hi parts,
+// then its 16 lo parts; transpose: each block stored transposed)
+void launch_to_bf16x2(hipStream_t s, int64_t nblocks, int transpose, const double *in, short *out);
+// BF16x3 Taylor term at b = 4 over row runs of 16 (a.ch_*, alpha a.alpha_re) from split
+// operands: u += u_sign * tau, and tau stored split and transposed in c16 (if set)
+void launch_spgemm_r16(hipStream_t s, const SpgemmArgs &a, const short *a16, const short *b16, short *c16,
+                       double *u, double u_sign);
 // y += a * (double)x
 void launch_axpy_f32(hipStream_t s, int64_t n, double a, const float *x, double *y);
 // out[p] = in[p]^T for every b x b block (nblocks blocks).

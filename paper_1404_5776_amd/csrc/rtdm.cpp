@@ -873,6 +873,15 @@ void build_propagator(rtdm_ctx *c, double dt, hipStream_t s)
     const int64_t ne = elems(c, A);
     const int p = c->opt.taylor_order;
     const bool low32 = c->opt.precision == RTDM_PREC_FP32_TAYLOR && c->Ac32.p != nullptr;
+    // BF16x3 late terms at b = 4 over row runs: operands stored split (the
+    // FP32 buffers hold the hi and lo planes), the sum into U fused
+    const bool low16 = c->opt.precision == RTDM_PREC_BF16X3_TAYLOR && c->b == 4 && c->Ac32.p != nullptr &&
+                       c->run_b4 == 16 && [&] {
+                           Sched &S = schedule(c, RTDM_PROD_AT);
+                           auto r = S.runs.find(16);
+                           return r != S.runs.end() && r->second->nch > 0;
+                       }();
+    auto as16 = [](float *p) { return reinterpret_cast<short *>(p); };
     int n0 = 2, low = all_products_prec(c);
     switch (c->opt.precision) {
     case RTDM_PREC_FP64: n0 = p + 1; break;
@@ -895,13 +904,45 @@ void build_propagator(rtdm_ctx *c, double dt, hipStream_t s)
         if (t64) launch_axpby(s, ne, sign, t64, 1.0, dst, dst);
         else launch_axpy_f32(s, ne, sign, t32, dst);
     };
-    int cur = 0;          // tau[cur] (FP64) or tau32[cur] (FP32) holds tau_{k-1}
+    int cur = 0;          // tau[cur] (FP64) or tau32[cur] (FP32 or split BF16) holds tau_{k-1}
     bool in32 = false;
+    if (low16 && n0 <= p) launch_to_bf16x2(s, pat_of(c, R_P).nnzb, 0, A.re.p, as16(c->Ac32.p));
     // FP32 copy of A: of its column-major copy at b = 13, of A itself (row-major) at b = 4
     if (low32 && n0 <= p)
         launch_to_f32(s, pat_of(c, R_P).nnzb, c->b, 0, c->b == 13 ? c->Ac.re.p : A.re.p, c->Ac32.p);
     for (int k = 2; k <= p; ++k) {
-        if (low32 && k >= n0) {
+        if (low16 && k >= n0) {
+            if (!in32) {
+                launch_to_bf16x2(s, pat_of(c, R_P).nnzb, 1, c->tau[cur].re.p, as16(c->tau32[cur].p));
+                in32 = true;
+            }
+            Sched &S = schedule(c, RTDM_PROD_AT);
+            const Runs &R = *S.runs.find(16)->second;
+            SpgemmArgs a;
+            a.nout = S.nout;
+            a.b = c->b;
+            a.alpha_re = dt / k;
+            a.nj = R.nj;
+            a.nch = R.nch;
+            a.ch_off = R.off.p;
+            a.ch_a = R.a.p;
+            a.ch_b = R.b.p;
+            a.ch_out = R.out.p;
+            // (-i)^k: k%4 == 0 -> +Re, 1 -> -Im, 2 -> -Re, 3 -> +Im
+            const double sign = (k % 4 == 0 || k % 4 == 3) ? 1.0 : -1.0;
+            double *udst = (k % 2 == 0) ? U.re.p : U.im.p;
+            const bool more = k < p;
+            const bool rec = c->timing && !c->capturing;
+            const size_t ev = 2 * c->recs.size();
+            if (rec) RT_HIP(hipEventRecord(event_at(c, ev), s));
+            launch_spgemm_r16(s, a, as16(c->Ac32.p), as16(c->tau32[cur].p), more ? as16(c->tau32[1 - cur].p) : nullptr,
+                              udst, sign);
+            if (rec) {
+                RT_HIP(hipEventRecord(event_at(c, ev + 1), s));
+                const double b3 = (double)c->b * c->b * c->b;
+                c->recs.push_back({RTDM_PROD_AT, (int)ev, (double)S.ntrip * 2.0 * b3});
+            }
+        } else if (low32 && k >= n0) {
             if (!in32) {
                 launch_to_f32(s, pat_of(c, R_P).nnzb, c->b, 0, c->tau[cur].re.p, c->tau32[cur].p);
                 in32 = true;
@@ -1347,7 +1388,10 @@ int rtdm_set_ranges(rtdm_ctx *c, double R_hs, double R_p, double R_k)
     c->Ac32.release();
     c->tau32[0].release();
     c->tau32[1].release();
-    if ((c->b == 13 || c->b == 4) && c->opt.precision == RTDM_PREC_FP32_TAYLOR) {
+    // FP32 copies of A and tau (FP32 late Taylor terms), or at b = 4 the same
+    // bytes as BF16 hi / lo planes (BF16x3 late Taylor terms)
+    if (((c->b == 13 || c->b == 4) && c->opt.precision == RTDM_PREC_FP32_TAYLOR) ||
+        (c->b == 4 && c->opt.precision == RTDM_PREC_BF16X3_TAYLOR)) {
         const int64_t ne = pat_of(c, R_P).nnzb * (int64_t)c->b * c->b;
         c->Ac32.alloc(ne);
         c->tau32[0].alloc(ne);

@@ -1706,6 +1706,119 @@ __global__ __launch_bounds__(256) void k_spgemm_b4r32(
     for (int e = 0; e < 4; ++e) c32[c * 16 + e * 4 + r] = alpha * h[e];
 }
 
+// BF16 x 2 storage of b = 4 blocks for the BF16x3 late Taylor terms: x =
+// hi + lo with the split of the register-split kernels (Split4<0>: round to
+// FP32, hi its BF16 rounding, lo that of the remainder).  Block p takes 32
+// values, its 16 hi parts then its 16 lo parts (64 bytes, one memory sector
+// like an FP32 block); `transpose` stores each block transposed, so that
+// column r of a right operand is four contiguous values.
+__global__ void k_to_bf16x2(int64_t n, int transpose, const double *__restrict__ in, short *__restrict__ out)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int w = (int)(e & 15);
+        const int64_t o = (e >> 4) * 32 + (transpose ? (w & 3) * 4 + (w >> 2) : w);
+        short h, l;
+        Split4<0>::split(in[e], 1.0f, h, l);
+        out[o] = h;
+        out[o + 16] = l;
+    }
+}
+
+void launch_to_bf16x2(hipStream_t s, int64_t nblocks, int transpose, const double *in, short *out)
+{
+    const int64_t n = nblocks * 16;
+    if (n == 0) return;
+    int64_t g = (n + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_to_bf16x2, dim3((unsigned)g), dim3(256), 0, s, n, transpose, in, out);
+    RT_HIP(hipGetLastError());
+}
+
+// BF16x3 late Taylor term at b = 4 over row runs of 16 outputs, operands
+// stored split (launch_to_bf16x2: A row-major, tau transposed): one wave per
+// run, lane 4 blk + r holding row r of the entry's A block and column r of
+// output blk's B block as four BF16 values per part (8-byte loads), three
+// v_mfma_f32_4x4x4_16b_bf16 per entry (hi hi, then hi lo and lo hi into a
+// second accumulator).  The result tau = alpha (h + m) is added into the FP64
+// plane u (u += u_sign tau: the propagator's sum) and, when c16 is set,
+// stored split and transposed as the next term's right operand.  The split,
+// the products and their order per output are those of the register-split
+// kernel (k_spgemm_b4x<..., 1, true>); this one moves half of its operand
+// bytes per triple (two 16-bit values instead of one FP64 per element).
+__global__ __launch_bounds__(256) void k_spgemm_b4r16(
+    int64_t nch, const int64_t *__restrict__ off, const int32_t *__restrict__ ea, const int32_t *__restrict__ eb,
+    const int32_t *__restrict__ rout, const short *__restrict__ a16, const short *__restrict__ b16,
+    short *__restrict__ c16, double alpha, double *__restrict__ u, double u_sign)
+{
+    typedef short v4 __attribute__((ext_vector_type(4)));
+    const int lane = threadIdx.x & 63;
+    const int blk = lane >> 2, r = lane & 3;
+    const int64_t wv = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wv >= nch) return;                     // uniform across the wave
+    const int64_t c = rout[wv * 16 + blk];
+    const int64_t t0 = off[wv];
+    const int nt = (int)(off[wv + 1] - t0);
+    const int slot = (blk & 3) * 4 + (blk >> 2);
+    f32x4 h = {0, 0, 0, 0}, m = {0, 0, 0, 0};
+    struct Ops {
+        v4 ah, al, bh, bl;
+    };
+    auto load_idx = [&](int t) { return make_int2(ea[t0 + t], eb[(t0 + t) * 16 + slot]); };
+    auto load_ops = [&](int2 ab, Ops &o) {
+        o.ah = o.al = o.bh = o.bl = v4{0, 0, 0, 0};
+        if (ab.y >= 0) {
+            const short *pa = a16 + (int64_t)ab.x * 32 + r * 4, *pb = b16 + (int64_t)ab.y * 32 + r * 4;
+            o.ah = *reinterpret_cast<const v4 *>(pa);        // A[r][0..3]
+            o.al = *reinterpret_cast<const v4 *>(pa + 16);
+            o.bh = *reinterpret_cast<const v4 *>(pb);        // B[0..3][r]
+            o.bl = *reinterpret_cast<const v4 *>(pb + 16);
+        }
+    };
+    if (nt > 0) {
+        // software pipeline as in b4_run_entries: indices two entries ahead, operands one
+        Ops cur, nxt;
+        int2 ab_n = make_int2(0, -1);
+        const int2 ab0 = load_idx(0);
+        if (1 < nt) ab_n = load_idx(1);
+        load_ops(ab0, cur);
+        for (int t = 0; t < nt; ++t) {
+            int2 ab_nn = make_int2(0, -1);
+            if (t + 2 < nt) ab_nn = load_idx(t + 2);
+            if (t + 1 < nt) load_ops(ab_n, nxt);
+            h = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(cur.ah, cur.bh, h, 0, 0, 0);
+            m = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(cur.ah, cur.bl, m, 0, 0, 0);
+            m = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(cur.al, cur.bh, m, 0, 0, 0);
+            cur = nxt;
+            ab_n = ab_nn;
+        }
+    }
+    if (c < 0) return;
+    v4 sh, sl;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const double v = alpha * ((double)h[e] + 1.0 * (double)m[e]);
+        const int64_t o = c * 16 + e * 4 + r;
+        u[o] = u[o] + u_sign * v;
+        short hh, ll;
+        Split4<0>::split(v, 1.0f, hh, ll);
+        sh[e] = hh;
+        sl[e] = ll;
+    }
+    if (c16) {
+        *reinterpret_cast<v4 *>(c16 + c * 32 + r * 4) = sh;        // transposed: column r of the block
+        *reinterpret_cast<v4 *>(c16 + c * 32 + 16 + r * 4) = sl;
+    }
+}
+
+void launch_spgemm_r16(hipStream_t s, const SpgemmArgs &a, const short *a16, const short *b16, short *c16,
+                       double *u, double u_sign)
+{
+    RT_CHECK(a.b == 4 && a.nch > 0 && a.nj == 16, RTDM_E_ARG, "split BF16 Taylor terms need b = 4 row runs of 16");
+    hipLaunchKernelGGL(k_spgemm_b4r16, dim3((unsigned)((a.nch + 3) / 4)), dim3(256), 0, s, a.nch, a.ch_off, a.ch_a,
+                       a.ch_b, a.ch_out, a16, b16, c16, a.alpha_re, u, u_sign);
+    RT_HIP(hipGetLastError());
+}
+
 void launch_spgemm_r32(hipStream_t s, const SpgemmArgs &a, const float *a32, const float *b32, float *c32,
                        const float *zero32)
 {

@@ -178,3 +178,20 @@ def test_b4_row_runs_reduced_precision(precision):
     bound = 1e-5 if precision == "fp32" else 1e-8
     print(f"{precision}: runs vs per-output K rel {rel(K16, K1):.2e}")
     assert rel(K16, K1) <= bound
+
+
+def test_b4_bf16_taylor_terms_from_split_storage_equal_register_split():
+    """bf16x3_taylor at b = 4 over row runs takes its late Taylor terms from A
+    and tau stored as BF16 hi / lo planes (k_spgemm_b4r16, the sum into U
+    fused); over per-output lists the kernel splits the FP64 operands in
+    registers.  The split and the products per output are the same, so the
+    two agree as closely as the FP64 products over runs and over lists
+    (test_b4_row_runs_match_oracle_and_single_outputs), far inside the form's
+    own error (1e-8 of K against FP64)."""
+    s = _b4_lattice()
+    K16, tr16, q16 = _run(s, 2, 2, run_b4=16, precision="bf16x3_taylor")
+    K1, tr1, q1 = _run(s, 2, 2, run_b4=1, precision="bf16x3_taylor")
+    print(f"split storage vs register split: K rel {rel(K16, K1):.2e}")
+    assert rel(K16, K1) <= 1e-13
+    np.testing.assert_allclose(tr16[:, 4], tr1[:, 4], rtol=1e-13)
+    np.testing.assert_allclose(q16, q1, rtol=0, atol=1e-13 * np.abs(q1).max())
