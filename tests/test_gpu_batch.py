@@ -147,7 +147,8 @@ def test_sixteen_step_graphs_equal_eager_steps_over_a_long_run():
 def _members():
     """Contexts of differing kinds: b = 4 and b = 13 kick sets (fixed H: the
     first step builds U eagerly), a Mulliken-H b = 13 lattice with two
-    corrector steps after the kick (eager too), and an ETRS b = 4 lattice."""
+    corrector steps after the kick (eager too), and an ETRS b = 4 lattice of
+    1,728 atoms (row runs on the whole chip, the stored U^dagger)."""
     kicks = [(0.01, 0, 0), (0, 0.01, 0), (0, 0, 0.01)]
     out = []
     for b in (4, 13):
@@ -157,7 +158,7 @@ def _members():
         rtdm.rtdm_apply_kicks(ctx.h, ctx.kick_vectors)
         out.append(ctx)
     s13 = synth.diamond_lattice((2, 2, 2), 13, 10.0, 16.0, seed=25, k0="local", h_model="mulliken")
-    s4 = synth.diamond_lattice((3, 3, 3), 4, 10.0, 12.0, seed=26, h_model="mulliken")
+    s4 = synth.diamond_lattice((6, 6, 6), 4, 10.0, 12.0, seed=26, h_model="mulliken")
     for s, opts in ((s13, dict(h_model="mulliken", sc_steps=2, sc_iters=1)),
                     (s4, dict(h_model="mulliken", propagator="etrs"))):
         ctx = gpu_context(s, **opts)
