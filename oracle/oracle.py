@@ -227,8 +227,9 @@ def spgemm(A: BSM, B: BSM, pat_c: Pattern, alpha: complex = 1.0, op_a: int = 0, 
     """
     b = A.b
     n = A.pat.n
-    a_val = np.ascontiguousarray(A.val).view(np.float64)
-    b_val = np.ascontiguousarray(B.val).view(np.float64)
+    # the C product reads interleaved complex128 blocks: real arrays are converted
+    a_val = np.ascontiguousarray(A.val, dtype=np.complex128).view(np.float64)
+    b_val = np.ascontiguousarray(B.val, dtype=np.complex128).view(np.float64)
     C = zeros(pat_c, b)
     c_val = C.val.view(np.float64)
     lo, hi = (0, n) if rows is None else rows
