@@ -202,10 +202,13 @@ int rtdm_destroy(rtdm_ctx *ctx);
  * size b, S and X carry the identity on an atom's padded functions and every
  * other matrix zeros, so the padded functions never mix with the atom's own
  * (all products act on them as on a separate identity block) and the
- * results on the real functions are those of the unpadded method.  Mixed
- * sizes need the FP64 exponential-midpoint step without corrector passes and
- * the block-Jacobi or previous inverse start (RTDM_E_UNSUPPORTED otherwise,
- * and for the external field, the ground state and training samples).  The
+ * results on the real functions are those of the unpadded method.  The
+ * on-site term of the Mulliken H leaves the padded functions out; the
+ * field's term reaches them only through the padded identity of S, where it
+ * stays on its own diagonal (K is zero there, so it changes nothing).  Mixed
+ * sizes need FP64 products and the block-Jacobi or previous inverse start
+ * (RTDM_E_UNSUPPORTED otherwise, and for the ground state and training
+ * samples); every propagator, the corrector and the field run.  The
  * caller's blocks are then nbf_i x nbf_j (row-major) in every upload and
  * download.  Invalidates ranges, matrices and schedules. */
 int rtdm_set_geometry(rtdm_ctx *ctx, int64_t n_atoms, const double *xyz, const int32_t *nbf);

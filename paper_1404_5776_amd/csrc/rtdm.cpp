@@ -1316,11 +1316,8 @@ int rtdm_set_geometry(rtdm_ctx *c, int64_t n_atoms, const double *xyz, const int
         RT_CHECK(b == 4 || b == 13, RTDM_E_UNSUPPORTED,
                  "mixed block sizes need a largest size of 4 or 13 (the padded size)");
         RT_CHECK(c->opt.precision == RTDM_PREC_FP64 && c->opt.inv_start != RTDM_INV_COLD &&
-                     c->opt.inv_start != RTDM_INV_LEARNED && c->opt.propagator == RTDM_PROP_EM &&
-                     c->opt.sc_steps == 0,
-                 RTDM_E_UNSUPPORTED,
-                 "mixed block sizes run the FP64 exponential-midpoint step (no corrector) with the block-Jacobi "
-                 "or previous start");
+                     c->opt.inv_start != RTDM_INV_LEARNED,
+                 RTDM_E_UNSUPPORTED, "mixed block sizes run FP64 products with the block-Jacobi or previous start");
     }
     for (int64_t e = 0; e < 3 * n_atoms; ++e) RT_CHECK(std::isfinite(xyz[e]), RTDM_E_ARG, "non-finite position");
     RT_HIP(hipDeviceSynchronize());
@@ -2114,7 +2111,6 @@ void step_ready(rtdm_ctx *c, double dt, int64_t n_steps)
                 c->uploaded[RTDM_MAT_S],
             "upload S, H0, K and build (or upload) the inverse first");
     RT_CHECK(std::isfinite(dt) && n_steps >= 0, RTDM_E_ARG, "bad step arguments");
-    RT_CHECK(!(c->mixed && c->field_on), RTDM_E_UNSUPPORTED, "the external field needs equal block sizes");
 }
 
 // Trace room, charges and the device step state for n_steps more steps.

@@ -67,3 +67,33 @@ def small_clusters(b):
         xyz = synth.cluster_positions(n, np.random.default_rng(91 + k))
         out.append(synth.build_system(f"c{n}_b{b}", xyz, b, ranges[0], ranges[1], 95 + k, k0="exact"))
     return out
+
+
+def padded_system(ms, b=13):
+    """A mixed-size system (synth.MixedSystem) as an equal-size system of b
+    functions per atom: identity in S on each atom's padded functions, zeros
+    in H0 and K0 there (the representation the library stores)."""
+    def pad(c, eye):
+        data = np.zeros((c.nnzb, b, b))
+        at = 0
+        for t, (i, j) in enumerate(zip(c.rows, c.cols)):
+            ni, nj = ms.nbf[i], ms.nbf[j]
+            data[t, :ni, :nj] = c.data[at:at + ni * nj].reshape(ni, nj)
+            if eye and i == j:
+                data[t, ni:, ni:] = np.eye(b - ni)
+            at += ni * nj
+        return synth.BlockCOO(c.rows, c.cols, data)
+
+    return synth.System(name="padded", xyz=ms.xyz, b=b, R_HS=ms.R_HS, R_K=ms.R_K, R_P=ms.R_P,
+                        S=pad(ms.S, True), H0=pad(ms.H0, False), K0=pad(ms.K0, False))
+
+
+def strip_padding(Kb: "O.BSM", ms) -> np.ndarray:
+    """Dense matrix over the real functions from padded blocks."""
+    off = np.concatenate([[0], np.cumsum(ms.nbf)])
+    out = np.zeros((off[-1], off[-1]), dtype=Kb.val.dtype)
+    r = Kb.pat.rows()
+    for p in range(Kb.pat.nnzb):
+        i, j = int(r[p]), int(Kb.pat.col[p])
+        out[off[i]:off[i + 1], off[j]:off[j + 1]] = Kb.val[p, :ms.nbf[i], :ms.nbf[j]]
+    return out

@@ -4,7 +4,10 @@ The library pads every block to 13 functions (identity in S and X on the
 padded functions, zeros elsewhere); the caller's blocks keep their own
 sizes.  K, X, the per-atom charges and the traces must equal the mixed-size
 oracle (dense over functions, no padding) at the FP64 bar, for a fixed and
-a Mulliken H.
+a Mulliken H.  The ETRS and fourth-order Magnus propagators, the corrector
+and the Gaussian field are checked against the block-sparse oracle run on
+the padded system (the reduction the mixed-size pins establish), started
+from the mixed-size oracle's inverse so that both take the same X.
 """
 
 import numpy as np
@@ -12,7 +15,8 @@ import pytest
 
 from oracle import mixed as M
 from paper_1404_5776_amd import rtdm, synth
-from tests._common import TOL, dipole_floor, gpu_charges, rel
+from oracle import oracle as O
+from tests._common import TOL, dipole_floor, gpu_charges, padded_system, rel, strip_padding
 
 pytestmark = pytest.mark.gpu
 
@@ -60,6 +64,71 @@ def test_mixed_sizes_match_oracle(h_model):
     Z = M.product(ref.U.conj().T, V, mt.mask_p)
     u_ref = M.frob(Z - mt.S) / M.frob(mt.S)
     assert abs(u_gpu - u_ref) <= 1e-6 * u_ref + 1e-14
+
+
+def _padded_inverse(ms, mt, st):
+    """The mixed-size oracle's converged X as padded blocks on the padded pattern."""
+    X, res = M.hotelling(mt)
+    pat = st.pat_p
+    val = np.zeros((pat.nnzb, st.S.b, st.S.b), dtype=np.complex128)   # the oracle's block type
+    rows = pat.rows()
+    for p in range(pat.nnzb):
+        i, j = int(rows[p]), int(pat.col[p])
+        ni, nj = ms.nbf[i], ms.nbf[j]
+        val[p, :ni, :nj] = X[mt.off[i]:mt.off[i + 1], mt.off[j]:mt.off[j + 1]]
+        if i == j:
+            val[p, ni:, ni:] = np.eye(st.S.b - ni)
+    return O.InverseResult(O.BSM(pat, st.S.b, val), len(res), res)
+
+
+CASES = {
+    "etrs": dict(propagator="etrs"),
+    "m4": dict(propagator="m4"),
+    "corrector": dict(sc_steps=2, sc_iters=1),
+    "field": dict(field=O.Field((0.02, -0.01, 0.005), 0.1, 0.05)),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_mixed_sizes_propagators_corrector_and_field(case):
+    opts = dict(CASES[case])
+    field = opts.pop("field", None)
+    ms = synth.mixed_cluster(36, 13, h_model="mulliken")
+    kappa = (0.0, 0.0, 0.0) if field is not None else ms.kappa
+    n_steps, dt = 5, 0.05
+    print(f"[gpu] mixed cluster {ms.n_atoms} atoms, {case}", flush=True)
+    ctx = rtdm.Context(0, h_model="mulliken", **opts).load_mixed(ms)
+    if field is not None:
+        rtdm.rtdm_set_field(ctx.h, field.E0, field.t0, field.sigma)
+    rtdm.rtdm_build_inverse(ctx.h)
+    rtdm.rtdm_apply_kick(ctx.h, kappa)
+    rtdm.rtdm_step(ctx.h, dt, 2)
+    rtdm.rtdm_step(ctx.h, dt, n_steps - 2)
+    K, _ = rtdm.rtdm_download_mixed(ctx.h, "K", ms.nbf)
+    tr = rtdm.rtdm_dipole_trace(ctx.h)
+    q = gpu_charges(ctx, ms.n_atoms)
+    rk, ck = _blocks(ctx, "K", None)
+    ctx.close()
+
+    mt = M.setup(ms)
+    ps = padded_system(ms)
+    st = O.setup(ps)
+    ref = O.propagate(st, n_steps, dt, kappa, h_model="mulliken", X=_padded_inverse(ms, mt, st),
+                      propagator=opts.get("propagator", "em"), field=field,
+                      sc_steps=opts.get("sc_steps", 0), sc_iters=opts.get("sc_iters", 0))
+    Kd = strip_padding(ref.K, ms)
+    e = rel(K, M.to_blocks(Kd, mt.off, rk, ck))
+    q_ref = O.mulliken(ref.K, st.S)
+    dq = float(np.abs(q - q_ref).max())
+    q0 = M.mulliken(mt, M.kick(mt, mt.K0, kappa))
+    P0 = O.dipole(q0, ms.xyz)
+    induced = np.abs(ref.rows[:, 1:4] - P0).max()
+    err = np.abs(tr[:, 1:4] - ref.rows[:, 1:4]).max()
+    print(f"K rel {e:.2e}, charges {dq:.2e}, dipole {err:.2e} of induced {induced:.2e}")
+    assert e <= TOL
+    assert dq <= TOL * np.abs(q_ref).max()
+    assert err <= TOL * induced + dipole_floor(q0, ms.xyz, dq)
+    assert np.abs(tr[:, 4] - ref.rows[:, 4]).max() <= TOL * abs(ref.rows[0, 4])
 
 
 def test_mixed_sizes_refuse_what_they_do_not_support():

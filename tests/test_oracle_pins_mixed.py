@@ -18,6 +18,7 @@ import pytest
 from oracle import mixed as M
 from oracle import oracle as O
 from paper_1404_5776_amd import synth
+from tests._common import padded_system as _padded, strip_padding as _strip
 
 pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
 
@@ -28,34 +29,6 @@ def _as_mixed(sys_):
         return synth.MixedCOO(c.rows, c.cols, c.data.reshape(-1))
     return synth.MixedSystem(name=sys_.name, xyz=sys_.xyz, nbf=sys_.nbf, R_HS=sys_.R_HS, R_K=sys_.R_K,
                              R_P=sys_.R_P, S=conv(sys_.S), H0=conv(sys_.H0), K0=conv(sys_.K0))
-
-
-def _padded(ms, b=13):
-    """The mixed system as an equal-size system of b functions per atom."""
-    def pad(c, eye):
-        data = np.zeros((c.nnzb, b, b))
-        at = 0
-        for t, (i, j) in enumerate(zip(c.rows, c.cols)):
-            ni, nj = ms.nbf[i], ms.nbf[j]
-            data[t, :ni, :nj] = c.data[at:at + ni * nj].reshape(ni, nj)
-            if eye and i == j:
-                data[t, ni:, ni:] = np.eye(b - ni)
-            at += ni * nj
-        return synth.BlockCOO(c.rows, c.cols, data)
-
-    return synth.System(name="padded", xyz=ms.xyz, b=b, R_HS=ms.R_HS, R_K=ms.R_K, R_P=ms.R_P,
-                        S=pad(ms.S, True), H0=pad(ms.H0, False), K0=pad(ms.K0, False))
-
-
-def _strip(Kb: O.BSM, ms) -> np.ndarray:
-    """Dense real-function matrix from padded blocks."""
-    off = ms.offsets
-    out = np.zeros((off[-1], off[-1]), dtype=Kb.val.dtype)
-    r = Kb.pat.rows()
-    for p in range(Kb.pat.nnzb):
-        i, j = int(r[p]), int(Kb.pat.col[p])
-        out[off[i]:off[i + 1], off[j]:off[j + 1]] = Kb.val[p, :ms.nbf[i], :ms.nbf[j]]
-    return out
 
 
 def _rel(a, b):
