@@ -524,7 +524,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU path (spatial "
+        print(json.dumps({"error": "bench.py runs on one GPU only; the multi-GPU path (spatial "
                                    "domain decomposition with halo exchange) is a design, not built",
                           "n_gpus": args.gpus}))
         sys.exit(2)

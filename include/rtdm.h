@@ -58,7 +58,7 @@ enum {
     RTDM_E_HIP = -4,          /* a HIP runtime call failed */
     RTDM_E_NOCONV = -5,       /* Hotelling iteration did not converge */
     RTDM_E_NUMERIC = -6,      /* non-finite value detected */
-    RTDM_E_UNSUPPORTED = -7   /* valid request this build does not implement */
+    RTDM_E_UNSUPPORTED = -7   /* valid request the library does not implement */
 };
 
 /* Matrix slots.  Range and value type of each slot:

@@ -72,7 +72,7 @@ def test_fullsize_triple_counts(big):
         Z = O.zeros(pp, s.b)
         _, t = O.spgemm(Z, Z, pp, rows=(i, i + 1))
         assert t == cnt
-    # survey sizing: about 1.06e8 triples for A T on this lattice
+    # expected size (a sampled count of the lattice's triples): about 1.06e8 triples for A T on this lattice
     assert 0.9e8 < out["AT"][1] < 1.2e8
 
 

@@ -72,7 +72,7 @@ def test_fullsize_b4_triple_counts(big4):
         Z = O.zeros(pp, s.b)
         _, t = O.spgemm(Z, Z, pp, rows=(i, i + 1))
         assert t == cnt
-    # survey sizing for this workload: about 4.1e8 triples for A T and U K
+    # expected size for this workload (a sampled count): about 4.1e8 triples for A T and U K
     assert 3.7e8 < out["AT"][1] < 4.5e8
     assert 3.7e8 < out["UK"][1] < 4.5e8
 
