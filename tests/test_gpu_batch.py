@@ -72,14 +72,16 @@ def _run(s, steps_chunks, use_graph, **opts):
     return out
 
 
-@pytest.mark.parametrize("which", ["fixed_b4", "mulliken_b4", "mulliken_b13"])
+@pytest.mark.parametrize("which", ["fixed_b4", "mulliken_b4", "mulliken_b4_1728", "mulliken_b13"])
 @pytest.mark.parametrize("graph_steps", [1, 4])
 def test_graph_replays_equal_eager_steps(which, graph_steps):
     """Steps replayed from captured graphs (one step per graph, or four: the
     calls of 4, 5 and 9 steps replay 4-step graphs and the one-step graph for
-    the rest) repeat the eager steps bit for bit."""
+    the rest) repeat the eager steps bit for bit (the 1,728-atom lattice with
+    row runs on the whole chip and the stored U^dagger)."""
     s = {"fixed_b4": synth.config1,
          "mulliken_b4": lambda: synth.diamond_lattice((3, 3, 3), 4, 10.0, 12.0, seed=22, h_model="mulliken"),
+         "mulliken_b4_1728": lambda: synth.diamond_lattice((6, 6, 6), 4, 10.0, 12.0, seed=24, h_model="mulliken"),
          "mulliken_b13": lambda: synth.diamond_lattice((2, 2, 2), 13, 10.0, 16.0, seed=21, k0="local",
                                                        h_model="mulliken")}[which]()
     chunks = (3, 4, 5, 9)
