@@ -77,3 +77,8 @@ def test_changes_reach_the_propagation():
     for change in ("H0", "X", "inverse", "field"):
         Kc, _ = _run(s, 0, 0, change)
         assert rel(Kc, K) > 1e3 * AGREE, change
+
+
+def test_xh_every_step_takes_zero_or_one():
+    with pytest.raises(rtdm.RtdmError):
+        rtdm.Context(0, h_model="mulliken", xh_every_step=2)
